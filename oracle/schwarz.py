@@ -1,0 +1,225 @@
+"""Overlapping Schwarz preconditioners with subdomain ILU(0) — plain Python, FP64.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Section 3.1: the domain is split into np non-overlapping boxes Omega_k, each
+extended by delta cell layers to Omega_k^delta.  R_k^delta restricts a vector to
+Omega_k^delta; A_k = R_k^delta J (R_k^delta)^T; inv(A_k) is approximated by an
+incomplete LU factorisation.  Classical AS (eq. invM) sums (R_k^delta)^T inv(A_k)
+R_k^delta; the left-restricted variant writes back only the owned part Omega_k,
+the right-restricted variant restricts the input to the owned part.
+
+Readings where the paper is silent (shared with the HIP path):
+* split sizes: n cells into m parts of sizes floor(n/m) or floor(n/m)+1, the
+  larger ones first; Neumann boxes are clipped at the domain boundary; periodic
+  boxes wrap, and every periodic direction must have at least 2 parts with box
+  length <= n-2 so no box touches itself across the wrap;
+* unknown order inside Omega_k^delta: cells lexicographic with x fastest, and at
+  each cell u before v (the interleaved X of Section 3.1);
+* ILU(0) pattern: the structural stencil pattern of the Jacobian restricted to
+  the box (u-row: u on the radius-2 diamond, v on the radius-1 star; v-row: v on
+  the star and u at the cell), independent of numerically zero values.
+
+Pins: textbook ILU(0) property (LU)_ij = A_ij on the pattern; ILU(0) equals the
+exact LU when the pattern admits no fill; one subdomain with zero overlap and an
+exact subdomain solve reproduces the global solve (tests).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def split(n: int, parts: int) -> List[Tuple[int, int]]:
+    """(start, length) of ``parts`` contiguous pieces of n cells."""
+    base, rem = divmod(n, parts)
+    out, s = [], 0
+    for k in range(parts):
+        ln = base + (1 if k < rem else 0)
+        out.append((s, ln))
+        s += ln
+    return out
+
+
+def stencil_offsets(dim: int, radius: int):
+    """Offsets d with |d|_1 <= radius, in array-axis order (axis 0 slowest)."""
+    rng = range(-radius, radius + 1)
+    out = []
+    for d in np.ndindex(*([2 * radius + 1] * dim)):
+        off = tuple(int(x) - radius for x in d)
+        if sum(abs(x) for x in off) <= radius:
+            out.append(off)
+    return out
+
+
+def row_pattern(dim: int):
+    """Structural Jacobian pattern: list of (row type, offset, column type), type 0 = u, 1 = v."""
+    pat = []
+    for off in stencil_offsets(dim, 2):
+        pat.append((0, off, 0))
+    for off in stencil_offsets(dim, 1):
+        pat.append((0, off, 1))
+    for off in stencil_offsets(dim, 1):
+        pat.append((1, off, 1))
+    pat.append((1, tuple([0] * dim), 0))
+    return pat
+
+
+@dataclass
+class Subdomain:
+    box_start: Tuple[int, ...]     # unwrapped start of Omega_k^delta (array-axis order)
+    box_len: Tuple[int, ...]
+    own_start: Tuple[int, ...]     # Omega_k, also unwrapped
+    own_len: Tuple[int, ...]
+    cells: List[Tuple[int, ...]]   # box coordinates of existing cells, lexicographic
+    gcell: np.ndarray              # flat global cell index per entry of ``cells``
+    owned: np.ndarray              # bool per entry of ``cells``
+
+    def unknowns(self, ncell: int) -> np.ndarray:
+        """Global indices (stacked [u; v] vector) in interleaved order u_c, v_c."""
+        idx = np.empty(2 * len(self.cells), dtype=np.int64)
+        idx[0::2] = self.gcell
+        idx[1::2] = self.gcell + ncell
+        return idx
+
+
+def decompose(shape, parts, overlap: int, bc: str) -> List[Subdomain]:
+    """Overlapping boxes Omega_k^delta of Section 3.1 (array-axis order for shape/parts)."""
+    dim = len(shape)
+    pieces = [split(shape[a], parts[a]) for a in range(dim)]
+    if bc == "periodic":
+        for a in range(dim):
+            if parts[a] < 2:
+                raise ValueError("periodic directions need at least 2 subdomains")
+            longest = max(ln for _, ln in pieces[a]) + 2 * overlap
+            if longest > shape[a] - 2:
+                raise ValueError("overlapping box would touch itself across the periodic wrap")
+    subs = []
+    for combo in np.ndindex(*parts):
+        own_start = tuple(pieces[a][combo[a]][0] for a in range(dim))
+        own_len = tuple(pieces[a][combo[a]][1] for a in range(dim))
+        box_start = tuple(s - overlap for s in own_start)
+        box_len = tuple(l + 2 * overlap for l in own_len)
+        cells, gcell, owned = [], [], []
+        for b in np.ndindex(*box_len):
+            g = [box_start[a] + b[a] for a in range(dim)]
+            if bc == "periodic":
+                g = [g[a] % shape[a] for a in range(dim)]
+            elif any(g[a] < 0 or g[a] >= shape[a] for a in range(dim)):
+                continue
+            cells.append(tuple(b))
+            gcell.append(int(np.ravel_multi_index(tuple(g), shape)))
+            owned.append(all(overlap <= b[a] < overlap + own_len[a] for a in range(dim)))
+        subs.append(Subdomain(box_start, box_len, own_start, own_len, cells,
+                              np.array(gcell, dtype=np.int64), np.array(owned, dtype=bool)))
+    return subs
+
+
+def subdomain_matrix(J, sub: Subdomain, shape) -> Dict[int, Dict[int, float]]:
+    """A_k = R_k^delta J (R_k^delta)^T on the structural pattern, as row -> {col: value}
+    in the subdomain's interleaved order."""
+    dim = len(shape)
+    ncell = int(np.prod(shape))
+    J = J.tocsr()
+    local = {c: i for i, c in enumerate(sub.cells)}
+    rows: Dict[int, Dict[int, float]] = {}
+    for i, c in enumerate(sub.cells):
+        for t in (0, 1):
+            rows[2 * i + t] = {}
+    for rt, off, ct in row_pattern(dim):
+        for i, c in enumerate(sub.cells):
+            nb = tuple(c[a] + off[a] for a in range(dim))
+            j = local.get(nb)
+            if j is None:
+                continue
+            grow = int(sub.gcell[i]) + rt * ncell
+            gcol = int(sub.gcell[j]) + ct * ncell
+            rows[2 * i + rt][2 * j + ct] = float(J[grow, gcol])
+    return rows
+
+
+def ilu0(rows: Dict[int, Dict[int, float]]):
+    """Textbook ILU(0) (IKJ order) on the pattern of ``rows``.
+
+    Returns a dict row -> {col: value} holding L (unit diagonal, entries col < row)
+    and U (col >= row) in place, with (LU)_ij = A_ij for every (i, j) in the pattern."""
+    a = {i: dict(r) for i, r in rows.items()}
+    n = len(a)
+    for i in range(n):
+        ri = a[i]
+        for k in sorted(c for c in ri if c < i):
+            ri[k] = ri[k] / a[k][k]
+            lik = ri[k]
+            for j, ukj in a[k].items():
+                if j > k and j in ri:
+                    ri[j] -= lik * ukj
+    return a
+
+
+def ilu_solve(fac, b):
+    """Solve L U x = b with the factors of ilu0 (forward then backward substitution)."""
+    n = len(fac)
+    y = np.array(b, dtype=np.float64)
+    for i in range(n):
+        s = y[i]
+        for j, v in fac[i].items():
+            if j < i:
+                s -= v * y[j]
+        y[i] = s
+    x = y
+    for i in range(n - 1, -1, -1):
+        s = x[i]
+        for j, v in fac[i].items():
+            if j > i:
+                s -= v * x[j]
+        x[i] = s / fac[i][i]
+    return x
+
+
+def to_dense(rows, n=None):
+    n = n or len(rows)
+    M = np.zeros((n, n))
+    for i, r in rows.items():
+        for j, v in r.items():
+            M[i, j] = v
+    return M
+
+
+class Schwarz:
+    """Additive Schwarz preconditioner M^{-1} with subdomain ILU(0) (or exact LU).
+
+    kind: "left" (restricted extension; the paper's choice), "right" (restricted
+    restriction) or "classical" (eq. invM)."""
+
+    def __init__(self, J, shape, parts, overlap, bc, kind="left", exact=False):
+        self.shape = tuple(shape)
+        self.ncell = int(np.prod(shape))
+        self.kind = kind
+        self.subs = decompose(self.shape, parts, overlap, bc)
+        self.factors = []
+        self.exact = exact
+        for sub in self.subs:
+            rows = subdomain_matrix(J, sub, self.shape)
+            if exact:
+                self.factors.append(np.linalg.inv(to_dense(rows)))
+            else:
+                self.factors.append(ilu0(rows))
+
+    def apply(self, r):
+        r = np.asarray(r, dtype=np.float64)
+        z = np.zeros_like(r)
+        for sub, fac in zip(self.subs, self.factors):
+            idx = sub.unknowns(self.ncell)
+            own = np.repeat(sub.owned, 2)
+            rk = r[idx].copy()
+            if self.kind == "right":
+                rk[~own] = 0.0
+            xk = fac @ rk if self.exact else ilu_solve(fac, rk)
+            if self.kind == "left":
+                z[idx[own]] += xk[own]
+            else:
+                z[idx] += xk
+        return z

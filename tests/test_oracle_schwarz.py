@@ -1,0 +1,116 @@
+"""Pins for the oracle's overlapping Schwarz preconditioners and textbook ILU(0)
+(Section 3.1, eq. invM and the restricted variants)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from acch_inputs import perturbed_pair
+from oracle import jacobian, schwarz
+from oracle.params import Problem
+
+
+def _J(shape, bc, seed=1, dt=1e-2):
+    prob = Problem(bc=bc, lengths=(1.0, 1.0, 1.0)[:len(shape)])
+    u1, v1, u0, v0 = perturbed_pair(shape, seed)
+    return jacobian.jacobian(u1, v1, u0, v0, dt, prob)
+
+
+def test_split_sizes():
+    assert schwarz.split(10, 3) == [(0, 4), (4, 3), (7, 3)]
+    assert schwarz.split(64, 2) == [(0, 32), (32, 32)]
+    assert sum(l for _, l in schwarz.split(97, 8)) == 97
+
+
+def test_pattern_counts():
+    assert len(schwarz.row_pattern(2)) == 24
+    assert len(schwarz.row_pattern(3)) == 40
+
+
+@pytest.mark.parametrize("bc,parts,ov", [("periodic", (2, 2), 1), ("neumann", (2, 3), 2), ("neumann", (1, 1), 0)])
+def test_ilu0_defining_property(bc, parts, ov):
+    """(LU)_ij = A_ij for every (i, j) in the pattern of A_k (textbook ILU(0))."""
+    shape = (12, 14)
+    J = _J(shape, bc)
+    for sub in schwarz.decompose(shape, parts, ov, bc)[:2]:
+        rows = schwarz.subdomain_matrix(J, sub, shape)
+        fac = schwarz.ilu0(rows)
+        F = schwarz.to_dense(fac)
+        L = np.tril(F, -1) + np.eye(len(F))
+        U = np.triu(F)
+        LU = L @ U
+        A = schwarz.to_dense(rows)
+        for i, r in rows.items():
+            for j in r:
+                assert abs(LU[i, j] - A[i, j]) <= 1e-13 * np.max(np.abs(A))
+
+
+def test_ilu0_equals_lu_without_fill():
+    """A tridiagonal matrix has no fill, so ILU(0) is its exact LU."""
+    n = 12
+    rng = np.random.default_rng(0)
+    main = rng.uniform(4, 5, n)
+    off1 = rng.uniform(-1, 1, n - 1)
+    off2 = rng.uniform(-1, 1, n - 1)
+    A = np.diag(main) + np.diag(off1, 1) + np.diag(off2, -1)
+    rows = {i: {j: A[i, j] for j in range(max(0, i - 1), min(n, i + 2))} for i in range(n)}
+    fac = schwarz.ilu0(rows)
+    b = rng.standard_normal(n)
+    assert np.allclose(schwarz.ilu_solve(fac, b), np.linalg.solve(A, b), rtol=1e-13, atol=1e-14)
+
+
+def test_subdomain_matrix_is_restriction():
+    """A_k equals the principal submatrix R J R^T of the global Jacobian."""
+    shape = (10, 12)
+    J = _J(shape, "periodic")
+    sub = schwarz.decompose(shape, (2, 2), 1, "periodic")[3]
+    idx = sub.unknowns(int(np.prod(shape)))
+    want = J.toarray()[np.ix_(idx, idx)]
+    got = schwarz.to_dense(schwarz.subdomain_matrix(J, sub, shape))
+    assert np.array_equal(got, want)
+
+
+def test_decomposition_owned_sets_partition():
+    for bc, shape, parts, ov in [("periodic", (12, 16), (2, 4), 2), ("neumann", (9, 11), (3, 2), 1)]:
+        subs = schwarz.decompose(shape, parts, ov, bc)
+        owned = np.concatenate([s.gcell[s.owned] for s in subs])
+        assert np.array_equal(np.sort(owned), np.arange(int(np.prod(shape))))
+
+
+def test_periodic_box_must_not_wrap_onto_itself():
+    with pytest.raises(ValueError):
+        schwarz.decompose((8, 8), (1, 2), 1, "periodic")
+    with pytest.raises(ValueError):
+        schwarz.decompose((8, 8), (2, 2), 2, "periodic")
+
+
+def test_single_exact_subdomain_is_the_inverse():
+    """One Neumann subdomain without overlap and an exact subdomain solve: M^{-1} = J^{-1}."""
+    shape = (6, 7)
+    J = _J(shape, "neumann")
+    P = schwarz.Schwarz(J, shape, (1, 1), 0, "neumann", kind="left", exact=True)
+    r = np.random.default_rng(3).standard_normal(J.shape[0])
+    assert np.allclose(P.apply(r), spla.spsolve(J.tocsc(), r), rtol=1e-11, atol=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["left", "right", "classical"])
+def test_schwarz_variants_precondition_gmres(kind):
+    """Each variant is a usable preconditioner: GMRES converges to the direct solution."""
+    shape = (16, 16)
+    J = _J(shape, "periodic", dt=5e-2)
+    P = schwarz.Schwarz(J, shape, (2, 2), 1, "periodic", kind=kind)
+    r = np.random.default_rng(4).standard_normal(J.shape[0])
+    M = spla.LinearOperator(J.shape, matvec=P.apply)
+    x, info = spla.gmres(J, r, M=M, rtol=1e-11, restart=30, maxiter=200)
+    assert info == 0
+    assert np.linalg.norm(J @ x - r) <= 1e-10 * np.linalg.norm(r)
+
+
+def test_left_ras_writes_each_unknown_once():
+    """Left-RAS with identity subdomain matrices is the identity map."""
+    shape = (16, 18)
+    n = 2 * int(np.prod(shape))
+    I = sp.identity(n, format="csr")
+    P = schwarz.Schwarz(I, shape, (2, 3), 2, "periodic", kind="left")
+    r = np.random.default_rng(5).standard_normal(n)
+    assert np.allclose(P.apply(r), r, rtol=0, atol=0)
