@@ -1,0 +1,193 @@
+/*
+ * acch — energy-stable Allen–Cahn/Cahn–Hilliard time stepping on one MI355X (gfx950).
+ *
+ * Each accepted time step solves the nonlinear system of scheme (2.20)
+ * (Section 2: (U^{n+1} - U^n)/dt_n = -A~ G~^S with the truncated-series discrete
+ * variational derivative G~^S of Lemma 2.2 / eq. D2-1) by the Newton–Krylov–Schwarz
+ * method of Section 3.1 (inexact Newton + line search, right-preconditioned restarted
+ * GMRES, restricted additive Schwarz with subdomain ILU(0)), with the adaptive time
+ * step control of Section 3.2 (eq. sencondt, sqrt(2) retries, eta doubling).
+ *
+ * Conventions for every entry point below
+ *  - Return value: ACCH_OK (0) or one of the ACCH_E* codes; no exceptions cross this
+ *    boundary.  acch_strerror() names a code; acch_last_error() returns a message
+ *    for the last failure on the calling thread.
+ *  - "host" pointers point to CPU memory, "device" pointers to GPU memory of the
+ *    device that was current at acch_create.  The library never allocates device
+ *    memory: every device buffer is carved out of the caller's workspace
+ *    (acch_params.workspace), which must stay alive until acch_destroy.
+ *  - Fields are FP64 arrays of nx*ny (2D) cells, x fastest; a "state vector" is
+ *    2*ncell doubles: the u field followed by the v field.
+ *  - Work is enqueued on acch_params.stream (a hipStream_t, NULL = default stream);
+ *    calls that return host values synchronise that stream.
+ *  - A context is not thread safe; distinct contexts may be used concurrently.
+ */
+#ifndef ACCH_H
+#define ACCH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ACCH_OK = 0,
+  ACCH_EINVAL = 1,     /* invalid argument or parameter, workspace too small      */
+  ACCH_EDOMAIN = 2,    /* a state outside the admissible set u+-v in (0,1)         */
+  ACCH_EDIVERGED = 3,  /* Newton–Krylov–Schwarz failed at dt_min (or the fixed dt) */
+  ACCH_EDEVICE = 4,    /* a HIP runtime error                                      */
+  ACCH_EUNSUPPORTED = 5/* a configuration this build does not implement            */
+};
+
+enum { ACCH_BC_PERIODIC = 0, ACCH_BC_NEUMANN = 1 };
+/* Schwarz variant (Section 3.1): left-restricted (restricted extension, the paper's
+ * choice), right-restricted (restricted restriction) or classical (eq. invM). */
+enum { ACCH_RAS_LEFT = 0, ACCH_RAS_RIGHT = 1, ACCH_AS_CLASSICAL = 2 };
+/* Precision of the subdomain ILU(0) factors and triangular solves; the residual,
+ * Jacobian products, Arnoldi process, Newton update and diagnostics stay FP64. */
+enum { ACCH_PREC_FP64 = 0, ACCH_PREC_MIXED = 1 };
+/* Time level of the mobility c(u,v) inside A~ (Section 2 writes c^n but builds the
+ * scheme by the trapezoidal rule at the half step): midpoint state (default),
+ * average of the two end values, or the explicit level-n value. */
+enum { ACCH_MOB_MIDPOINT = 0, ACCH_MOB_AVERAGE = 1, ACCH_MOB_EXPLICIT = 2 };
+
+typedef struct {
+  int dim;              /* 2 (3 reserved)                                            */
+  int n[3];             /* cells per direction (x, y, z)                              */
+  double L[3];          /* domain lengths; 0 means 1.0                                */
+  int bc;               /* ACCH_BC_*                                                  */
+  double alpha, beta, theta, gamma, rho;  /* Section 1 coefficients, all > 0         */
+  int S;                /* series order of Lemma 2.2; 0 means 10 (Section 4)          */
+  int adaptive;         /* 1: eq. sencondt control; 0: fixed dt_fixed                 */
+  double dt_fixed, dt_min, dt_max, eta0;
+  double newton_rtol, newton_atol;        /* eps_r, eps_a of Section 3.1; 0 -> 1e-8, 1e-13 */
+  int newton_max_it;                      /* 0 -> 50                                  */
+  double gmres_rtol, gmres_atol;          /* xi_r, xi_a; 0 -> 1e-8, 1e-14             */
+  int gmres_restart;                      /* 0 -> 30 (maximum 30)                     */
+  int gmres_max_restarts;                 /* 0 -> 10                                  */
+  int ras_type;                           /* ACCH_RAS_* (left only in this build)     */
+  int sub[3];                             /* subdomains per direction                 */
+  int overlap;                            /* delta, cell layers                       */
+  int ilu_reuse;                          /* 1: factor once per step attempt (default) */
+  int precision;                          /* ACCH_PREC_*                              */
+  int mobility_mode;                      /* ACCH_MOB_*                               */
+  int xd_norm;                            /* 0: plain 2-norm of X^n - X^{n-1};
+                                             1: cell-volume weighted                 */
+  int mass_projection;                    /* 1 (default): remove the mean of the u part
+                                             of each Newton direction              */
+  int log_energy;                         /* 1 (default): energy and mass per step     */
+  double ilu_shift;                       /* sigma >= 0: the subdomain ILU(0) factors
+                                             A_k + sigma diag(A_k); 0 is plain ILU(0) */
+  void *workspace;                        /* device buffer, >= acch_workspace_bytes    */
+  size_t workspace_bytes;
+  void *stream;                           /* hipStream_t                              */
+} acch_params;
+
+typedef struct {
+  double t, dt, eta, energy, mass, fnorm;
+  int newton_its;       /* Newton iterations of all attempts of this step          */
+  int gmres_its;        /* GMRES iterations of all attempts of this step           */
+  int retries;          /* diverged attempts before acceptance                       */
+  int status;           /* ACCH_OK                                                   */
+} acch_step_info;
+
+typedef struct acch_ctx acch_ctx;
+
+/* Fill unset fields with the documented defaults (paper values of Section 4 where
+ * it states them).  Host pointer; never fails on a valid pointer. */
+void acch_params_default(acch_params *p);
+
+/* Device bytes the workspace must hold for parameters p (host pointer). */
+int acch_workspace_bytes(const acch_params *p, size_t *bytes);
+
+/* Create a solver for the initial fields u0, v0 (host arrays, copied).  Validates the
+ * parameters and the admissible set (ACCH_EDOMAIN), carves the workspace, builds the
+ * subdomain maps of Section 3.1.  *out receives a context owned by the library. */
+int acch_create(const acch_params *p, const double *u0, const double *v0, acch_ctx **out);
+
+/* Advance nsteps accepted time steps.  info (host, may be NULL) receives one record
+ * per accepted step; *accepted (may be NULL) the number accepted.  On ACCH_EDIVERGED
+ * the state stays at the last accepted step. */
+int acch_step(acch_ctx *c, int nsteps, acch_step_info *info, int *accepted);
+
+/* Discrete energy E~ (eqs. relations, freeenergy, exact Phi) and mass sum(u) h^d of
+ * the current state, as host doubles. */
+int acch_energy(acch_ctx *c, double *energy, double *mass);
+
+int acch_destroy(acch_ctx *c);
+
+/* Copy the current state out to / in from host arrays of ncell doubles each.
+ * set_fields checks admissibility (ACCH_EDOMAIN) and resets the step history
+ * (the next adaptive step predicts as a first step) but keeps t and eta. */
+int acch_get_fields(acch_ctx *c, double *u, double *v);
+int acch_set_fields(acch_ctx *c, const double *u, const double *v);
+
+/* Controller state: time, last accepted dt, eta. */
+int acch_get_time(acch_ctx *c, double *t, double *dt_prev, double *eta);
+
+/* ---- operator level entry points (one stage of the per-step solve each) ----
+ * All vectors are device state vectors (2*ncell doubles) unless stated. */
+
+/* F(X; Xn, dt) of scheme (2.20) into F.  *fnorm2 (host, may be NULL) = ||F||^2;
+ * *inadmissible (host, may be NULL) = number of cells of X outside the admissible set. */
+int acch_residual(acch_ctx *c, const double *X, const double *Xn, double dt, double *F,
+                  double *fnorm2, int *inadmissible);
+
+/* Analytic Jacobian dF/dX at (X; Xn, dt) (Section 3.1, J_m) into the context's
+ * matrix storage: slot arrays J[slot][cell], 24 slots in 2D:
+ *   u-row/u-col offsets (dx,dy): 0:(0,0) 1:(-1,0) 2:(1,0) 3:(0,-1) 4:(0,1) 5:(-2,0)
+ *     6:(2,0) 7:(0,-2) 8:(0,2) 9:(-1,-1) 10:(1,-1) 11:(-1,1) 12:(1,1)
+ *   u-row/v-col: 13:(0,0) 14:(-1,0) 15:(1,0) 16:(0,-1) 17:(0,1)
+ *   v-row/v-col: 18:(0,0) 19:(-1,0) 20:(1,0) 21:(0,-1) 22:(0,1)
+ *   v-row/u-col: 23:(0,0)
+ * Entries whose neighbour lies outside a Neumann domain are zero. */
+int acch_jacobian(acch_ctx *c, const double *X, const double *Xn, double dt);
+
+/* y = J x with the context's Jacobian. */
+int acch_apply_jacobian(acch_ctx *c, const double *x, double *y);
+
+/* Extract the subdomain matrices A_k = R_k J R_k^T and factor them by ILU(0)
+ * (of A_k + ilu_shift * diag(A_k)). */
+int acch_factor(acch_ctx *c);
+
+/* z = M^{-1} r, the Schwarz preconditioner with the current factors. */
+int acch_precondition(acch_ctx *c, const double *r, double *z);
+
+/* Solve J S = -F by right-preconditioned restarted (flexible) GMRES from S = 0 with
+ * the context's Jacobian and factors; *iterations and *resid (host, may be NULL)
+ * receive the total iterations and the final residual estimate. */
+int acch_gmres(acch_ctx *c, const double *F, double *S, int *iterations, double *resid);
+
+/* One Newton solve of scheme (2.20) at the given dt from the current state, without
+ * the dt controller; on success the state advances (t += dt).  info may be NULL. */
+int acch_solve_step(acch_ctx *c, double dt, acch_step_info *info);
+
+/* Copy an internal buffer to a device buffer `out` of at least *bytes bytes
+ * (call with out = NULL to query *bytes):
+ *   ACCH_EXPORT_JACOBIAN: J[slot][cell] FP64 (layout above);
+ *   ACCH_EXPORT_FACTORS:  ILU(0) factors as FP64 [sub][slot][by][bx] over each
+ *     subdomain box (box-lexicographic, x fastest), 24 slots in 2D:
+ *     L of the u-row (unit diagonal): 0:u(-1,0) 1:u(-2,0) 2:u(1,-1) 3:u(0,-1)
+ *       4:u(-1,-1) 5:u(0,-2) 6:v(-1,0) 7:v(0,-1);  L of the v-row: 8:v(-1,0)
+ *       9:v(0,-1) 10:u(0,0);
+ *     U of the u-row: 11: 1/diag, 12:u(1,0) 13:u(2,0) 14:u(-1,1) 15:u(0,1)
+ *       16:u(1,1) 17:u(0,2) 18:v(0,0) 19:v(1,0) 20:v(0,1);
+ *     U of the v-row: 21: 1/diag, 22:v(1,0) 23:v(0,1).
+ *   ACCH_EXPORT_BOXES: int32 [sub][4] = box origin x, y (unwrapped) and box
+ *     width, height (all boxes padded to the same width/height). */
+enum { ACCH_EXPORT_JACOBIAN = 0, ACCH_EXPORT_FACTORS = 1, ACCH_EXPORT_BOXES = 2 };
+int acch_export(acch_ctx *c, int which, void *out, size_t *bytes);
+
+/* Number of cells and of subdomains, the padded box size, and the kernel-launch
+ * statistics of the last acch_step call (launches, host synchronisations). */
+int acch_info(acch_ctx *c, long *ncell, int *nsub, int *box_w, int *box_h);
+
+const char *acch_strerror(int code);
+const char *acch_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACCH_H */

@@ -159,6 +159,17 @@ def ilu0(rows: Dict[int, Dict[int, float]]):
     return a
 
 
+def shifted(rows, sigma):
+    """A + sigma diag(A): the diagonal entries scaled by (1 + sigma).  Plain ILU(0) of the
+    biharmonic-dominated u-block can produce pivots of either sign once the
+    dt h^{-4} term dominates; the shifted matrix keeps them positive (a Manteuffel
+    shift).  The preconditioner changes, the Newton root does not."""
+    out = {i: dict(r) for i, r in rows.items()}
+    for i in out:
+        out[i][i] = out[i][i] * (1.0 + sigma)
+    return out
+
+
 def ilu_solve(fac, b):
     """Solve L U x = b with the factors of ilu0 (forward then backward substitution)."""
     n = len(fac)
@@ -194,7 +205,7 @@ class Schwarz:
     kind: "left" (restricted extension; the paper's choice), "right" (restricted
     restriction) or "classical" (eq. invM)."""
 
-    def __init__(self, J, shape, parts, overlap, bc, kind="left", exact=False):
+    def __init__(self, J, shape, parts, overlap, bc, kind="left", exact=False, shift=0.0):
         self.shape = tuple(shape)
         self.ncell = int(np.prod(shape))
         self.kind = kind
@@ -203,6 +214,8 @@ class Schwarz:
         self.exact = exact
         for sub in self.subs:
             rows = subdomain_matrix(J, sub, self.shape)
+            if shift:
+                rows = shifted(rows, shift)
             if exact:
                 self.factors.append(np.linalg.inv(to_dense(rows)))
             else:

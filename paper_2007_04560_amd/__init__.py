@@ -1,0 +1,9 @@
+"""acch: energy-stable Allen–Cahn/Cahn–Hilliard time stepping on MI355X (gfx950).
+
+The per-time-step Newton–Krylov–Schwarz solve of scheme (2.20) runs in the HIP
+library libacch.so (include/acch.h); this package only builds and binds it.
+"""
+from .binding import (AcchError, Params, Solver, StepInfo, load_library, make_params,  # noqa: F401
+                      LIB_PATH, EXPORTED)
+
+__all__ = ["AcchError", "Params", "Solver", "StepInfo", "load_library", "make_params", "LIB_PATH", "EXPORTED"]

@@ -1,0 +1,150 @@
+// Shared definitions of the acch HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace acch {
+
+constexpr int kMaxRestart = 30;     // GMRES(m) with m <= 30 (device Hessenberg storage)
+constexpr int kMaxS = 64;           // series order limit of Lemma 2.2's truncation
+constexpr int kRedBlocks = 1024;    // grid size of the vector reduction kernels
+constexpr int kNSlot2D = 24;        // Jacobian / factor slots per cell in 2D
+
+// Physical and mesh parameters seen by the stencil kernels.
+struct Phys {
+  int nx, ny;
+  int periodic;
+  double wx, wy;          // 1/hx^2, 1/hy^2
+  double alpha, beta, theta, gamma, rho;
+  int S;
+  int mob;                // 0 midpoint, 1 average, 2 explicit
+};
+
+// Scratch used by the two-level reductions: per-block partial sums and a ticket.
+struct RedBuf {
+  double *partials;       // [nv][gridblocks]
+  unsigned *counter;      // zero between kernels; the last block resets it
+  double *out;            // [nv] final sums
+};
+
+// Geometry of the padded subdomain boxes Omega_k^delta (all boxes share bw x bh).
+struct BoxGeom {
+  int bw, bh;             // padded box width/height (cells)
+  int nlev;               // levels of the i + 2j wavefront: bw + 2(bh-1)
+  int ncb;                // bw * bh
+  int nsub;
+};
+
+// One subdomain: unwrapped box origin, its real extent inside the padded box and
+// the owned rectangle Omega_k in box coordinates.
+struct SubInfo {
+  int ox, oy;             // global coordinates of box cell (0,0), may be negative
+  int ex, ey;             // real box extent (<= bw, bh); cells beyond are padding
+  int own_x0, own_x1, own_y0, own_y1;
+};
+
+// Device-resident state of one restarted GMRES cycle (flexible, right preconditioned).
+struct GmresState {
+  double H[(kMaxRestart + 1) * kMaxRestart];   // column-major Hessenberg, after rotations
+  double cs[kMaxRestart], sn[kMaxRestart];
+  double g[kMaxRestart + 1];
+  double y[kMaxRestart];
+  double hcol[kMaxRestart + 1];                // dots of the current Arnoldi step
+  double inv_norm[kMaxRestart + 1];            // V_i is stored unnormalised: v_i = inv_norm[i] * W_i
+  double beta;            // ||r_0|| of the cycle
+  double tol;             // absolute stopping tolerance
+  double resid;           // current residual estimate |g[j]|
+  double shift;           // mean of the u part of the final direction (mass projection)
+  int j;                  // Arnoldi steps done in this cycle
+  int m;                  // restart length
+  int done;               // cycle finished (converged, breakdown or j == m)
+  int converged;
+  int total_its;
+  int pad[3];
+};
+
+// Small pinned-host mirror of the values the host control flow reads.
+struct HostMirror {
+  double vals[8];
+  int ivals[8];
+};
+
+#define ACCH_DEV __device__ __forceinline__
+
+// ---------------------------------------------------------------------------
+// Reductions: wave64 shuffles, then LDS across waves, then a last-block pass.
+// ---------------------------------------------------------------------------
+
+ACCH_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sums NV values over the block; the result is valid in thread 0.  nthreads must
+// be a multiple of 64 and at most 1024.
+template <int NV>
+ACCH_DEV void block_sum(double (&v)[NV], int tid, int nthreads) {
+  __shared__ double s_red[NV][16];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  const int lane = tid & 63, wid = tid >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s_red[k][wid] = v[k];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int nw = nthreads >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double a = 0.0;
+      for (int w = 0; w < nw; ++w) a += s_red[k][w];
+      v[k] = a;
+    }
+  }
+}
+
+// Grid-wide sum of NV values per thread (only the first nv_used are reduced).  Each
+// block stores its partial sums; the block that arrives last (device-scope ticket)
+// sums the partials in block order, which makes the result independent of
+// scheduling, and writes red.out[0..nv_used).  Returns true in every thread of the
+// last block (red.out is then valid there).
+template <int NV>
+ACCH_DEV bool grid_sum(double (&v)[NV], const RedBuf &red, int tid, int nthreads, int bid,
+                       int nblocks, int nv_used = NV) {
+  __shared__ int s_last;
+  block_sum<NV>(v, tid, nthreads);
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nv_used) red.partials[k * nblocks + bid] = v[k];
+    __threadfence();
+    const unsigned prev = atomicAdd(red.counter, 1u);
+    s_last = (prev == (unsigned)(nblocks - 1));
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double a = 0.0;
+    if (k < nv_used)
+      for (int b = tid; b < nblocks; b += nthreads) a += red.partials[k * nblocks + b];
+    acc[k] = a;
+  }
+  block_sum<NV>(acc, tid, nthreads);
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if (k < nv_used) red.out[k] = acc[k];
+    *red.counter = 0u;
+  }
+  __syncthreads();
+  return true;
+}
+
+}  // namespace acch

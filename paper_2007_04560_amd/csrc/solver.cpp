@@ -1,0 +1,764 @@
+// Host driver of the acch library: parameter validation, subdomain maps, workspace
+// layout, and the control flow of one time step (Sections 3.1 and 3.2): inexact
+// Newton with a backtracking line search, restarted flexible GMRES preconditioned
+// by restricted additive Schwarz with subdomain ILU(0) (factored once per step
+// attempt), and the adaptive time step with sqrt(2) retries and eta doubling.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/acch.h"
+#include "kernels.h"
+
+using namespace acch;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess)                                                                          \
+      return fail(ACCH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Split n cells into `parts` pieces, the larger ones first (shared reading with the
+// oracle's decomposition).
+void split(int n, int parts, std::vector<int> &start, std::vector<int> &len) {
+  start.resize(parts);
+  len.resize(parts);
+  const int base = n / parts, rem = n % parts;
+  int s = 0;
+  for (int k = 0; k < parts; ++k) {
+    start[k] = s;
+    len[k] = base + (k < rem ? 1 : 0);
+    s += len[k];
+  }
+}
+
+struct Layout {
+  size_t off_Xn, off_Xprev, off_X, off_Xt, off_F, off_Ft, off_S, off_W;
+  size_t off_J, off_V, off_Z, off_fac, off_y, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
+  size_t total;
+};
+
+struct Geometry {
+  long ncell = 0;
+  BoxGeom G{};
+  std::vector<SubInfo> subs;
+  std::vector<int> lvl;  // nlev + 1 prefix counts
+  int tile_blocks = 0;
+};
+
+}  // namespace
+
+struct acch_ctx {
+  acch_params p{};
+  Phys P{};
+  Geometry geo;
+  Layout lay{};
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  double *Xn, *Xprev, *X, *Xt, *F, *Ft, *S, *W, *J, *V, *Z;
+  void *fac, *ybuf;
+  SubInfo *d_subs;
+  int *d_lvl;
+  GmresState *st;
+  RedBuf red{};
+  HostMirror *host = nullptr;  // pinned
+  char *host_state = nullptr;  // pinned, holds the tail of GmresState
+  double hvol = 1.0;           // cell volume
+  double t = 0.0, dt_prev = 0.0, eta = 0.0;
+  bool have_history = false;
+  bool factored = false;
+  int its_guess = 4;
+  long launches = 0, syncs = 0;
+};
+
+// ---------------------------------------------------------------------------
+// parameters, geometry, workspace
+// ---------------------------------------------------------------------------
+extern "C" void acch_params_default(acch_params *p) {
+  if (!p) return;
+  if (p->dim == 0) p->dim = 2;
+  for (int d = 0; d < 3; ++d)
+    if (p->L[d] == 0.0) p->L[d] = 1.0;
+  if (p->S == 0) p->S = 10;
+  if (p->newton_rtol == 0.0) p->newton_rtol = 1e-8;
+  if (p->newton_atol == 0.0) p->newton_atol = 1e-13;
+  if (p->newton_max_it == 0) p->newton_max_it = 50;
+  if (p->gmres_rtol == 0.0) p->gmres_rtol = 1e-8;
+  if (p->gmres_atol == 0.0) p->gmres_atol = 1e-14;
+  if (p->gmres_restart == 0) p->gmres_restart = 30;
+  if (p->gmres_max_restarts == 0) p->gmres_max_restarts = 10;
+  for (int d = 0; d < 3; ++d)
+    if (p->sub[d] == 0) p->sub[d] = 1;
+}
+
+static int validate(const acch_params &p) {
+  if (p.dim != 2) return fail(ACCH_EUNSUPPORTED, "only dim = 2 is implemented");
+  if (p.n[0] < 2 || p.n[1] < 2) return fail(ACCH_EINVAL, "need at least 2 cells per direction");
+  if (p.bc != ACCH_BC_PERIODIC && p.bc != ACCH_BC_NEUMANN) return fail(ACCH_EINVAL, "bc");
+  if (p.bc == ACCH_BC_PERIODIC && (p.n[0] < 5 || p.n[1] < 5))
+    return fail(ACCH_EINVAL, "periodic grids need at least 5 cells per direction");
+  if (!(p.alpha > 0 && p.beta > 0 && p.theta > 0 && p.gamma > 0 && p.rho > 0))
+    return fail(ACCH_EINVAL, "alpha, beta, theta, gamma, rho must be positive");
+  if (p.S < 1 || p.S > kMaxS) return fail(ACCH_EINVAL, "S out of range");
+  if (p.gmres_restart < 1 || p.gmres_restart > kMaxRestart) return fail(ACCH_EINVAL, "gmres_restart must be 1..30");
+  if (p.ras_type != ACCH_RAS_LEFT) return fail(ACCH_EUNSUPPORTED, "only the left-restricted Schwarz variant is built");
+  if (p.precision != ACCH_PREC_FP64 && p.precision != ACCH_PREC_MIXED) return fail(ACCH_EINVAL, "precision");
+  if (p.mobility_mode < 0 || p.mobility_mode > 2) return fail(ACCH_EINVAL, "mobility_mode");
+  if (p.overlap < 0) return fail(ACCH_EINVAL, "overlap");
+  if (!(p.ilu_shift >= 0.0 && p.ilu_shift < 10.0)) return fail(ACCH_EINVAL, "ilu_shift must be in [0, 10)");
+  if (p.adaptive) {
+    if (!(p.dt_min > 0 && p.dt_max >= p.dt_min && p.eta0 > 0)) return fail(ACCH_EINVAL, "dt_min, dt_max, eta0");
+  } else if (!(p.dt_fixed > 0)) {
+    return fail(ACCH_EINVAL, "dt_fixed");
+  }
+  for (int d = 0; d < 2; ++d) {
+    if (p.sub[d] < 1 || p.sub[d] > p.n[d]) return fail(ACCH_EINVAL, "sub");
+    if (p.bc == ACCH_BC_PERIODIC) {
+      if (p.sub[d] < 2) return fail(ACCH_EINVAL, "periodic directions need at least 2 subdomains");
+      const int longest = (p.n[d] + p.sub[d] - 1) / p.sub[d] + 2 * p.overlap;
+      if (longest > p.n[d] - 2) return fail(ACCH_EINVAL, "overlapping box would touch itself across the periodic wrap");
+    }
+  }
+  return ACCH_OK;
+}
+
+static int build_geometry(const acch_params &p, Geometry &geo) {
+  const int nx = p.n[0], ny = p.n[1], d = p.overlap;
+  geo.ncell = (long)nx * ny;
+  std::vector<int> sx, lx, sy, ly;
+  split(nx, p.sub[0], sx, lx);
+  split(ny, p.sub[1], sy, ly);
+  int bw = 0, bh = 0;
+  for (int v : lx) bw = std::max(bw, v + 2 * d);
+  for (int v : ly) bh = std::max(bh, v + 2 * d);
+  geo.G.bw = bw;
+  geo.G.bh = bh;
+  geo.G.nlev = bw + 2 * (bh - 1);
+  geo.G.ncb = bw * bh;
+  geo.G.nsub = p.sub[0] * p.sub[1];
+  if (schwarz_waves(geo.G) == 0) return fail(ACCH_EINVAL, "subdomain box wider than 511 cells");
+  geo.subs.clear();
+  for (int by = 0; by < p.sub[1]; ++by)
+    for (int bx = 0; bx < p.sub[0]; ++bx) {
+      SubInfo s{};
+      s.ox = sx[bx] - d;
+      s.oy = sy[by] - d;
+      s.ex = lx[bx] + 2 * d;
+      s.ey = ly[by] + 2 * d;
+      s.own_x0 = d;
+      s.own_x1 = d + lx[bx];
+      s.own_y0 = d;
+      s.own_y1 = d + ly[by];
+      geo.subs.push_back(s);
+    }
+  // wavefront w = i + 2j holds rows j in [lo(w), hi(w)]
+  geo.lvl.assign(geo.G.nlev + 1, 0);
+  for (int w = 0; w < geo.G.nlev; ++w) {
+    const int lo = std::max(0, (w - bw + 2) >> 1);
+    const int hi = std::min(bh - 1, w >> 1);
+    geo.lvl[w + 1] = geo.lvl[w] + std::max(0, hi - lo + 1);
+  }
+  if (geo.lvl[geo.G.nlev] != geo.G.ncb) return fail(ACCH_EINVAL, "internal: wavefront table");
+  geo.tile_blocks = ((nx + 31) / 32) * ((ny + 7) / 8);
+  return ACCH_OK;
+}
+
+static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
+  const size_t n2 = 2 * (size_t)geo.ncell * sizeof(double);
+  const int m = p.gmres_restart;
+  const size_t fsz = p.precision == ACCH_PREC_MIXED ? sizeof(float) : sizeof(double);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.off_Xn = take(n2);
+  L.off_Xprev = take(n2);
+  L.off_X = take(n2);
+  L.off_Xt = take(n2);
+  L.off_F = take(n2);
+  L.off_Ft = take(n2);
+  L.off_S = take(n2);
+  L.off_W = take(n2);
+  L.off_J = take((size_t)kNSlot2D * geo.ncell * sizeof(double));
+  L.off_V = take((size_t)(m + 1) * n2);
+  L.off_Z = take((size_t)m * n2);
+  L.off_fac = take((size_t)geo.G.nsub * kNSlot2D * geo.G.ncb * fsz);
+  L.off_y = take((size_t)geo.G.nsub * 2 * geo.G.ncb * fsz);
+  L.off_subs = take(geo.subs.size() * sizeof(SubInfo));
+  L.off_lvl = take(geo.lvl.size() * sizeof(int));
+  L.off_state = take(sizeof(GmresState));
+  const size_t nparts = std::max<size_t>((size_t)(kMaxRestart + 1) * kRedBlocks, 2 * (size_t)geo.tile_blocks);
+  L.off_part = take(nparts * sizeof(double));
+  L.off_cnt = take(64);
+  L.off_out = take(64 * sizeof(double));
+  L.total = o;
+}
+
+extern "C" int acch_workspace_bytes(const acch_params *pin, size_t *bytes) {
+  if (!pin || !bytes) return fail(ACCH_EINVAL, "null argument");
+  acch_params p = *pin;
+  acch_params_default(&p);
+  int rc = validate(p);
+  if (rc) return rc;
+  Geometry geo;
+  rc = build_geometry(p, geo);
+  if (rc) return rc;
+  Layout L;
+  make_layout(p, geo, L);
+  *bytes = L.total;
+  return ACCH_OK;
+}
+
+static bool admissible_host(const double *u, const double *v, long n) {
+  for (long k = 0; k < n; ++k) {
+    const double pp = u[k] + v[k], q = u[k] - v[k];
+    if (!(pp > 0.0 && pp < 1.0 && q > 0.0 && q < 1.0)) return false;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// small helpers on a context
+// ---------------------------------------------------------------------------
+namespace {
+
+int sync_read(acch_ctx *c, const void *dev, void *host, size_t bytes) {
+  HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->syncs++;
+  return ACCH_OK;
+}
+
+// Launch helper that records the launch and maps errors.
+#define LAUNCH(c, expr)                                                                            \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    (c)->launches++;                                                                               \
+    if (e_ != hipSuccess) return fail(ACCH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int residual_eval(acch_ctx *c, const double *X, const double *Sdir, double lam, const double *shift,
+                  const double *Xn, double dt, double *Xt, double *F, double &f2, double &bad) {
+  LAUNCH(c, launch_residual2d(c->P, X, Sdir, lam, shift, Xn, dt, Xt, F, c->red, c->stream));
+  int rc = sync_read(c, c->red.out, c->host->vals, 2 * sizeof(double));
+  if (rc) return rc;
+  f2 = c->host->vals[0];
+  bad = c->host->vals[1];
+  return ACCH_OK;
+}
+
+int factor(acch_ctx *c) {
+  LAUNCH(c, launch_ilu_factor2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->J,
+                                c->p.ilu_shift, c->fac, c->p.precision == ACCH_PREC_MIXED, c->stream));
+  c->factored = true;
+  return ACCH_OK;
+}
+
+// Solve J S = -F (S from 0).  Returns ACCH_OK when converged, ACCH_EDIVERGED if not.
+int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid) {
+  const long n2 = 2 * c->geo.ncell;
+  const long vs = n2;
+  const int m = c->p.gmres_restart;
+  const int fp32 = c->p.precision == ACCH_PREC_MIXED;
+  const int project = c->p.mass_projection;
+  LAUNCH(c, launch_reset_state(c->st, c->stream));
+  its = 0;
+  resid = 0.0;
+  const size_t tail = offsetof(GmresState, beta);
+  GmresState hs{};
+  for (int cycle = 0; cycle < c->p.gmres_max_restarts; ++cycle) {
+    if (cycle > 0) LAUNCH(c, launch_spmv2d(c->P, c->J, S, c->W, c->stream));
+    LAUNCH(c, launch_gmres_start(n2, F, cycle > 0 ? c->W : nullptr, c->V, c->st, m, c->p.gmres_rtol,
+                                 c->p.gmres_atol, c->red, c->stream));
+    int launched = 0;
+    int chunk = cycle == 0 ? std::max(1, std::min(m, c->its_guess)) : std::max(1, m / 2);
+    while (true) {
+      for (int k = 0; k < chunk && launched < m; ++k, ++launched) {
+        LAUNCH(c, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->fac, c->ybuf,
+                                     c->V, c->Z, c->st, vs, fp32, c->stream));
+        LAUNCH(c, launch_spmv_dots2d(c->P, c->J, c->Z, c->V, vs, c->st, c->red, c->stream));
+        LAUNCH(c, launch_gmres_orth(n2, c->V, vs, c->st, c->red, c->stream));
+      }
+      LAUNCH(c, launch_gmres_update(c->geo.ncell, S, c->Z, vs, c->st, cycle > 0, project, c->red, c->stream));
+      int rc = sync_read(c, (const char *)c->st + tail, c->host_state, sizeof(GmresState) - tail);
+      if (rc) return rc;
+      memcpy((char *)&hs + tail, c->host_state, sizeof(GmresState) - tail);
+      if (hs.done || launched >= m) break;
+      chunk = 2;
+    }
+    its = hs.total_its;
+    resid = hs.resid;
+    if (!hs.done) return fail(ACCH_EDIVERGED, "GMRES cycle did not finish");
+    if (hs.converged) {
+      c->its_guess = std::max(1, std::min(m, its));
+      return ACCH_OK;
+    }
+    if (!(resid == resid)) return fail(ACCH_EDIVERGED, "GMRES residual is not finite");
+    if (hs.total_its == 0) return fail(ACCH_EDIVERGED, "GMRES made no progress");
+  }
+  return fail(ACCH_EDIVERGED, "GMRES did not converge within the restart limit");
+}
+
+// Backtracking line search along S (with the mass shift) from X; the reading of the
+// unspecified line search shared with the oracle: Armijo test on ||F||^2/2 with
+// alpha = 1e-4 and slope -||F||^2, quadratic then cubic models clamped to
+// [0.1, 0.5] lambda, halving on an inadmissible or non-finite trial, failure below
+// lambda = 1e-8.  On success Xt/Ft hold the accepted point.
+int line_search(acch_ctx *c, double dt, double fnorm, double &f2_new, double &lam_out) {
+  const double alpha = 1e-4, lam_min = 1e-8;
+  const double f0 = 0.5 * fnorm * fnorm;
+  const double slope = -2.0 * f0;
+  double lam = 1.0;
+  bool have_prev = false;
+  double lp = 0.0, fp = 0.0;
+  const double *shift = c->p.mass_projection ? &c->st->shift : nullptr;
+  while (lam >= lam_min) {
+    double f2, bad;
+    int rc = residual_eval(c, c->X, c->S, lam, shift, c->Xn, dt, c->Xt, c->Ft, f2, bad);
+    if (rc) return rc;
+    if (bad > 0.0 || !(f2 == f2) || isinf(f2)) {
+      lam *= 0.5;
+      continue;
+    }
+    const double ft = 0.5 * f2;
+    if (ft <= f0 + alpha * lam * slope) {
+      f2_new = f2;
+      lam_out = lam;
+      return ACCH_OK;
+    }
+    double nl;
+    if (!have_prev) {
+      nl = -slope * lam * lam / (2.0 * (ft - f0 - slope * lam));
+    } else {
+      const double t1 = ft - f0 - slope * lam, t2 = fp - f0 - slope * lp;
+      const double a = (t1 / (lam * lam) - t2 / (lp * lp)) / (lam - lp);
+      const double b = (-lp * t1 / (lam * lam) + lam * t2 / (lp * lp)) / (lam - lp);
+      if (a == 0.0) {
+        nl = -slope / (2.0 * b);
+      } else {
+        const double disc = b * b - 3.0 * a * slope;
+        nl = disc >= 0.0 ? (-b + sqrt(disc)) / (3.0 * a) : 0.5 * lam;
+      }
+    }
+    if (!isfinite(nl)) nl = 0.5 * lam;
+    nl = std::min(std::max(nl, 0.1 * lam), 0.5 * lam);
+    have_prev = true;
+    lp = lam;
+    fp = ft;
+    lam = nl;
+  }
+  return fail(ACCH_EDIVERGED, "line search failed");
+}
+
+struct SolveStats {
+  int newton = 0, gmres = 0;
+  double fnorm = 0.0;
+};
+
+// Newton solve of scheme (2.20) at dt from Xn; on success X holds the root.
+int nks_solve(acch_ctx *c, double dt, SolveStats &stats) {
+  const long n2 = 2 * c->geo.ncell;
+  HIP_TRY(hipMemcpyAsync(c->X, c->Xn, n2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  double f2, bad;
+  int rc = residual_eval(c, c->X, nullptr, 0.0, nullptr, c->Xn, dt, nullptr, c->F, f2, bad);
+  if (rc) return rc;
+  double fnorm = sqrt(f2);
+  stats.fnorm = fnorm;
+  if (!isfinite(fnorm)) return fail(ACCH_EDIVERGED, "initial residual is not finite");
+  const double tol = std::max(c->p.newton_rtol * fnorm, c->p.newton_atol);
+  if (fnorm <= tol) return ACCH_OK;
+  for (int it = 1; it <= c->p.newton_max_it; ++it) {
+    LAUNCH(c, launch_jacobian2d(c->P, c->X, c->Xn, dt, c->J, c->stream));
+    if (it == 1 || !c->p.ilu_reuse) {
+      rc = factor(c);
+      if (rc) return rc;
+    }
+    int its = 0;
+    double lres = 0.0;
+    rc = gmres(c, c->F, c->S, its, lres);
+    stats.gmres += its;
+    if (rc) return rc;
+    double f2n, lam;
+    rc = line_search(c, dt, fnorm, f2n, lam);
+    stats.newton = it;
+    if (rc) return rc;
+    std::swap(c->X, c->Xt);
+    std::swap(c->F, c->Ft);
+    fnorm = sqrt(f2n);
+    stats.fnorm = fnorm;
+    if (!isfinite(fnorm)) return fail(ACCH_EDIVERGED, "residual is not finite");
+    if (fnorm <= tol) return ACCH_OK;
+  }
+  return fail(ACCH_EDIVERGED, "Newton iteration limit reached");
+}
+
+int energy_mass(acch_ctx *c, const double *X, double &E, double &M) {
+  LAUNCH(c, launch_energy2d(c->P, X, c->red, c->stream));
+  int rc = sync_read(c, c->red.out, c->host->vals, 2 * sizeof(double));
+  if (rc) return rc;
+  E = c->host->vals[0] * c->hvol;
+  M = c->host->vals[1] * c->hvol;
+  return ACCH_OK;
+}
+
+// Accept the iterate X as the new state.
+void accept(acch_ctx *c, double dt) {
+  std::swap(c->Xprev, c->Xn);  // Xprev <- old state
+  std::swap(c->Xn, c->X);      // Xn <- root; X gets the free buffer
+  c->t += dt;
+  c->dt_prev = dt;
+  c->have_history = true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" int acch_create(const acch_params *pin, const double *u0, const double *v0, acch_ctx **out) {
+  if (!pin || !u0 || !v0 || !out) return fail(ACCH_EINVAL, "null argument");
+  *out = nullptr;
+  acch_params p = *pin;
+  acch_params_default(&p);
+  int rc = validate(p);
+  if (rc) return rc;
+  acch_ctx *c = new (std::nothrow) acch_ctx();
+  if (!c) return fail(ACCH_EINVAL, "host allocation failed");
+  c->p = p;
+  rc = build_geometry(p, c->geo);
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  make_layout(p, c->geo, c->lay);
+  if (!p.workspace || p.workspace_bytes < c->lay.total) {
+    delete c;
+    return fail(ACCH_EINVAL, "workspace missing or smaller than acch_workspace_bytes()");
+  }
+  if (((uintptr_t)p.workspace) % kAlign) {
+    delete c;
+    return fail(ACCH_EINVAL, "workspace must be 256-byte aligned");
+  }
+  const long n = c->geo.ncell;
+  if (!admissible_host(u0, v0, n)) {
+    delete c;
+    return fail(ACCH_EDOMAIN, "initial state outside the admissible set");
+  }
+  c->stream = (hipStream_t)p.stream;
+  c->ws = (char *)p.workspace;
+  const Layout &L = c->lay;
+  c->Xn = (double *)(c->ws + L.off_Xn);
+  c->Xprev = (double *)(c->ws + L.off_Xprev);
+  c->X = (double *)(c->ws + L.off_X);
+  c->Xt = (double *)(c->ws + L.off_Xt);
+  c->F = (double *)(c->ws + L.off_F);
+  c->Ft = (double *)(c->ws + L.off_Ft);
+  c->S = (double *)(c->ws + L.off_S);
+  c->W = (double *)(c->ws + L.off_W);
+  c->J = (double *)(c->ws + L.off_J);
+  c->V = (double *)(c->ws + L.off_V);
+  c->Z = (double *)(c->ws + L.off_Z);
+  c->fac = c->ws + L.off_fac;
+  c->ybuf = c->ws + L.off_y;
+  c->d_subs = (SubInfo *)(c->ws + L.off_subs);
+  c->d_lvl = (int *)(c->ws + L.off_lvl);
+  c->st = (GmresState *)(c->ws + L.off_state);
+  c->red.partials = (double *)(c->ws + L.off_part);
+  c->red.counter = (unsigned *)(c->ws + L.off_cnt);
+  c->red.out = (double *)(c->ws + L.off_out);
+  c->P.nx = p.n[0];
+  c->P.ny = p.n[1];
+  c->P.periodic = p.bc == ACCH_BC_PERIODIC;
+  const double hx = p.L[0] / p.n[0], hy = p.L[1] / p.n[1];
+  c->P.wx = 1.0 / (hx * hx);
+  c->P.wy = 1.0 / (hy * hy);
+  c->hvol = hx * hy;
+  c->P.alpha = p.alpha;
+  c->P.beta = p.beta;
+  c->P.theta = p.theta;
+  c->P.gamma = p.gamma;
+  c->P.rho = p.rho;
+  c->P.S = p.S;
+  c->P.mob = p.mobility_mode;
+  c->eta = p.eta0;
+  if (hipHostMalloc((void **)&c->host, sizeof(GmresState) + sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return fail(ACCH_EDEVICE, "hipHostMalloc failed");
+  }
+  c->host_state = (char *)c->host + sizeof(HostMirror);
+  auto cleanup = [&](int code) {
+    (void)hipHostFree(c->host);
+    delete c;
+    return code;
+  };
+  if (hipMemcpyAsync(c->Xn, u0, n * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->Xn + n, v0, n * sizeof(double), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->d_subs, c->geo.subs.data(), c->geo.subs.size() * sizeof(SubInfo), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->d_lvl, c->geo.lvl.data(), c->geo.lvl.size() * sizeof(int), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipMemsetAsync(c->red.counter, 0, 64, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->st, 0, sizeof(GmresState), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return cleanup(fail(ACCH_EDEVICE, "initial upload failed"));
+  *out = c;
+  return ACCH_OK;
+}
+
+extern "C" int acch_destroy(acch_ctx *c) {
+  if (!c) return ACCH_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->host) (void)hipHostFree(c->host);
+  delete c;
+  return ACCH_OK;
+}
+
+extern "C" int acch_step(acch_ctx *c, int nsteps, acch_step_info *info, int *accepted) {
+  if (!c || nsteps < 0) return fail(ACCH_EINVAL, "bad arguments");
+  if (accepted) *accepted = 0;
+  const acch_params &p = c->p;
+  const long n2 = 2 * c->geo.ncell;
+  for (int s = 0; s < nsteps; ++s) {
+    double dt;
+    if (!p.adaptive) {
+      dt = p.dt_fixed;
+    } else if (!c->have_history) {
+      dt = p.dt_min;
+    } else {
+      LAUNCH(c, launch_norm2_diff(n2, c->Xn, c->Xprev, c->red, c->stream));
+      int rc = sync_read(c, c->red.out, c->host->vals, sizeof(double));
+      if (rc) return rc;
+      double dn = sqrt(c->host->vals[0]);
+      if (p.xd_norm == 1) dn *= sqrt(c->hvol);
+      const double xd = dn / c->dt_prev;
+      dt = std::max(p.dt_min, p.dt_max / sqrt(1.0 + c->eta * xd * xd));
+    }
+    SolveStats tot;
+    int retries = 0;
+    while (true) {
+      SolveStats st;
+      int rc = nks_solve(c, dt, st);
+      tot.newton += st.newton;
+      tot.gmres += st.gmres;
+      tot.fnorm = st.fnorm;
+      if (rc == ACCH_OK) break;
+      if (rc != ACCH_EDIVERGED) return rc;
+      if (!p.adaptive) return fail(ACCH_EDIVERGED, "NKS diverged at the fixed dt: " + g_last_error);
+      c->eta *= 2.0;
+      if (dt <= p.dt_min) return fail(ACCH_EDIVERGED, "NKS diverged at dt_min: " + g_last_error);
+      dt = std::max(dt / sqrt(2.0), p.dt_min);
+      ++retries;
+    }
+    accept(c, dt);
+    acch_step_info rec{};
+    rec.t = c->t;
+    rec.dt = dt;
+    rec.eta = c->eta;
+    rec.fnorm = tot.fnorm;
+    rec.newton_its = tot.newton;
+    rec.gmres_its = tot.gmres;
+    rec.retries = retries;
+    rec.status = ACCH_OK;
+    rec.energy = rec.mass = NAN;
+    if (p.log_energy) {
+      int rc = energy_mass(c, c->Xn, rec.energy, rec.mass);
+      if (rc) return rc;
+    }
+    if (info) info[s] = rec;
+    if (accepted) *accepted = s + 1;
+  }
+  return ACCH_OK;
+}
+
+extern "C" int acch_solve_step(acch_ctx *c, double dt, acch_step_info *info) {
+  if (!c || !(dt > 0)) return fail(ACCH_EINVAL, "bad arguments");
+  SolveStats st;
+  int rc = nks_solve(c, dt, st);
+  if (rc) return rc;
+  accept(c, dt);
+  if (info) {
+    acch_step_info rec{};
+    rec.t = c->t;
+    rec.dt = dt;
+    rec.eta = c->eta;
+    rec.fnorm = st.fnorm;
+    rec.newton_its = st.newton;
+    rec.gmres_its = st.gmres;
+    rec.energy = rec.mass = NAN;
+    if (c->p.log_energy) {
+      rc = energy_mass(c, c->Xn, rec.energy, rec.mass);
+      if (rc) return rc;
+    }
+    *info = rec;
+  }
+  return ACCH_OK;
+}
+
+extern "C" int acch_energy(acch_ctx *c, double *energy, double *mass) {
+  if (!c) return fail(ACCH_EINVAL, "null context");
+  double E, M;
+  int rc = energy_mass(c, c->Xn, E, M);
+  if (rc) return rc;
+  if (energy) *energy = E;
+  if (mass) *mass = M;
+  return ACCH_OK;
+}
+
+extern "C" int acch_get_fields(acch_ctx *c, double *u, double *v) {
+  if (!c || !u || !v) return fail(ACCH_EINVAL, "null argument");
+  const long n = c->geo.ncell;
+  HIP_TRY(hipMemcpyAsync(u, c->Xn, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(v, c->Xn + n, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return ACCH_OK;
+}
+
+extern "C" int acch_set_fields(acch_ctx *c, const double *u, const double *v) {
+  if (!c || !u || !v) return fail(ACCH_EINVAL, "null argument");
+  const long n = c->geo.ncell;
+  if (!admissible_host(u, v, n)) return fail(ACCH_EDOMAIN, "state outside the admissible set");
+  HIP_TRY(hipMemcpyAsync(c->Xn, u, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->Xn + n, v, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->have_history = false;
+  return ACCH_OK;
+}
+
+extern "C" int acch_get_time(acch_ctx *c, double *t, double *dt_prev, double *eta) {
+  if (!c) return fail(ACCH_EINVAL, "null context");
+  if (t) *t = c->t;
+  if (dt_prev) *dt_prev = c->dt_prev;
+  if (eta) *eta = c->eta;
+  return ACCH_OK;
+}
+
+extern "C" int acch_residual(acch_ctx *c, const double *X, const double *Xn, double dt, double *F, double *fnorm2,
+                             int *inadmissible) {
+  if (!c || !X || !Xn || !F || !(dt > 0)) return fail(ACCH_EINVAL, "bad arguments");
+  double f2, bad;
+  int rc = residual_eval(c, X, nullptr, 0.0, nullptr, Xn, dt, nullptr, F, f2, bad);
+  if (rc) return rc;
+  if (fnorm2) *fnorm2 = f2;
+  if (inadmissible) *inadmissible = (int)bad;
+  return ACCH_OK;
+}
+
+extern "C" int acch_jacobian(acch_ctx *c, const double *X, const double *Xn, double dt) {
+  if (!c || !X || !Xn || !(dt > 0)) return fail(ACCH_EINVAL, "bad arguments");
+  LAUNCH(c, launch_jacobian2d(c->P, X, Xn, dt, c->J, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return ACCH_OK;
+}
+
+extern "C" int acch_apply_jacobian(acch_ctx *c, const double *x, double *y) {
+  if (!c || !x || !y) return fail(ACCH_EINVAL, "bad arguments");
+  LAUNCH(c, launch_spmv2d(c->P, c->J, x, y, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return ACCH_OK;
+}
+
+extern "C" int acch_factor(acch_ctx *c) {
+  if (!c) return fail(ACCH_EINVAL, "null context");
+  int rc = factor(c);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return ACCH_OK;
+}
+
+extern "C" int acch_precondition(acch_ctx *c, const double *r, double *z) {
+  if (!c || !r || !z) return fail(ACCH_EINVAL, "bad arguments");
+  if (!c->factored) return fail(ACCH_EINVAL, "no factorisation: call acch_factor first");
+  LAUNCH(c, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->fac, c->ybuf, r, z,
+                               nullptr, 0, c->p.precision == ACCH_PREC_MIXED, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return ACCH_OK;
+}
+
+extern "C" int acch_gmres(acch_ctx *c, const double *F, double *S, int *iterations, double *resid) {
+  if (!c || !F || !S) return fail(ACCH_EINVAL, "bad arguments");
+  if (!c->factored) return fail(ACCH_EINVAL, "no factorisation: call acch_factor first");
+  int its = 0;
+  double r = 0.0;
+  int rc = gmres(c, F, S, its, r);
+  if (iterations) *iterations = its;
+  if (resid) *resid = r;
+  return rc;
+}
+
+extern "C" int acch_export(acch_ctx *c, int which, void *out, size_t *bytes) {
+  if (!c || !bytes) return fail(ACCH_EINVAL, "bad arguments");
+  const BoxGeom &G = c->geo.G;
+  size_t need = 0;
+  if (which == ACCH_EXPORT_JACOBIAN) need = (size_t)kNSlot2D * c->geo.ncell * sizeof(double);
+  else if (which == ACCH_EXPORT_FACTORS) need = (size_t)G.nsub * kNSlot2D * G.ncb * sizeof(double);
+  else if (which == ACCH_EXPORT_BOXES) need = (size_t)G.nsub * 4 * sizeof(int);
+  else return fail(ACCH_EINVAL, "unknown export");
+  if (!out) {
+    *bytes = need;
+    return ACCH_OK;
+  }
+  if (*bytes < need) return fail(ACCH_EINVAL, "output buffer too small");
+  if (which == ACCH_EXPORT_JACOBIAN) {
+    HIP_TRY(hipMemcpyAsync(out, c->J, need, hipMemcpyDeviceToDevice, c->stream));
+  } else if (which == ACCH_EXPORT_FACTORS) {
+    if (!c->factored) return fail(ACCH_EINVAL, "no factorisation");
+    LAUNCH(c, launch_export_factors2d(G, c->d_lvl, c->fac, c->p.precision == ACCH_PREC_MIXED, (double *)out,
+                                      c->stream));
+  } else {
+    std::vector<int> b;
+    for (const SubInfo &s : c->geo.subs) {
+      b.push_back(s.ox);
+      b.push_back(s.oy);
+      b.push_back(G.bw);
+      b.push_back(G.bh);
+    }
+    HIP_TRY(hipMemcpyAsync(out, b.data(), need, hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *bytes = need;
+  return ACCH_OK;
+}
+
+extern "C" int acch_info(acch_ctx *c, long *ncell, int *nsub, int *box_w, int *box_h) {
+  if (!c) return fail(ACCH_EINVAL, "null context");
+  if (ncell) *ncell = c->geo.ncell;
+  if (nsub) *nsub = c->geo.G.nsub;
+  if (box_w) *box_w = c->geo.G.bw;
+  if (box_h) *box_h = c->geo.G.bh;
+  return ACCH_OK;
+}
+
+extern "C" const char *acch_strerror(int code) {
+  switch (code) {
+    case ACCH_OK: return "ok";
+    case ACCH_EINVAL: return "invalid argument";
+    case ACCH_EDOMAIN: return "state outside the admissible set";
+    case ACCH_EDIVERGED: return "Newton-Krylov-Schwarz diverged";
+    case ACCH_EDEVICE: return "HIP runtime error";
+    case ACCH_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+  }
+}
+
+extern "C" const char *acch_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,368 @@
+// 2D stencil kernels of scheme (2.20): residual, discrete energy and mass,
+// analytic Jacobian assembly and the Jacobian product.
+//
+// Fields are FP64, x fastest; a state vector holds the u field then the v field.
+// The residual and Jacobian kernels stage a (32+4) x (8+4) tile of the four
+// fields in LDS (the radius-2 dependence of F_u), evaluate the cell quantities
+// (mu, c, ...) once on the tile plus a one-cell halo, and then the face fluxes.
+#include "kernels.h"
+#include "physics.h"
+
+namespace acch {
+namespace {
+
+constexpr int TX = 32, TY = 8;             // output tile, one cell per thread
+constexpr int LX2 = TX + 4, LY2 = TY + 4;  // fields with halo 2
+constexpr int LX1 = TX + 2, LY1 = TY + 2;  // cell quantities with halo 1
+
+// Periodic wrap, or clamping (the Neumann ghost copies the boundary cell, which
+// makes every boundary difference vanish, as in Section 2).  Offsets are within
+// +-2 of the domain and periodic grids have at least 5 cells.
+ACCH_DEV int wrap_index(int g, int n, int periodic) {
+  if (periodic) return g < 0 ? g + n : (g >= n ? g - n : g);
+  return g < 0 ? 0 : (g >= n ? n - 1 : g);
+}
+
+ACCH_DEV bool face_exists(int g, int dir, int n, int periodic) {
+  return periodic || (dir < 0 ? g > 0 : g < n - 1);
+}
+
+// Load the four fields of a tile with a 2-cell halo.  With Sdir the unknown state is
+// the line-search trial X + lam (S - shift e_u).
+ACCH_DEV void load_tile(const Phys &P, const double *__restrict__ X, const double *__restrict__ Sdir,
+                        double lam, const double *shift_ptr, const double *__restrict__ Xn, int bx0, int by0,
+                        int tid, double (*su1)[LX2], double (*sv1)[LX2], double (*su0)[LX2],
+                        double (*sv0)[LX2]) {
+  const long n = (long)P.nx * P.ny;
+  const double shift = shift_ptr ? *shift_ptr : 0.0;
+  for (int k = tid; k < LX2 * LY2; k += TX * TY) {
+    const int ly = k / LX2, lx = k - ly * LX2;
+    const int gx = wrap_index(bx0 + lx - 2, P.nx, P.periodic);
+    const int gy = wrap_index(by0 + ly - 2, P.ny, P.periodic);
+    const long g = (long)gy * P.nx + gx;
+    double u1 = X[g], v1 = X[n + g];
+    if (Sdir) {
+      u1 = fma(lam, Sdir[g] - shift, u1);
+      v1 = fma(lam, Sdir[n + g], v1);
+    }
+    su1[ly][lx] = u1;
+    sv1[ly][lx] = v1;
+    su0[ly][lx] = Xn[g];
+    sv0[ly][lx] = Xn[n + g];
+  }
+}
+
+ACCH_DEV double lap5(double (*s)[LX2], int cy, int cx, double wx, double wy) {
+  const double c = s[cy][cx];
+  return (s[cy][cx - 1] - c + (s[cy][cx + 1] - c)) * wx + (s[cy - 1][cx] - c + (s[cy + 1][cx] - c)) * wy;
+}
+
+// ---------------------------------------------------------------------------
+// Residual F(X; Xn, dt), optional trial state, ||F||^2 and admissibility count.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TX *TY) void k_residual2d(Phys P, const double *__restrict__ X,
+                                                        const double *__restrict__ Sdir, double lam,
+                                                        const double *shift, const double *__restrict__ Xn,
+                                                        double inv_dt, double *__restrict__ Xt,
+                                                        double *__restrict__ F, RedBuf red) {
+  __shared__ double su1[LY2][LX2], sv1[LY2][LX2], su0[LY2][LX2], sv0[LY2][LX2];
+  __shared__ double smu[LY1][LX1], sc[LY1][LX1], spm[LY1][LX1];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  const int bx0 = blockIdx.x * TX, by0 = blockIdx.y * TY;
+  const long n = (long)P.nx * P.ny;
+  load_tile(P, X, Sdir, lam, shift, Xn, bx0, by0, tid, su1, sv1, su0, sv0);
+  __syncthreads();
+  const double hg = 0.5 * P.gamma;
+  for (int k = tid; k < LX1 * LY1; k += TX * TY) {
+    const int ly = k / LX1, lx = k - ly * LX1;
+    const int cy = ly + 1, cx = lx + 1;
+    const double u1 = su1[cy][cx], v1 = sv1[cy][cx], u0 = su0[cy][cx], v0 = sv0[cy][cx];
+    const double phi = g2s(u1 + v1, u0 + v0, P.S);
+    const double psi = g2s(u1 - v1, u0 - v0, P.S);
+    const double lap = lap5(su1, cy, cx, P.wx, P.wy) + lap5(su0, cy, cx, P.wx, P.wy);
+    smu[ly][lx] = -0.5 * P.alpha * (u1 + u0 - 1.0) + P.theta * (phi + psi) - hg * lap;
+    sc[ly][lx] = mobility_of(P.mob, u1, v1, u0, v0);
+    spm[ly][lx] = P.theta * (phi - psi);
+  }
+  __syncthreads();
+  const int gx = bx0 + tx, gy = by0 + ty;
+  double acc[2] = {0.0, 0.0};
+  if (gx < P.nx && gy < P.ny) {
+    const int cy = ty + 2, cx = tx + 2, my = ty + 1, mx = tx + 1;
+    const double u1 = su1[cy][cx], v1 = sv1[cy][cx], u0 = su0[cy][cx], v0 = sv0[cy][cx];
+    const double lapv = lap5(sv1, cy, cx, P.wx, P.wy) + lap5(sv0, cy, cx, P.wx, P.wy);
+    const double nu = -0.5 * P.beta * (v1 + v0) + spm[my][mx] - hg * lapv;
+    const double ck = sc[my][mx], muk = smu[my][mx];
+    const double Fv = (v1 - v0) * inv_dt + ck * nu / P.rho;
+    double div = 0.0;
+    if (face_exists(gx, -1, P.nx, P.periodic)) div += 0.5 * (ck + sc[my][mx - 1]) * (smu[my][mx - 1] - muk) * P.wx;
+    if (face_exists(gx, 1, P.nx, P.periodic)) div += 0.5 * (ck + sc[my][mx + 1]) * (smu[my][mx + 1] - muk) * P.wx;
+    if (face_exists(gy, -1, P.ny, P.periodic)) div += 0.5 * (ck + sc[my - 1][mx]) * (smu[my - 1][mx] - muk) * P.wy;
+    if (face_exists(gy, 1, P.ny, P.periodic)) div += 0.5 * (ck + sc[my + 1][mx]) * (smu[my + 1][mx] - muk) * P.wy;
+    const double Fu = (u1 - u0) * inv_dt - div;
+    const long g = (long)gy * P.nx + gx;
+    F[g] = Fu;
+    F[n + g] = Fv;
+    if (Xt) {
+      Xt[g] = u1;
+      Xt[n + g] = v1;
+    }
+    acc[0] = Fu * Fu + Fv * Fv;
+    const double p = u1 + v1, q = u1 - v1;
+    acc[1] = (p > 0.0 && p < 1.0 && q > 0.0 && q < 1.0) ? 0.0 : 1.0;
+  }
+  grid_sum<2>(acc, red, tid, TX * TY, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+}
+
+// ---------------------------------------------------------------------------
+// Discrete energy (eqs. relations, freeenergy) with the exact Phi, and sum u.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_energy2d(Phys P, const double *__restrict__ X, RedBuf red) {
+  const long n = (long)P.nx * P.ny;
+  double acc[2] = {0.0, 0.0};
+  for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
+    const int gy = (int)(g / P.nx), gx = (int)(g - (long)gy * P.nx);
+    const double u = X[g], v = X[n + g];
+    double e = 0.5 * P.alpha * u * (1.0 - u) - 0.5 * P.beta * v * v + P.theta * (Phi(u + v) + Phi(u - v));
+    const long gw = (long)gy * P.nx + wrap_index(gx - 1, P.nx, P.periodic);
+    const long ge = (long)gy * P.nx + wrap_index(gx + 1, P.nx, P.periodic);
+    const long gs = (long)wrap_index(gy - 1, P.ny, P.periodic) * P.nx + gx;
+    const long gn = (long)wrap_index(gy + 1, P.ny, P.periodic) * P.nx + gx;
+    double grad = 0.0;
+    for (int c = 0; c < 2; ++c) {
+      const double *f = X + c * n;
+      const double fk = f[g];
+      const double dw = fk - f[gw], de = f[ge] - fk, ds = fk - f[gs], dn = f[gn] - fk;
+      grad += 0.5 * (dw * dw + de * de) * P.wx + 0.5 * (ds * ds + dn * dn) * P.wy;
+    }
+    e += 0.5 * P.gamma * grad;
+    acc[0] += e;
+    acc[1] += u;
+  }
+  grid_sum<2>(acc, red, threadIdx.x, 256, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Analytic Jacobian, 24 slot arrays J[slot][cell] (slot table in include/acch.h).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TX *TY) void k_jacobian2d(Phys P, const double *__restrict__ X,
+                                                        const double *__restrict__ Xn, double inv_dt,
+                                                        double *__restrict__ J) {
+  __shared__ double su1[LY2][LX2], sv1[LY2][LX2], su0[LY2][LX2], sv0[LY2][LX2];
+  __shared__ double smu[LY1][LX1], sc[LY1][LX1], scu[LY1][LX1], scv[LY1][LX1], sAm[LY1][LX1], sav[LY1][LX1];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  const int bx0 = blockIdx.x * TX, by0 = blockIdx.y * TY;
+  const long n = (long)P.nx * P.ny;
+  load_tile(P, X, nullptr, 0.0, nullptr, Xn, bx0, by0, tid, su1, sv1, su0, sv0);
+  __syncthreads();
+  const double hg = 0.5 * P.gamma;
+  for (int k = tid; k < LX1 * LY1; k += TX * TY) {
+    const int ly = k / LX1, lx = k - ly * LX1;
+    const int cy = ly + 1, cx = lx + 1;
+    const int gx = bx0 + lx - 1, gy = by0 + ly - 1;   // unwrapped; only the existence tests use it
+    const double u1 = su1[cy][cx], v1 = sv1[cy][cx], u0 = su0[cy][cx], v0 = sv0[cy][cx];
+    double phi, dphi, psi, dpsi, c, cu, cv;
+    g2s_d(u1 + v1, u0 + v0, P.S, phi, dphi);
+    g2s_d(u1 - v1, u0 - v0, P.S, psi, dpsi);
+    mobility_d(P.mob, u1, v1, u0, v0, c, cu, cv);
+    const double lap = lap5(su1, cy, cx, P.wx, P.wy) + lap5(su0, cy, cx, P.wx, P.wy);
+    double wsum = 0.0;
+    if (face_exists(gx, -1, P.nx, P.periodic)) wsum += P.wx;
+    if (face_exists(gx, 1, P.nx, P.periodic)) wsum += P.wx;
+    if (face_exists(gy, -1, P.ny, P.periodic)) wsum += P.wy;
+    if (face_exists(gy, 1, P.ny, P.periodic)) wsum += P.wy;
+    smu[ly][lx] = -0.5 * P.alpha * (u1 + u0 - 1.0) + P.theta * (phi + psi) - hg * lap;
+    sc[ly][lx] = c;
+    scu[ly][lx] = cu;
+    scv[ly][lx] = cv;
+    sAm[ly][lx] = -0.5 * P.alpha + P.theta * (dphi + dpsi) + hg * wsum;
+    sav[ly][lx] = P.theta * (dphi - dpsi);
+  }
+  __syncthreads();
+  const int gx = bx0 + tx, gy = by0 + ty;
+  if (gx >= P.nx || gy >= P.ny) return;
+  const int cy = ty + 2, cx = tx + 2, my = ty + 1, mx = tx + 1;
+  const double u1 = su1[cy][cx], v1 = sv1[cy][cx], u0 = su0[cy][cx], v0 = sv0[cy][cx];
+  double phi, dphi, psi, dpsi;
+  g2s_d(u1 + v1, u0 + v0, P.S, phi, dphi);
+  g2s_d(u1 - v1, u0 - v0, P.S, psi, dpsi);
+  const double lapv = lap5(sv1, cy, cx, P.wx, P.wy) + lap5(sv0, cy, cx, P.wx, P.wy);
+  const double nu = -0.5 * P.beta * (v1 + v0) + P.theta * (phi - psi) - hg * lapv;
+  const bool eW = face_exists(gx, -1, P.nx, P.periodic), eE = face_exists(gx, 1, P.nx, P.periodic);
+  const bool eS = face_exists(gy, -1, P.ny, P.periodic), eN = face_exists(gy, 1, P.ny, P.periodic);
+  const double wsum = (eW ? P.wx : 0.0) + (eE ? P.wx : 0.0) + (eS ? P.wy : 0.0) + (eN ? P.wy : 0.0);
+  const double Bnu = -0.5 * P.beta + P.theta * (dphi + dpsi) + hg * wsum;
+  const double ck = sc[my][mx], muk = smu[my][mx], cuk = scu[my][mx], cvk = scv[my][mx];
+  const double Amk = sAm[my][mx], avk = sav[my][mx];
+  // faces W, E, S, N: neighbour (dy, dx) in the halo-1 arrays, weight, existence
+  const int fdy[4] = {0, 0, -1, 1}, fdx[4] = {-1, 1, 0, 0};
+  const double fw[4] = {P.wx, P.wx, P.wy, P.wy};
+  const bool fe[4] = {eW, eE, eS, eN};
+  double D[4], ct[4];
+  double Wc = 0.0, sWD = 0.0, sW2c = 0.0;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int yy = my + fdy[f], xx = mx + fdx[f];
+    D[f] = smu[yy][xx] - muk;
+    ct[f] = 0.5 * (ck + sc[yy][xx]);
+    if (fe[f]) {
+      Wc += fw[f] * ct[f];
+      sWD += fw[f] * D[f];
+      sW2c += fw[f] * fw[f] * ct[f];
+    }
+  }
+  double s[kNSlot2D];
+  s[0] = inv_dt - 0.5 * cuk * sWD + Amk * Wc + hg * sW2c;
+  // first neighbours (slots 1..4 = W, E, S, N)
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int yy = my + fdy[f], xx = mx + fdx[f];
+    s[1 + f] = fe[f] ? -fw[f] * (0.5 * scu[yy][xx] * D[f] + ct[f] * sAm[yy][xx] + hg * Wc) : 0.0;
+    s[14 + f] = fe[f] ? -fw[f] * (0.5 * scv[yy][xx] * D[f] + ct[f] * sav[yy][xx]) : 0.0;
+    s[19 + f] = fe[f] ? -ck * hg * fw[f] / P.rho : 0.0;
+  }
+  // second neighbours along the axes: (-2,0), (2,0), (0,-2), (0,2)
+  s[5] = (eW && face_exists(gx - 1, -1, P.nx, P.periodic)) ? hg * P.wx * P.wx * ct[0] : 0.0;
+  s[6] = (eE && face_exists(gx + 1, 1, P.nx, P.periodic)) ? hg * P.wx * P.wx * ct[1] : 0.0;
+  s[7] = (eS && face_exists(gy - 1, -1, P.ny, P.periodic)) ? hg * P.wy * P.wy * ct[2] : 0.0;
+  s[8] = (eN && face_exists(gy + 1, 1, P.ny, P.periodic)) ? hg * P.wy * P.wy * ct[3] : 0.0;
+  // diagonal neighbours: two paths, through the x face and through the y face
+  const double wxy = hg * P.wx * P.wy;
+  s[9] = (eW && eS) ? wxy * (ct[0] + ct[2]) : 0.0;   // (-1,-1)
+  s[10] = (eE && eS) ? wxy * (ct[1] + ct[2]) : 0.0;  // (1,-1)
+  s[11] = (eW && eN) ? wxy * (ct[0] + ct[3]) : 0.0;  // (-1,1)
+  s[12] = (eE && eN) ? wxy * (ct[1] + ct[3]) : 0.0;  // (1,1)
+  s[13] = -0.5 * cvk * sWD + avk * Wc;
+  s[18] = inv_dt + (cvk * nu + ck * Bnu) / P.rho;
+  s[23] = (cuk * nu + ck * avk) / P.rho;
+  const long g = (long)gy * P.nx + gx;
+#pragma unroll
+  for (int k = 0; k < kNSlot2D; ++k) J[k * n + g] = s[k];
+}
+
+// y = J x for the 24-slot layout.
+ACCH_DEV void spmv_cell(const Phys &P, const double *__restrict__ J, const double *__restrict__ x, long n,
+                        int gx, int gy, double &yu, double &yv) {
+  const int xm2 = wrap_index(gx - 2, P.nx, P.periodic), xm1 = wrap_index(gx - 1, P.nx, P.periodic);
+  const int xp1 = wrap_index(gx + 1, P.nx, P.periodic), xp2 = wrap_index(gx + 2, P.nx, P.periodic);
+  const int ym2 = wrap_index(gy - 2, P.ny, P.periodic), ym1 = wrap_index(gy - 1, P.ny, P.periodic);
+  const int yp1 = wrap_index(gy + 1, P.ny, P.periodic), yp2 = wrap_index(gy + 2, P.ny, P.periodic);
+  const long r0 = (long)gy * P.nx, rm1 = (long)ym1 * P.nx, rp1 = (long)yp1 * P.nx;
+  const long rm2 = (long)ym2 * P.nx, rp2 = (long)yp2 * P.nx;
+  const long g = r0 + gx;
+  const double *xu = x, *xv = x + n;
+  const long iw = r0 + xm1, ie = r0 + xp1, is = rm1 + gx, in_ = rp1 + gx;
+  double a = J[0 * n + g] * xu[g];
+  a = fma(J[1 * n + g], xu[iw], a);
+  a = fma(J[2 * n + g], xu[ie], a);
+  a = fma(J[3 * n + g], xu[is], a);
+  a = fma(J[4 * n + g], xu[in_], a);
+  a = fma(J[5 * n + g], xu[r0 + xm2], a);
+  a = fma(J[6 * n + g], xu[r0 + xp2], a);
+  a = fma(J[7 * n + g], xu[rm2 + gx], a);
+  a = fma(J[8 * n + g], xu[rp2 + gx], a);
+  a = fma(J[9 * n + g], xu[rm1 + xm1], a);
+  a = fma(J[10 * n + g], xu[rm1 + xp1], a);
+  a = fma(J[11 * n + g], xu[rp1 + xm1], a);
+  a = fma(J[12 * n + g], xu[rp1 + xp1], a);
+  a = fma(J[13 * n + g], xv[g], a);
+  a = fma(J[14 * n + g], xv[iw], a);
+  a = fma(J[15 * n + g], xv[ie], a);
+  a = fma(J[16 * n + g], xv[is], a);
+  a = fma(J[17 * n + g], xv[in_], a);
+  double b = J[18 * n + g] * xv[g];
+  b = fma(J[19 * n + g], xv[iw], b);
+  b = fma(J[20 * n + g], xv[ie], b);
+  b = fma(J[21 * n + g], xv[is], b);
+  b = fma(J[22 * n + g], xv[in_], b);
+  b = fma(J[23 * n + g], xu[g], b);
+  yu = a;
+  yv = b;
+}
+
+__global__ __launch_bounds__(256) void k_spmv2d(Phys P, const double *__restrict__ J, const double *__restrict__ x,
+                                                 double *__restrict__ y) {
+  const long n = (long)P.nx * P.ny;
+  for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
+    const int gy = (int)(g / P.nx), gx = (int)(g - (long)gy * P.nx);
+    double yu, yv;
+    spmv_cell(P, J, x, n, gx, gy, yu, yv);
+    y[g] = yu;
+    y[n + g] = yv;
+  }
+}
+
+// w = J z_j (written to the Arnoldi slot j+1), fused with the classical Gram–Schmidt
+// dots h_ij = inv_norm_i <w, W_i>, i <= j.  Skipped when the cycle is finished.
+__global__ __launch_bounds__(256) void k_spmv_dots2d(Phys P, const double *__restrict__ J,
+                                                      const double *__restrict__ Z, double *__restrict__ V,
+                                                      long vstride, GmresState *st, RedBuf red) {
+  if (st->done) return;
+  const int j = st->j;
+  const long n = (long)P.nx * P.ny;
+  const double *z = Z + (long)j * vstride;
+  double *w = V + (long)(j + 1) * vstride;
+  double acc[kMaxRestart + 1];
+#pragma unroll
+  for (int i = 0; i <= kMaxRestart; ++i) acc[i] = 0.0;
+  for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
+    const int gy = (int)(g / P.nx), gx = (int)(g - (long)gy * P.nx);
+    double yu, yv;
+    spmv_cell(P, J, z, n, gx, gy, yu, yv);
+    w[g] = yu;
+    w[n + g] = yv;
+#pragma unroll
+    for (int i = 0; i <= kMaxRestart; ++i)
+      if (i <= j) acc[i] = fma(yu, V[(long)i * vstride + g], fma(yv, V[(long)i * vstride + n + g], acc[i]));
+  }
+  const bool last = grid_sum<kMaxRestart + 1>(acc, red, threadIdx.x, 256, blockIdx.x, gridDim.x, j + 1);
+  if (last && threadIdx.x <= j) st->hcol[threadIdx.x] = red.out[threadIdx.x] * st->inv_norm[threadIdx.x];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline dim3 tile_grid(const Phys &P) { return dim3((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY); }
+
+int reduce_blocks(long n) {
+  long b = (n + 255) / 256;
+  if (b > kRedBlocks) b = kRedBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t launch_residual2d(const Phys &P, const double *X, const double *Sdir, double lam, const double *shift,
+                             const double *Xn, double dt, double *Xt, double *F, const RedBuf &red,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_residual2d, tile_grid(P), dim3(TX, TY), 0, s, P, X, Sdir, lam, shift, Xn, 1.0 / dt, Xt, F,
+                     red);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy2d(const Phys &P, const double *X, const RedBuf &red, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy2d, dim3(reduce_blocks((long)P.nx * P.ny)), dim3(256), 0, s, P, X, red);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobian2d(const Phys &P, const double *X, const double *Xn, double dt, double *J,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_jacobian2d, tile_grid(P), dim3(TX, TY), 0, s, P, X, Xn, 1.0 / dt, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv2d(const Phys &P, const double *J, const double *x, double *y, hipStream_t s) {
+  const long n = (long)P.nx * P.ny;
+  hipLaunchKernelGGL(k_spmv2d, dim3((int)((n + 255) / 256)), dim3(256), 0, s, P, J, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_dots2d(const Phys &P, const double *J, const double *Z, double *V, long vstride,
+                              GmresState *st, const RedBuf &red, hipStream_t s) {
+  hipLaunchKernelGGL(k_spmv_dots2d, dim3(reduce_blocks((long)P.nx * P.ny)), dim3(256), 0, s, P, J, Z, V, vstride,
+                     st, red);
+  return hipGetLastError();
+}
+
+}  // namespace acch
