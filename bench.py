@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-time-step Newton–Krylov–Schwarz solve of scheme (2.20).
+
+Workload (one "step" = one accepted time step, all Newton iterations included):
+2D periodic [0,1]^2, 512 x 512 cells, alpha = beta = 1.2, theta = 0.1, gamma = 1e-3,
+rho = 1, seeded initial data u0 = 0.5 + 0.05 U(-1,1), v0 = 0.05 U(-1,1); adaptive
+dt in [1e-4, 1e-1] (eta0 = 1e4); FP64 Newton (tol 1e-8) with right-preconditioned
+GMRES(30) and left-restricted additive Schwarz on 8 x 8 subdomains, overlap 2,
+subdomain ILU(0) (shifted by 0.02 diag, factored once per step attempt).  The
+default run is the workload's 200 steps from the initial data.
+
+Metric: dof * Newton iterations / s with dof = 2 * cells, counting every Newton
+iteration of every attempt, over the timed steps (inputs resident in HBM).
+
+Also printed: the roofline of the dominant kernel (algorithmic bytes per launch
+over its average duration, measured live with HIP events on the library's stream)
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = dict(name="periodic512", shape=(512, 512), bc="periodic", sub=(8, 8), overlap=2,
+                adaptive=True, dt_min=1e-4, dt_max=1e-1, eta0=1e4, newton_rtol=1e-8, newton_atol=1e-13,
+                gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30, ilu_shift=0.02, precision="fp64", seed=0)
+
+
+def ras_bytes_per_cell(box_cells: float, owned_cells: float, nslot: int = 24, sp: int = 8) -> float:
+    """Algorithmic bytes of one left-RAS apply per owned cell: read r on the extended
+    box (16 B per box cell), read the factors (nslot * sp per box cell), write z on the
+    owned cells (16 B)."""
+    omega = box_cells / owned_cells
+    return omega * 16.0 + omega * nslot * sp + 16.0
+
+
+def spmv_dots_bytes_per_cell(j_avg: float) -> float:
+    """J z (24 coefficients + z) written to w, plus one read of j+1 basis vectors."""
+    return 24 * 8 + 16 + 16 + 16 * (j_avg + 1)
+
+
+def run_gpu(steps: int, warmup: int, timing: bool):
+    import numpy as np
+    import torch
+    from acch_inputs import random_ic
+    from paper_2007_04560_amd import Solver
+
+    w = WORKLOAD
+    u0, v0 = random_ic(w["shape"], w["seed"])
+    kw = dict(bc=w["bc"], sub=w["sub"], overlap=w["overlap"], adaptive=w["adaptive"], dt_min=w["dt_min"],
+              dt_max=w["dt_max"], eta0=w["eta0"], newton_rtol=w["newton_rtol"], newton_atol=w["newton_atol"],
+              gmres_rtol=w["gmres_rtol"], gmres_atol=w["gmres_atol"], gmres_restart=w["gmres_restart"],
+              ilu_shift=w["ilu_shift"], precision=w["precision"])
+    if warmup > 0:
+        with Solver(u0, v0, **kw) as s:
+            s.step(warmup)
+    s = Solver(u0, v0, **kw)
+    E0, M0 = s.energy()
+    s.timing(timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = s.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = s.kernel_stats() if timing else {}
+    launches, syncs = s.counters()
+    info = s.info()
+    E1, M1 = s.energy()
+    s.close()
+    return dict(elapsed=t1 - t0, recs=recs, stats=stats, info=info, launches=launches, syncs=syncs,
+                E0=E0, E1=E1, M0=M0, M1=M1, ncell=u0.size)
+
+
+def cpu_baseline(budget_s: float = 20.0):
+    """The FP64 oracle (NumPy residual/Jacobian, SuperLU direct Newton solves, same dt
+    controller) on a bounded sample: the same workload's physics, controller and
+    initial-data recipe on a 128 x 128 grid, stepped until about budget_s seconds."""
+    import numpy as np
+    from acch_inputs import random_ic
+    from oracle import controller, newton
+    from oracle.params import Problem
+
+    w = WORKLOAD
+    shape = (128, 128)
+    u0, v0 = random_ic(shape, w["seed"])
+    run = controller.Run(Problem(bc=w["bc"]), u0, v0, adaptive=True, dt_min=w["dt_min"], dt_max=w["dt_max"],
+                         eta=w["eta0"], newton=newton.NewtonOptions(rtol=w["newton_rtol"], atol=w["newton_atol"]))
+    t0 = time.perf_counter()
+    its = 0
+    steps = 0
+    while time.perf_counter() - t0 < budget_s and steps < 50:
+        its += run.step().newton_its
+        steps += 1
+    el = time.perf_counter() - t0
+    dof = 2 * u0.size
+    return {"value": dof * its / el, "unit": "dof*Newton/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle on the same workload at 128x128 (2D periodic, same parameters, controller and "
+                      f"seeded initial data): {steps} time steps, {its} Newton iterations in {el:.1f} s; "
+                      f"SuperLU and NumPy single-threaded, host has {os.cpu_count()} logical CPUs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP-event timers")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition is "
+              "not part of this build", file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    r = run_gpu(args.steps, args.warmup, timing=not args.no_timing)
+    recs = r["recs"]
+    newton_its = sum(int(x["newton_its"]) for x in recs)
+    gmres_its = sum(int(x["gmres_its"]) for x in recs)
+    dof = 2 * r["ncell"]
+    value = dof * newton_its / r["elapsed"]
+    info = r["info"]
+    box = info["box_w"] * info["box_h"]
+    owned = r["ncell"] / info["nsub"]
+    roofline = None
+    stats = r["stats"]
+    if stats and stats["ras"][1] > 0:
+        ras_ms, ras_n = stats["ras"]
+        avg_s = ras_ms / ras_n * 1e-3
+        bytes_launch = ras_bytes_per_cell(box, owned) * r["ncell"]
+        achieved = bytes_launch / avg_s / 1e9
+        dom = max(stats, key=lambda k: stats[k][0])
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_ras_apply2d",
+                    "avg_us": round(avg_s * 1e6, 2), "launches": ras_n,
+                    "bytes_per_launch": int(bytes_launch), "dominant_by_time": dom}
+    line = {
+        "metric": "dof*Newton-steps/s at 1e-8 tol",
+        "value": round(value, 1),
+        "unit": "dof*Newton/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["elapsed"] / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "periodic512: 2D periodic 512x512, 200 adaptive steps dt in [1e-4,1e-1], "
+                               "FP64 NKS, left-RAS 8x8 overlap 2, ILU(0) shift 0.02, GMRES(30), tol 1e-8",
+                   "cells": r["ncell"], "dof": dof, "newton_its": newton_its, "gmres_its": gmres_its,
+                   "gmres_per_newton": round(gmres_its / max(1, newton_its), 2),
+                   "t_final": recs[-1]["t"] if recs else 0.0,
+                   "dt_last": recs[-1]["dt"] if recs else 0.0,
+                   "energy_first_last": [r["E0"], r["E1"]],
+                   "mass_drift_rel": abs(r["M1"] - r["M0"]) / r["M0"],
+                   "launches": r["launches"], "host_syncs": r["syncs"],
+                   "kernel_ms": {k: round(v[0], 3) for k, v in stats.items() if v[1]}},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

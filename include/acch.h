@@ -183,6 +183,25 @@ int acch_export(acch_ctx *c, int which, void *out, size_t *bytes);
  * statistics of the last acch_step call (launches, host synchronisations). */
 int acch_info(acch_ctx *c, long *ncell, int *nsub, int *box_w, int *box_h);
 
+/* Kernel classes of the per-step solve, for acch_kernel_stats. */
+enum {
+  ACCH_KERNEL_RESIDUAL = 0, ACCH_KERNEL_JACOBIAN = 1, ACCH_KERNEL_FACTOR = 2, ACCH_KERNEL_RAS = 3,
+  ACCH_KERNEL_SPMV_DOTS = 4, ACCH_KERNEL_ORTH = 5, ACCH_KERNEL_GMRES_START = 6, ACCH_KERNEL_GMRES_UPDATE = 7,
+  ACCH_KERNEL_ENERGY = 8, ACCH_KERNEL_SPMV = 9, ACCH_KERNEL_OTHER = 10, ACCH_KERNEL_KINDS = 11
+};
+
+/* Enable (1) or disable (0) per-kernel timing: HIP events recorded on the context's
+ * stream around every launch, accumulated per kernel class.  Resets the totals and
+ * the launch / synchronisation counters.  Synchronises the stream. */
+int acch_timing(acch_ctx *c, int enable);
+
+/* Accumulated device time (ms, host double) and launch count of one kernel class
+ * since the last acch_timing call. */
+int acch_kernel_stats(acch_ctx *c, int kind, double *total_ms, long *count);
+
+/* Kernel launches and host synchronisations since the last acch_timing call. */
+int acch_counters(acch_ctx *c, long *launches, long *syncs);
+
 const char *acch_strerror(int code);
 const char *acch_last_error(void);
 

@@ -23,7 +23,10 @@ EXPORTED = [
     "acch_destroy", "acch_get_fields", "acch_set_fields", "acch_get_time", "acch_residual",
     "acch_jacobian", "acch_apply_jacobian", "acch_factor", "acch_precondition", "acch_gmres",
     "acch_solve_step", "acch_export", "acch_info", "acch_strerror", "acch_last_error",
+    "acch_timing", "acch_kernel_stats", "acch_counters",
 ]
+KERNEL_KINDS = ["residual", "jacobian", "factor", "ras", "spmv_dots", "orth", "gmres_start", "gmres_update",
+                "energy", "spmv", "other"]
 
 
 class Params(ctypes.Structure):
@@ -97,6 +100,9 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "acch_info": (ctypes.c_int, [ctx, ctypes.POINTER(ctypes.c_long), ip, ip, ip]),
         "acch_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "acch_last_error": (ctypes.c_char_p, []),
+        "acch_timing": (ctypes.c_int, [ctx, ctypes.c_int]),
+        "acch_kernel_stats": (ctypes.c_int, [ctx, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_long)]),
+        "acch_counters": (ctypes.c_int, [ctx, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -238,6 +244,22 @@ class Solver:
         t, dtp, eta = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _check(self.lib, self.lib.acch_get_time(self.ctx, ctypes.byref(t), ctypes.byref(dtp), ctypes.byref(eta)))
         return t.value, dtp.value, eta.value
+
+    def timing(self, enable: bool = True):
+        _check(self.lib, self.lib.acch_timing(self.ctx, int(bool(enable))))
+
+    def kernel_stats(self) -> Dict[str, Tuple[float, int]]:
+        out = {}
+        for k, name in enumerate(KERNEL_KINDS):
+            ms, cnt = ctypes.c_double(), ctypes.c_long()
+            _check(self.lib, self.lib.acch_kernel_stats(self.ctx, k, ctypes.byref(ms), ctypes.byref(cnt)))
+            out[name] = (ms.value, cnt.value)
+        return out
+
+    def counters(self) -> Tuple[int, int]:
+        a, b = ctypes.c_long(), ctypes.c_long()
+        _check(self.lib, self.lib.acch_counters(self.ctx, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def info(self):
         n, ns, bw, bh = ctypes.c_long(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

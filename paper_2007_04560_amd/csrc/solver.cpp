@@ -57,6 +57,18 @@ struct Layout {
   size_t total;
 };
 
+// Optional per-kernel-class timing with HIP events recorded on the context's stream
+// around each launch; harvested whenever the host synchronises anyway.
+struct KernelTimer {
+  static constexpr int kPool = 2048;
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  std::vector<int> kind;
+  int used = 0;
+  double total_ms[ACCH_KERNEL_KINDS] = {};
+  long count[ACCH_KERNEL_KINDS] = {};
+};
+
 struct Geometry {
   long ncell = 0;
   BoxGeom G{};
@@ -88,6 +100,7 @@ struct acch_ctx {
   bool factored = false;
   int its_guess = 4;
   long launches = 0, syncs = 0;
+  KernelTimer timer;
 };
 
 // ---------------------------------------------------------------------------
@@ -243,24 +256,59 @@ static bool admissible_host(const double *u, const double *v, long n) {
 // ---------------------------------------------------------------------------
 namespace {
 
+// Fold the completed event pairs into the per-kind totals (the stream is idle).
+int harvest_timer(acch_ctx *c) {
+  KernelTimer &T = c->timer;
+  for (int i = 0; i < T.used; ++i) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
+    T.total_ms[T.kind[i]] += ms;
+    T.count[T.kind[i]] += 1;
+  }
+  T.used = 0;
+  return ACCH_OK;
+}
+
 int sync_read(acch_ctx *c, const void *dev, void *host, size_t bytes) {
   HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->syncs++;
+  if (c->timer.on && c->timer.used) return harvest_timer(c);
   return ACCH_OK;
 }
 
-// Launch helper that records the launch and maps errors.
-#define LAUNCH(c, expr)                                                                            \
+int timer_begin(acch_ctx *c, int kind) {
+  KernelTimer &T = c->timer;
+  if (!T.on) return -1;
+  if (T.used == KernelTimer::kPool) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int rc = harvest_timer(c);
+    if (rc) return -1;
+  }
+  const int slot = T.used++;
+  T.kind[slot] = kind;
+  if (hipEventRecord(T.ev[2 * slot], c->stream) != hipSuccess) return -1;
+  return slot;
+}
+
+void timer_end(acch_ctx *c, int slot) {
+  if (slot >= 0) (void)hipEventRecord(c->timer.ev[2 * slot + 1], c->stream);
+}
+
+// Launch helper: counts the launch, optionally times it, maps errors.
+#define LAUNCHK(c, kind, expr)                                                                     \
   do {                                                                                             \
+    const int slot_ = timer_begin((c), (kind));                                                    \
     hipError_t e_ = (expr);                                                                        \
+    timer_end((c), slot_);                                                                         \
     (c)->launches++;                                                                               \
     if (e_ != hipSuccess) return fail(ACCH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
+#define LAUNCH(c, expr) LAUNCHK(c, ACCH_KERNEL_OTHER, expr)
 
 int residual_eval(acch_ctx *c, const double *X, const double *Sdir, double lam, const double *shift,
                   const double *Xn, double dt, double *Xt, double *F, double &f2, double &bad) {
-  LAUNCH(c, launch_residual2d(c->P, X, Sdir, lam, shift, Xn, dt, Xt, F, c->red, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_RESIDUAL, launch_residual2d(c->P, X, Sdir, lam, shift, Xn, dt, Xt, F, c->red, c->stream));
   int rc = sync_read(c, c->red.out, c->host->vals, 2 * sizeof(double));
   if (rc) return rc;
   f2 = c->host->vals[0];
@@ -269,7 +317,7 @@ int residual_eval(acch_ctx *c, const double *X, const double *Sdir, double lam, 
 }
 
 int factor(acch_ctx *c) {
-  LAUNCH(c, launch_ilu_factor2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->J,
+  LAUNCHK(c, ACCH_KERNEL_FACTOR, launch_ilu_factor2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->J,
                                 c->p.ilu_shift, c->fac, c->p.precision == ACCH_PREC_MIXED, c->stream));
   c->factored = true;
   return ACCH_OK;
@@ -288,19 +336,19 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid) {
   const size_t tail = offsetof(GmresState, beta);
   GmresState hs{};
   for (int cycle = 0; cycle < c->p.gmres_max_restarts; ++cycle) {
-    if (cycle > 0) LAUNCH(c, launch_spmv2d(c->P, c->J, S, c->W, c->stream));
-    LAUNCH(c, launch_gmres_start(n2, F, cycle > 0 ? c->W : nullptr, c->V, c->st, m, c->p.gmres_rtol,
+    if (cycle > 0) LAUNCHK(c, ACCH_KERNEL_SPMV, launch_spmv2d(c->P, c->J, S, c->W, c->stream));
+    LAUNCHK(c, ACCH_KERNEL_GMRES_START, launch_gmres_start(n2, F, cycle > 0 ? c->W : nullptr, c->V, c->st, m, c->p.gmres_rtol,
                                  c->p.gmres_atol, c->red, c->stream));
     int launched = 0;
     int chunk = cycle == 0 ? std::max(1, std::min(m, c->its_guess)) : std::max(1, m / 2);
     while (true) {
       for (int k = 0; k < chunk && launched < m; ++k, ++launched) {
-        LAUNCH(c, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->fac, c->ybuf,
+        LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->fac, c->ybuf,
                                      c->V, c->Z, c->st, vs, fp32, c->stream));
-        LAUNCH(c, launch_spmv_dots2d(c->P, c->J, c->Z, c->V, vs, c->st, c->red, c->stream));
-        LAUNCH(c, launch_gmres_orth(n2, c->V, vs, c->st, c->red, c->stream));
+        LAUNCHK(c, ACCH_KERNEL_SPMV_DOTS, launch_spmv_dots2d(c->P, c->J, c->Z, c->V, vs, c->st, c->red, c->stream));
+        LAUNCHK(c, ACCH_KERNEL_ORTH, launch_gmres_orth(n2, c->V, vs, c->st, c->red, c->stream));
       }
-      LAUNCH(c, launch_gmres_update(c->geo.ncell, S, c->Z, vs, c->st, cycle > 0, project, c->red, c->stream));
+      LAUNCHK(c, ACCH_KERNEL_GMRES_UPDATE, launch_gmres_update(c->geo.ncell, S, c->Z, vs, c->st, cycle > 0, project, c->red, c->stream));
       int rc = sync_read(c, (const char *)c->st + tail, c->host_state, sizeof(GmresState) - tail);
       if (rc) return rc;
       memcpy((char *)&hs + tail, c->host_state, sizeof(GmresState) - tail);
@@ -389,7 +437,7 @@ int nks_solve(acch_ctx *c, double dt, SolveStats &stats) {
   const double tol = std::max(c->p.newton_rtol * fnorm, c->p.newton_atol);
   if (fnorm <= tol) return ACCH_OK;
   for (int it = 1; it <= c->p.newton_max_it; ++it) {
-    LAUNCH(c, launch_jacobian2d(c->P, c->X, c->Xn, dt, c->J, c->stream));
+    LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->P, c->X, c->Xn, dt, c->J, c->stream));
     if (it == 1 || !c->p.ilu_reuse) {
       rc = factor(c);
       if (rc) return rc;
@@ -414,7 +462,7 @@ int nks_solve(acch_ctx *c, double dt, SolveStats &stats) {
 }
 
 int energy_mass(acch_ctx *c, const double *X, double &E, double &M) {
-  LAUNCH(c, launch_energy2d(c->P, X, c->red, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_ENERGY, launch_energy2d(c->P, X, c->red, c->stream));
   int rc = sync_read(c, c->red.out, c->host->vals, 2 * sizeof(double));
   if (rc) return rc;
   E = c->host->vals[0] * c->hvol;
@@ -526,9 +574,52 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   return ACCH_OK;
 }
 
+extern "C" int acch_timing(acch_ctx *c, int enable) {
+  if (!c) return fail(ACCH_EINVAL, "null context");
+  KernelTimer &T = c->timer;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (T.on && T.used) {
+    int rc = harvest_timer(c);
+    if (rc) return rc;
+  }
+  if (enable && T.ev.empty()) {
+    T.ev.resize(2 * KernelTimer::kPool);
+    T.kind.resize(KernelTimer::kPool);
+    for (auto &e : T.ev) HIP_TRY(hipEventCreate(&e));
+  }
+  T.on = enable != 0;
+  for (int k = 0; k < ACCH_KERNEL_KINDS; ++k) {
+    T.total_ms[k] = 0.0;
+    T.count[k] = 0;
+  }
+  c->launches = 0;
+  c->syncs = 0;
+  return ACCH_OK;
+}
+
+extern "C" int acch_kernel_stats(acch_ctx *c, int kind, double *total_ms, long *count) {
+  if (!c || kind < 0 || kind >= ACCH_KERNEL_KINDS) return fail(ACCH_EINVAL, "bad arguments");
+  if (c->timer.on && c->timer.used) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    int rc = harvest_timer(c);
+    if (rc) return rc;
+  }
+  if (total_ms) *total_ms = c->timer.total_ms[kind];
+  if (count) *count = c->timer.count[kind];
+  return ACCH_OK;
+}
+
+extern "C" int acch_counters(acch_ctx *c, long *launches, long *syncs) {
+  if (!c) return fail(ACCH_EINVAL, "null context");
+  if (launches) *launches = c->launches;
+  if (syncs) *syncs = c->syncs;
+  return ACCH_OK;
+}
+
 extern "C" int acch_destroy(acch_ctx *c) {
   if (!c) return ACCH_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto &e : c->timer.ev) (void)hipEventDestroy(e);
   if (c->host) (void)hipHostFree(c->host);
   delete c;
   return ACCH_OK;
@@ -666,7 +757,7 @@ extern "C" int acch_residual(acch_ctx *c, const double *X, const double *Xn, dou
 
 extern "C" int acch_jacobian(acch_ctx *c, const double *X, const double *Xn, double dt) {
   if (!c || !X || !Xn || !(dt > 0)) return fail(ACCH_EINVAL, "bad arguments");
-  LAUNCH(c, launch_jacobian2d(c->P, X, Xn, dt, c->J, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->P, X, Xn, dt, c->J, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;
 }
@@ -689,7 +780,7 @@ extern "C" int acch_factor(acch_ctx *c) {
 extern "C" int acch_precondition(acch_ctx *c, const double *r, double *z) {
   if (!c || !r || !z) return fail(ACCH_EINVAL, "bad arguments");
   if (!c->factored) return fail(ACCH_EINVAL, "no factorisation: call acch_factor first");
-  LAUNCH(c, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->fac, c->ybuf, r, z,
+  LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->fac, c->ybuf, r, z,
                                nullptr, 0, c->p.precision == ACCH_PREC_MIXED, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;
