@@ -8,7 +8,7 @@ namespace acch {
 
 constexpr int kMaxRestart = 30;     // GMRES(m) with m <= 30 (device Hessenberg storage)
 constexpr int kMaxS = 64;           // series order limit of Lemma 2.2's truncation
-constexpr int kRedBlocks = 1024;    // grid size of the vector reduction kernels
+constexpr int kRedBlocks = 512;     // grid size of the vector reduction kernels
 constexpr int kNSlot2D = 24;        // Jacobian / factor slots per cell in 2D
 
 // Physical and mesh parameters seen by the stencil kernels.
@@ -21,18 +21,20 @@ struct Phys {
   int mob;                // 0 midpoint, 1 average, 2 explicit
 };
 
-// Scratch used by the two-level reductions: per-block partial sums and a ticket.
+// Scratch of the two-kernel reductions: per-block partial sums and final values.
 struct RedBuf {
   double *partials;       // [nv][gridblocks]
-  unsigned *counter;      // zero between kernels; the last block resets it
+  unsigned *counter;      // unused (kept zero)
   double *out;            // [nv] final sums
 };
 
 // Geometry of the padded subdomain boxes Omega_k^delta (all boxes share bw x bh).
+// Per-box factor and scratch storage is wavefront-major: cell (i, j) lives at slot
+// (i + 2j) * bh + j of nlev * bh slots, so a wavefront's cells are contiguous.
 struct BoxGeom {
   int bw, bh;             // padded box width/height (cells)
   int nlev;               // levels of the i + 2j wavefront: bw + 2(bh-1)
-  int ncb;                // bw * bh
+  int ncb;                // bw * bh (cells of a box; storage is padded to nlev * bh slots)
   int nsub;
 };
 
@@ -107,44 +109,34 @@ ACCH_DEV void block_sum(double (&v)[NV], int tid, int nthreads) {
   }
 }
 
-// Grid-wide sum of NV values per thread (only the first nv_used are reduced).  Each
-// block stores its partial sums; the block that arrives last (device-scope ticket)
-// sums the partials in block order, which makes the result independent of
-// scheduling, and writes red.out[0..nv_used).  Returns true in every thread of the
-// last block (red.out is then valid there).
+// Two-kernel grid reductions.  A reduction kernel stores one partial sum per block
+// (block_partial); a one-block finalize kernel adds the partials in block order
+// (final_sum), which makes the result independent of scheduling.  The kernel
+// boundary orders the two: no device-scope fence (on this GPU a full L2 write-back
+// per block) is needed.
 template <int NV>
-ACCH_DEV bool grid_sum(double (&v)[NV], const RedBuf &red, int tid, int nthreads, int bid,
-                       int nblocks, int nv_used = NV) {
-  __shared__ int s_last;
+ACCH_DEV void block_partial(double (&v)[NV], double *partials, int tid, int nthreads, int bid, int nblocks,
+                            int nv_used = NV) {
   block_sum<NV>(v, tid, nthreads);
   if (tid == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k)
-      if (k < nv_used) red.partials[k * nblocks + bid] = v[k];
-    __threadfence();
-    const unsigned prev = atomicAdd(red.counter, 1u);
-    s_last = (prev == (unsigned)(nblocks - 1));
+      if (k < nv_used) partials[k * nblocks + bid] = v[k];
   }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  double acc[NV];
+}
+
+// Sum of the partials of the first nv_used values; valid in thread 0.
+template <int NV>
+ACCH_DEV void final_sum(const double *partials, int nblocks, int tid, int nthreads, double (&acc)[NV],
+                        int nv_used = NV) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double a = 0.0;
     if (k < nv_used)
-      for (int b = tid; b < nblocks; b += nthreads) a += red.partials[k * nblocks + b];
+      for (int b = tid; b < nblocks; b += nthreads) a += partials[k * nblocks + b];
     acc[k] = a;
   }
   block_sum<NV>(acc, tid, nthreads);
-  if (tid == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-      if (k < nv_used) red.out[k] = acc[k];
-    *red.counter = 0u;
-  }
-  __syncthreads();
-  return true;
 }
 
 }  // namespace acch

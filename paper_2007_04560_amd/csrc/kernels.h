@@ -6,6 +6,16 @@
 namespace acch {
 
 int reduce_blocks(long n);
+
+// Second stage of the two-kernel reductions (krylov.hip).
+enum { kFinPlain = 0, kFinStart = 1, kFinDots = 2, kFinOrth = 3, kFinUpdate = 4 };
+struct FinalizeArgs {
+  int first, m, project;
+  double rtol, atol;
+  long ncell;
+};
+hipError_t launch_finalize(int mode, int nv, const RedBuf &red, int nblocks, GmresState *st, const FinalizeArgs &fa,
+                           hipStream_t s);
 int schwarz_waves(const BoxGeom &G);
 
 // stencil2d.hip
@@ -21,8 +31,8 @@ hipError_t launch_spmv_dots2d(const Phys &P, const double *J, const double *Z, d
 hipError_t launch_ilu_factor2d(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
                                const double *J, double shift, void *fac, int fp32, hipStream_t s);
 hipError_t launch_ras_apply2d(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
-                              const void *fac, void *ybuf, const double *r, double *z, const GmresState *st,
-                              long vstride, int fp32, hipStream_t s);
+                              const void *fac, void *ybuf, const double *r, double *z, double *dump,
+                              const GmresState *st, long vstride, int fp32, hipStream_t s);
 hipError_t launch_export_factors2d(const BoxGeom &G, const int *lvl, const void *fac, int fp32, double *out,
                                    hipStream_t s);
 

@@ -25,19 +25,21 @@ __global__ __launch_bounds__(256) void k_gmres_start(long n2, const double *__re
     V0[e] = r;
     acc[0] = fma(r, r, acc[0]);
   }
-  if (grid_sum<1>(acc, red, threadIdx.x, 256, blockIdx.x, gridDim.x) && threadIdx.x == 0) {
-    const double beta = sqrt(red.out[0]);
-    st->beta = beta;
-    if (!JS) st->tol = fmax(rtol * beta, atol);
-    const double tol = st->tol;
-    st->m = m;
-    st->j = 0;
-    st->g[0] = beta;
-    st->resid = beta;
-    st->inv_norm[0] = beta > 0.0 ? 1.0 / beta : 0.0;
-    st->converged = (beta <= tol) ? 1 : 0;
-    st->done = st->converged;
-  }
+  block_partial<1>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x);
+}
+
+ACCH_DEV void start_tail(GmresState *st, double sum, int first, int m, double rtol, double atol) {
+  const double beta = sqrt(sum);
+  st->beta = beta;
+  if (first) st->tol = fmax(rtol * beta, atol);
+  const double tol = st->tol;
+  st->m = m;
+  st->j = 0;
+  st->g[0] = beta;
+  st->resid = beta;
+  st->inv_norm[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+  st->converged = (beta <= tol) ? 1 : 0;
+  st->done = st->converged;
 }
 
 // W_{j+1} -= sum_{i<=j} h_ij v_i (classical Gram–Schmidt, one pass), then the norm,
@@ -57,9 +59,14 @@ __global__ __launch_bounds__(256) void k_gmres_orth(long n2, double *__restrict_
     w[e] = x;
     acc[0] = fma(x, x, acc[0]);
   }
-  if (!grid_sum<1>(acc, red, threadIdx.x, 256, blockIdx.x, gridDim.x)) return;
-  if (threadIdx.x != 0) return;
-  const double hn = sqrt(red.out[0]);
+  block_partial<1>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x);
+}
+
+// The serial part of an Arnoldi step (one thread): Hessenberg column, Givens
+// rotations, residual estimate, stopping test and, at the end of a cycle, y.
+ACCH_DEV void orth_tail(GmresState *st, double sum) {
+  const int j = st->j;
+  const double hn = sqrt(sum);
   const int M1 = kMaxRestart + 1;
   // new Hessenberg column: the dots, then ||w||; apply the previous rotations
   double *h = st->H + j * M1;
@@ -123,8 +130,7 @@ __global__ __launch_bounds__(256) void k_gmres_update(long ncell, double *__rest
     S[e] = x;
     if (e < ncell) acc[0] += x;
   }
-  if (grid_sum<1>(acc, red, threadIdx.x, 256, blockIdx.x, gridDim.x) && threadIdx.x == 0)
-    st->shift = project ? red.out[0] / (double)ncell : 0.0;
+  block_partial<1>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x);
 }
 
 // ||a - b||^2 (b may be null), for the dt controller and diagnostics.
@@ -135,7 +141,42 @@ __global__ __launch_bounds__(256) void k_norm2_diff(long n2, const double *__res
     const double d = b ? a[e] - b[e] : a[e];
     acc[0] = fma(d, d, acc[0]);
   }
-  grid_sum<1>(acc, red, threadIdx.x, 256, blockIdx.x, gridDim.x);
+  block_partial<1>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x);
+}
+
+// One-block second stage of every reduction (see block_partial / final_sum).
+template <int NV>
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int nblocks, int nv,
+                                                   double *__restrict__ out, GmresState *st, int mode,
+                                                   FinalizeArgs fa) {
+  if (mode == kFinDots || mode == kFinOrth) {
+    if (st->done) return;   // the partial kernel skipped as well
+  } else if (mode == kFinUpdate) {
+    if (!st->done) return;
+  }
+  if (mode == kFinDots) nv = st->j + 1;
+  double acc[NV];
+  final_sum<NV>(partials, nblocks, threadIdx.x, 256, acc, nv);
+  if (threadIdx.x != 0) return;
+  switch (mode) {
+    case kFinPlain:
+      for (int k = 0; k < NV; ++k)
+        if (k < nv) out[k] = acc[k];
+      break;
+    case kFinStart:
+      start_tail(st, acc[0], fa.first, fa.m, fa.rtol, fa.atol);
+      break;
+    case kFinDots:
+      for (int k = 0; k < NV; ++k)
+        if (k < nv) st->hcol[k] = acc[k] * st->inv_norm[k];
+      break;
+    case kFinOrth:
+      orth_tail(st, acc[0]);
+      break;
+    case kFinUpdate:
+      st->shift = fa.project ? acc[0] / (double)fa.ncell : 0.0;
+      break;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_reset_state(GmresState *st) {
@@ -150,28 +191,56 @@ __global__ __launch_bounds__(256) void k_reset_state(GmresState *st) {
 
 }  // namespace
 
-hipError_t launch_gmres_start(long n2, const double *F, const double *JS, double *V0, GmresState *st, int m,
-                              double rtol, double atol, const RedBuf &red, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_start, dim3(reduce_blocks(n2)), dim3(256), 0, s, n2, F, JS, V0, st, m, rtol, atol,
-                     red);
+hipError_t launch_finalize(int mode, int nv, const RedBuf &red, int nblocks, GmresState *st, const FinalizeArgs &fa,
+                           hipStream_t s) {
+  if (nv > 2)
+    hipLaunchKernelGGL(k_finalize<kMaxRestart + 1>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st,
+                       mode, fa);
+  else
+    hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, mode, fa);
   return hipGetLastError();
 }
 
+hipError_t launch_gmres_start(long n2, const double *F, const double *JS, double *V0, GmresState *st, int m,
+                              double rtol, double atol, const RedBuf &red, hipStream_t s) {
+  const int nb = reduce_blocks(n2);
+  hipLaunchKernelGGL(k_gmres_start, dim3(nb), dim3(256), 0, s, n2, F, JS, V0, st, m, rtol, atol, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  FinalizeArgs fa{};
+  fa.first = JS ? 0 : 1;
+  fa.m = m;
+  fa.rtol = rtol;
+  fa.atol = atol;
+  return launch_finalize(kFinStart, 1, red, nb, st, fa, s);
+}
+
 hipError_t launch_gmres_orth(long n2, double *V, long vstride, GmresState *st, const RedBuf &red, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_orth, dim3(reduce_blocks(n2)), dim3(256), 0, s, n2, V, vstride, st, red);
-  return hipGetLastError();
+  const int nb = reduce_blocks(n2);
+  hipLaunchKernelGGL(k_gmres_orth, dim3(nb), dim3(256), 0, s, n2, V, vstride, st, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(kFinOrth, 1, red, nb, st, FinalizeArgs{}, s);
 }
 
 hipError_t launch_gmres_update(long ncell, double *S, const double *Z, long vstride, GmresState *st, int accumulate,
                                int project, const RedBuf &red, hipStream_t s) {
-  hipLaunchKernelGGL(k_gmres_update, dim3(reduce_blocks(2 * ncell)), dim3(256), 0, s, ncell, S, Z, vstride, st,
-                     accumulate, project, red);
-  return hipGetLastError();
+  const int nb = reduce_blocks(2 * ncell);
+  hipLaunchKernelGGL(k_gmres_update, dim3(nb), dim3(256), 0, s, ncell, S, Z, vstride, st, accumulate, project, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  FinalizeArgs fa{};
+  fa.project = project;
+  fa.ncell = ncell;
+  return launch_finalize(kFinUpdate, 1, red, nb, st, fa, s);
 }
 
 hipError_t launch_norm2_diff(long n2, const double *a, const double *b, const RedBuf &red, hipStream_t s) {
-  hipLaunchKernelGGL(k_norm2_diff, dim3(reduce_blocks(n2)), dim3(256), 0, s, n2, a, b, red);
-  return hipGetLastError();
+  const int nb = reduce_blocks(n2);
+  hipLaunchKernelGGL(k_norm2_diff, dim3(nb), dim3(256), 0, s, n2, a, b, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(kFinPlain, 1, red, nb, nullptr, FinalizeArgs{}, s);
 }
 
 hipError_t launch_reset_state(GmresState *st, hipStream_t s) {

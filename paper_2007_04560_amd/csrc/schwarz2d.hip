@@ -154,7 +154,8 @@ __global__ __launch_bounds__(64 * NW) void k_ilu_factor2d(BoxGeom G, const SubIn
   const int t = threadIdx.x;
   const SubInfo si = subs[blockIdx.x];
   const long n = (long)nx * ny;
-  FT *Fk = fac + (long)blockIdx.x * kNSlot2D * G.ncb;
+  const long ncb = (long)G.nlev * G.bh;
+  FT *Fk = fac + (long)blockIdx.x * kNSlot2D * ncb;
   for (int w = 0; w < G.nlev; ++w) {
     const int j = row_on_level<T>(w, t, G.bw, G.bh);
     if (j >= 0) {
@@ -235,13 +236,14 @@ __global__ __launch_bounds__(64 * NW) void k_ilu_factor2d(BoxGeom G, const SubIn
       for (int e = 0; e < 10; ++e) dst[e] = a[8 + e];
 #pragma unroll
       for (int e = 0; e < 3; ++e) dst[10 + e] = b[3 + e];
-      // store the factors in the solve's slot order
-      const long idx = lvl[w] + (j - level_lo(w, G.bw));
+      // store the factors in the solve's slot order, wavefront-major (padded to bh rows)
+      const long idx = (long)w * G.bh + j;
       const double s[kNSlot2D] = {a[6],  a[5],       a[4],  a[2],  a[1],  a[0],  a[7],  a[3],
                                   b[1],  b[0],       b[2],  1.0 / a[8], a[10], a[12], a[13], a[14],
                                   a[16], a[17],      a[9],  a[11], a[15], 1.0 / b[3], b[4], b[5]};
+      constexpr int per = 16 / (int)sizeof(FT);   // chunked layout of the solve kernel
 #pragma unroll
-      for (int k = 0; k < kNSlot2D; ++k) Fk[(long)k * G.ncb + idx] = (FT)s[k];
+      for (int k = 0; k < kNSlot2D; ++k) Fk[((long)(k / per) * ncb + idx) * per + (k % per)] = (FT)s[k];
     }
     __syncthreads();
   }
@@ -250,18 +252,73 @@ __global__ __launch_bounds__(64 * NW) void k_ilu_factor2d(BoxGeom G, const SubIn
 // ---------------------------------------------------------------------------
 // z = M^{-1} r, left-restricted Schwarz (restricted extension) with ILU(0) solves.
 // ---------------------------------------------------------------------------
-// Values of thread t-1 (L sweep) or t+1 (U sweep) handed over between waves.
-template <typename FT, int NW>
-ACCH_DEV void neighbour_fetch(int dir, int w, int lane, int wave, FT o1u, FT o1v, FT a3u, FT a3v, FT &Au,
-                              FT &Av, FT &Mu, FT &Mv, FT (*xch)[NW][4]) {
-  const int src = (lane + (dir < 0 ? 63 : 1)) & 63;
-  Au = __shfl(o1u, src, 64);
-  Av = __shfl(o1v, src, 64);
-  Mu = __shfl(a3u, src, 64);
-  Mv = __shfl(a3v, src, 64);
+// Factor storage: per subdomain, the 24 slots of a cell are packed into 16-byte
+// chunks (2 FP64 or 4 FP32 values), chunk-major over the wavefront-ordered cells, so
+// each wavefront's chunk loads coalesce and a sweep needs 6-7 wide loads per cell.
+template <typename FT>
+struct ChunkOf;
+template <>
+struct ChunkOf<double> {
+  using T = double2;
+  using Pair = double2;
+  static constexpr int per = 2;
+};
+template <>
+struct ChunkOf<float> {
+  using T = float4;
+  using Pair = float2;
+  static constexpr int per = 4;
+};
+
+template <int K>
+ACCH_DEV double comp(const double2 &c) {
+  if constexpr (K == 0) return c.x;
+  else return c.y;
+}
+template <int K>
+ACCH_DEV float comp(const float4 &c) {
+  if constexpr (K == 0) return c.x;
+  else if constexpr (K == 1) return c.y;
+  else if constexpr (K == 2) return c.z;
+  else return c.w;
+}
+
+// Slot S of a cell from its loaded chunks c[0..), the first of which is chunk BASE.
+template <int S, int BASE, typename FT, typename T, int N>
+ACCH_DEV FT slot(const T (&c)[N]) {
+  constexpr int per = ChunkOf<FT>::per;
+  static_assert(S / per - BASE >= 0 && S / per - BASE < N, "slot outside the loaded chunks");
+  return comp<S % per>(c[S / per - BASE]);
+}
+
+// Lane rotation inside a wave64: value of lane (t-1) mod 64 (L sweep) or (t+1) mod 64.
+template <int DIR>
+ACCH_DEV int rot_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, DIR < 0 ? 0x13C : 0x134, 0xF, 0xF, false);  // wave_ror:1 / wave_rol:1
+}
+template <int DIR>
+ACCH_DEV double rot(double x) {
+  const int lo = rot_i<DIR>(__double2loint(x));
+  const int hi = rot_i<DIR>(__double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+template <int DIR>
+ACCH_DEV float rot(float x) {
+  return __int_as_float(rot_i<DIR>(__float_as_int(x)));
+}
+
+// Values of thread t-1 (DIR < 0) or t+1 (DIR > 0): within the wave by lane rotation,
+// across waves through LDS (one barrier per wavefront).
+template <int DIR, typename FT, int NW>
+ACCH_DEV void neighbour_fetch(int w, int lane, int wave, FT o1u, FT o1v, FT a3u, FT a3v, FT &Au, FT &Av, FT &Mu,
+                              FT &Mv, FT (*xch)[NW][4]) {
+  Au = rot<DIR>(o1u);
+  Av = rot<DIR>(o1v);
+  Mu = rot<DIR>(a3u);
+  Mv = rot<DIR>(a3v);
   if constexpr (NW > 1) {
     const int buf = w & 1;
-    const int pub = dir < 0 ? 63 : 0;    // the lane whose values cross to the next wave
+    const int pub = DIR < 0 ? 63 : 0;    // the lane whose values cross to the next wave
     if (lane == pub) {
       xch[buf][wave][0] = o1u;
       xch[buf][wave][1] = o1v;
@@ -269,9 +326,9 @@ ACCH_DEV void neighbour_fetch(int dir, int w, int lane, int wave, FT o1u, FT o1v
       xch[buf][wave][3] = a3v;
     }
     __syncthreads();
-    const int take = dir < 0 ? 0 : 63;
+    const int take = DIR < 0 ? 0 : 63;
     if (lane == take) {
-      const int pw = dir < 0 ? (wave + NW - 1) % NW : (wave + 1) % NW;
+      const int pw = DIR < 0 ? (wave + NW - 1) % NW : (wave + 1) % NW;
       Au = xch[buf][pw][0];
       Av = xch[buf][pw][1];
       Mu = xch[buf][pw][2];
@@ -280,13 +337,25 @@ ACCH_DEV void neighbour_fetch(int dir, int w, int lane, int wave, FT o1u, FT o1v
   }
 }
 
-template <typename FT, int NW>
+// Per-thread data of one wavefront, loaded D wavefronts ahead of its use.  The loop
+// bodies are branch-free (inactive lanes load from a valid cell and store to a dump
+// slot), so the compiler can count the loads in flight exactly.
+template <typename FT, int NCH>
+struct Stage {
+  typename ChunkOf<FT>::T c[NCH];
+  FT a, b;      // L sweep: r_u, r_v;  U sweep: y_u, y_v
+  int idx;      // wavefront-ordered cell index (dump slot ncb if the lane has no cell)
+  bool act;     // the lane has a cell on this wavefront
+  long g;       // U sweep: global cell to write, or -1 (not owned / not a real cell)
+};
+
+template <typename FT, int NW, int D>
 __global__ __launch_bounds__(64 * NW) void k_ras_apply2d(BoxGeom G, const SubInfo *__restrict__ subs,
                                                          const int *__restrict__ lvl, int nx, int ny,
-                                                         int periodic, const FT *__restrict__ fac,
-                                                         FT *__restrict__ ybuf, const double *__restrict__ r,
-                                                         double *__restrict__ z, const GmresState *st,
-                                                         long vstride) {
+                                                         int periodic, const void *__restrict__ fac_,
+                                                         void *__restrict__ ybuf_, const double *__restrict__ r,
+                                                         double *__restrict__ z, double *__restrict__ dump,
+                                                         const GmresState *st, long vstride) {
   // Inside GMRES the input is the current basis vector v_j = inv_norm[j] W_j and the
   // output is z_j; the whole kernel is skipped once the cycle has finished.
   double sc = 1.0;
@@ -297,86 +366,131 @@ __global__ __launch_bounds__(64 * NW) void k_ras_apply2d(BoxGeom G, const SubInf
     z += (long)jj * vstride;
     sc = st->inv_norm[jj];
   }
-  constexpr int T = 64 * NW;
+  using C = ChunkOf<FT>;
+  using T = typename C::T;
+  using P2 = typename C::Pair;
+  constexpr int per = C::per;
+  constexpr int NCH = kNSlot2D / per;          // chunks per cell
+  constexpr int NLC = (11 + per - 1) / per;    // chunks holding slots 0..10
+  constexpr int U0C = 11 / per;                // first chunk of slots 11..23
+  constexpr int NUC = NCH - U0C;
+  constexpr int TT = 64 * NW;
   __shared__ FT xch[2][NW][4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const SubInfo si = subs[blockIdx.x];
   const long n = (long)nx * ny;
-  const FT *Fk = fac + (long)blockIdx.x * kNSlot2D * G.ncb;
-  FT *yk = ybuf + (long)blockIdx.x * 2 * G.ncb;
+  const int ncb = G.nlev * G.bh;   // padded wavefront-major cell slots
+  const T *Fk = (const T *)fac_ + (long)blockIdx.x * NCH * ncb;
+  P2 *yk = (P2 *)ybuf_ + (long)blockIdx.x * (ncb + 1);   // entry ncb is this box's dump slot
   const FT zero = (FT)0;
+  const int nlev = G.nlev;
+  const int nround = (nlev + D - 1) / D * D;
+
   // ---- forward sweep: L y = R_k r -------------------------------------------
+  auto prefetch_L = [&](Stage<FT, NLC> &s, int w) {
+    const int wc = w < nlev ? w : nlev - 1;
+    const int j = row_on_level<TT>(wc, t, G.bw, G.bh);
+    s.act = (w < nlev) && (j >= 0);
+    const int jj = s.act ? j : 0;
+    const int i = wc - 2 * jj;
+    s.idx = s.act ? wc * G.bh + jj : ncb;
+    const int li = s.act ? s.idx : 0;
+#pragma unroll
+    for (int q = 0; q < NLC; ++q) s.c[q] = Fk[(long)q * ncb + li];
+    const long g = s.act ? box_to_global(si, i, jj, nx, ny, periodic) : -1;
+    const long gs = g >= 0 ? g : 0;
+    const double ra = r[gs], rb = r[n + gs];
+    s.a = g >= 0 ? (FT)(sc * ra) : zero;
+    s.b = g >= 0 ? (FT)(sc * rb) : zero;
+  };
+  Stage<FT, NLC> ring[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) prefetch_L(ring[k], k);
   FT o1u = zero, o1v = zero, o2u = zero, o2v = zero;
   FT a1u = zero, a1v = zero, a2u = zero, a2v = zero, a3u = zero, a3v = zero;
-  for (int w = 0; w < G.nlev; ++w) {
-    const int j = row_on_level<T>(w, t, G.bw, G.bh);
-    FT Au, Av, Mu, Mv;
-    neighbour_fetch<FT, NW>(-1, w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
-    FT yu = zero, yv = zero;
-    if (j >= 0) {
-      const int i = w - 2 * j;
-      const long idx = lvl[w] + (j - level_lo(w, G.bw));
-      const long g = box_to_global(si, i, j, nx, ny, periodic);
-      const FT ru = g >= 0 ? (FT)(sc * r[g]) : zero;
-      const FT rv = g >= 0 ? (FT)(sc * r[n + g]) : zero;
-      const FT *L = Fk + idx;
-      const long s = G.ncb;
-      FT acc = L[0] * o1u;
-      acc = fma(L[1 * s], o2u, acc);
-      acc = fma(L[2 * s], Au, acc);
-      acc = fma(L[3 * s], a1u, acc);
-      acc = fma(L[4 * s], a2u, acc);
-      acc = fma(L[5 * s], Mu, acc);
-      acc = fma(L[6 * s], o1v, acc);
-      acc = fma(L[7 * s], a1v, acc);
-      yu = ru - acc;
-      FT accv = L[8 * s] * o1v;
-      accv = fma(L[9 * s], a1v, accv);
-      accv = fma(L[10 * s], yu, accv);
-      yv = rv - accv;
-      yk[idx] = yu;
-      yk[s + idx] = yv;
+  for (int w0 = 0; w0 < nround; w0 += D) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int w = w0 + k;
+      FT Au, Av, Mu, Mv;
+      neighbour_fetch<-1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
+      Stage<FT, NLC> &s = ring[k];
+      FT acc = slot<0, 0, FT>(s.c) * o1u;
+      acc = fma(slot<1, 0, FT>(s.c), o2u, acc);
+      acc = fma(slot<3, 0, FT>(s.c), a1u, acc);
+      acc = fma(slot<4, 0, FT>(s.c), a2u, acc);
+      acc = fma(slot<6, 0, FT>(s.c), o1v, acc);
+      acc = fma(slot<7, 0, FT>(s.c), a1v, acc);
+      acc = fma(slot<2, 0, FT>(s.c), Au, acc);
+      acc = fma(slot<5, 0, FT>(s.c), Mu, acc);
+      FT yu = s.a - acc;
+      FT accv = slot<8, 0, FT>(s.c) * o1v;
+      accv = fma(slot<9, 0, FT>(s.c), a1v, accv);
+      accv = fma(slot<10, 0, FT>(s.c), yu, accv);
+      FT yv = s.b - accv;
+      yu = s.act ? yu : zero;
+      yv = s.act ? yv : zero;
+      P2 y2;
+      y2.x = yu;
+      y2.y = yv;
+      yk[s.idx] = y2;
+      a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
+      o2u = o1u; o2v = o1v; o1u = yu; o1v = yv;
+      prefetch_L(s, w + D);
     }
-    a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
-    o2u = o1u; o2v = o1v; o1u = yu; o1v = yv;
   }
   // ---- backward sweep: U x = y, write the owned part ------------------------
+  auto prefetch_U = [&](Stage<FT, NUC> &s, int w) {
+    const int wc = w >= 0 ? w : 0;
+    const int j = row_on_level<TT>(wc, t, G.bw, G.bh);
+    s.act = (w >= 0) && (j >= 0);
+    const int jj = s.act ? j : 0;
+    const int i = wc - 2 * jj;
+    s.idx = s.act ? wc * G.bh + jj : ncb;
+    const int li = s.act ? s.idx : 0;
+#pragma unroll
+    for (int q = 0; q < NUC; ++q) s.c[q] = Fk[(long)(U0C + q) * ncb + li];
+    const P2 y2 = yk[s.idx];
+    s.a = y2.x;
+    s.b = y2.y;
+    const bool own = s.act && i >= si.own_x0 && i < si.own_x1 && jj >= si.own_y0 && jj < si.own_y1;
+    s.g = own ? box_to_global(si, i, jj, nx, ny, periodic) : -1;
+  };
+  Stage<FT, NUC> ringu[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) prefetch_U(ringu[k], nlev - 1 - k);
   o1u = o1v = o2u = o2v = zero;
   a1u = a1v = a2u = a2v = a3u = a3v = zero;
-  for (int w = G.nlev - 1; w >= 0; --w) {
-    const int j = row_on_level<T>(w, t, G.bw, G.bh);
-    FT Au, Av, Mu, Mv;
-    neighbour_fetch<FT, NW>(1, w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
-    FT xu = zero, xv = zero;
-    if (j >= 0) {
-      const int i = w - 2 * j;
-      const long idx = lvl[w] + (j - level_lo(w, G.bw));
-      const long s = G.ncb;
-      const FT *U = Fk + idx;
-      const FT yu = yk[idx], yv = yk[s + idx];
-      FT accv = U[22 * s] * o1v;
-      accv = fma(U[23 * s], a1v, accv);
-      xv = (yv - accv) * U[21 * s];
-      FT acc = U[12 * s] * o1u;
-      acc = fma(U[13 * s], o2u, acc);
-      acc = fma(U[14 * s], Au, acc);
-      acc = fma(U[15 * s], a1u, acc);
-      acc = fma(U[16 * s], a2u, acc);
-      acc = fma(U[17 * s], Mu, acc);
-      acc = fma(U[18 * s], xv, acc);
-      acc = fma(U[19 * s], o1v, acc);
-      acc = fma(U[20 * s], a1v, acc);
-      xu = (yu - acc) * U[11 * s];
-      if (i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1) {
-        const long g = box_to_global(si, i, j, nx, ny, periodic);
-        if (g >= 0) {
-          z[g] = (double)xu;
-          z[n + g] = (double)xv;
-        }
-      }
+  for (int w0 = nlev - 1; w0 > nlev - 1 - nround; w0 -= D) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int w = w0 - k;
+      FT Au, Av, Mu, Mv;
+      neighbour_fetch<1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
+      Stage<FT, NUC> &s = ringu[k];
+      FT accv = slot<22, U0C, FT>(s.c) * o1v;
+      accv = fma(slot<23, U0C, FT>(s.c), a1v, accv);
+      FT xv = (s.b - accv) * slot<21, U0C, FT>(s.c);
+      FT acc = slot<12, U0C, FT>(s.c) * o1u;
+      acc = fma(slot<13, U0C, FT>(s.c), o2u, acc);
+      acc = fma(slot<15, U0C, FT>(s.c), a1u, acc);
+      acc = fma(slot<16, U0C, FT>(s.c), a2u, acc);
+      acc = fma(slot<19, U0C, FT>(s.c), o1v, acc);
+      acc = fma(slot<20, U0C, FT>(s.c), a1v, acc);
+      acc = fma(slot<14, U0C, FT>(s.c), Au, acc);
+      acc = fma(slot<17, U0C, FT>(s.c), Mu, acc);
+      acc = fma(slot<18, U0C, FT>(s.c), xv, acc);
+      FT xu = (s.a - acc) * slot<11, U0C, FT>(s.c);
+      xu = s.act ? xu : zero;
+      xv = s.act ? xv : zero;
+      double *pu = s.g >= 0 ? z + s.g : dump;
+      double *pv = s.g >= 0 ? z + n + s.g : dump + 1;
+      *pu = (double)xu;
+      *pv = (double)xv;
+      a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
+      o2u = o1u; o2v = o1v; o1u = xu; o1v = xv;
+      prefetch_U(s, w - D);
     }
-    a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
-    o2u = o1u; o2v = o1v; o1u = xu; o1v = xv;
   }
 }
 
@@ -390,8 +504,12 @@ __global__ void k_export_factors2d(BoxGeom G, const int *__restrict__ lvl, const
     const long ss = e / G.ncb;  // sub * 24 + slot
     const int j = (int)(cell / G.bw), i = (int)(cell - (long)j * G.bw);
     const int w = i + 2 * j;
-    const long idx = lvl[w] + (j - level_lo(w, G.bw));
-    out[e] = (double)fac[ss * G.ncb + idx];
+    const long ncbp = (long)G.nlev * G.bh;
+    const long idx = (long)w * G.bh + j;
+    constexpr int per = 16 / (int)sizeof(FT);
+    const long sub = ss / kNSlot2D;
+    const int k = (int)(ss - sub * kNSlot2D);
+    out[e] = (double)fac[sub * kNSlot2D * ncbp + ((long)(k / per) * ncbp + idx) * per + (k % per)];
   }
 }
 
@@ -409,12 +527,14 @@ hipError_t factor_impl(const BoxGeom &G, const SubInfo *subs, const int *lvl, in
   return hipGetLastError();
 }
 
+constexpr int kPrefetch = 8;   // wavefronts loaded ahead of their use in the solves
+
 template <typename FT, int NW>
 hipError_t apply_impl(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
-                      const void *fac, void *ybuf, const double *r, double *z, const GmresState *st, long vstride,
-                      hipStream_t s) {
-  hipLaunchKernelGGL((k_ras_apply2d<FT, NW>), dim3(G.nsub), dim3(64 * NW), 0, s, G, subs, lvl, nx, ny, periodic,
-                     (const FT *)fac, (FT *)ybuf, r, z, st, vstride);
+                      const void *fac, void *ybuf, const double *r, double *z, double *dump, const GmresState *st,
+                      long vstride, hipStream_t s) {
+  hipLaunchKernelGGL((k_ras_apply2d<FT, NW, kPrefetch>), dim3(G.nsub), dim3(64 * NW), 0, s, G, subs, lvl, nx, ny,
+                     periodic, fac, ybuf, r, z, dump, st, vstride);
   return hipGetLastError();
 }
 
@@ -444,17 +564,17 @@ hipError_t launch_ilu_factor2d(const BoxGeom &G, const SubInfo *subs, const int 
 }
 
 hipError_t launch_ras_apply2d(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
-                              const void *fac, void *ybuf, const double *r, double *z, const GmresState *st,
-                              long vstride, int fp32, hipStream_t s) {
+                              const void *fac, void *ybuf, const double *r, double *z, double *dump,
+                              const GmresState *st, long vstride, int fp32, hipStream_t s) {
   const int nw = schwarz_waves(G);
   if (fp32) {
-    if (nw == 1) return apply_impl<float, 1>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, st, vstride, s);
-    if (nw == 2) return apply_impl<float, 2>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, st, vstride, s);
-    if (nw == 4) return apply_impl<float, 4>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, st, vstride, s);
+    if (nw == 1) return apply_impl<float, 1>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 2) return apply_impl<float, 2>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 4) return apply_impl<float, 4>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
   } else {
-    if (nw == 1) return apply_impl<double, 1>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, st, vstride, s);
-    if (nw == 2) return apply_impl<double, 2>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, st, vstride, s);
-    if (nw == 4) return apply_impl<double, 4>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, st, vstride, s);
+    if (nw == 1) return apply_impl<double, 1>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 2) return apply_impl<double, 2>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 4) return apply_impl<double, 4>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
   }
   return hipErrorInvalidValue;
 }

@@ -53,7 +53,7 @@ void split(int n, int parts, std::vector<int> &start, std::vector<int> &len) {
 
 struct Layout {
   size_t off_Xn, off_Xprev, off_X, off_Xt, off_F, off_Ft, off_S, off_W;
-  size_t off_J, off_V, off_Z, off_fac, off_y, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
+  size_t off_J, off_V, off_Z, off_fac, off_y, off_dump, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
   size_t total;
 };
 
@@ -88,6 +88,7 @@ struct acch_ctx {
   char *ws = nullptr;
   double *Xn, *Xprev, *X, *Xt, *F, *Ft, *S, *W, *J, *V, *Z;
   void *fac, *ybuf;
+  double *dump;
   SubInfo *d_subs;
   int *d_lvl;
   GmresState *st;
@@ -216,8 +217,10 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_J = take((size_t)kNSlot2D * geo.ncell * sizeof(double));
   L.off_V = take((size_t)(m + 1) * n2);
   L.off_Z = take((size_t)m * n2);
-  L.off_fac = take((size_t)geo.G.nsub * kNSlot2D * geo.G.ncb * fsz);
-  L.off_y = take((size_t)geo.G.nsub * 2 * geo.G.ncb * fsz);
+  const size_t slots = (size_t)geo.G.nlev * geo.G.bh;   // padded wavefront-major cells per box
+  L.off_fac = take((size_t)geo.G.nsub * kNSlot2D * slots * fsz);
+  L.off_y = take((size_t)geo.G.nsub * 2 * (slots + 1) * fsz);   // + one dump slot per box
+  L.off_dump = take(64 * sizeof(double));
   L.off_subs = take(geo.subs.size() * sizeof(SubInfo));
   L.off_lvl = take(geo.lvl.size() * sizeof(int));
   L.off_state = take(sizeof(GmresState));
@@ -344,7 +347,7 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid) {
     while (true) {
       for (int k = 0; k < chunk && launched < m; ++k, ++launched) {
         LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->fac, c->ybuf,
-                                     c->V, c->Z, c->st, vs, fp32, c->stream));
+                                     c->V, c->Z, c->dump, c->st, vs, fp32, c->stream));
         LAUNCHK(c, ACCH_KERNEL_SPMV_DOTS, launch_spmv_dots2d(c->P, c->J, c->Z, c->V, vs, c->st, c->red, c->stream));
         LAUNCHK(c, ACCH_KERNEL_ORTH, launch_gmres_orth(n2, c->V, vs, c->st, c->red, c->stream));
       }
@@ -529,6 +532,7 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->Z = (double *)(c->ws + L.off_Z);
   c->fac = c->ws + L.off_fac;
   c->ybuf = c->ws + L.off_y;
+  c->dump = (double *)(c->ws + L.off_dump);
   c->d_subs = (SubInfo *)(c->ws + L.off_subs);
   c->d_lvl = (int *)(c->ws + L.off_lvl);
   c->st = (GmresState *)(c->ws + L.off_state);
@@ -781,7 +785,7 @@ extern "C" int acch_precondition(acch_ctx *c, const double *r, double *z) {
   if (!c || !r || !z) return fail(ACCH_EINVAL, "bad arguments");
   if (!c->factored) return fail(ACCH_EINVAL, "no factorisation: call acch_factor first");
   LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->fac, c->ybuf, r, z,
-                               nullptr, 0, c->p.precision == ACCH_PREC_MIXED, c->stream));
+                               c->dump, nullptr, 0, c->p.precision == ACCH_PREC_MIXED, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;
 }

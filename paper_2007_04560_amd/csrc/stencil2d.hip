@@ -111,7 +111,7 @@ __global__ __launch_bounds__(TX *TY) void k_residual2d(Phys P, const double *__r
     const double p = u1 + v1, q = u1 - v1;
     acc[1] = (p > 0.0 && p < 1.0 && q > 0.0 && q < 1.0) ? 0.0 : 1.0;
   }
-  grid_sum<2>(acc, red, tid, TX * TY, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  block_partial<2>(acc, red.partials, tid, TX * TY, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_energy2d(Phys P, const double *__restri
     acc[0] += e;
     acc[1] += u;
   }
-  grid_sum<2>(acc, red, threadIdx.x, 256, blockIdx.x, gridDim.x);
+  block_partial<2>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -315,8 +315,7 @@ __global__ __launch_bounds__(256) void k_spmv_dots2d(Phys P, const double *__res
     for (int i = 0; i <= kMaxRestart; ++i)
       if (i <= j) acc[i] = fma(yu, V[(long)i * vstride + g], fma(yv, V[(long)i * vstride + n + g], acc[i]));
   }
-  const bool last = grid_sum<kMaxRestart + 1>(acc, red, threadIdx.x, 256, blockIdx.x, gridDim.x, j + 1);
-  if (last && threadIdx.x <= j) st->hcol[threadIdx.x] = red.out[threadIdx.x] * st->inv_norm[threadIdx.x];
+  block_partial<kMaxRestart + 1>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x, j + 1);
 }
 
 }  // namespace
@@ -336,14 +335,19 @@ int reduce_blocks(long n) {
 hipError_t launch_residual2d(const Phys &P, const double *X, const double *Sdir, double lam, const double *shift,
                              const double *Xn, double dt, double *Xt, double *F, const RedBuf &red,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_residual2d, tile_grid(P), dim3(TX, TY), 0, s, P, X, Sdir, lam, shift, Xn, 1.0 / dt, Xt, F,
-                     red);
-  return hipGetLastError();
+  const dim3 grid = tile_grid(P);
+  hipLaunchKernelGGL(k_residual2d, grid, dim3(TX, TY), 0, s, P, X, Sdir, lam, shift, Xn, 1.0 / dt, Xt, F, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(kFinPlain, 2, red, (int)(grid.x * grid.y), nullptr, FinalizeArgs{}, s);
 }
 
 hipError_t launch_energy2d(const Phys &P, const double *X, const RedBuf &red, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy2d, dim3(reduce_blocks((long)P.nx * P.ny)), dim3(256), 0, s, P, X, red);
-  return hipGetLastError();
+  const int nb = reduce_blocks((long)P.nx * P.ny);
+  hipLaunchKernelGGL(k_energy2d, dim3(nb), dim3(256), 0, s, P, X, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(kFinPlain, 2, red, nb, nullptr, FinalizeArgs{}, s);
 }
 
 hipError_t launch_jacobian2d(const Phys &P, const double *X, const double *Xn, double dt, double *J,
@@ -360,9 +364,11 @@ hipError_t launch_spmv2d(const Phys &P, const double *J, const double *x, double
 
 hipError_t launch_spmv_dots2d(const Phys &P, const double *J, const double *Z, double *V, long vstride,
                               GmresState *st, const RedBuf &red, hipStream_t s) {
-  hipLaunchKernelGGL(k_spmv_dots2d, dim3(reduce_blocks((long)P.nx * P.ny)), dim3(256), 0, s, P, J, Z, V, vstride,
-                     st, red);
-  return hipGetLastError();
+  const int nb = reduce_blocks((long)P.nx * P.ny);
+  hipLaunchKernelGGL(k_spmv_dots2d, dim3(nb), dim3(256), 0, s, P, J, Z, V, vstride, st, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(kFinDots, kMaxRestart + 1, red, nb, st, FinalizeArgs{}, s);
 }
 
 }  // namespace acch

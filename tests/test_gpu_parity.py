@@ -266,7 +266,7 @@ def test_periodic512_sampled_residual_and_root():
     shape = (512, 512)
     u0, v0 = random_ic(shape, 0)
     P = prob("periodic")
-    s = solver(u0, v0, "periodic", sub=(8, 8), overlap=2, dt_fixed=1e-4, newton_rtol=1e-10)
+    s = solver(u0, v0, "periodic", sub=(8, 8), overlap=2, dt_fixed=1e-4, newton_rtol=1e-10, ilu_shift=0.02)
     rng = np.random.default_rng(99)
     u1 = u0 + 0.01 * rng.uniform(-1, 1, shape)
     v1 = v0 + 0.01 * rng.uniform(-1, 1, shape)
