@@ -23,7 +23,7 @@ EXPORTED = [
     "acch_destroy", "acch_get_fields", "acch_set_fields", "acch_get_time", "acch_residual",
     "acch_jacobian", "acch_apply_jacobian", "acch_factor", "acch_precondition", "acch_gmres",
     "acch_solve_step", "acch_export", "acch_info", "acch_strerror", "acch_last_error",
-    "acch_timing", "acch_kernel_stats", "acch_counters",
+    "acch_timing", "acch_kernel_stats", "acch_counters", "acch_set_option",
 ]
 KERNEL_KINDS = ["residual", "jacobian", "factor", "ras", "spmv_dots", "orth", "gmres_start", "gmres_update",
                 "energy", "spmv", "other"]
@@ -103,6 +103,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "acch_timing": (ctypes.c_int, [ctx, ctypes.c_int]),
         "acch_kernel_stats": (ctypes.c_int, [ctx, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_long)]),
         "acch_counters": (ctypes.c_int, [ctx, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]),
+        "acch_set_option": (ctypes.c_int, [ctx, ctypes.c_int, ctypes.c_long]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

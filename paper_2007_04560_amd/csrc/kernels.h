@@ -17,6 +17,8 @@ struct FinalizeArgs {
 hipError_t launch_finalize(int mode, int nv, const RedBuf &red, int nblocks, GmresState *st, const FinalizeArgs &fa,
                            hipStream_t s);
 int schwarz_waves(const BoxGeom &G);
+void set_ras_prefetch(int d);
+int get_ras_prefetch();
 
 // stencil2d.hip
 hipError_t launch_residual2d(const Phys &P, const double *X, const double *Sdir, double lam, const double *shift,

@@ -294,7 +294,8 @@ ACCH_DEV FT slot(const T (&c)[N]) {
 // Lane rotation inside a wave64: value of lane (t-1) mod 64 (L sweep) or (t+1) mod 64.
 template <int DIR>
 ACCH_DEV int rot_i(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, DIR < 0 ? 0x13C : 0x134, 0xF, 0xF, false);  // wave_ror:1 / wave_rol:1
+  // wave_ror:1 / wave_rol:1; every lane has a source, so the old value is never used
+  return __builtin_amdgcn_update_dpp(x, x, DIR < 0 ? 0x13C : 0x134, 0xF, 0xF, false);
 }
 template <int DIR>
 ACCH_DEV double rot(double x) {
@@ -343,10 +344,12 @@ ACCH_DEV void neighbour_fetch(int w, int lane, int wave, FT o1u, FT o1v, FT a3u,
 template <typename FT, int NCH>
 struct Stage {
   typename ChunkOf<FT>::T c[NCH];
-  FT a, b;      // L sweep: r_u, r_v;  U sweep: y_u, y_v
+  FT a, b;      // U sweep: y_u, y_v
+  double ra, rb;  // L sweep: r_u, r_v as loaded (masked and scaled only when used)
+  bool real;    // L sweep: the cell is a real cell of the domain
   int idx;      // wavefront-ordered cell index (dump slot ncb if the lane has no cell)
   bool act;     // the lane has a cell on this wavefront
-  long g;       // U sweep: global cell to write, or -1 (not owned / not a real cell)
+  int g;        // U sweep: global cell to write, or -1 (not owned / not a real cell)
 };
 
 template <typename FT, int NW, int D>
@@ -387,21 +390,36 @@ __global__ __launch_bounds__(64 * NW) void k_ras_apply2d(BoxGeom G, const SubInf
   const int nround = (nlev + D - 1) / D * D;
 
   // ---- forward sweep: L y = R_k r -------------------------------------------
+  // Closed-form cell of this thread on wavefront w (no branches): row j = t + TT q with
+  // q = floor((w - 2t) / (2 TT)), column i = w - 2j; real cell and ownership by compares.
+  const int pnx = periodic ? nx : 0, pny = periodic ? ny : 0;
+  auto cell_of = [&](int w, int &idx, bool &act, int &g, bool &own) {
+    const int wc = w < 0 ? 0 : (w < nlev ? w : nlev - 1);
+    const int d = wc - 2 * t;
+    const int q = d < 0 ? 0 : (d >> (7 + (NW == 2 ? 1 : (NW == 4 ? 2 : 0))));
+    const int j = t + TT * q;
+    const int i = wc - 2 * j;
+    act = (w >= 0) && (w < nlev) && (d >= 0) && (i < G.bw) && (j < G.bh);
+    idx = act ? wc * G.bh + j : ncb;
+    int gx = si.ox + i, gy = si.oy + j;
+    const bool inside = (unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny;
+    gx = gx < 0 ? gx + pnx : (gx >= nx ? gx - pnx : gx);
+    gy = gy < 0 ? gy + pny : (gy >= ny ? gy - pny : gy);
+    const bool real = act && i < si.ex && j < si.ey && (periodic || inside);
+    g = real ? gy * nx + gx : -1;
+    own = real && i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1;
+  };
   auto prefetch_L = [&](Stage<FT, NLC> &s, int w) {
-    const int wc = w < nlev ? w : nlev - 1;
-    const int j = row_on_level<TT>(wc, t, G.bw, G.bh);
-    s.act = (w < nlev) && (j >= 0);
-    const int jj = s.act ? j : 0;
-    const int i = wc - 2 * jj;
-    s.idx = s.act ? wc * G.bh + jj : ncb;
+    int g;
+    bool own;
+    cell_of(w, s.idx, s.act, g, own);
     const int li = s.act ? s.idx : 0;
 #pragma unroll
     for (int q = 0; q < NLC; ++q) s.c[q] = Fk[(long)q * ncb + li];
-    const long g = s.act ? box_to_global(si, i, jj, nx, ny, periodic) : -1;
-    const long gs = g >= 0 ? g : 0;
-    const double ra = r[gs], rb = r[n + gs];
-    s.a = g >= 0 ? (FT)(sc * ra) : zero;
-    s.b = g >= 0 ? (FT)(sc * rb) : zero;
+    const int gs = g >= 0 ? g : 0;
+    s.ra = r[gs];
+    s.rb = r[n + gs];
+    s.real = g >= 0;
   };
   Stage<FT, NLC> ring[D];
 #pragma unroll
@@ -415,19 +433,22 @@ __global__ __launch_bounds__(64 * NW) void k_ras_apply2d(BoxGeom G, const SubInf
       FT Au, Av, Mu, Mv;
       neighbour_fetch<-1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
       Stage<FT, NLC> &s = ring[k];
-      FT acc = slot<0, 0, FT>(s.c) * o1u;
-      acc = fma(slot<1, 0, FT>(s.c), o2u, acc);
+      // values of earlier wavefronts first; o1 (own, w-1) and A (neighbour, w-1) last
+      FT acc = slot<1, 0, FT>(s.c) * o2u;
       acc = fma(slot<3, 0, FT>(s.c), a1u, acc);
       acc = fma(slot<4, 0, FT>(s.c), a2u, acc);
-      acc = fma(slot<6, 0, FT>(s.c), o1v, acc);
       acc = fma(slot<7, 0, FT>(s.c), a1v, acc);
-      acc = fma(slot<2, 0, FT>(s.c), Au, acc);
       acc = fma(slot<5, 0, FT>(s.c), Mu, acc);
-      FT yu = s.a - acc;
-      FT accv = slot<8, 0, FT>(s.c) * o1v;
-      accv = fma(slot<9, 0, FT>(s.c), a1v, accv);
+      acc = fma(slot<0, 0, FT>(s.c), o1u, acc);
+      acc = fma(slot<6, 0, FT>(s.c), o1v, acc);
+      acc = fma(slot<2, 0, FT>(s.c), Au, acc);
+      const FT ru = s.real ? (FT)(sc * s.ra) : zero;
+      const FT rv = s.real ? (FT)(sc * s.rb) : zero;
+      FT yu = ru - acc;
+      FT accv = slot<9, 0, FT>(s.c) * a1v;
+      accv = fma(slot<8, 0, FT>(s.c), o1v, accv);
       accv = fma(slot<10, 0, FT>(s.c), yu, accv);
-      FT yv = s.b - accv;
+      FT yv = rv - accv;
       yu = s.act ? yu : zero;
       yv = s.act ? yv : zero;
       P2 y2;
@@ -441,20 +462,16 @@ __global__ __launch_bounds__(64 * NW) void k_ras_apply2d(BoxGeom G, const SubInf
   }
   // ---- backward sweep: U x = y, write the owned part ------------------------
   auto prefetch_U = [&](Stage<FT, NUC> &s, int w) {
-    const int wc = w >= 0 ? w : 0;
-    const int j = row_on_level<TT>(wc, t, G.bw, G.bh);
-    s.act = (w >= 0) && (j >= 0);
-    const int jj = s.act ? j : 0;
-    const int i = wc - 2 * jj;
-    s.idx = s.act ? wc * G.bh + jj : ncb;
+    int g;
+    bool own;
+    cell_of(w, s.idx, s.act, g, own);
     const int li = s.act ? s.idx : 0;
 #pragma unroll
     for (int q = 0; q < NUC; ++q) s.c[q] = Fk[(long)(U0C + q) * ncb + li];
     const P2 y2 = yk[s.idx];
     s.a = y2.x;
     s.b = y2.y;
-    const bool own = s.act && i >= si.own_x0 && i < si.own_x1 && jj >= si.own_y0 && jj < si.own_y1;
-    s.g = own ? box_to_global(si, i, jj, nx, ny, periodic) : -1;
+    s.g = own ? g : -1;
   };
   Stage<FT, NUC> ringu[D];
 #pragma unroll
@@ -468,17 +485,17 @@ __global__ __launch_bounds__(64 * NW) void k_ras_apply2d(BoxGeom G, const SubInf
       FT Au, Av, Mu, Mv;
       neighbour_fetch<1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
       Stage<FT, NUC> &s = ringu[k];
-      FT accv = slot<22, U0C, FT>(s.c) * o1v;
-      accv = fma(slot<23, U0C, FT>(s.c), a1v, accv);
+      FT accv = slot<23, U0C, FT>(s.c) * a1v;
+      accv = fma(slot<22, U0C, FT>(s.c), o1v, accv);
       FT xv = (s.b - accv) * slot<21, U0C, FT>(s.c);
-      FT acc = slot<12, U0C, FT>(s.c) * o1u;
-      acc = fma(slot<13, U0C, FT>(s.c), o2u, acc);
+      FT acc = slot<13, U0C, FT>(s.c) * o2u;
       acc = fma(slot<15, U0C, FT>(s.c), a1u, acc);
       acc = fma(slot<16, U0C, FT>(s.c), a2u, acc);
-      acc = fma(slot<19, U0C, FT>(s.c), o1v, acc);
       acc = fma(slot<20, U0C, FT>(s.c), a1v, acc);
-      acc = fma(slot<14, U0C, FT>(s.c), Au, acc);
       acc = fma(slot<17, U0C, FT>(s.c), Mu, acc);
+      acc = fma(slot<12, U0C, FT>(s.c), o1u, acc);
+      acc = fma(slot<19, U0C, FT>(s.c), o1v, acc);
+      acc = fma(slot<14, U0C, FT>(s.c), Au, acc);
       acc = fma(slot<18, U0C, FT>(s.c), xv, acc);
       FT xu = (s.a - acc) * slot<11, U0C, FT>(s.c);
       xu = s.act ? xu : zero;
@@ -527,18 +544,34 @@ hipError_t factor_impl(const BoxGeom &G, const SubInfo *subs, const int *lvl, in
   return hipGetLastError();
 }
 
-constexpr int kPrefetch = 8;   // wavefronts loaded ahead of their use in the solves
+// Wavefronts loaded ahead of their use in the solves (selectable for tuning).
+int g_ras_prefetch = 8;
+
+template <typename FT, int NW, int D>
+hipError_t apply_d(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
+                   const void *fac, void *ybuf, const double *r, double *z, double *dump, const GmresState *st,
+                   long vstride, hipStream_t s) {
+  hipLaunchKernelGGL((k_ras_apply2d<FT, NW, D>), dim3(G.nsub), dim3(64 * NW), 0, s, G, subs, lvl, nx, ny, periodic,
+                     fac, ybuf, r, z, dump, st, vstride);
+  return hipGetLastError();
+}
 
 template <typename FT, int NW>
 hipError_t apply_impl(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
                       const void *fac, void *ybuf, const double *r, double *z, double *dump, const GmresState *st,
                       long vstride, hipStream_t s) {
-  hipLaunchKernelGGL((k_ras_apply2d<FT, NW, kPrefetch>), dim3(G.nsub), dim3(64 * NW), 0, s, G, subs, lvl, nx, ny,
-                     periodic, fac, ybuf, r, z, dump, st, vstride);
-  return hipGetLastError();
+  switch (g_ras_prefetch) {
+    case 2: return apply_d<FT, NW, 2>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
+    case 4: return apply_d<FT, NW, 4>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
+    case 16: return apply_d<FT, NW, 16>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
+    default: return apply_d<FT, NW, 8>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
+  }
 }
 
 }  // namespace
+
+void set_ras_prefetch(int d) { g_ras_prefetch = (d == 2 || d == 4 || d == 16) ? d : 8; }
+int get_ras_prefetch() { return g_ras_prefetch; }
 
 int schwarz_waves(const BoxGeom &G) {
   // bw < 2T keeps one active cell per thread per wavefront (and clean histories)

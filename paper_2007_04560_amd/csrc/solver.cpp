@@ -613,6 +613,15 @@ extern "C" int acch_kernel_stats(acch_ctx *c, int kind, double *total_ms, long *
   return ACCH_OK;
 }
 
+extern "C" int acch_set_option(acch_ctx *c, int option, long value) {
+  (void)c;
+  if (option == ACCH_OPT_RAS_PREFETCH) {
+    set_ras_prefetch((int)value);
+    return ACCH_OK;
+  }
+  return fail(ACCH_EINVAL, "unknown option");
+}
+
 extern "C" int acch_counters(acch_ctx *c, long *launches, long *syncs) {
   if (!c) return fail(ACCH_EINVAL, "null context");
   if (launches) *launches = c->launches;
