@@ -29,9 +29,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = dict(name="periodic512", shape=(512, 512), bc="periodic", sub=(8, 8), overlap=2,
-                adaptive=True, dt_min=1e-4, dt_max=1e-1, eta0=1e4, newton_rtol=1e-8, newton_atol=1e-13,
-                gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30, ilu_shift=0.02, precision="fp64", seed=0)
+WORKLOADS = {
+    # the headline configuration (one accepted step = one bench step)
+    "periodic512": dict(name="periodic512", shape=(512, 512), bc="periodic", sub=(8, 8), overlap=2,
+                        adaptive=True, dt_min=1e-4, dt_max=1e-1, eta0=1e4, newton_rtol=1e-8, newton_atol=1e-13,
+                        gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30, ilu_shift=0.02, precision="fp64",
+                        seed=0, steps=200,
+                        text="periodic512: 2D periodic 512x512, 200 adaptive steps dt in [1e-4,1e-1], FP64 NKS, "
+                             "left-RAS 8x8 overlap 2, ILU(0) shift 0.02, GMRES(30), tol 1e-8"),
+    # the 2048^2 Neumann configuration with FP32 subdomain factors and solves
+    "neumann2048": dict(name="neumann2048", shape=(2048, 2048), bc="neumann", sub=(16, 16), overlap=2,
+                        adaptive=True, dt_min=1e-4, dt_max=1e-1, eta0=1e4, newton_rtol=1e-8, newton_atol=1e-13,
+                        gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30, ilu_shift=0.02, precision="mixed",
+                        seed=0, steps=50,
+                        text="neumann2048: 2D Neumann 2048x2048, 50 adaptive steps dt in [1e-4,1e-1], FP64 NKS "
+                             "with FP32 subdomain ILU(0) factors/solves, left-RAS 16x16 overlap 2, shift 0.02, "
+                             "GMRES(30), tol 1e-8"),
+}
+WORKLOAD = WORKLOADS["periodic512"]
 
 
 def ras_bytes_per_cell(box_cells: float, owned_cells: float, nslot: int = 24, sp: int = 8) -> float:
@@ -63,13 +78,13 @@ def measured_traffic(kernel: str = "void k_ras_apply2d<double, 1, 8>"):
     return k["hbm_bytes_per_launch"] if k else None
 
 
-def run_gpu(steps: int, warmup: int, timing: bool):
+def run_gpu(steps: int, warmup: int, timing: bool, w=None):
     import numpy as np
     import torch
     from acch_inputs import random_ic
     from paper_2007_04560_amd import Solver
 
-    w = WORKLOAD
+    w = w or WORKLOAD
     u0, v0 = random_ic(w["shape"], w["seed"])
     kw = dict(bc=w["bc"], sub=w["sub"], overlap=w["overlap"], adaptive=w["adaptive"], dt_min=w["dt_min"],
               dt_max=w["dt_max"], eta0=w["eta0"], newton_rtol=w["newton_rtol"], newton_atol=w["newton_atol"],
@@ -126,11 +141,18 @@ def cpu_baseline(budget_s: float = 20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None, help="default: the workload's step count")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP-event timers")
+    ap.add_argument("--workload", default="periodic512", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     args = ap.parse_args()
+    w = dict(WORKLOADS[args.workload])
+    if args.precision:
+        w["precision"] = args.precision
+    if args.steps is None:
+        args.steps = w["steps"]
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition is "
               "not part of this build", file=sys.stderr)
@@ -139,7 +161,7 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
-    r = run_gpu(args.steps, args.warmup, timing=not args.no_timing)
+    r = run_gpu(args.steps, args.warmup, timing=not args.no_timing, w=w)
     recs = r["recs"]
     newton_its = sum(int(x["newton_its"]) for x in recs)
     gmres_its = sum(int(x["gmres_its"]) for x in recs)
@@ -153,11 +175,14 @@ def main():
     if stats and stats["ras"][1] > 0:
         ras_ms, ras_n = stats["ras"]
         avg_s = ras_ms / ras_n * 1e-3
-        bytes_launch = ras_bytes_per_cell(box, owned) * r["ncell"]
+        sp = 4 if w["precision"] == "mixed" else 8
+        bytes_launch = ras_bytes_per_cell(box, owned, sp=sp) * r["ncell"]
         achieved = bytes_launch / avg_s / 1e9
         dom = max(stats, key=lambda k: stats[k][0])
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(), "kernel": "k_ras_apply2d",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic() if w["name"] == "periodic512" and sp == 8 else None,
+                    "kernel": "k_ras_apply2d",
                     "avg_us": round(avg_s * 1e6, 2), "launches": ras_n,
                     "bytes_per_launch": int(bytes_launch), "dominant_by_time": dom}
     line = {
@@ -171,10 +196,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if w["precision"] == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "periodic512: 2D periodic 512x512, 200 adaptive steps dt in [1e-4,1e-1], "
-                               "FP64 NKS, left-RAS 8x8 overlap 2, ILU(0) shift 0.02, GMRES(30), tol 1e-8",
+        "config": {"workload": w["text"] if w["precision"] == WORKLOADS[w["name"]]["precision"]
+                   else w["text"] + f" (precision {w['precision']})",
                    "cells": r["ncell"], "dof": dof, "newton_its": newton_its, "gmres_its": gmres_its,
                    "gmres_per_newton": round(gmres_its / max(1, newton_its), 2),
                    "t_final": recs[-1]["t"] if recs else 0.0,
@@ -185,7 +210,7 @@ def main():
                    "kernel_ms": {k: round(v[0], 3) for k, v in stats.items() if v[1]}},
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "periodic512":
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
     return 0

@@ -109,6 +109,50 @@ ACCH_DEV void block_sum(double (&v)[NV], int tid, int nthreads) {
   }
 }
 
+// Many sums at once (NV a power of two): each butterfly step halves the number of
+// values a lane carries and trades the other half with its partner, so NV values
+// need about NV shuffles instead of 6 NV.  On return lane l holds the wave total of
+// value l / (64 / NV).
+template <int C, int O, int NV>
+ACCH_DEV void multi_step(double (&v)[NV], int lane) {
+  if constexpr (C >= 1) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const double send = up ? v[k] : v[k + C];
+      const double keep = up ? v[k + C] : v[k];
+      v[k] = keep + __shfl_xor(send, O, 64);
+    }
+    multi_step<C / 2, O / 2, NV>(v, lane);
+  }
+}
+
+template <int NV>
+ACCH_DEV double wave_multi_sum(double (&v)[NV], int lane) {
+  static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two <= 64");
+  multi_step<NV / 2, 32, NV>(v, lane);
+  double r = v[0];
+#pragma unroll
+  for (int o = 32 / NV; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+  return r;
+}
+
+// Block totals of the first nv_used of NV values, written by threads 0..nv_used-1.
+template <int NV>
+ACCH_DEV void block_multi_sum(double (&v)[NV], int tid, int nthreads, int nv_used, double *s_out) {
+  __shared__ double s_red[16][NV];
+  constexpr int R = 64 / NV;
+  const int lane = tid & 63, wid = tid >> 6;
+  const double r = wave_multi_sum<NV>(v, lane);
+  if (lane % R == 0) s_red[wid][lane / R] = r;
+  __syncthreads();
+  if (tid < nv_used) {
+    double a = 0.0;
+    for (int w = 0; w < (nthreads >> 6); ++w) a += s_red[w][tid];
+    *s_out = a;
+  }
+}
+
 // Two-kernel grid reductions.  A reduction kernel stores one partial sum per block
 // (block_partial); a one-block finalize kernel adds the partials in block order
 // (final_sum), which makes the result independent of scheduling.  The kernel
@@ -123,6 +167,15 @@ ACCH_DEV void block_partial(double (&v)[NV], double *partials, int tid, int nthr
     for (int k = 0; k < NV; ++k)
       if (k < nv_used) partials[k * nblocks + bid] = v[k];
   }
+}
+
+// block_partial for many values (NV a power of two, see wave_multi_sum).
+template <int NV>
+ACCH_DEV void block_partial_multi(double (&v)[NV], double *partials, int tid, int nthreads, int bid, int nblocks,
+                                  int nv_used) {
+  double a;
+  block_multi_sum<NV>(v, tid, nthreads, nv_used, &a);
+  if (tid < nv_used) partials[tid * nblocks + bid] = a;
 }
 
 // Sum of the partials of the first nv_used values; valid in thread 0.

@@ -62,54 +62,84 @@ __global__ __launch_bounds__(256) void k_gmres_orth(long n2, double *__restrict_
   block_partial<1>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x);
 }
 
-// The serial part of an Arnoldi step (one thread): Hessenberg column, Givens
-// rotations, residual estimate, stopping test and, at the end of a cycle, y.
+// The serial part of an Arnoldi step: Hessenberg column, Givens rotations, residual
+// estimate, stopping test and, at the end of a cycle, y.  The block first stages the
+// small GMRES arrays in LDS (one round trip), thread 0 works on LDS only, then the
+// block writes the results back.
 ACCH_DEV void orth_tail(GmresState *st, double sum) {
+  constexpr int M1 = kMaxRestart + 1;
+  __shared__ double sH[M1 * kMaxRestart];
+  __shared__ double sc_[kMaxRestart], ss_[kMaxRestart], sg[M1], sy[kMaxRestart];
+  __shared__ int s_done;
+  const int tid = threadIdx.x;
   const int j = st->j;
+  for (int e = tid; e < (j + 1) * M1; e += blockDim.x) {
+    const int col = e / M1, row = e - col * M1;
+    sH[e] = (col < j) ? st->H[e] : (row <= j ? st->hcol[row] : 0.0);
+  }
+  if (tid < j) {
+    sc_[tid] = st->cs[tid];
+    ss_[tid] = st->sn[tid];
+  }
+  if (tid <= j) sg[tid] = st->g[tid];
+  __syncthreads();
   const double hn = sqrt(sum);
-  const int M1 = kMaxRestart + 1;
-  // new Hessenberg column: the dots, then ||w||; apply the previous rotations
-  double *h = st->H + j * M1;
-  for (int i = 0; i <= j; ++i) h[i] = st->hcol[i];
-  double hj1 = hn;
-  for (int i = 0; i < j; ++i) {
-    const double a = h[i], b = h[i + 1];
-    h[i] = st->cs[i] * a + st->sn[i] * b;
-    h[i + 1] = -st->sn[i] * a + st->cs[i] * b;
-  }
-  const double rr = hypot(h[j], hj1);
-  double c = 1.0, s = 0.0;
-  if (rr > 0.0) {
-    c = h[j] / rr;
-    s = hj1 / rr;
-  }
-  st->cs[j] = c;
-  st->sn[j] = s;
-  h[j] = rr;
-  const double gj = st->g[j];
-  st->g[j] = c * gj;
-  st->g[j + 1] = -s * gj;
-  const double resid = fabs(st->g[j + 1]);
-  st->resid = resid;
-  const int jn = j + 1;
-  st->j = jn;
-  st->total_its += 1;
-  const bool breakdown = !(hn > 1e-300 * st->beta);
-  st->inv_norm[jn] = breakdown ? 0.0 : 1.0 / hn;
-  if (resid <= st->tol || breakdown) {
-    st->converged = 1;
-    st->done = 1;
-  } else if (jn >= st->m || !(resid == resid)) {
-    st->done = 1;
-  }
-  if (st->done) {
-    // back substitution H(0:jn,0:jn) y = g
-    for (int i = jn - 1; i >= 0; --i) {
-      double a = st->g[i];
-      for (int k = i + 1; k < jn; ++k) a -= st->H[k * M1 + i] * st->y[k];
-      const double d = st->H[i * M1 + i];
-      st->y[i] = d != 0.0 ? a / d : 0.0;
+  if (tid == 0) {
+    double *h = sH + j * M1;
+    for (int i = 0; i < j; ++i) {
+      const double a = h[i], b = h[i + 1];
+      h[i] = sc_[i] * a + ss_[i] * b;
+      h[i + 1] = -ss_[i] * a + sc_[i] * b;
     }
+    const double rr = hypot(h[j], hn);
+    double c = 1.0, s = 0.0;
+    if (rr > 0.0) {
+      c = h[j] / rr;
+      s = hn / rr;
+    }
+    sc_[j] = c;
+    ss_[j] = s;
+    h[j] = rr;
+    const double gj = sg[j];
+    sg[j] = c * gj;
+    sg[j + 1] = -s * gj;
+    const double resid = fabs(sg[j + 1]);
+    const int jn = j + 1;
+    const bool breakdown = !(hn > 1e-300 * st->beta);
+    int done = 0;
+    if (resid <= st->tol || breakdown) {
+      st->converged = 1;
+      done = 1;
+    } else if (jn >= st->m || !(resid == resid)) {
+      done = 1;
+    }
+    if (done) {  // back substitution H(0:jn,0:jn) y = g
+      for (int i = jn - 1; i >= 0; --i) {
+        double a = sg[i];
+        for (int q = i + 1; q < jn; ++q) a -= sH[q * M1 + i] * sy[q];
+        const double d = sH[i * M1 + i];
+        sy[i] = d != 0.0 ? a / d : 0.0;
+      }
+    }
+    st->resid = resid;
+    st->inv_norm[jn] = breakdown ? 0.0 : 1.0 / hn;
+    st->total_its += 1;
+    s_done = done;
+  }
+  __syncthreads();
+  const int jn = j + 1;
+  if (tid <= j) st->H[j * M1 + tid] = sH[j * M1 + tid];
+  if (tid == 0) {
+    st->cs[j] = sc_[j];
+    st->sn[j] = ss_[j];
+    st->g[j] = sg[j];
+    st->g[j + 1] = sg[j + 1];
+  }
+  if (s_done && tid < jn) st->y[tid] = sy[tid];
+  __syncthreads();
+  if (tid == 0) {
+    st->j = jn;
+    st->done = s_done;
   }
 }
 
@@ -144,38 +174,52 @@ __global__ __launch_bounds__(256) void k_norm2_diff(long n2, const double *__res
   block_partial<1>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x);
 }
 
-// One-block second stage of every reduction (see block_partial / final_sum).
-template <int NV>
+// One-block second stages of the reductions (see block_partial / final_sum), one
+// kernel per kind so that profiles tell them apart.
+template <int MODE>
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int nblocks, int nv,
-                                                   double *__restrict__ out, GmresState *st, int mode,
-                                                   FinalizeArgs fa) {
-  if (mode == kFinDots || mode == kFinOrth) {
+                                                   double *__restrict__ out, GmresState *st, FinalizeArgs fa) {
+  if constexpr (MODE == kFinDots || MODE == kFinOrth) {
     if (st->done) return;   // the partial kernel skipped as well
-  } else if (mode == kFinUpdate) {
+  } else if constexpr (MODE == kFinUpdate) {
     if (!st->done) return;
   }
-  if (mode == kFinDots) nv = st->j + 1;
-  double acc[NV];
-  final_sum<NV>(partials, nblocks, threadIdx.x, 256, acc, nv);
-  if (threadIdx.x != 0) return;
-  switch (mode) {
-    case kFinPlain:
-      for (int k = 0; k < NV; ++k)
+  if constexpr (MODE == kFinDots) {
+    // h_ij = inv_norm_i * sum of the block partials of dot i, i <= j
+    constexpr int NV = 32;
+    const int jj = st->j;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double a = 0.0;
+      if (k <= jj)
+        for (int b = threadIdx.x; b < nblocks; b += 256) a += partials[k * nblocks + b];
+      acc[k] = a;
+    }
+    double tot;
+    block_multi_sum<NV>(acc, threadIdx.x, 256, jj + 1, &tot);
+    if ((int)threadIdx.x <= jj) st->hcol[threadIdx.x] = tot * st->inv_norm[threadIdx.x];
+  } else if constexpr (MODE == kFinOrth) {
+    double acc[1];
+    final_sum<1>(partials, nblocks, threadIdx.x, 256, acc);
+    __shared__ double s_sum;
+    if (threadIdx.x == 0) s_sum = acc[0];
+    __syncthreads();
+    orth_tail(st, s_sum);
+  } else if constexpr (MODE == kFinPlain) {
+    double acc[2];
+    final_sum<2>(partials, nblocks, threadIdx.x, 256, acc, nv);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 2; ++k)
         if (k < nv) out[k] = acc[k];
-      break;
-    case kFinStart:
+  } else {
+    double acc[1];
+    final_sum<1>(partials, nblocks, threadIdx.x, 256, acc);
+    if (threadIdx.x != 0) return;
+    if constexpr (MODE == kFinStart)
       start_tail(st, acc[0], fa.first, fa.m, fa.rtol, fa.atol);
-      break;
-    case kFinDots:
-      for (int k = 0; k < NV; ++k)
-        if (k < nv) st->hcol[k] = acc[k] * st->inv_norm[k];
-      break;
-    case kFinOrth:
-      orth_tail(st, acc[0]);
-      break;
-    case kFinUpdate:
+    else
       st->shift = fa.project ? acc[0] / (double)fa.ncell : 0.0;
-      break;
   }
 }
 
@@ -193,11 +237,26 @@ __global__ __launch_bounds__(256) void k_reset_state(GmresState *st) {
 
 hipError_t launch_finalize(int mode, int nv, const RedBuf &red, int nblocks, GmresState *st, const FinalizeArgs &fa,
                            hipStream_t s) {
-  if (nv > 2)
-    hipLaunchKernelGGL(k_finalize<kMaxRestart + 1>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st,
-                       mode, fa);
-  else
-    hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, mode, fa);
+  switch (mode) {
+    case kFinPlain:
+      if (nv > 2) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_finalize<kFinPlain>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
+      break;
+    case kFinStart:
+      hipLaunchKernelGGL(k_finalize<kFinStart>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
+      break;
+    case kFinDots:
+      hipLaunchKernelGGL(k_finalize<kFinDots>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
+      break;
+    case kFinOrth:
+      hipLaunchKernelGGL(k_finalize<kFinOrth>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
+      break;
+    case kFinUpdate:
+      hipLaunchKernelGGL(k_finalize<kFinUpdate>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

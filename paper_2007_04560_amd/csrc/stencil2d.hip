@@ -302,9 +302,11 @@ __global__ __launch_bounds__(256) void k_spmv_dots2d(Phys P, const double *__res
   const long n = (long)P.nx * P.ny;
   const double *z = Z + (long)j * vstride;
   double *w = V + (long)(j + 1) * vstride;
-  double acc[kMaxRestart + 1];
+  constexpr int NV = 32;   // kMaxRestart + 1 dots, padded to a power of two
+  static_assert(kMaxRestart + 1 <= NV, "dot count");
+  double acc[NV];
 #pragma unroll
-  for (int i = 0; i <= kMaxRestart; ++i) acc[i] = 0.0;
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
     const int gy = (int)(g / P.nx), gx = (int)(g - (long)gy * P.nx);
     double yu, yv;
@@ -315,7 +317,7 @@ __global__ __launch_bounds__(256) void k_spmv_dots2d(Phys P, const double *__res
     for (int i = 0; i <= kMaxRestart; ++i)
       if (i <= j) acc[i] = fma(yu, V[(long)i * vstride + g], fma(yv, V[(long)i * vstride + n + g], acc[i]));
   }
-  block_partial<kMaxRestart + 1>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x, j + 1);
+  block_partial_multi<NV>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x, j + 1);
 }
 
 }  // namespace

@@ -304,3 +304,56 @@ def test_errors_are_reported():
     assert e.value.code == 3
     ug, vg = s.fields()
     assert np.array_equal(ug, u0) and np.array_equal(vg, v0)
+
+
+def test_wide_boxes_use_two_waves_and_match_oracle():
+    """Boxes wider than 127 cells run the two-wave solve (lane hand-over through LDS)."""
+    shape = (40, 262)
+    u1, v1, u0, v0 = perturbed_pair(shape, 51, amp=0.03)
+    P = prob("neumann")
+    dt = 2e-4
+    s = solver(u0, v0, "neumann", sub=(2, 1), overlap=2, ilu_shift=0.02)
+    assert s.info()["box_w"] > 127
+    s.jacobian(dev(vec(u1, v1)), dev(vec(u0, v0)), dt)
+    s.factor()
+    Jo = jacobian.jacobian(u1, v1, u0, v0, dt, P)
+    r = np.random.default_rng(8).standard_normal(2 * u1.size)
+    z = s.precondition(dev(r)).cpu().numpy()
+    zo = schwarz.Schwarz(Jo, shape, (1, 2), 2, "neumann", kind="left", shift=0.02).apply(r)
+    assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
+
+
+@pytest.mark.parametrize("shape,bc,sub,ov", [((64, 64), "periodic", (2, 2), 1), ((45, 100), "neumann", (3, 2), 2)])
+def test_mixed_precision_preconditioner_close_to_fp64(shape, bc, sub, ov):
+    """FP32 factors and solves: the preconditioner output is the FP64 one to FP32 accuracy."""
+    u1, v1, u0, v0 = perturbed_pair(shape, 61, amp=0.03)
+    P = prob(bc)
+    dt = 1e-3
+    out = {}
+    for prec in ["fp64", "mixed"]:
+        s = solver(u0, v0, bc, sub=sub, overlap=ov, ilu_shift=0.02, precision=prec)
+        s.jacobian(dev(vec(u1, v1)), dev(vec(u0, v0)), dt)
+        s.factor()
+        r = np.random.default_rng(9).standard_normal(2 * u1.size)
+        out[prec] = s.precondition(dev(r)).cpu().numpy()
+    rel = np.max(np.abs(out["mixed"] - out["fp64"])) / np.max(np.abs(out["fp64"]))
+    assert 1e-9 < rel < 1e-4
+
+
+def test_mixed_precision_steps_match_fp64_oracle():
+    """The FP32 preconditioner changes the iteration, not the root: 10 steps of the 64x64
+    periodic workload in mixed precision match the FP64 oracle to 1e-10 per step."""
+    shape = (64, 64)
+    u0, v0 = random_ic(shape, 0)
+    P = prob("periodic")
+    s = solver(u0, v0, "periodic", sub=(2, 2), overlap=1, dt_fixed=1e-3, newton_rtol=1e-12,
+               newton_atol=1e-13, gmres_rtol=1e-12, precision="mixed")
+    run = controller.Run(P, u0.copy(), v0.copy(), adaptive=False, dt_fixed=1e-3,
+                         newton=newton.NewtonOptions(rtol=1e-12, atol=1e-13))
+    M0 = scheme.mass(u0, P)
+    for k in range(10):
+        info = s.step(1)[0]
+        run.step()
+        ug, vg = s.fields()
+        assert _rel_l2(ug, vg, run.u, run.v) <= 1e-10, k
+        assert abs(info["mass"] - M0) <= 1e-12 * M0
