@@ -208,6 +208,38 @@ int acch_set_option(acch_ctx *c, int option, long value);
 /* Kernel launches and host synchronisations since the last acch_timing call. */
 int acch_counters(acch_ctx *c, long *launches, long *syncs);
 
+/* ---- Discrete adjoint of the time-step map ----------------------------------
+ * A step solves F(X1; X0, dt) = 0 (scheme (2.20), Section 3.1).  With the step sizes
+ * held fixed, reverse differentiation of a loss L through the steps needs, per step,
+ *   J^T lambda = dL/dX1 (J = dF/dX1, the Newton Jacobian at the converged X1),
+ *   dL/dX0 = -(dF/dX0)^T lambda,   dL/dp -= lambda . dF/dp,
+ * for p = (alpha, beta, theta, gamma).  Vectors are device arrays of 2*ncell
+ * doubles (u then v), owned by the caller.  These calls reuse the context's
+ * Jacobian, factor and Krylov storage (its state, time and step history are left
+ * alone); the next acch_step refactors as usual. */
+
+/* y = J^T x with the context's Jacobian. */
+int acch_apply_jacobian_transpose(acch_ctx *c, const double *x, double *y);
+
+/* z = M^{-T} r: the exact transpose of the Schwarz preconditioner with the current
+ * factors, sum_k (R_k^delta)^T (L_k U_k)^{-T} R_k^0 r.  Needs overlap <= the
+ * smallest subdomain width (ACCH_EUNSUPPORTED otherwise). */
+int acch_precondition_transpose(acch_ctx *c, const double *r, double *z);
+
+/* Gradient of the discrete energy E~ (eqs. relations, freeenergy) at the device
+ * state X (NULL: the context's current state): g receives dE~/dX, dparams (host,
+ * 4 doubles) receives dE~/d(alpha, beta, theta, gamma). */
+int acch_energy_gradient(acch_ctx *c, const double *X, double *g, double *dparams);
+
+/* One step back: assemble J at (X1; X0, dt), factor, solve J^T lambda = g by GMRES
+ * preconditioned with M^{-T} (the context's tolerances and restart limits; no mass
+ * projection), then g_prev = -(dF/dX0)^T lambda and dparams[k] -= lambda . dF/dp_k
+ * (host, 4 doubles, accumulated).  g_prev may be g.  gmres_its / resid (host, may
+ * be NULL) receive the GMRES iterations and final residual estimate.  Returns
+ * ACCH_EDIVERGED if GMRES does not converge. */
+int acch_adjoint_step(acch_ctx *c, const double *X1, const double *X0, double dt, const double *g, double *g_prev,
+                      double *dparams, int *gmres_its, double *resid);
+
 const char *acch_strerror(int code);
 const char *acch_last_error(void);
 

@@ -11,9 +11,9 @@ with the dt sequence held fixed gives, with A_n = dF_n/dU^{n+1} and B_n = dF_n/d
 
 for n = N-1, ..., 0, plus the explicit dE~/dp at U^N.  g_0 = dL/dU^0.
 
-Pins (tests/test_oracle_adjoint.py): B_n, dF/dtheta, dF/dgamma and dE~/d(U, theta, gamma)
-against complex-step derivatives; the whole gradient against central differences of the
-forward run.
+Parameters p: alpha, beta, theta, gamma.  Pins (tests/test_oracle_adjoint.py): B_n, dF/dp
+and dE~/d(U, p) against complex-step derivatives; the whole gradient against central
+differences of the forward run.
 """
 from __future__ import annotations
 
@@ -88,18 +88,25 @@ def previous_state_jacobian(u1, v1, u0, v0, dt, prob: Problem):
     return sp.bmat([[Buu, Buv], [Bvu, Bvv]], format="csr")
 
 
+PARAMS = ("alpha", "beta", "theta", "gamma")
+
+
 def parameter_derivatives(u1, v1, u0, v0, dt, prob: Problem):
-    """dF/dtheta and dF/dgamma as stacked vectors: F_u depends on a parameter only through
-    mu (inside the flux), F_v through nu:
-      d mu/d theta = phi + psi, d nu/d theta = phi - psi,
+    """dF/dp for p in alpha, beta, theta, gamma as stacked vectors.  F_u depends on a
+    parameter only through mu (inside the flux), F_v only through nu (eq. dvds-2):
+      d mu/d alpha = -(u1 + u0 - 1)/2,  d nu/d beta = -(v1 + v0)/2,
+      d mu/d theta = phi + psi,         d nu/d theta = phi - psi,
       d mu/d gamma = -(Lap u1 + Lap u0)/2, d nu/d gamma = -(Lap v1 + Lap v0)/2."""
     h = prob.spacing(u1.shape)
     c = scheme.operator_mobility(u1, v1, u0, v0, prob)
     phi = scheme.g2_series(u1 + v1, u0 + v0, prob.S)
     psi = scheme.g2_series(u1 - v1, u0 - v0, prob.S)
     lap = lambda a: scheme.laplacian(a, h, prob.bc)
+    zero = np.zeros_like(u1)
     out = {}
-    for name, dmu, dnu in [("theta", phi + psi, phi - psi),
+    for name, dmu, dnu in [("alpha", -0.5 * (u1 + u0 - 1.0), zero),
+                           ("beta", zero, -0.5 * (v1 + v0)),
+                           ("theta", phi + psi, phi - psi),
                            ("gamma", -0.5 * (lap(u1) + lap(u0)), -0.5 * (lap(v1) + lap(v0)))]:
         Fu = -scheme.div_c_grad(c, dmu, h, prob.bc)
         Fv = c * dnu / prob.rho
@@ -108,20 +115,22 @@ def parameter_derivatives(u1, v1, u0, v0, dt, prob: Problem):
 
 
 def energy_gradient(u, v, prob: Problem):
-    """dE~/du, dE~/dv (fields) and dE~/dtheta, dE~/dgamma of eqs. relations/freeenergy:
-    the cell volume times alpha/2 (1-2u) + theta(Phi'(u+v) + Phi'(u-v)) - gamma Lap u, and
-    -beta v + theta(Phi'(u+v) - Phi'(u-v)) - gamma Lap v; sum of theta-terms / theta and
-    of gradient terms / gamma."""
+    """dE~/du, dE~/dv (fields) and dE~/dp of eqs. relations/freeenergy: the cell volume
+    times alpha/2 (1-2u) + theta(Phi'(u+v) + Phi'(u-v)) - gamma Lap u, and
+    -beta v + theta(Phi'(u+v) - Phi'(u-v)) - gamma Lap v; each parameter's own terms
+    divided by it for dE~/dp."""
     h = prob.spacing(u.shape)
     vol = scheme.cell_volume(u.shape, prob)
     dPhi = lambda z: np.log(z) - np.log(1.0 - z)
     lap = lambda a: scheme.laplacian(a, h, prob.bc)
     gu = vol * (0.5 * prob.alpha * (1 - 2 * u) + prob.theta * (dPhi(u + v) + dPhi(u - v)) - prob.gamma * lap(u))
     gv = vol * (-prob.beta * v + prob.theta * (dPhi(u + v) - dPhi(u - v)) - prob.gamma * lap(v))
-    gtheta = vol * float(np.sum(scheme.Phi(u + v) + scheme.Phi(u - v)))
-    ggamma = vol * 0.5 * float(np.sum(scheme.gradient_energy_density(u, h, prob.bc)
-                                      + scheme.gradient_energy_density(v, h, prob.bc)))
-    return gu, gv, gtheta, ggamma
+    gp = {"alpha": vol * 0.5 * float(np.sum(u * (1.0 - u))),
+          "beta": -vol * 0.5 * float(np.sum(v * v)),
+          "theta": vol * float(np.sum(scheme.Phi(u + v) + scheme.Phi(u - v))),
+          "gamma": vol * 0.5 * float(np.sum(scheme.gradient_energy_density(u, h, prob.bc)
+                                            + scheme.gradient_energy_density(v, h, prob.bc)))}
+    return gu, gv, gp
 
 
 def forward(u0, v0, dts, prob: Problem, opts: NewtonOptions):
@@ -137,22 +146,30 @@ def forward(u0, v0, dts, prob: Problem, opts: NewtonOptions):
     return states
 
 
-def gradient(u0, v0, dts, prob: Problem, opts: NewtonOptions = None):
-    """E~(U^N) and its gradient with respect to (u0, v0, theta, gamma), dt sequence fixed."""
+def adjoint_step(u1, v1, u0, v0, dt, prob: Problem, g1):
+    """One step back: solve A^T lambda = g1, return (g0, lambda, {p: -lambda . dF/dp})."""
+    A = jacobian.jacobian(u1, v1, u0, v0, dt, prob)
+    lam = spla.spsolve(A.T.tocsc(), g1)
+    pd = parameter_derivatives(u1, v1, u0, v0, dt, prob)
+    dp = {k: -float(lam @ pd[k]) for k in PARAMS}
+    B = previous_state_jacobian(u1, v1, u0, v0, dt, prob)
+    return -(B.T @ lam), lam, dp
+
+
+def gradient(u0, v0, dts, prob: Problem, opts: NewtonOptions = None, states=None):
+    """E~(U^N) and its gradient with respect to u0, v0 and the parameters (dict), the
+    dt sequence held fixed.  `states` may hold U^0..U^N of an earlier forward run."""
     opts = opts or NewtonOptions(rtol=1e-12, atol=1e-11)
-    states = forward(u0, v0, dts, prob, opts)
+    if states is None:
+        states = forward(u0, v0, dts, prob, opts)
     uN, vN = states[-1]
     E = scheme.energy(uN, vN, prob)
-    gu, gv, gth, gga = energy_gradient(uN, vN, prob)
+    gu, gv, gp = energy_gradient(uN, vN, prob)
     g = np.concatenate([gu.ravel(), gv.ravel()])
     for k in range(len(dts) - 1, -1, -1):
         (ua, va), (ub, vb) = states[k], states[k + 1]
-        A = jacobian.jacobian(ub, vb, ua, va, dts[k], prob)
-        lam = spla.spsolve(A.T.tocsc(), g)
-        pd = parameter_derivatives(ub, vb, ua, va, dts[k], prob)
-        gth -= float(lam @ pd["theta"])
-        gga -= float(lam @ pd["gamma"])
-        B = previous_state_jacobian(ub, vb, ua, va, dts[k], prob)
-        g = -(B.T @ lam)
+        g, _, dp = adjoint_step(ub, vb, ua, va, dts[k], prob, g)
+        for name in PARAMS:
+            gp[name] += dp[name]
     n = u0.size
-    return E, g[:n].reshape(u0.shape), g[n:].reshape(u0.shape), gth, gga
+    return E, g[:n].reshape(u0.shape), g[n:].reshape(u0.shape), gp

@@ -24,6 +24,7 @@ EXPORTED = [
     "acch_jacobian", "acch_apply_jacobian", "acch_factor", "acch_precondition", "acch_gmres",
     "acch_solve_step", "acch_export", "acch_info", "acch_strerror", "acch_last_error",
     "acch_timing", "acch_kernel_stats", "acch_counters", "acch_set_option",
+    "acch_apply_jacobian_transpose", "acch_precondition_transpose", "acch_energy_gradient", "acch_adjoint_step",
 ]
 KERNEL_KINDS = ["residual", "jacobian", "factor", "ras", "spmv_dots", "orth", "gmres_start", "gmres_update",
                 "energy", "spmv", "other"]
@@ -104,6 +105,10 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "acch_kernel_stats": (ctypes.c_int, [ctx, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_long)]),
         "acch_counters": (ctypes.c_int, [ctx, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]),
         "acch_set_option": (ctypes.c_int, [ctx, ctypes.c_int, ctypes.c_long]),
+        "acch_apply_jacobian_transpose": (ctypes.c_int, [ctx, vp, vp]),
+        "acch_precondition_transpose": (ctypes.c_int, [ctx, vp, vp]),
+        "acch_energy_gradient": (ctypes.c_int, [ctx, vp, vp, dp]),
+        "acch_adjoint_step": (ctypes.c_int, [ctx, vp, vp, ctypes.c_double, vp, vp, dp, ip, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -305,6 +310,36 @@ class Solver:
         res = ctypes.c_double()
         _check(self.lib, self.lib.acch_gmres(self.ctx, _ptr(F), _ptr(S), ctypes.byref(its), ctypes.byref(res)))
         return S, its.value, res.value
+
+    # -- discrete adjoint (device tensors of 2*ncell doubles) -------------------
+    def apply_jacobian_transpose(self, x):
+        y = self.vector()
+        _check(self.lib, self.lib.acch_apply_jacobian_transpose(self.ctx, _ptr(x), _ptr(y)))
+        return y
+
+    def precondition_transpose(self, r):
+        z = self.vector()
+        _check(self.lib, self.lib.acch_precondition_transpose(self.ctx, _ptr(r), _ptr(z)))
+        return z
+
+    def energy_gradient(self, X=None):
+        """(dE~/dX as a device tensor, dE~/d(alpha, beta, theta, gamma) as a float64 array)."""
+        g = self.vector()
+        dp = (ctypes.c_double * 4)()
+        _check(self.lib, self.lib.acch_energy_gradient(self.ctx, None if X is None else _ptr(X), _ptr(g), dp))
+        return g, np.array(dp[:], dtype=np.float64)
+
+    def adjoint_step(self, X1, X0, dt: float, g, dparams=None, out=None):
+        """One step back through F(X1; X0, dt) = 0: returns (dL/dX0, dparams updated by
+        -lambda . dF/dp, GMRES iterations, residual estimate)."""
+        out = self.vector() if out is None else out
+        acc = np.zeros(4) if dparams is None else np.array(dparams, dtype=np.float64)
+        dp = (ctypes.c_double * 4)(*acc.tolist())
+        its = ctypes.c_int()
+        res = ctypes.c_double()
+        _check(self.lib, self.lib.acch_adjoint_step(self.ctx, _ptr(X1), _ptr(X0), dt, _ptr(g), _ptr(out), dp,
+                                                    ctypes.byref(its), ctypes.byref(res)))
+        return out, np.array(dp[:], dtype=np.float64), its.value, res.value
 
     def _export(self, which, dtype):
         t = self.torch

@@ -74,6 +74,20 @@ struct HostMirror {
 
 #define ACCH_DEV __device__ __forceinline__
 
+constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 1) / 2); }
+
+// Periodic wrap, or clamping (the Neumann ghost copies the boundary cell, which
+// makes every boundary difference vanish, as in Section 2).  Offsets are within
+// +-2 of the domain and periodic grids have at least 5 cells.
+ACCH_DEV int wrap_index(int g, int n, int periodic) {
+  if (periodic) return g < 0 ? g + n : (g >= n ? g - n : g);
+  return g < 0 ? 0 : (g >= n ? n - 1 : g);
+}
+
+ACCH_DEV bool face_exists(int g, int dir, int n, int periodic) {
+  return periodic || (dir < 0 ? g > 0 : g < n - 1);
+}
+
 // ---------------------------------------------------------------------------
 // Reductions: wave64 shuffles, then LDS across waves, then a last-block pass.
 // ---------------------------------------------------------------------------

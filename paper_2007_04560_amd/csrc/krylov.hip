@@ -43,19 +43,27 @@ ACCH_DEV void start_tail(GmresState *st, double sum, int first, int m, double rt
 }
 
 // W_{j+1} -= sum_{i<=j} h_ij v_i (classical Gram–Schmidt, one pass), then the norm,
-// the Givens update of the Hessenberg column and the convergence test.
+// the Givens update of the Hessenberg column and the convergence test.  One
+// instantiation per step j, like k_spmv_dots2d.
+template <int J>
 __global__ __launch_bounds__(256) void k_gmres_orth(long n2, double *__restrict__ V, long vstride, GmresState *st,
                                                      RedBuf red) {
   if (st->done) return;
-  const int j = st->j;
-  __shared__ double coef[kMaxRestart + 1];
-  if (threadIdx.x <= j) coef[threadIdx.x] = st->hcol[threadIdx.x] * st->inv_norm[threadIdx.x];
+  __shared__ double coef[J + 1];
+  if (threadIdx.x <= J) coef[threadIdx.x] = st->hcol[threadIdx.x] * st->inv_norm[threadIdx.x];
   __syncthreads();
-  double *w = V + (long)(j + 1) * vstride;
+  double c[J + 1];
+#pragma unroll
+  for (int i = 0; i <= J; ++i) c[i] = coef[i];
+  double *w = V + (long)(J + 1) * vstride;
   double acc[1] = {0.0};
   for (long e = blockIdx.x * 256L + threadIdx.x; e < n2; e += (long)gridDim.x * 256) {
+    double b[J + 1];
+#pragma unroll
+    for (int i = 0; i <= J; ++i) b[i] = V[(long)i * vstride + e];
     double x = w[e];
-    for (int i = 0; i <= j; ++i) x = fma(-coef[i], V[(long)i * vstride + e], x);
+#pragma unroll
+    for (int i = 0; i <= J; ++i) x = fma(-c[i], b[i], x);
     w[e] = x;
     acc[0] = fma(x, x, acc[0]);
   }
@@ -176,6 +184,27 @@ __global__ __launch_bounds__(256) void k_norm2_diff(long n2, const double *__res
 
 // One-block second stages of the reductions (see block_partial / final_sum), one
 // kernel per kind so that profiles tell them apart.
+// h_ij = inv_norm_i * (sum of the block partials of dot i), i <= J.
+template <int J>
+__global__ __launch_bounds__(256) void k_finalize_dots(const double *__restrict__ partials, int nblocks,
+                                                        GmresState *st) {
+  if (st->done) return;
+  constexpr int NV = pow2_at_least(J + 1);
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) {
+    double p[J + 1];
+#pragma unroll
+    for (int k = 0; k <= J; ++k) p[k] = partials[k * nblocks + b];
+#pragma unroll
+    for (int k = 0; k <= J; ++k) acc[k] += p[k];
+  }
+  double tot;
+  block_multi_sum<NV>(acc, threadIdx.x, 256, J + 1, &tot);
+  if ((int)threadIdx.x <= J) st->hcol[threadIdx.x] = tot * st->inv_norm[threadIdx.x];
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int nblocks, int nv,
                                                    double *__restrict__ out, GmresState *st, FinalizeArgs fa) {
@@ -184,22 +213,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
   } else if constexpr (MODE == kFinUpdate) {
     if (!st->done) return;
   }
-  if constexpr (MODE == kFinDots) {
-    // h_ij = inv_norm_i * sum of the block partials of dot i, i <= j
-    constexpr int NV = 32;
-    const int jj = st->j;
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double a = 0.0;
-      if (k <= jj)
-        for (int b = threadIdx.x; b < nblocks; b += 256) a += partials[k * nblocks + b];
-      acc[k] = a;
-    }
-    double tot;
-    block_multi_sum<NV>(acc, threadIdx.x, 256, jj + 1, &tot);
-    if ((int)threadIdx.x <= jj) st->hcol[threadIdx.x] = tot * st->inv_norm[threadIdx.x];
-  } else if constexpr (MODE == kFinOrth) {
+  if constexpr (MODE == kFinOrth) {
     double acc[1];
     final_sum<1>(partials, nblocks, threadIdx.x, 256, acc);
     __shared__ double s_sum;
@@ -207,10 +221,10 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
     __syncthreads();
     orth_tail(st, s_sum);
   } else if constexpr (MODE == kFinPlain) {
-    double acc[2];
-    final_sum<2>(partials, nblocks, threadIdx.x, 256, acc, nv);
+    double acc[4];
+    final_sum<4>(partials, nblocks, threadIdx.x, 256, acc, nv);
     if (threadIdx.x == 0)
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < 4; ++k)
         if (k < nv) out[k] = acc[k];
   } else {
     double acc[1];
@@ -239,14 +253,11 @@ hipError_t launch_finalize(int mode, int nv, const RedBuf &red, int nblocks, Gmr
                            hipStream_t s) {
   switch (mode) {
     case kFinPlain:
-      if (nv > 2) return hipErrorInvalidValue;
+      if (nv > 4) return hipErrorInvalidValue;
       hipLaunchKernelGGL(k_finalize<kFinPlain>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
       break;
     case kFinStart:
       hipLaunchKernelGGL(k_finalize<kFinStart>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
-      break;
-    case kFinDots:
-      hipLaunchKernelGGL(k_finalize<kFinDots>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
       break;
     case kFinOrth:
       hipLaunchKernelGGL(k_finalize<kFinOrth>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
@@ -258,6 +269,32 @@ hipError_t launch_finalize(int mode, int nv, const RedBuf &red, int nblocks, Gmr
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int J>
+static hipError_t finalize_dots_at(int j, const RedBuf &red, int nblocks, GmresState *st, hipStream_t s) {
+  if (j == J) {
+    hipLaunchKernelGGL(k_finalize_dots<J>, dim3(1), dim3(256), 0, s, red.partials, nblocks, st);
+    return hipGetLastError();
+  }
+  if constexpr (J + 1 < kMaxRestart) return finalize_dots_at<J + 1>(j, red, nblocks, st, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize_dots(int j, const RedBuf &red, int nblocks, GmresState *st, hipStream_t s) {
+  if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
+  return finalize_dots_at<0>(j, red, nblocks, st, s);
+}
+
+template <int J>
+static hipError_t orth_at(int j, long n2, double *V, long vstride, GmresState *st, const RedBuf &red, int nb,
+                          hipStream_t s) {
+  if (j == J) {
+    hipLaunchKernelGGL(k_gmres_orth<J>, dim3(nb), dim3(256), 0, s, n2, V, vstride, st, red);
+    return hipGetLastError();
+  }
+  if constexpr (J + 1 < kMaxRestart) return orth_at<J + 1>(j, n2, V, vstride, st, red, nb, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_gmres_start(long n2, const double *F, const double *JS, double *V0, GmresState *st, int m,
@@ -274,10 +311,11 @@ hipError_t launch_gmres_start(long n2, const double *F, const double *JS, double
   return launch_finalize(kFinStart, 1, red, nb, st, fa, s);
 }
 
-hipError_t launch_gmres_orth(long n2, double *V, long vstride, GmresState *st, const RedBuf &red, hipStream_t s) {
+hipError_t launch_gmres_orth(long n2, double *V, long vstride, int j, GmresState *st, const RedBuf &red,
+                             hipStream_t s) {
+  if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
   const int nb = reduce_blocks(n2);
-  hipLaunchKernelGGL(k_gmres_orth, dim3(nb), dim3(256), 0, s, n2, V, vstride, st, red);
-  hipError_t e = hipGetLastError();
+  hipError_t e = orth_at<0>(j, n2, V, vstride, st, red, nb, s);
   if (e != hipSuccess) return e;
   return launch_finalize(kFinOrth, 1, red, nb, st, FinalizeArgs{}, s);
 }

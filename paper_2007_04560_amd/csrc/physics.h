@@ -67,6 +67,19 @@ ACCH_DEV void g2s_d(double x1, double x0, int S, double &g, double &dg) {
   dg = 0.5 * (fx1 + fs1 + fx2 - fs2);
 }
 
+// phi^S with both partial derivatives: d/dx1 as in g2s_d and
+// d phi^S / d x0 = 1/2 [f_x(z,s) - f_s(z,s) + f_x(1-z,s) + f_s(1-z,s)].
+ACCH_DEV void g2s_d01(double x1, double x0, int S, double &g, double &d1, double &d0) {
+  const double z = 0.5 * (x1 + x0);
+  const double s = 0.5 * (x1 - x0);
+  double f1, fx1, fs1, f2, fx2, fs2;
+  f_series_d(z, s, S, f1, fx1, fs1);
+  f_series_d(1.0 - z, s, S, f2, fx2, fs2);
+  g = f1 - f2;
+  d1 = 0.5 * (fx1 + fs1 + fx2 - fs2);
+  d0 = 0.5 * (fx1 - fs1 + fx2 + fs2);
+}
+
 // Mobility inside A~ and its derivatives with respect to (u1, v1).
 ACCH_DEV double mobility_of(int mob, double u1, double v1, double u0, double v0) {
   if (mob == 0) {
@@ -96,7 +109,29 @@ ACCH_DEV void mobility_d(int mob, double u1, double v1, double u0, double v0, do
   }
 }
 
+// Mobility inside A~ and its derivatives with respect to the previous state (u0, v0).
+ACCH_DEV void mobility_d0(int mob, double u1, double v1, double u0, double v0, double &c, double &cu,
+                          double &cv) {
+  if (mob == 0) {
+    const double ub = 0.5 * (u1 + u0), vb = 0.5 * (v1 + v0);
+    c = ub * (1.0 - ub) * (0.25 - vb * vb);
+    cu = 0.5 * (1.0 - 2.0 * ub) * (0.25 - vb * vb);
+    cv = -ub * (1.0 - ub) * vb;
+  } else if (mob == 1) {
+    c = 0.5 * (u1 * (1.0 - u1) * (0.25 - v1 * v1) + u0 * (1.0 - u0) * (0.25 - v0 * v0));
+    cu = 0.5 * (1.0 - 2.0 * u0) * (0.25 - v0 * v0);
+    cv = -u0 * (1.0 - u0) * v0;
+  } else {
+    c = u0 * (1.0 - u0) * (0.25 - v0 * v0);
+    cu = (1.0 - 2.0 * u0) * (0.25 - v0 * v0);
+    cv = -2.0 * u0 * (1.0 - u0) * v0;
+  }
+}
+
 // Phi(z) = z ln z + (1-z) ln(1-z) (exact, for the energy diagnostic).
 ACCH_DEV double Phi(double z) { return z * log(z) + (1.0 - z) * log(1.0 - z); }
+
+// Phi'(z) = ln z - ln(1-z).
+ACCH_DEV double dPhi(double z) { return log(z) - log(1.0 - z); }
 
 }  // namespace acch

@@ -13,6 +13,7 @@
 // one wavefront are contiguous, so a wavefront's loads coalesce).
 #include <utility>
 
+#include "boxes.h"
 #include "kernels.h"
 
 namespace acch {
@@ -115,30 +116,6 @@ ACCH_DEV void elim_v_row(double (&b)[6], double l, const double *prow, std::inte
 ACCH_DEV int level_lo(int w, int bw) {
   const int d = w - bw + 2;
   return d > 0 ? (d >> 1) : 0;
-}
-
-// Row of thread t on wavefront w (rows j = t mod T, 0 <= w - 2j < bw), or -1.
-template <int T>
-ACCH_DEV int row_on_level(int w, int t, int bw, int bh) {
-  const int jmax = w >> 1;
-  if (jmax < t) return -1;
-  const int j = jmax - ((jmax - t) & (T - 1));
-  if (j >= bh || w - 2 * j >= bw) return -1;
-  return j;
-}
-
-// Global cell of box cell (i, j) of subdomain si, or -1 if it is padding or outside
-// a Neumann domain.
-ACCH_DEV long box_to_global(const SubInfo &si, int i, int j, int nx, int ny, int periodic) {
-  if (i >= si.ex || j >= si.ey) return -1;
-  int gx = si.ox + i, gy = si.oy + j;
-  if (periodic) {
-    gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
-    gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
-  } else if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) {
-    return -1;
-  }
-  return (long)gy * nx + gx;
 }
 
 // ---------------------------------------------------------------------------

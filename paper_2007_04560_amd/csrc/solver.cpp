@@ -54,6 +54,7 @@ void split(int n, int parts, std::vector<int> &start, std::vector<int> &len) {
 struct Layout {
   size_t off_Xn, off_Xprev, off_X, off_Xt, off_F, off_Ft, off_S, off_W;
   size_t off_J, off_V, off_Z, off_fac, off_y, off_dump, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
+  size_t off_tbox, off_own;
   size_t total;
 };
 
@@ -74,6 +75,8 @@ struct Geometry {
   BoxGeom G{};
   std::vector<SubInfo> subs;
   std::vector<int> lvl;  // nlev + 1 prefix counts
+  std::vector<int> own;  // owner subdomain of each grid column (nx), then of each row (ny)
+  int min_part = 0;      // smallest owned width / height
   int tile_blocks = 0;
 };
 
@@ -88,9 +91,9 @@ struct acch_ctx {
   char *ws = nullptr;
   double *Xn, *Xprev, *X, *Xt, *F, *Ft, *S, *W, *J, *V, *Z;
   void *fac, *ybuf;
-  double *dump;
+  double *dump, *tbox;
   SubInfo *d_subs;
-  int *d_lvl;
+  int *d_lvl, *d_own;
   GmresState *st;
   RedBuf red{};
   HostMirror *host = nullptr;  // pinned
@@ -184,6 +187,12 @@ static int build_geometry(const acch_params &p, Geometry &geo) {
       s.own_y1 = d + ly[by];
       geo.subs.push_back(s);
     }
+  geo.own.assign(nx + ny, 0);
+  for (int k = 0; k < p.sub[0]; ++k)
+    for (int x = sx[k]; x < sx[k] + lx[k]; ++x) geo.own[x] = k;
+  for (int k = 0; k < p.sub[1]; ++k)
+    for (int y = sy[k]; y < sy[k] + ly[k]; ++y) geo.own[nx + y] = k;
+  geo.min_part = std::min(*std::min_element(lx.begin(), lx.end()), *std::min_element(ly.begin(), ly.end()));
   // wavefront w = i + 2j holds rows j in [lo(w), hi(w)]
   geo.lvl.assign(geo.G.nlev + 1, 0);
   for (int w = 0; w < geo.G.nlev; ++w) {
@@ -228,6 +237,8 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_part = take(nparts * sizeof(double));
   L.off_cnt = take(64);
   L.off_out = take(64 * sizeof(double));
+  L.off_tbox = take((size_t)geo.G.nsub * 2 * geo.G.ncb * sizeof(double));   // transposed Schwarz boxes
+  L.off_own = take(geo.own.size() * sizeof(int));
   L.total = o;
 }
 
@@ -326,30 +337,46 @@ int factor(acch_ctx *c) {
   return ACCH_OK;
 }
 
-// Solve J S = -F (S from 0).  Returns ACCH_OK when converged, ACCH_EDIVERGED if not.
-int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid) {
+int precondition_t(acch_ctx *c, const double *r, double *z, const GmresState *st, long vs) {
+  LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_t_apply2d(c->geo.G, c->d_subs, c->P.nx, c->P.ny, c->P.periodic, c->p.sub[0],
+                                                   c->p.sub[1], c->d_own, c->d_own + c->P.nx, c->fac, c->tbox, r, z,
+                                                   st, vs, c->p.precision == ACCH_PREC_MIXED, c->stream));
+  return ACCH_OK;
+}
+
+// Solve J S = -F (J^T S = -F when transpose) with S from 0.  Returns ACCH_OK when
+// converged, ACCH_EDIVERGED if not.  The transposed solve is preconditioned by the
+// transposed Schwarz operator and never projects the mass.
+int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int transpose = 0) {
   const long n2 = 2 * c->geo.ncell;
   const long vs = n2;
   const int m = c->p.gmres_restart;
   const int fp32 = c->p.precision == ACCH_PREC_MIXED;
-  const int project = c->p.mass_projection;
+  const int project = transpose ? 0 : c->p.mass_projection;
   LAUNCH(c, launch_reset_state(c->st, c->stream));
   its = 0;
   resid = 0.0;
   const size_t tail = offsetof(GmresState, beta);
   GmresState hs{};
   for (int cycle = 0; cycle < c->p.gmres_max_restarts; ++cycle) {
-    if (cycle > 0) LAUNCHK(c, ACCH_KERNEL_SPMV, launch_spmv2d(c->P, c->J, S, c->W, c->stream));
+    if (cycle > 0) LAUNCHK(c, ACCH_KERNEL_SPMV, launch_spmv2d(c->P, c->J, S, c->W, transpose, c->stream));
     LAUNCHK(c, ACCH_KERNEL_GMRES_START, launch_gmres_start(n2, F, cycle > 0 ? c->W : nullptr, c->V, c->st, m, c->p.gmres_rtol,
                                  c->p.gmres_atol, c->red, c->stream));
     int launched = 0;
     int chunk = cycle == 0 ? std::max(1, std::min(m, c->its_guess)) : std::max(1, m / 2);
     while (true) {
       for (int k = 0; k < chunk && launched < m; ++k, ++launched) {
-        LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->fac, c->ybuf,
-                                     c->V, c->Z, c->dump, c->st, vs, fp32, c->stream));
-        LAUNCHK(c, ACCH_KERNEL_SPMV_DOTS, launch_spmv_dots2d(c->P, c->J, c->Z, c->V, vs, c->st, c->red, c->stream));
-        LAUNCHK(c, ACCH_KERNEL_ORTH, launch_gmres_orth(n2, c->V, vs, c->st, c->red, c->stream));
+        if (transpose) {
+          int rc = precondition_t(c, c->V, c->Z, c->st, vs);
+          if (rc) return rc;
+        } else {
+          LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic,
+                                                         c->fac, c->ybuf, c->V, c->Z, c->dump, c->st, vs, fp32,
+                                                         c->stream));
+        }
+        LAUNCHK(c, ACCH_KERNEL_SPMV_DOTS,
+                launch_spmv_dots2d(c->P, c->J, c->Z, c->V, vs, launched, transpose, c->st, c->red, c->stream));
+        LAUNCHK(c, ACCH_KERNEL_ORTH, launch_gmres_orth(n2, c->V, vs, launched, c->st, c->red, c->stream));
       }
       LAUNCHK(c, ACCH_KERNEL_GMRES_UPDATE, launch_gmres_update(c->geo.ncell, S, c->Z, vs, c->st, cycle > 0, project, c->red, c->stream));
       int rc = sync_read(c, (const char *)c->st + tail, c->host_state, sizeof(GmresState) - tail);
@@ -533,8 +560,10 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->fac = c->ws + L.off_fac;
   c->ybuf = c->ws + L.off_y;
   c->dump = (double *)(c->ws + L.off_dump);
+  c->tbox = (double *)(c->ws + L.off_tbox);
   c->d_subs = (SubInfo *)(c->ws + L.off_subs);
   c->d_lvl = (int *)(c->ws + L.off_lvl);
+  c->d_own = (int *)(c->ws + L.off_own);
   c->st = (GmresState *)(c->ws + L.off_state);
   c->red.partials = (double *)(c->ws + L.off_part);
   c->red.counter = (unsigned *)(c->ws + L.off_cnt);
@@ -569,6 +598,8 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
       hipMemcpyAsync(c->d_subs, c->geo.subs.data(), c->geo.subs.size() * sizeof(SubInfo), hipMemcpyHostToDevice,
                      c->stream) != hipSuccess ||
       hipMemcpyAsync(c->d_lvl, c->geo.lvl.data(), c->geo.lvl.size() * sizeof(int), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->d_own, c->geo.own.data(), c->geo.own.size() * sizeof(int), hipMemcpyHostToDevice,
                      c->stream) != hipSuccess ||
       hipMemsetAsync(c->red.counter, 0, 64, c->stream) != hipSuccess ||
       hipMemsetAsync(c->st, 0, sizeof(GmresState), c->stream) != hipSuccess ||
@@ -777,8 +808,64 @@ extern "C" int acch_jacobian(acch_ctx *c, const double *X, const double *Xn, dou
 
 extern "C" int acch_apply_jacobian(acch_ctx *c, const double *x, double *y) {
   if (!c || !x || !y) return fail(ACCH_EINVAL, "bad arguments");
-  LAUNCH(c, launch_spmv2d(c->P, c->J, x, y, c->stream));
+  LAUNCH(c, launch_spmv2d(c->P, c->J, x, y, 0, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  return ACCH_OK;
+}
+
+extern "C" int acch_apply_jacobian_transpose(acch_ctx *c, const double *x, double *y) {
+  if (!c || !x || !y) return fail(ACCH_EINVAL, "bad arguments");
+  LAUNCHK(c, ACCH_KERNEL_SPMV, launch_spmv2d(c->P, c->J, x, y, 1, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return ACCH_OK;
+}
+
+static int adjoint_ready(acch_ctx *c) {
+  if (c->p.overlap > c->geo.min_part)
+    return fail(ACCH_EUNSUPPORTED, "transposed Schwarz operator needs overlap <= the smallest subdomain width");
+  return ACCH_OK;
+}
+
+extern "C" int acch_precondition_transpose(acch_ctx *c, const double *r, double *z) {
+  if (!c || !r || !z) return fail(ACCH_EINVAL, "bad arguments");
+  if (!c->factored) return fail(ACCH_EINVAL, "no factorisation: call acch_factor first");
+  int rc = adjoint_ready(c);
+  if (rc) return rc;
+  rc = precondition_t(c, r, z, nullptr, 0);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return ACCH_OK;
+}
+
+extern "C" int acch_energy_gradient(acch_ctx *c, const double *X, double *g, double *dparams) {
+  if (!c || !g || !dparams) return fail(ACCH_EINVAL, "bad arguments");
+  LAUNCHK(c, ACCH_KERNEL_ENERGY, launch_energy_grad2d(c->P, X ? X : c->Xn, c->hvol, g, c->red, c->stream));
+  int rc = sync_read(c, c->red.out, c->host->vals, 4 * sizeof(double));
+  if (rc) return rc;
+  for (int k = 0; k < 4; ++k) dparams[k] = c->host->vals[k];
+  return ACCH_OK;
+}
+
+extern "C" int acch_adjoint_step(acch_ctx *c, const double *X1, const double *X0, double dt, const double *g,
+                                 double *g_prev, double *dparams, int *gmres_its, double *resid) {
+  if (!c || !X1 || !X0 || !g || !g_prev || !dparams) return fail(ACCH_EINVAL, "bad arguments");
+  if (!(dt > 0.0)) return fail(ACCH_EINVAL, "dt must be positive");
+  int rc = adjoint_ready(c);
+  if (rc) return rc;
+  LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->P, X1, X0, dt, c->J, c->stream));
+  rc = factor(c);
+  if (rc) return rc;
+  int its = 0;
+  double res = 0.0;
+  rc = gmres(c, g, c->S, its, res, 1);   // J^T S = -g: S = -lambda
+  if (gmres_its) *gmres_its = its;
+  if (resid) *resid = res;
+  if (rc) return rc;
+  // g_prev = (dF/dX0)^T S and red.out = S . dF/dp, i.e. -lambda . dF/dp
+  LAUNCH(c, launch_adjoint_prev2d(c->P, X1, X0, dt, c->S, 1.0, c->W, g_prev, c->red, c->stream));
+  rc = sync_read(c, c->red.out, c->host->vals, 4 * sizeof(double));
+  if (rc) return rc;
+  for (int k = 0; k < 4; ++k) dparams[k] += c->host->vals[k];
   return ACCH_OK;
 }
 

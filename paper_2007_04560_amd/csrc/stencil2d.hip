@@ -15,18 +15,6 @@ constexpr int TX = 32, TY = 8;             // output tile, one cell per thread
 constexpr int LX2 = TX + 4, LY2 = TY + 4;  // fields with halo 2
 constexpr int LX1 = TX + 2, LY1 = TY + 2;  // cell quantities with halo 1
 
-// Periodic wrap, or clamping (the Neumann ghost copies the boundary cell, which
-// makes every boundary difference vanish, as in Section 2).  Offsets are within
-// +-2 of the domain and periodic grids have at least 5 cells.
-ACCH_DEV int wrap_index(int g, int n, int periodic) {
-  if (periodic) return g < 0 ? g + n : (g >= n ? g - n : g);
-  return g < 0 ? 0 : (g >= n ? n - 1 : g);
-}
-
-ACCH_DEV bool face_exists(int g, int dir, int n, int periodic) {
-  return periodic || (dir < 0 ? g > 0 : g < n - 1);
-}
-
 // Load the four fields of a tile with a 2-cell halo.  With Sdir the unknown state is
 // the line-search trial X + lam (S - shift e_u).
 ACCH_DEV void load_tile(const Phys &P, const double *__restrict__ X, const double *__restrict__ Sdir,
@@ -280,44 +268,105 @@ ACCH_DEV void spmv_cell(const Phys &P, const double *__restrict__ J, const doubl
   yv = b;
 }
 
+// y = J^T x for the 24-slot layout: the entry of slot k (column offset o_k) of row
+// r = c - o_k lands in column c.  Rows outside a Neumann domain do not exist; slots
+// that point outside it are zero, so the two descriptions agree.
+ACCH_DEV void spmv_t_cell(const Phys &P, const double *__restrict__ J, const double *__restrict__ x, long n,
+                          int gx, int gy, double &yu, double &yv) {
+  const double *xu = x, *xv = x + n;
+  auto row = [&](int dx, int dy, long &r) -> bool {
+    const int rx = gx + dx, ry = gy + dy;
+    r = (long)wrap_index(ry, P.ny, P.periodic) * P.nx + wrap_index(rx, P.nx, P.periodic);
+    return P.periodic || (rx >= 0 && rx < P.nx && ry >= 0 && ry < P.ny);
+  };
+  auto term = [&](int slot, int dx, int dy, const double *xf) -> double {
+    long r;
+    const bool ok = row(dx, dy, r);
+    const double a = J[(long)slot * n + r] * xf[r];
+    return ok ? a : 0.0;
+  };
+  double a = term(0, 0, 0, xu);
+  a += term(1, 1, 0, xu);
+  a += term(2, -1, 0, xu);
+  a += term(3, 0, 1, xu);
+  a += term(4, 0, -1, xu);
+  a += term(5, 2, 0, xu);
+  a += term(6, -2, 0, xu);
+  a += term(7, 0, 2, xu);
+  a += term(8, 0, -2, xu);
+  a += term(9, 1, 1, xu);
+  a += term(10, -1, 1, xu);
+  a += term(11, 1, -1, xu);
+  a += term(12, -1, -1, xu);
+  a += term(23, 0, 0, xv);
+  double b = term(13, 0, 0, xu);
+  b += term(14, 1, 0, xu);
+  b += term(15, -1, 0, xu);
+  b += term(16, 0, 1, xu);
+  b += term(17, 0, -1, xu);
+  b += term(18, 0, 0, xv);
+  b += term(19, 1, 0, xv);
+  b += term(20, -1, 0, xv);
+  b += term(21, 0, 1, xv);
+  b += term(22, 0, -1, xv);
+  yu = a;
+  yv = b;
+}
+
+template <bool TR>
+ACCH_DEV void matvec_cell(const Phys &P, const double *__restrict__ J, const double *__restrict__ x, long n, int gx,
+                          int gy, double &yu, double &yv) {
+  if constexpr (TR) spmv_t_cell(P, J, x, n, gx, gy, yu, yv);
+  else spmv_cell(P, J, x, n, gx, gy, yu, yv);
+}
+
+// y = J x (TR = false) or J^T x (TR = true).
+template <bool TR>
 __global__ __launch_bounds__(256) void k_spmv2d(Phys P, const double *__restrict__ J, const double *__restrict__ x,
                                                  double *__restrict__ y) {
   const long n = (long)P.nx * P.ny;
   for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
     const int gy = (int)(g / P.nx), gx = (int)(g - (long)gy * P.nx);
     double yu, yv;
-    spmv_cell(P, J, x, n, gx, gy, yu, yv);
+    matvec_cell<TR>(P, J, x, n, gx, gy, yu, yv);
     y[g] = yu;
     y[n + g] = yv;
   }
 }
 
-// w = J z_j (written to the Arnoldi slot j+1), fused with the classical Gram–Schmidt
-// dots h_ij = inv_norm_i <w, W_i>, i <= j.  Skipped when the cycle is finished.
-__global__ __launch_bounds__(256) void k_spmv_dots2d(Phys P, const double *__restrict__ J,
+// w = J z_j (J^T z_j when TR) written to the Arnoldi slot j+1, fused with the
+// classical Gram–Schmidt dots h_ij = inv_norm_i <w, W_i>, i <= j.  One instantiation
+// per Arnoldi step j (the host knows j: a cycle's steps are enqueued in order), so
+// every basis load of a cell is issued before the first is used.  Skipped when the
+// cycle is finished.
+template <int J, bool TR>
+__global__ __launch_bounds__(256) void k_spmv_dots2d(Phys P, const double *__restrict__ Jm,
                                                       const double *__restrict__ Z, double *__restrict__ V,
                                                       long vstride, GmresState *st, RedBuf red) {
   if (st->done) return;
-  const int j = st->j;
+  constexpr int NV = pow2_at_least(J + 1);
   const long n = (long)P.nx * P.ny;
-  const double *z = Z + (long)j * vstride;
-  double *w = V + (long)(j + 1) * vstride;
-  constexpr int NV = 32;   // kMaxRestart + 1 dots, padded to a power of two
-  static_assert(kMaxRestart + 1 <= NV, "dot count");
+  const double *z = Z + (long)J * vstride;
+  double *w = V + (long)(J + 1) * vstride;
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
   for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
     const int gy = (int)(g / P.nx), gx = (int)(g - (long)gy * P.nx);
+    double bu[J + 1], bv[J + 1];
+#pragma unroll
+    for (int i = 0; i <= J; ++i) {
+      bu[i] = V[(long)i * vstride + g];
+      bv[i] = V[(long)i * vstride + n + g];
+    }
     double yu, yv;
-    spmv_cell(P, J, z, n, gx, gy, yu, yv);
+    matvec_cell<TR>(P, Jm, z, n, gx, gy, yu, yv);
     w[g] = yu;
     w[n + g] = yv;
 #pragma unroll
-    for (int i = 0; i <= kMaxRestart; ++i)
-      if (i <= j) acc[i] = fma(yu, V[(long)i * vstride + g], fma(yv, V[(long)i * vstride + n + g], acc[i]));
+    for (int i = 0; i <= J; ++i) acc[i] = fma(yu, bu[i], fma(yv, bv[i], acc[i]));
   }
-  block_partial_multi<NV>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x, j + 1);
+  block_partial_multi<NV>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x, J + 1);
 }
 
 }  // namespace
@@ -358,19 +407,35 @@ hipError_t launch_jacobian2d(const Phys &P, const double *X, const double *Xn, d
   return hipGetLastError();
 }
 
-hipError_t launch_spmv2d(const Phys &P, const double *J, const double *x, double *y, hipStream_t s) {
+hipError_t launch_spmv2d(const Phys &P, const double *J, const double *x, double *y, int transpose, hipStream_t s) {
   const long n = (long)P.nx * P.ny;
-  hipLaunchKernelGGL(k_spmv2d, dim3((int)((n + 255) / 256)), dim3(256), 0, s, P, J, x, y);
+  const dim3 grid((int)((n + 255) / 256));
+  if (transpose)
+    hipLaunchKernelGGL(k_spmv2d<true>, grid, dim3(256), 0, s, P, J, x, y);
+  else
+    hipLaunchKernelGGL(k_spmv2d<false>, grid, dim3(256), 0, s, P, J, x, y);
   return hipGetLastError();
 }
 
-hipError_t launch_spmv_dots2d(const Phys &P, const double *J, const double *Z, double *V, long vstride,
-                              GmresState *st, const RedBuf &red, hipStream_t s) {
+template <int J, bool TR>
+static hipError_t spmv_dots_at(int j, const Phys &P, const double *Jm, const double *Z, double *V, long vstride,
+                               GmresState *st, const RedBuf &red, int nb, hipStream_t s) {
+  if (j == J) {
+    hipLaunchKernelGGL((k_spmv_dots2d<J, TR>), dim3(nb), dim3(256), 0, s, P, Jm, Z, V, vstride, st, red);
+    return hipGetLastError();
+  }
+  if constexpr (J + 1 < kMaxRestart) return spmv_dots_at<J + 1, TR>(j, P, Jm, Z, V, vstride, st, red, nb, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_spmv_dots2d(const Phys &P, const double *J, const double *Z, double *V, long vstride, int j,
+                              int transpose, GmresState *st, const RedBuf &red, hipStream_t s) {
+  if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
   const int nb = reduce_blocks((long)P.nx * P.ny);
-  hipLaunchKernelGGL(k_spmv_dots2d, dim3(nb), dim3(256), 0, s, P, J, Z, V, vstride, st, red);
-  hipError_t e = hipGetLastError();
+  hipError_t e = transpose ? spmv_dots_at<0, true>(j, P, J, Z, V, vstride, st, red, nb, s)
+                           : spmv_dots_at<0, false>(j, P, J, Z, V, vstride, st, red, nb, s);
   if (e != hipSuccess) return e;
-  return launch_finalize(kFinDots, kMaxRestart + 1, red, nb, st, FinalizeArgs{}, s);
+  return launch_finalize_dots(j, red, nb, st, s);
 }
 
 }  // namespace acch
