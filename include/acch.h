@@ -240,6 +240,46 @@ int acch_energy_gradient(acch_ctx *c, const double *X, double *g, double *dparam
 int acch_adjoint_step(acch_ctx *c, const double *X1, const double *X0, double dt, const double *g, double *g_prev,
                       double *dparams, int *gmres_its, double *resid);
 
+/* ---- Batches of independent instances ----------------------------------------
+ * count instances, each described by its own acch_params (grid, boundary,
+ * parameters, subdomains), advanced together at the common fixed dt of instance 0
+ * (adaptive must be 0; overlap, precision and dt_fixed must agree).  Every kernel of
+ * a Newton-Krylov-Schwarz stage runs once for all instances: all subdomain
+ * factorisations and triangular solves of all instances in one launch each; Newton
+ * iterations, line searches and GMRES cycles run in lockstep with per-instance
+ * masks, so every instance follows the operation sequence of its own
+ * single-instance run.  The Arnoldi steps of a GMRES cycle are recorded once into
+ * HIP graphs and replayed (ACCH_BATCH_OPT_GRAPH, default on; the stream of
+ * instance 0 must then be a created stream, not the null stream).  Instance 0 also
+ * supplies the tolerances, restart limits, ilu_shift, mass projection, workspace
+ * (acch_batch_workspace_bytes) and stream. */
+typedef struct acch_batch acch_batch;
+enum { ACCH_BATCH_OPT_GRAPH = 0 };
+
+int acch_batch_workspace_bytes(const acch_params *inst, int count, size_t *bytes);
+
+/* u0[i], v0[i]: host arrays of instance i's ncell doubles (x fastest), copied. */
+int acch_batch_create(const acch_params *inst, int count, const double *const *u0, const double *const *v0,
+                      acch_batch **out);
+
+/* nsteps fixed-dt steps of every instance; newton_its / gmres_its (host arrays of
+ * count ints, may be NULL) are incremented per instance.  If any instance fails
+ * the call returns ACCH_EDIVERGED and no instance advances in that step. */
+int acch_batch_step(acch_batch *b, int nsteps, int *newton_its, int *gmres_its);
+
+/* Discrete energy and mass of every instance (host arrays of count doubles). */
+int acch_batch_energy(acch_batch *b, double *energy, double *mass);
+
+/* Copy instance i's state to host arrays of its ncell doubles each. */
+int acch_batch_get_fields(acch_batch *b, int i, double *u, double *v);
+
+int acch_batch_set_option(acch_batch *b, int option, long value);
+
+/* Kernel launches, graph launches and host synchronisations so far. */
+int acch_batch_counters(acch_batch *b, long *launches, long *graph_launches, long *syncs);
+
+int acch_batch_destroy(acch_batch *b);
+
 const char *acch_strerror(int code);
 const char *acch_last_error(void);
 

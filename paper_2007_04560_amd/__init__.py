@@ -3,7 +3,8 @@
 The per-time-step Newton–Krylov–Schwarz solve of scheme (2.20) runs in the HIP
 library libacch.so (include/acch.h); this package only builds and binds it.
 """
-from .binding import (AcchError, Params, Solver, StepInfo, load_library, make_params,  # noqa: F401
+from .binding import (AcchError, BatchSolver, Params, Solver, StepInfo, load_library, make_params,  # noqa: F401
                       LIB_PATH, EXPORTED)
 
-__all__ = ["AcchError", "Params", "Solver", "StepInfo", "load_library", "make_params", "LIB_PATH", "EXPORTED"]
+__all__ = ["AcchError", "BatchSolver", "Params", "Solver", "StepInfo", "load_library", "make_params", "LIB_PATH",
+           "EXPORTED"]

@@ -25,6 +25,8 @@ EXPORTED = [
     "acch_solve_step", "acch_export", "acch_info", "acch_strerror", "acch_last_error",
     "acch_timing", "acch_kernel_stats", "acch_counters", "acch_set_option",
     "acch_apply_jacobian_transpose", "acch_precondition_transpose", "acch_energy_gradient", "acch_adjoint_step",
+    "acch_batch_workspace_bytes", "acch_batch_create", "acch_batch_step", "acch_batch_energy",
+    "acch_batch_get_fields", "acch_batch_set_option", "acch_batch_counters", "acch_batch_destroy",
 ]
 KERNEL_KINDS = ["residual", "jacobian", "factor", "ras", "spmv_dots", "orth", "gmres_start", "gmres_update",
                 "energy", "spmv", "other"]
@@ -109,6 +111,15 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "acch_precondition_transpose": (ctypes.c_int, [ctx, vp, vp]),
         "acch_energy_gradient": (ctypes.c_int, [ctx, vp, vp, dp]),
         "acch_adjoint_step": (ctypes.c_int, [ctx, vp, vp, ctypes.c_double, vp, vp, dp, ip, dp]),
+        "acch_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(sz)]),
+        "acch_batch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int, vp, vp, ctypes.POINTER(ctx)]),
+        "acch_batch_step": (ctypes.c_int, [ctx, ctypes.c_int, ip, ip]),
+        "acch_batch_energy": (ctypes.c_int, [ctx, dp, dp]),
+        "acch_batch_get_fields": (ctypes.c_int, [ctx, ctypes.c_int, vp, vp]),
+        "acch_batch_set_option": (ctypes.c_int, [ctx, ctypes.c_int, ctypes.c_long]),
+        "acch_batch_counters": (ctypes.c_int, [ctx, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long),
+                                               ctypes.POINTER(ctypes.c_long)]),
+        "acch_batch_destroy": (ctypes.c_int, [ctx]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -360,3 +371,95 @@ class Solver:
 
     def export_boxes(self):
         return self._export(EXPORT_BOXES, np.int32).reshape(-1, 4)
+
+
+class BatchSolver:
+    """Many independent instances advanced together by acch_batch_* (one launch per
+    stage for all instances).  ``fields`` is a list of (u0, v0) host arrays, ``params``
+    a list of per-instance keyword dicts for make_params (bc, L, alpha, ..., sub);
+    ``common`` holds the settings shared by the batch (dt_fixed, tolerances,
+    precision, overlap, ilu_shift ...).  The batch runs on its own created stream so
+    that its GMRES cycles can be recorded into HIP graphs."""
+
+    def __init__(self, fields, params=None, device=None, graph: bool = True, **common):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("acch needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.lib = load_library()
+        self.torch = torch
+        self.count = len(fields)
+        params = params or [{} for _ in fields]
+        if len(params) != self.count:
+            raise ValueError("one parameter dict per instance")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._u = [np.ascontiguousarray(u, dtype=np.float64) for u, _ in fields]
+        self._v = [np.ascontiguousarray(v, dtype=np.float64) for _, v in fields]
+        self.shapes = [u.shape for u in self._u]
+        arr = (Params * self.count)()
+        for i in range(self.count):
+            kw = dict(common)
+            kw.update(params[i])
+            arr[i] = make_params(self.shapes[i], **kw)
+        self.params = arr
+        nbytes = ctypes.c_size_t(0)
+        _check(self.lib, self.lib.acch_batch_workspace_bytes(arr, self.count, ctypes.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.device(self.device):
+            self._ws_raw = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.Stream(device=self.device)
+        base = self._ws_raw.data_ptr()
+        arr[0].workspace = (base + 255) // 256 * 256
+        arr[0].workspace_bytes = self.workspace_bytes
+        arr[0].stream = self.stream.cuda_stream
+        pu = (ctypes.c_void_p * self.count)(*[u.ctypes.data for u in self._u])
+        pv = (ctypes.c_void_p * self.count)(*[v.ctypes.data for v in self._v])
+        self.ctx = ctypes.c_void_p()
+        # the workspace tensor was made on the current stream: finish before the batch stream uses it
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(self.lib, self.lib.acch_batch_create(arr, self.count, pu, pv, ctypes.byref(self.ctx)))
+        if not graph:
+            self.set_graph(False)
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            self.lib.acch_batch_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_graph(self, enable: bool):
+        _check(self.lib, self.lib.acch_batch_set_option(self.ctx, 0, int(bool(enable))))
+
+    def step(self, nsteps: int = 1):
+        """Returns per-instance Newton and GMRES iteration counts of these steps."""
+        nit = (ctypes.c_int * self.count)()
+        git = (ctypes.c_int * self.count)()
+        _check(self.lib, self.lib.acch_batch_step(self.ctx, nsteps, nit, git))
+        return np.array(nit[:]), np.array(git[:])
+
+    def energy(self):
+        e = (ctypes.c_double * self.count)()
+        m = (ctypes.c_double * self.count)()
+        _check(self.lib, self.lib.acch_batch_energy(self.ctx, e, m))
+        return np.array(e[:]), np.array(m[:])
+
+    def fields(self, i: int):
+        u = np.empty(self.shapes[i])
+        v = np.empty(self.shapes[i])
+        _check(self.lib, self.lib.acch_batch_get_fields(self.ctx, i, u.ctypes.data, v.ctypes.data))
+        return u, v
+
+    def counters(self):
+        a, g, s = ctypes.c_long(), ctypes.c_long(), ctypes.c_long()
+        _check(self.lib, self.lib.acch_batch_counters(self.ctx, ctypes.byref(a), ctypes.byref(g), ctypes.byref(s)))
+        return {"launches": a.value, "graph_launches": g.value, "syncs": s.value}

@@ -347,7 +347,7 @@ hipError_t launch_adjoint_prev2d(const Phys &P, const double *X1, const double *
                      red);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_finalize(kFinPlain, 4, red, nb, nullptr, FinalizeArgs{}, s);
+  e = launch_finalize(kFinPlain, 4, red, single_launch(P, 0), kFamCell, nullptr, FinalizeArgs{}, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_adjoint_prev_b2d, dim3(nb), dim3(256), 0, s, P, bar, out);
   return hipGetLastError();
@@ -359,7 +359,7 @@ hipError_t launch_energy_grad2d(const Phys &P, const double *X, double vol, doub
   hipLaunchKernelGGL(k_energy_grad2d, dim3(nb), dim3(256), 0, s, P, X, vol, g, red);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_finalize(kFinPlain, 4, red, nb, nullptr, FinalizeArgs{}, s);
+  return launch_finalize(kFinPlain, 4, red, single_launch(P, 0), kFamCell, nullptr, FinalizeArgs{}, s);
 }
 
 }  // namespace acch

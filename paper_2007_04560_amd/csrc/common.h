@@ -63,7 +63,29 @@ struct GmresState {
   int done;               // cycle finished (converged, breakdown or j == m)
   int converged;
   int total_its;
-  int pad[3];
+  int first;              // the next cycle is the first of a solve (fixes tol)
+  int applied;            // this cycle's update has been added to S
+  int pad;
+};
+
+// ---- batches of independent instances ---------------------------------------
+// Kernels are launched over "families" of blocks; in a batch every block belongs to
+// one instance, found through a per-family map (global block -> instance, local
+// block).  A null map means a single instance whose blocks are the whole grid.
+enum { kFamTile = 0, kFamCell = 1, kFamElem = 2, kFamSub = 3, kFamilies = 4 };
+
+struct Inst {
+  Phys P;
+  long xoff;              // first element of the instance in a batched state vector (2 n)
+  long joff;              // first element of its Jacobian block (24 n)
+  int blk0[kFamilies];    // first global block of each family
+  int nblk[kFamilies];    // blocks of each family
+};
+
+struct Batch {
+  const Inst *inst;
+  const int2 *map[kFamilies];
+  const int *active;      // per-instance mask (null: all active)
 };
 
 // Small pinned-host mirror of the values the host control flow reads.
@@ -192,18 +214,44 @@ ACCH_DEV void block_partial_multi(double (&v)[NV], double *partials, int tid, in
   if (tid < nv_used) partials[tid * nblocks + bid] = a;
 }
 
-// Sum of the partials of the first nv_used values; valid in thread 0.
+// Sum of the partials of blocks [b0, b0 + nb) of the first nv_used values, the
+// partials of value k being stored at k * stride + block; valid in thread 0.
 template <int NV>
-ACCH_DEV void final_sum(const double *partials, int nblocks, int tid, int nthreads, double (&acc)[NV],
-                        int nv_used = NV) {
+ACCH_DEV void final_sum(const double *partials, int stride, int b0, int nb, int tid, int nthreads,
+                        double (&acc)[NV], int nv_used = NV) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double a = 0.0;
     if (k < nv_used)
-      for (int b = tid; b < nblocks; b += nthreads) a += partials[k * nblocks + b];
+      for (int b = tid; b < nb; b += nthreads) a += partials[(long)k * stride + b0 + b];
     acc[k] = a;
   }
   block_sum<NV>(acc, tid, nthreads);
+}
+
+// Where a block of a (possibly batched) launch works.
+struct Loc {
+  int b;      // instance
+  int lb;     // block index within the instance
+  int nb;     // blocks of the instance
+  bool on;    // instance active
+};
+
+ACCH_DEV Loc locate(const Batch &bt, int fam) {
+  Loc L;
+  if (bt.map[fam] == nullptr) {
+    L.b = 0;
+    L.lb = blockIdx.x;
+    L.nb = gridDim.x;
+    L.on = true;
+    return L;
+  }
+  const int2 m = bt.map[fam][blockIdx.x];
+  L.b = m.x;
+  L.lb = m.y;
+  L.nb = bt.inst[m.x].nblk[fam];
+  L.on = bt.active == nullptr || bt.active[m.x] != 0;
+  return L;
 }
 
 }  // namespace acch

@@ -7,50 +7,72 @@ namespace acch {
 
 int reduce_blocks(long n);
 
-// Second stage of the two-kernel reductions (krylov.hip).
+// A launch over one instance (null maps in bt) or over a whole batch.
+struct BatchLaunch {
+  Phys P0;               // the instance of a single-instance launch
+  Batch bt;              // device description (maps null for one instance)
+  int grid[kFamilies];   // blocks of each family over the launch
+  int count;             // instances
+  long ncell;            // cells of a single instance
+};
+BatchLaunch single_launch(const Phys &P, int nsub);
+// Blocks of each family for one instance (tiles, cells, elements, subdomains).
+void family_blocks(const Phys &P, int nsub, int (&nb)[kFamilies]);
+
+// Second stage of the two-kernel reductions (krylov.hip): one block per instance,
+// out[4 b + k] for kFinPlain.
 enum { kFinPlain = 0, kFinStart = 1, kFinDots = 2, kFinOrth = 3, kFinUpdate = 4 };
 struct FinalizeArgs {
-  int first, m, project;
+  int m, project;
   double rtol, atol;
   long ncell;
 };
-hipError_t launch_finalize(int mode, int nv, const RedBuf &red, int nblocks, GmresState *st, const FinalizeArgs &fa,
-                           hipStream_t s);
+hipError_t launch_finalize(int mode, int nv, const RedBuf &red, const BatchLaunch &bl, int fam, GmresState *st,
+                           const FinalizeArgs &fa, hipStream_t s);
 // second stage of the Arnoldi dots of step j (0 <= j < kMaxRestart)
-hipError_t launch_finalize_dots(int j, const RedBuf &red, int nblocks, GmresState *st, hipStream_t s);
+hipError_t launch_finalize_dots(int j, const RedBuf &red, const BatchLaunch &bl, GmresState *st, hipStream_t s);
 int schwarz_waves(const BoxGeom &G);
 void set_ras_prefetch(int d);
 int get_ras_prefetch();
 
-// stencil2d.hip
-hipError_t launch_residual2d(const Phys &P, const double *X, const double *Sdir, double lam, const double *shift,
-                             const double *Xn, double dt, double *Xt, double *F, const RedBuf &red, hipStream_t s);
-hipError_t launch_energy2d(const Phys &P, const double *X, const RedBuf &red, hipStream_t s);
-hipError_t launch_jacobian2d(const Phys &P, const double *X, const double *Xn, double dt, double *J, hipStream_t s);
+// stencil2d.hip.  lam_b (per instance, may be null: lam0) and shift_st (the mass
+// shift of each instance's GMRES state, may be null) describe the trial state.
+hipError_t launch_residual2d(const BatchLaunch &bl, const double *X, const double *Sdir, double lam0,
+                             const double *lam_b, const GmresState *shift_st, const double *Xn, double dt, double *Xt,
+                             double *F, const RedBuf &red, hipStream_t s);
+hipError_t launch_energy2d(const BatchLaunch &bl, const double *X, const RedBuf &red, hipStream_t s);
+hipError_t launch_jacobian2d(const BatchLaunch &bl, const double *X, const double *Xn, double dt, double *J,
+                             hipStream_t s);
 // y = J x, or J^T x when transpose
-hipError_t launch_spmv2d(const Phys &P, const double *J, const double *x, double *y, int transpose, hipStream_t s);
+hipError_t launch_spmv2d(const BatchLaunch &bl, const double *J, const double *x, double *y, int transpose,
+                         hipStream_t s);
 // Arnoldi step j of the cycle (the device state's j must equal it unless the cycle is done)
-hipError_t launch_spmv_dots2d(const Phys &P, const double *J, const double *Z, double *V, long vstride, int j,
+hipError_t launch_spmv_dots2d(const BatchLaunch &bl, const double *J, const double *Z, double *V, long vstride, int j,
                               int transpose, GmresState *st, const RedBuf &red, hipStream_t s);
 
-// schwarz2d.hip
-hipError_t launch_ilu_factor2d(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
+// schwarz2d.hip (subs: every subdomain of the launch, in block order)
+hipError_t launch_ilu_factor2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
                                const double *J, double shift, void *fac, int fp32, hipStream_t s);
-hipError_t launch_ras_apply2d(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
+hipError_t launch_ras_apply2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
                               const void *fac, void *ybuf, const double *r, double *z, double *dump,
                               const GmresState *st, long vstride, int fp32, hipStream_t s);
 hipError_t launch_export_factors2d(const BoxGeom &G, const int *lvl, const void *fac, int fp32, double *out,
                                    hipStream_t s);
 
 // krylov.hip
-hipError_t launch_gmres_start(long n2, const double *F, const double *JS, double *V0, GmresState *st, int m,
-                              double rtol, double atol, const RedBuf &red, hipStream_t s);
-hipError_t launch_gmres_orth(long n2, double *V, long vstride, int j, GmresState *st, const RedBuf &red,
+hipError_t launch_gmres_start(const BatchLaunch &bl, const double *F, const double *JS, double *V0, GmresState *st,
+                              int m, double rtol, double atol, const RedBuf &red, hipStream_t s);
+hipError_t launch_gmres_orth(const BatchLaunch &bl, double *V, long vstride, int j, GmresState *st,
+                             const RedBuf &red, hipStream_t s);
+hipError_t launch_gmres_update(const BatchLaunch &bl, double *S, const double *Z, long vstride, GmresState *st,
+                               int accumulate, int project, const RedBuf &red, hipStream_t s);
+hipError_t launch_norm2_diff(const BatchLaunch &bl, const double *a, const double *b, const RedBuf &red,
                              hipStream_t s);
-hipError_t launch_gmres_update(long ncell, double *S, const double *Z, long vstride, GmresState *st, int accumulate,
-                               int project, const RedBuf &red, hipStream_t s);
-hipError_t launch_norm2_diff(long n2, const double *a, const double *b, const RedBuf &red, hipStream_t s);
-hipError_t launch_reset_state(GmresState *st, hipStream_t s);
+hipError_t launch_reset_state(const BatchLaunch &bl, GmresState *st, hipStream_t s);
+// d1 = s1 (d1 = 0 when s1 is null) and d2 = s2 (if d2) on the active instances; a
+// kernel, so it may be part of a captured graph.
+hipError_t launch_copy2(const BatchLaunch &bl, double *d1, const double *s1, double *d2, const double *s2,
+                        hipStream_t s);
 
 // adjoint2d.hip
 // z = M^{-T} r (the transposed left-restricted Schwarz operator with the current

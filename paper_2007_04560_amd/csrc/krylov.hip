@@ -4,7 +4,9 @@
 // preconditioned vectors z_j = M^{-1} v_j are kept (flexible variant), which makes
 // x = Z y valid also for the single-precision preconditioner.  Every kernel of an
 // Arnoldi step returns at once when the cycle is finished, so the host may enqueue
-// several steps ahead of its convergence check.
+// several steps ahead of its convergence check.  Every kernel also runs batched: a
+// block finds its instance through the launch family's map (common.h), and the
+// one-block second stages run one block per instance.
 #include <math.h>
 
 #include "kernels.h"
@@ -12,15 +14,37 @@
 namespace acch {
 namespace {
 
-// V_0 = -(F + J S) (J S computed by the caller into JS, or absent on the first
-// cycle) and beta = ||V_0||; the last block starts the cycle.
-// On the first cycle the absolute tolerance becomes max(rtol * beta, atol); later
-// cycles keep it.
-__global__ __launch_bounds__(256) void k_gmres_start(long n2, const double *__restrict__ F,
+// Instance of this block in a (possibly batched) vector launch over 2n elements.
+struct ElemLoc {
+  Loc L;
+  long n2;
+  long xo;
+};
+ACCH_DEV ElemLoc elem_loc(const Batch &bt, long n2_single) {
+  ElemLoc E;
+  E.L = locate(bt, kFamElem);
+  if (bt.map[kFamElem]) {
+    const Inst &I = bt.inst[E.L.b];
+    E.n2 = 2L * I.P.nx * I.P.ny;
+    E.xo = I.xoff;
+  } else {
+    E.n2 = n2_single;
+    E.xo = 0;
+  }
+  return E;
+}
+
+// V_0 = -(F + J S) (J S computed by the caller into JS, or absent) and beta = ||V_0||.
+__global__ __launch_bounds__(256) void k_gmres_start(Batch bt, long n2s, const double *__restrict__ F,
                                                       const double *__restrict__ JS, double *__restrict__ V0,
-                                                      GmresState *st, int m, double rtol, double atol, RedBuf red) {
+                                                      RedBuf red) {
+  const ElemLoc E = elem_loc(bt, n2s);
+  if (!E.L.on) return;
+  F += E.xo;
+  V0 += E.xo;
+  if (JS) JS += E.xo;
   double acc[1] = {0.0};
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < n2; e += (long)gridDim.x * 256) {
+  for (long e = E.L.lb * 256L + threadIdx.x; e < E.n2; e += (long)E.L.nb * 256) {
     const double r = JS ? -(F[e] + JS[e]) : -F[e];
     V0[e] = r;
     acc[0] = fma(r, r, acc[0]);
@@ -28,13 +52,17 @@ __global__ __launch_bounds__(256) void k_gmres_start(long n2, const double *__re
   block_partial<1>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x);
 }
 
-ACCH_DEV void start_tail(GmresState *st, double sum, int first, int m, double rtol, double atol) {
+// Starts a cycle.  The first cycle after a reset fixes the absolute tolerance
+// max(rtol * beta, atol); later cycles keep it.
+ACCH_DEV void start_tail(GmresState *st, double sum, int m, double rtol, double atol) {
   const double beta = sqrt(sum);
   st->beta = beta;
-  if (first) st->tol = fmax(rtol * beta, atol);
+  if (st->first) st->tol = fmax(rtol * beta, atol);
+  st->first = 0;
   const double tol = st->tol;
   st->m = m;
   st->j = 0;
+  st->applied = 0;
   st->g[0] = beta;
   st->resid = beta;
   st->inv_norm[0] = beta > 0.0 ? 1.0 / beta : 0.0;
@@ -46,18 +74,22 @@ ACCH_DEV void start_tail(GmresState *st, double sum, int first, int m, double rt
 // the Givens update of the Hessenberg column and the convergence test.  One
 // instantiation per step j, like k_spmv_dots2d.
 template <int J>
-__global__ __launch_bounds__(256) void k_gmres_orth(long n2, double *__restrict__ V, long vstride, GmresState *st,
-                                                     RedBuf red) {
-  if (st->done) return;
+__global__ __launch_bounds__(256) void k_gmres_orth(Batch bt, long n2s, double *__restrict__ V, long vstride,
+                                                     GmresState *st, RedBuf red) {
+  const ElemLoc E = elem_loc(bt, n2s);
+  if (!E.L.on) return;
+  GmresState *sb = st + E.L.b;
+  if (sb->done) return;
+  V += E.xo;
   __shared__ double coef[J + 1];
-  if (threadIdx.x <= J) coef[threadIdx.x] = st->hcol[threadIdx.x] * st->inv_norm[threadIdx.x];
+  if (threadIdx.x <= J) coef[threadIdx.x] = sb->hcol[threadIdx.x] * sb->inv_norm[threadIdx.x];
   __syncthreads();
   double c[J + 1];
 #pragma unroll
   for (int i = 0; i <= J; ++i) c[i] = coef[i];
   double *w = V + (long)(J + 1) * vstride;
   double acc[1] = {0.0};
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < n2; e += (long)gridDim.x * 256) {
+  for (long e = E.L.lb * 256L + threadIdx.x; e < E.n2; e += (long)E.L.nb * 256) {
     double b[J + 1];
 #pragma unroll
     for (int i = 0; i <= J; ++i) b[i] = V[(long)i * vstride + e];
@@ -152,17 +184,22 @@ ACCH_DEV void orth_tail(GmresState *st, double sum) {
 }
 
 // S (+)= sum_{i<k} y_i Z_i, with the sum of the u part for the mass projection.
-__global__ __launch_bounds__(256) void k_gmres_update(long ncell, double *__restrict__ S, const double *__restrict__ Z,
-                                                       long vstride, GmresState *st, int accumulate, int project,
-                                                       RedBuf red) {
-  if (!st->done) return;   // enqueued speculatively after each chunk of Arnoldi steps
-  const int k = st->j;
+__global__ __launch_bounds__(256) void k_gmres_update(Batch bt, long n2s, double *__restrict__ S,
+                                                       const double *__restrict__ Z, long vstride, GmresState *st,
+                                                       int accumulate, RedBuf red) {
+  const ElemLoc E = elem_loc(bt, n2s);
+  if (!E.L.on) return;
+  GmresState *sb = st + E.L.b;
+  if (!sb->done || sb->applied) return;   // enqueued speculatively after each chunk of Arnoldi steps
+  S += E.xo;
+  Z += E.xo;
+  const int k = sb->j;
   __shared__ double y[kMaxRestart];
-  if (threadIdx.x < k) y[threadIdx.x] = st->y[threadIdx.x];
+  if (threadIdx.x < k) y[threadIdx.x] = sb->y[threadIdx.x];
   __syncthreads();
-  const long n2 = 2 * ncell;
+  const long ncell = E.n2 / 2;
   double acc[1] = {0.0};
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < n2; e += (long)gridDim.x * 256) {
+  for (long e = E.L.lb * 256L + threadIdx.x; e < E.n2; e += (long)E.L.nb * 256) {
     double x = accumulate ? S[e] : 0.0;
     for (int i = 0; i < k; ++i) x = fma(y[i], Z[(long)i * vstride + e], x);
     S[e] = x;
@@ -172,98 +209,167 @@ __global__ __launch_bounds__(256) void k_gmres_update(long ncell, double *__rest
 }
 
 // ||a - b||^2 (b may be null), for the dt controller and diagnostics.
-__global__ __launch_bounds__(256) void k_norm2_diff(long n2, const double *__restrict__ a, const double *__restrict__ b,
-                                                     RedBuf red) {
+__global__ __launch_bounds__(256) void k_norm2_diff(Batch bt, long n2s, const double *__restrict__ a,
+                                                     const double *__restrict__ b, RedBuf red) {
+  const ElemLoc E = elem_loc(bt, n2s);
+  if (!E.L.on) return;
+  a += E.xo;
+  if (b) b += E.xo;
   double acc[1] = {0.0};
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < n2; e += (long)gridDim.x * 256) {
+  for (long e = E.L.lb * 256L + threadIdx.x; e < E.n2; e += (long)E.L.nb * 256) {
     const double d = b ? a[e] - b[e] : a[e];
     acc[0] = fma(d, d, acc[0]);
   }
   block_partial<1>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x);
 }
 
-// One-block second stages of the reductions (see block_partial / final_sum), one
-// kernel per kind so that profiles tell them apart.
+// d1 = s1 and d2 = s2 (d2 may be null) on the active instances; with s1 null, d1 = 0.
+__global__ __launch_bounds__(256) void k_copy2(Batch bt, long n2s, double *__restrict__ d1,
+                                                const double *__restrict__ s1, double *__restrict__ d2,
+                                                const double *__restrict__ s2) {
+  const ElemLoc E = elem_loc(bt, n2s);
+  if (!E.L.on) return;
+  for (long e = E.L.lb * 256L + threadIdx.x; e < E.n2; e += (long)E.L.nb * 256) {
+    d1[E.xo + e] = s1 ? s1[E.xo + e] : 0.0;
+    if (d2) d2[E.xo + e] = s2[E.xo + e];
+  }
+}
+
+// Second stages of the reductions (see block_partial / final_sum): one block per
+// instance, summing that instance's blocks of the partial kernel; one kernel per
+// kind so that profiles tell them apart.
+struct FinRange {
+  int b, b0, nb;
+  bool on;
+};
+ACCH_DEV FinRange fin_range(const Inst *inst, const int *active, int fam, int nblocks) {
+  FinRange R;
+  R.b = blockIdx.x;
+  if (inst) {
+    R.b0 = inst[R.b].blk0[fam];
+    R.nb = inst[R.b].nblk[fam];
+  } else {
+    R.b0 = 0;
+    R.nb = nblocks;
+  }
+  R.on = active == nullptr || active[R.b] != 0;
+  return R;
+}
+
 // h_ij = inv_norm_i * (sum of the block partials of dot i), i <= J.
 template <int J>
-__global__ __launch_bounds__(256) void k_finalize_dots(const double *__restrict__ partials, int nblocks,
-                                                        GmresState *st) {
-  if (st->done) return;
+__global__ __launch_bounds__(256) void k_finalize_dots(const double *__restrict__ partials, int stride,
+                                                        const Inst *inst, const int *active, GmresState *st) {
+  const FinRange R = fin_range(inst, active, kFamCell, stride);
+  GmresState *sb = st + R.b;
+  if (!R.on || sb->done) return;
   constexpr int NV = pow2_at_least(J + 1);
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += 256) {
+  for (int b = threadIdx.x; b < R.nb; b += 256) {
     double p[J + 1];
 #pragma unroll
-    for (int k = 0; k <= J; ++k) p[k] = partials[k * nblocks + b];
+    for (int k = 0; k <= J; ++k) p[k] = partials[(long)k * stride + R.b0 + b];
 #pragma unroll
     for (int k = 0; k <= J; ++k) acc[k] += p[k];
   }
   double tot;
   block_multi_sum<NV>(acc, threadIdx.x, 256, J + 1, &tot);
-  if ((int)threadIdx.x <= J) st->hcol[threadIdx.x] = tot * st->inv_norm[threadIdx.x];
+  if ((int)threadIdx.x <= J) sb->hcol[threadIdx.x] = tot * sb->inv_norm[threadIdx.x];
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int nblocks, int nv,
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int stride, int fam,
+                                                   const Inst *inst, const int *active, int nv,
                                                    double *__restrict__ out, GmresState *st, FinalizeArgs fa) {
-  if constexpr (MODE == kFinDots || MODE == kFinOrth) {
-    if (st->done) return;   // the partial kernel skipped as well
+  const FinRange R = fin_range(inst, active, fam, stride);
+  GmresState *sb = st ? st + R.b : nullptr;
+  if constexpr (MODE == kFinStart) {
+    if (!R.on) {   // an inactive instance does not take part in this solve
+      if (threadIdx.x == 0) {
+        sb->done = 1;
+        sb->converged = 1;
+        sb->applied = 1;
+        sb->j = 0;
+      }
+      return;
+    }
+  } else {
+    if (!R.on) return;
+  }
+  if constexpr (MODE == kFinOrth) {
+    if (sb->done) return;   // the partial kernel skipped as well
   } else if constexpr (MODE == kFinUpdate) {
-    if (!st->done) return;
+    if (!sb->done || sb->applied) return;
   }
   if constexpr (MODE == kFinOrth) {
     double acc[1];
-    final_sum<1>(partials, nblocks, threadIdx.x, 256, acc);
+    final_sum<1>(partials, stride, R.b0, R.nb, threadIdx.x, 256, acc);
     __shared__ double s_sum;
     if (threadIdx.x == 0) s_sum = acc[0];
     __syncthreads();
-    orth_tail(st, s_sum);
+    orth_tail(sb, s_sum);
   } else if constexpr (MODE == kFinPlain) {
     double acc[4];
-    final_sum<4>(partials, nblocks, threadIdx.x, 256, acc, nv);
+    final_sum<4>(partials, stride, R.b0, R.nb, threadIdx.x, 256, acc, nv);
     if (threadIdx.x == 0)
       for (int k = 0; k < 4; ++k)
-        if (k < nv) out[k] = acc[k];
+        if (k < nv) out[4 * R.b + k] = acc[k];
   } else {
     double acc[1];
-    final_sum<1>(partials, nblocks, threadIdx.x, 256, acc);
+    final_sum<1>(partials, stride, R.b0, R.nb, threadIdx.x, 256, acc);
     if (threadIdx.x != 0) return;
-    if constexpr (MODE == kFinStart)
-      start_tail(st, acc[0], fa.first, fa.m, fa.rtol, fa.atol);
-    else
-      st->shift = fa.project ? acc[0] / (double)fa.ncell : 0.0;
+    if constexpr (MODE == kFinStart) {
+      start_tail(sb, acc[0], fa.m, fa.rtol, fa.atol);
+    } else {
+      const long ncell = inst ? (long)inst[R.b].P.nx * inst[R.b].P.ny : fa.ncell;
+      sb->shift = fa.project ? acc[0] / (double)ncell : 0.0;
+      sb->applied = 1;
+    }
   }
 }
 
-__global__ __launch_bounds__(256) void k_reset_state(GmresState *st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->total_its = 0;
-    st->done = 0;
-    st->converged = 0;
-    st->j = 0;
-    st->shift = 0.0;
+__global__ __launch_bounds__(64) void k_reset_state(GmresState *st, int count) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (b < count) {
+    st[b].total_its = 0;
+    st[b].done = 0;
+    st[b].converged = 0;
+    st[b].j = 0;
+    st[b].first = 1;
+    st[b].applied = 0;
+    st[b].shift = 0.0;
   }
 }
 
 }  // namespace
 
-hipError_t launch_finalize(int mode, int nv, const RedBuf &red, int nblocks, GmresState *st, const FinalizeArgs &fa,
-                           hipStream_t s) {
+static const Inst *fin_inst(const BatchLaunch &bl, int fam) { return bl.bt.map[fam] ? bl.bt.inst : nullptr; }
+
+hipError_t launch_finalize(int mode, int nv, const RedBuf &red, const BatchLaunch &bl, int fam, GmresState *st,
+                           const FinalizeArgs &fa, hipStream_t s) {
+  const dim3 g(bl.count);
+  const int stride = bl.grid[fam];
+  const Inst *in = fin_inst(bl, fam);
+  const int *act = bl.bt.active;
   switch (mode) {
     case kFinPlain:
       if (nv > 4) return hipErrorInvalidValue;
-      hipLaunchKernelGGL(k_finalize<kFinPlain>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
+      hipLaunchKernelGGL(k_finalize<kFinPlain>, g, dim3(256), 0, s, red.partials, stride, fam, in, act, nv, red.out,
+                         st, fa);
       break;
     case kFinStart:
-      hipLaunchKernelGGL(k_finalize<kFinStart>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
+      hipLaunchKernelGGL(k_finalize<kFinStart>, g, dim3(256), 0, s, red.partials, stride, fam, in, act, nv, red.out,
+                         st, fa);
       break;
     case kFinOrth:
-      hipLaunchKernelGGL(k_finalize<kFinOrth>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
+      hipLaunchKernelGGL(k_finalize<kFinOrth>, g, dim3(256), 0, s, red.partials, stride, fam, in, act, nv, red.out,
+                         st, fa);
       break;
     case kFinUpdate:
-      hipLaunchKernelGGL(k_finalize<kFinUpdate>, dim3(1), dim3(256), 0, s, red.partials, nblocks, nv, red.out, st, fa);
+      hipLaunchKernelGGL(k_finalize<kFinUpdate>, g, dim3(256), 0, s, red.partials, stride, fam, in, act, nv, red.out,
+                         st, fa);
       break;
     default:
       return hipErrorInvalidValue;
@@ -272,76 +378,81 @@ hipError_t launch_finalize(int mode, int nv, const RedBuf &red, int nblocks, Gmr
 }
 
 template <int J>
-static hipError_t finalize_dots_at(int j, const RedBuf &red, int nblocks, GmresState *st, hipStream_t s) {
+static hipError_t finalize_dots_at(int j, const RedBuf &red, const BatchLaunch &bl, GmresState *st, hipStream_t s) {
   if (j == J) {
-    hipLaunchKernelGGL(k_finalize_dots<J>, dim3(1), dim3(256), 0, s, red.partials, nblocks, st);
+    hipLaunchKernelGGL(k_finalize_dots<J>, dim3(bl.count), dim3(256), 0, s, red.partials, bl.grid[kFamCell],
+                       fin_inst(bl, kFamCell), bl.bt.active, st);
     return hipGetLastError();
   }
-  if constexpr (J + 1 < kMaxRestart) return finalize_dots_at<J + 1>(j, red, nblocks, st, s);
+  if constexpr (J + 1 < kMaxRestart) return finalize_dots_at<J + 1>(j, red, bl, st, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_finalize_dots(int j, const RedBuf &red, int nblocks, GmresState *st, hipStream_t s) {
+hipError_t launch_finalize_dots(int j, const RedBuf &red, const BatchLaunch &bl, GmresState *st, hipStream_t s) {
   if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
-  return finalize_dots_at<0>(j, red, nblocks, st, s);
+  return finalize_dots_at<0>(j, red, bl, st, s);
 }
 
 template <int J>
-static hipError_t orth_at(int j, long n2, double *V, long vstride, GmresState *st, const RedBuf &red, int nb,
+static hipError_t orth_at(int j, const BatchLaunch &bl, double *V, long vstride, GmresState *st, const RedBuf &red,
                           hipStream_t s) {
   if (j == J) {
-    hipLaunchKernelGGL(k_gmres_orth<J>, dim3(nb), dim3(256), 0, s, n2, V, vstride, st, red);
+    hipLaunchKernelGGL(k_gmres_orth<J>, dim3(bl.grid[kFamElem]), dim3(256), 0, s, bl.bt, 2 * bl.ncell, V, vstride, st,
+                       red);
     return hipGetLastError();
   }
-  if constexpr (J + 1 < kMaxRestart) return orth_at<J + 1>(j, n2, V, vstride, st, red, nb, s);
+  if constexpr (J + 1 < kMaxRestart) return orth_at<J + 1>(j, bl, V, vstride, st, red, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_gmres_start(long n2, const double *F, const double *JS, double *V0, GmresState *st, int m,
-                              double rtol, double atol, const RedBuf &red, hipStream_t s) {
-  const int nb = reduce_blocks(n2);
-  hipLaunchKernelGGL(k_gmres_start, dim3(nb), dim3(256), 0, s, n2, F, JS, V0, st, m, rtol, atol, red);
+hipError_t launch_gmres_start(const BatchLaunch &bl, const double *F, const double *JS, double *V0, GmresState *st,
+                              int m, double rtol, double atol, const RedBuf &red, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_start, dim3(bl.grid[kFamElem]), dim3(256), 0, s, bl.bt, 2 * bl.ncell, F, JS, V0, red);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   FinalizeArgs fa{};
-  fa.first = JS ? 0 : 1;
   fa.m = m;
   fa.rtol = rtol;
   fa.atol = atol;
-  return launch_finalize(kFinStart, 1, red, nb, st, fa, s);
+  return launch_finalize(kFinStart, 1, red, bl, kFamElem, st, fa, s);
 }
 
-hipError_t launch_gmres_orth(long n2, double *V, long vstride, int j, GmresState *st, const RedBuf &red,
-                             hipStream_t s) {
+hipError_t launch_gmres_orth(const BatchLaunch &bl, double *V, long vstride, int j, GmresState *st,
+                             const RedBuf &red, hipStream_t s) {
   if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
-  const int nb = reduce_blocks(n2);
-  hipError_t e = orth_at<0>(j, n2, V, vstride, st, red, nb, s);
+  hipError_t e = orth_at<0>(j, bl, V, vstride, st, red, s);
   if (e != hipSuccess) return e;
-  return launch_finalize(kFinOrth, 1, red, nb, st, FinalizeArgs{}, s);
+  return launch_finalize(kFinOrth, 1, red, bl, kFamElem, st, FinalizeArgs{}, s);
 }
 
-hipError_t launch_gmres_update(long ncell, double *S, const double *Z, long vstride, GmresState *st, int accumulate,
-                               int project, const RedBuf &red, hipStream_t s) {
-  const int nb = reduce_blocks(2 * ncell);
-  hipLaunchKernelGGL(k_gmres_update, dim3(nb), dim3(256), 0, s, ncell, S, Z, vstride, st, accumulate, project, red);
+hipError_t launch_gmres_update(const BatchLaunch &bl, double *S, const double *Z, long vstride, GmresState *st,
+                               int accumulate, int project, const RedBuf &red, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_update, dim3(bl.grid[kFamElem]), dim3(256), 0, s, bl.bt, 2 * bl.ncell, S, Z, vstride,
+                     st, accumulate, red);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   FinalizeArgs fa{};
   fa.project = project;
-  fa.ncell = ncell;
-  return launch_finalize(kFinUpdate, 1, red, nb, st, fa, s);
+  fa.ncell = bl.ncell;
+  return launch_finalize(kFinUpdate, 1, red, bl, kFamElem, st, fa, s);
 }
 
-hipError_t launch_norm2_diff(long n2, const double *a, const double *b, const RedBuf &red, hipStream_t s) {
-  const int nb = reduce_blocks(n2);
-  hipLaunchKernelGGL(k_norm2_diff, dim3(nb), dim3(256), 0, s, n2, a, b, red);
+hipError_t launch_norm2_diff(const BatchLaunch &bl, const double *a, const double *b, const RedBuf &red,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_norm2_diff, dim3(bl.grid[kFamElem]), dim3(256), 0, s, bl.bt, 2 * bl.ncell, a, b, red);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_finalize(kFinPlain, 1, red, nb, nullptr, FinalizeArgs{}, s);
+  return launch_finalize(kFinPlain, 1, red, bl, kFamElem, nullptr, FinalizeArgs{}, s);
 }
 
-hipError_t launch_reset_state(GmresState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, st);
+hipError_t launch_copy2(const BatchLaunch &bl, double *d1, const double *s1, double *d2, const double *s2,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_copy2, dim3(bl.grid[kFamElem]), dim3(256), 0, s, bl.bt, 2 * bl.ncell, d1, s1, d2, s2);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_state(const BatchLaunch &bl, GmresState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_state, dim3((bl.count + 63) / 64), dim3(64), 0, s, st, bl.count);
   return hipGetLastError();
 }
 

@@ -122,12 +122,17 @@ ACCH_DEV int level_lo(int w, int bw) {
 // Extraction of A_k = R_k J R_k^T and its ILU(0) factorisation, one box per block.
 // ---------------------------------------------------------------------------
 template <typename FT, int NW>
-__global__ __launch_bounds__(64 * NW) void k_ilu_factor2d(BoxGeom G, const SubInfo *__restrict__ subs,
-                                                          const int *__restrict__ lvl, int nx, int ny,
-                                                          int periodic, const double *__restrict__ J,
+__global__ __launch_bounds__(64 * NW) void k_ilu_factor2d(Phys P0, Batch bt, BoxGeom G,
+                                                          const SubInfo *__restrict__ subs,
+                                                          const int *__restrict__ lvl, const double *__restrict__ J,
                                                           double shift, FT *__restrict__ fac) {
   constexpr int T = 64 * NW;
   extern __shared__ double ring[];  // [5][bh][kRing]
+  const Loc Lc = locate(bt, kFamSub);
+  if (!Lc.on) return;
+  const Phys &Pi = bt.map[kFamSub] ? bt.inst[Lc.b].P : P0;
+  const int nx = Pi.nx, ny = Pi.ny, periodic = Pi.periodic;
+  if (bt.map[kFamSub]) J += bt.inst[Lc.b].joff;
   const int t = threadIdx.x;
   const SubInfo si = subs[blockIdx.x];
   const long n = (long)nx * ny;
@@ -330,12 +335,21 @@ struct Stage {
 };
 
 template <typename FT, int NW, int D>
-__global__ __launch_bounds__(64 * NW) void k_ras_apply2d(BoxGeom G, const SubInfo *__restrict__ subs,
-                                                         const int *__restrict__ lvl, int nx, int ny,
-                                                         int periodic, const void *__restrict__ fac_,
+__global__ __launch_bounds__(64 * NW) void k_ras_apply2d(Phys P0, Batch bt, BoxGeom G,
+                                                         const SubInfo *__restrict__ subs,
+                                                         const int *__restrict__ lvl, const void *__restrict__ fac_,
                                                          void *__restrict__ ybuf_, const double *__restrict__ r,
                                                          double *__restrict__ z, double *__restrict__ dump,
                                                          const GmresState *st, long vstride) {
+  const Loc Lc = locate(bt, kFamSub);
+  if (!Lc.on) return;
+  const Phys &Pi = bt.map[kFamSub] ? bt.inst[Lc.b].P : P0;
+  const int nx = Pi.nx, ny = Pi.ny, periodic = Pi.periodic;
+  if (bt.map[kFamSub]) {
+    r += bt.inst[Lc.b].xoff;
+    z += bt.inst[Lc.b].xoff;
+  }
+  if (st) st += Lc.b;
   // Inside GMRES the input is the current basis vector v_j = inv_norm[j] W_j and the
   // output is z_j; the whole kernel is skipped once the cycle has finished.
   double sc = 1.0;
@@ -508,7 +522,7 @@ __global__ void k_export_factors2d(BoxGeom G, const int *__restrict__ lvl, const
 }
 
 template <typename FT, int NW>
-hipError_t factor_impl(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
+hipError_t factor_impl(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
                        const double *J, double shift, void *fac, hipStream_t s) {
   const size_t lds = (size_t)5 * G.bh * kRing * sizeof(double);
   if (lds > 65536) {
@@ -516,8 +530,8 @@ hipError_t factor_impl(const BoxGeom &G, const SubInfo *subs, const int *lvl, in
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_ilu_factor2d<FT, NW>), dim3(G.nsub), dim3(64 * NW), lds, s, G, subs, lvl, nx, ny, periodic,
-                     J, shift, (FT *)fac);
+  hipLaunchKernelGGL((k_ilu_factor2d<FT, NW>), dim3(bl.grid[kFamSub]), dim3(64 * NW), lds, s, bl.P0, bl.bt, G, subs,
+                     lvl, J, shift, (FT *)fac);
   return hipGetLastError();
 }
 
@@ -525,23 +539,23 @@ hipError_t factor_impl(const BoxGeom &G, const SubInfo *subs, const int *lvl, in
 int g_ras_prefetch = 8;
 
 template <typename FT, int NW, int D>
-hipError_t apply_d(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
-                   const void *fac, void *ybuf, const double *r, double *z, double *dump, const GmresState *st,
-                   long vstride, hipStream_t s) {
-  hipLaunchKernelGGL((k_ras_apply2d<FT, NW, D>), dim3(G.nsub), dim3(64 * NW), 0, s, G, subs, lvl, nx, ny, periodic,
-                     fac, ybuf, r, z, dump, st, vstride);
+hipError_t apply_d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl, const void *fac,
+                   void *ybuf, const double *r, double *z, double *dump, const GmresState *st, long vstride,
+                   hipStream_t s) {
+  hipLaunchKernelGGL((k_ras_apply2d<FT, NW, D>), dim3(bl.grid[kFamSub]), dim3(64 * NW), 0, s, bl.P0, bl.bt, G, subs,
+                     lvl, fac, ybuf, r, z, dump, st, vstride);
   return hipGetLastError();
 }
 
 template <typename FT, int NW>
-hipError_t apply_impl(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
-                      const void *fac, void *ybuf, const double *r, double *z, double *dump, const GmresState *st,
-                      long vstride, hipStream_t s) {
+hipError_t apply_impl(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl, const void *fac,
+                      void *ybuf, const double *r, double *z, double *dump, const GmresState *st, long vstride,
+                      hipStream_t s) {
   switch (g_ras_prefetch) {
-    case 2: return apply_d<FT, NW, 2>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
-    case 4: return apply_d<FT, NW, 4>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
-    case 16: return apply_d<FT, NW, 16>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
-    default: return apply_d<FT, NW, 8>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
+    case 2: return apply_d<FT, NW, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    case 4: return apply_d<FT, NW, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    case 16: return apply_d<FT, NW, 16>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    default: return apply_d<FT, NW, 8>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
   }
 }
 
@@ -558,33 +572,33 @@ int schwarz_waves(const BoxGeom &G) {
   return 0;
 }
 
-hipError_t launch_ilu_factor2d(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
+hipError_t launch_ilu_factor2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
                                const double *J, double shift, void *fac, int fp32, hipStream_t s) {
   const int nw = schwarz_waves(G);
   if (fp32) {
-    if (nw == 1) return factor_impl<float, 1>(G, subs, lvl, nx, ny, periodic, J, shift, fac, s);
-    if (nw == 2) return factor_impl<float, 2>(G, subs, lvl, nx, ny, periodic, J, shift, fac, s);
-    if (nw == 4) return factor_impl<float, 4>(G, subs, lvl, nx, ny, periodic, J, shift, fac, s);
+    if (nw == 1) return factor_impl<float, 1>(bl, G, subs, lvl, J, shift, fac, s);
+    if (nw == 2) return factor_impl<float, 2>(bl, G, subs, lvl, J, shift, fac, s);
+    if (nw == 4) return factor_impl<float, 4>(bl, G, subs, lvl, J, shift, fac, s);
   } else {
-    if (nw == 1) return factor_impl<double, 1>(G, subs, lvl, nx, ny, periodic, J, shift, fac, s);
-    if (nw == 2) return factor_impl<double, 2>(G, subs, lvl, nx, ny, periodic, J, shift, fac, s);
-    if (nw == 4) return factor_impl<double, 4>(G, subs, lvl, nx, ny, periodic, J, shift, fac, s);
+    if (nw == 1) return factor_impl<double, 1>(bl, G, subs, lvl, J, shift, fac, s);
+    if (nw == 2) return factor_impl<double, 2>(bl, G, subs, lvl, J, shift, fac, s);
+    if (nw == 4) return factor_impl<double, 4>(bl, G, subs, lvl, J, shift, fac, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_ras_apply2d(const BoxGeom &G, const SubInfo *subs, const int *lvl, int nx, int ny, int periodic,
+hipError_t launch_ras_apply2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
                               const void *fac, void *ybuf, const double *r, double *z, double *dump,
                               const GmresState *st, long vstride, int fp32, hipStream_t s) {
   const int nw = schwarz_waves(G);
   if (fp32) {
-    if (nw == 1) return apply_impl<float, 1>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
-    if (nw == 2) return apply_impl<float, 2>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
-    if (nw == 4) return apply_impl<float, 4>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 1) return apply_impl<float, 1>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 2) return apply_impl<float, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 4) return apply_impl<float, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
   } else {
-    if (nw == 1) return apply_impl<double, 1>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
-    if (nw == 2) return apply_impl<double, 2>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
-    if (nw == 4) return apply_impl<double, 4>(G, subs, lvl, nx, ny, periodic, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 1) return apply_impl<double, 1>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 2) return apply_impl<double, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 4) return apply_impl<double, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
   }
   return hipErrorInvalidValue;
 }

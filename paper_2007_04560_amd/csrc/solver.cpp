@@ -14,42 +14,21 @@
 #include <vector>
 
 #include "../../include/acch.h"
+#include "driver.h"
 #include "kernels.h"
 
 using namespace acch;
 
-namespace {
-
+namespace acch {
 thread_local std::string g_last_error;
 
 int fail(int code, const std::string &msg) {
   g_last_error = msg;
   return code;
 }
+}  // namespace acch
 
-#define HIP_TRY(expr)                                                                              \
-  do {                                                                                             \
-    hipError_t e_ = (expr);                                                                        \
-    if (e_ != hipSuccess)                                                                          \
-      return fail(ACCH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));               \
-  } while (0)
-
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// Split n cells into `parts` pieces, the larger ones first (shared reading with the
-// oracle's decomposition).
-void split(int n, int parts, std::vector<int> &start, std::vector<int> &len) {
-  start.resize(parts);
-  len.resize(parts);
-  const int base = n / parts, rem = n % parts;
-  int s = 0;
-  for (int k = 0; k < parts; ++k) {
-    start[k] = s;
-    len[k] = base + (k < rem ? 1 : 0);
-    s += len[k];
-  }
-}
+namespace {
 
 struct Layout {
   size_t off_Xn, off_Xprev, off_X, off_Xt, off_F, off_Ft, off_S, off_W;
@@ -68,16 +47,6 @@ struct KernelTimer {
   int used = 0;
   double total_ms[ACCH_KERNEL_KINDS] = {};
   long count[ACCH_KERNEL_KINDS] = {};
-};
-
-struct Geometry {
-  long ncell = 0;
-  BoxGeom G{};
-  std::vector<SubInfo> subs;
-  std::vector<int> lvl;  // nlev + 1 prefix counts
-  std::vector<int> own;  // owner subdomain of each grid column (nx), then of each row (ny)
-  int min_part = 0;      // smallest owned width / height
-  int tile_blocks = 0;
 };
 
 }  // namespace
@@ -105,6 +74,7 @@ struct acch_ctx {
   int its_guess = 4;
   long launches = 0, syncs = 0;
   KernelTimer timer;
+  BatchLaunch bl{};   // single-instance launch shapes
 };
 
 // ---------------------------------------------------------------------------
@@ -127,7 +97,7 @@ extern "C" void acch_params_default(acch_params *p) {
     if (p->sub[d] == 0) p->sub[d] = 1;
 }
 
-static int validate(const acch_params &p) {
+int acch::validate_params(const acch_params &p) {
   if (p.dim != 2) return fail(ACCH_EUNSUPPORTED, "only dim = 2 is implemented");
   if (p.n[0] < 2 || p.n[1] < 2) return fail(ACCH_EINVAL, "need at least 2 cells per direction");
   if (p.bc != ACCH_BC_PERIODIC && p.bc != ACCH_BC_NEUMANN) return fail(ACCH_EINVAL, "bc");
@@ -158,7 +128,7 @@ static int validate(const acch_params &p) {
   return ACCH_OK;
 }
 
-static int build_geometry(const acch_params &p, Geometry &geo) {
+int acch::build_geometry(const acch_params &p, Geometry &geo) {
   const int nx = p.n[0], ny = p.n[1], d = p.overlap;
   geo.ncell = (long)nx * ny;
   std::vector<int> sx, lx, sy, ly;
@@ -246,7 +216,7 @@ extern "C" int acch_workspace_bytes(const acch_params *pin, size_t *bytes) {
   if (!pin || !bytes) return fail(ACCH_EINVAL, "null argument");
   acch_params p = *pin;
   acch_params_default(&p);
-  int rc = validate(p);
+  int rc = validate_params(p);
   if (rc) return rc;
   Geometry geo;
   rc = build_geometry(p, geo);
@@ -320,9 +290,10 @@ void timer_end(acch_ctx *c, int slot) {
   } while (0)
 #define LAUNCH(c, expr) LAUNCHK(c, ACCH_KERNEL_OTHER, expr)
 
-int residual_eval(acch_ctx *c, const double *X, const double *Sdir, double lam, const double *shift,
+int residual_eval(acch_ctx *c, const double *X, const double *Sdir, double lam, const GmresState *shift,
                   const double *Xn, double dt, double *Xt, double *F, double &f2, double &bad) {
-  LAUNCHK(c, ACCH_KERNEL_RESIDUAL, launch_residual2d(c->P, X, Sdir, lam, shift, Xn, dt, Xt, F, c->red, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_RESIDUAL,
+          launch_residual2d(c->bl, X, Sdir, lam, nullptr, shift, Xn, dt, Xt, F, c->red, c->stream));
   int rc = sync_read(c, c->red.out, c->host->vals, 2 * sizeof(double));
   if (rc) return rc;
   f2 = c->host->vals[0];
@@ -331,7 +302,7 @@ int residual_eval(acch_ctx *c, const double *X, const double *Sdir, double lam, 
 }
 
 int factor(acch_ctx *c) {
-  LAUNCHK(c, ACCH_KERNEL_FACTOR, launch_ilu_factor2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->J,
+  LAUNCHK(c, ACCH_KERNEL_FACTOR, launch_ilu_factor2d(c->bl, c->geo.G, c->d_subs, c->d_lvl, c->J,
                                 c->p.ilu_shift, c->fac, c->p.precision == ACCH_PREC_MIXED, c->stream));
   c->factored = true;
   return ACCH_OK;
@@ -353,14 +324,14 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int 
   const int m = c->p.gmres_restart;
   const int fp32 = c->p.precision == ACCH_PREC_MIXED;
   const int project = transpose ? 0 : c->p.mass_projection;
-  LAUNCH(c, launch_reset_state(c->st, c->stream));
+  LAUNCH(c, launch_reset_state(c->bl, c->st, c->stream));
   its = 0;
   resid = 0.0;
   const size_t tail = offsetof(GmresState, beta);
   GmresState hs{};
   for (int cycle = 0; cycle < c->p.gmres_max_restarts; ++cycle) {
-    if (cycle > 0) LAUNCHK(c, ACCH_KERNEL_SPMV, launch_spmv2d(c->P, c->J, S, c->W, transpose, c->stream));
-    LAUNCHK(c, ACCH_KERNEL_GMRES_START, launch_gmres_start(n2, F, cycle > 0 ? c->W : nullptr, c->V, c->st, m, c->p.gmres_rtol,
+    if (cycle > 0) LAUNCHK(c, ACCH_KERNEL_SPMV, launch_spmv2d(c->bl, c->J, S, c->W, transpose, c->stream));
+    LAUNCHK(c, ACCH_KERNEL_GMRES_START, launch_gmres_start(c->bl, F, cycle > 0 ? c->W : nullptr, c->V, c->st, m, c->p.gmres_rtol,
                                  c->p.gmres_atol, c->red, c->stream));
     int launched = 0;
     int chunk = cycle == 0 ? std::max(1, std::min(m, c->its_guess)) : std::max(1, m / 2);
@@ -370,15 +341,15 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int 
           int rc = precondition_t(c, c->V, c->Z, c->st, vs);
           if (rc) return rc;
         } else {
-          LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic,
+          LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->bl, c->geo.G, c->d_subs, c->d_lvl,
                                                          c->fac, c->ybuf, c->V, c->Z, c->dump, c->st, vs, fp32,
                                                          c->stream));
         }
         LAUNCHK(c, ACCH_KERNEL_SPMV_DOTS,
-                launch_spmv_dots2d(c->P, c->J, c->Z, c->V, vs, launched, transpose, c->st, c->red, c->stream));
-        LAUNCHK(c, ACCH_KERNEL_ORTH, launch_gmres_orth(n2, c->V, vs, launched, c->st, c->red, c->stream));
+                launch_spmv_dots2d(c->bl, c->J, c->Z, c->V, vs, launched, transpose, c->st, c->red, c->stream));
+        LAUNCHK(c, ACCH_KERNEL_ORTH, launch_gmres_orth(c->bl, c->V, vs, launched, c->st, c->red, c->stream));
       }
-      LAUNCHK(c, ACCH_KERNEL_GMRES_UPDATE, launch_gmres_update(c->geo.ncell, S, c->Z, vs, c->st, cycle > 0, project, c->red, c->stream));
+      LAUNCHK(c, ACCH_KERNEL_GMRES_UPDATE, launch_gmres_update(c->bl, S, c->Z, vs, c->st, cycle > 0, project, c->red, c->stream));
       int rc = sync_read(c, (const char *)c->st + tail, c->host_state, sizeof(GmresState) - tail);
       if (rc) return rc;
       memcpy((char *)&hs + tail, c->host_state, sizeof(GmresState) - tail);
@@ -398,55 +369,22 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int 
   return fail(ACCH_EDIVERGED, "GMRES did not converge within the restart limit");
 }
 
-// Backtracking line search along S (with the mass shift) from X; the reading of the
-// unspecified line search shared with the oracle: Armijo test on ||F||^2/2 with
-// alpha = 1e-4 and slope -||F||^2, quadratic then cubic models clamped to
-// [0.1, 0.5] lambda, halving on an inadmissible or non-finite trial, failure below
-// lambda = 1e-8.  On success Xt/Ft hold the accepted point.
+// Backtracking line search along S (with the mass shift) from X (LineSearch in
+// driver.h).  On success Xt/Ft hold the accepted point.
 int line_search(acch_ctx *c, double dt, double fnorm, double &f2_new, double &lam_out) {
-  const double alpha = 1e-4, lam_min = 1e-8;
-  const double f0 = 0.5 * fnorm * fnorm;
-  const double slope = -2.0 * f0;
-  double lam = 1.0;
-  bool have_prev = false;
-  double lp = 0.0, fp = 0.0;
-  const double *shift = c->p.mass_projection ? &c->st->shift : nullptr;
-  while (lam >= lam_min) {
+  LineSearch ls;
+  ls.start(fnorm);
+  const GmresState *shift = c->p.mass_projection ? c->st : nullptr;
+  while (ls.state == LineSearch::kSearching) {
     double f2, bad;
-    int rc = residual_eval(c, c->X, c->S, lam, shift, c->Xn, dt, c->Xt, c->Ft, f2, bad);
+    int rc = residual_eval(c, c->X, c->S, ls.lam, shift, c->Xn, dt, c->Xt, c->Ft, f2, bad);
     if (rc) return rc;
-    if (bad > 0.0 || !(f2 == f2) || isinf(f2)) {
-      lam *= 0.5;
-      continue;
-    }
-    const double ft = 0.5 * f2;
-    if (ft <= f0 + alpha * lam * slope) {
-      f2_new = f2;
-      lam_out = lam;
-      return ACCH_OK;
-    }
-    double nl;
-    if (!have_prev) {
-      nl = -slope * lam * lam / (2.0 * (ft - f0 - slope * lam));
-    } else {
-      const double t1 = ft - f0 - slope * lam, t2 = fp - f0 - slope * lp;
-      const double a = (t1 / (lam * lam) - t2 / (lp * lp)) / (lam - lp);
-      const double b = (-lp * t1 / (lam * lam) + lam * t2 / (lp * lp)) / (lam - lp);
-      if (a == 0.0) {
-        nl = -slope / (2.0 * b);
-      } else {
-        const double disc = b * b - 3.0 * a * slope;
-        nl = disc >= 0.0 ? (-b + sqrt(disc)) / (3.0 * a) : 0.5 * lam;
-      }
-    }
-    if (!isfinite(nl)) nl = 0.5 * lam;
-    nl = std::min(std::max(nl, 0.1 * lam), 0.5 * lam);
-    have_prev = true;
-    lp = lam;
-    fp = ft;
-    lam = nl;
+    ls.trial(f2, bad);
   }
-  return fail(ACCH_EDIVERGED, "line search failed");
+  if (ls.state != LineSearch::kAccepted) return fail(ACCH_EDIVERGED, "line search failed");
+  f2_new = ls.f2;
+  lam_out = ls.lam;
+  return ACCH_OK;
 }
 
 struct SolveStats {
@@ -467,7 +405,7 @@ int nks_solve(acch_ctx *c, double dt, SolveStats &stats) {
   const double tol = std::max(c->p.newton_rtol * fnorm, c->p.newton_atol);
   if (fnorm <= tol) return ACCH_OK;
   for (int it = 1; it <= c->p.newton_max_it; ++it) {
-    LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->P, c->X, c->Xn, dt, c->J, c->stream));
+    LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->bl, c->X, c->Xn, dt, c->J, c->stream));
     if (it == 1 || !c->p.ilu_reuse) {
       rc = factor(c);
       if (rc) return rc;
@@ -492,7 +430,7 @@ int nks_solve(acch_ctx *c, double dt, SolveStats &stats) {
 }
 
 int energy_mass(acch_ctx *c, const double *X, double &E, double &M) {
-  LAUNCHK(c, ACCH_KERNEL_ENERGY, launch_energy2d(c->P, X, c->red, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_ENERGY, launch_energy2d(c->bl, X, c->red, c->stream));
   int rc = sync_read(c, c->red.out, c->host->vals, 2 * sizeof(double));
   if (rc) return rc;
   E = c->host->vals[0] * c->hvol;
@@ -519,7 +457,7 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   *out = nullptr;
   acch_params p = *pin;
   acch_params_default(&p);
-  int rc = validate(p);
+  int rc = validate_params(p);
   if (rc) return rc;
   acch_ctx *c = new (std::nothrow) acch_ctx();
   if (!c) return fail(ACCH_EINVAL, "host allocation failed");
@@ -583,6 +521,7 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->P.S = p.S;
   c->P.mob = p.mobility_mode;
   c->eta = p.eta0;
+  c->bl = single_launch(c->P, c->geo.G.nsub);
   if (hipHostMalloc((void **)&c->host, sizeof(GmresState) + sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(ACCH_EDEVICE, "hipHostMalloc failed");
@@ -673,7 +612,6 @@ extern "C" int acch_step(acch_ctx *c, int nsteps, acch_step_info *info, int *acc
   if (!c || nsteps < 0) return fail(ACCH_EINVAL, "bad arguments");
   if (accepted) *accepted = 0;
   const acch_params &p = c->p;
-  const long n2 = 2 * c->geo.ncell;
   for (int s = 0; s < nsteps; ++s) {
     double dt;
     if (!p.adaptive) {
@@ -681,7 +619,7 @@ extern "C" int acch_step(acch_ctx *c, int nsteps, acch_step_info *info, int *acc
     } else if (!c->have_history) {
       dt = p.dt_min;
     } else {
-      LAUNCH(c, launch_norm2_diff(n2, c->Xn, c->Xprev, c->red, c->stream));
+      LAUNCH(c, launch_norm2_diff(c->bl, c->Xn, c->Xprev, c->red, c->stream));
       int rc = sync_read(c, c->red.out, c->host->vals, sizeof(double));
       if (rc) return rc;
       double dn = sqrt(c->host->vals[0]);
@@ -801,21 +739,21 @@ extern "C" int acch_residual(acch_ctx *c, const double *X, const double *Xn, dou
 
 extern "C" int acch_jacobian(acch_ctx *c, const double *X, const double *Xn, double dt) {
   if (!c || !X || !Xn || !(dt > 0)) return fail(ACCH_EINVAL, "bad arguments");
-  LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->P, X, Xn, dt, c->J, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->bl, X, Xn, dt, c->J, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;
 }
 
 extern "C" int acch_apply_jacobian(acch_ctx *c, const double *x, double *y) {
   if (!c || !x || !y) return fail(ACCH_EINVAL, "bad arguments");
-  LAUNCH(c, launch_spmv2d(c->P, c->J, x, y, 0, c->stream));
+  LAUNCH(c, launch_spmv2d(c->bl, c->J, x, y, 0, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;
 }
 
 extern "C" int acch_apply_jacobian_transpose(acch_ctx *c, const double *x, double *y) {
   if (!c || !x || !y) return fail(ACCH_EINVAL, "bad arguments");
-  LAUNCHK(c, ACCH_KERNEL_SPMV, launch_spmv2d(c->P, c->J, x, y, 1, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_SPMV, launch_spmv2d(c->bl, c->J, x, y, 1, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;
 }
@@ -852,7 +790,7 @@ extern "C" int acch_adjoint_step(acch_ctx *c, const double *X1, const double *X0
   if (!(dt > 0.0)) return fail(ACCH_EINVAL, "dt must be positive");
   int rc = adjoint_ready(c);
   if (rc) return rc;
-  LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->P, X1, X0, dt, c->J, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->bl, X1, X0, dt, c->J, c->stream));
   rc = factor(c);
   if (rc) return rc;
   int its = 0;
@@ -880,7 +818,7 @@ extern "C" int acch_factor(acch_ctx *c) {
 extern "C" int acch_precondition(acch_ctx *c, const double *r, double *z) {
   if (!c || !r || !z) return fail(ACCH_EINVAL, "bad arguments");
   if (!c->factored) return fail(ACCH_EINVAL, "no factorisation: call acch_factor first");
-  LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->geo.G, c->d_subs, c->d_lvl, c->P.nx, c->P.ny, c->P.periodic, c->fac, c->ybuf, r, z,
+  LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->bl, c->geo.G, c->d_subs, c->d_lvl, c->fac, c->ybuf, r, z,
                                c->dump, nullptr, 0, c->p.precision == ACCH_PREC_MIXED, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;

@@ -48,15 +48,38 @@ ACCH_DEV double lap5(double (*s)[LX2], int cy, int cx, double wx, double wy) {
 // ---------------------------------------------------------------------------
 // Residual F(X; Xn, dt), optional trial state, ||F||^2 and admissibility count.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TX *TY) void k_residual2d(Phys P, const double *__restrict__ X,
-                                                        const double *__restrict__ Sdir, double lam,
-                                                        const double *shift, const double *__restrict__ Xn,
+// Tile origin of local tile lb (tiles of TX x TY cells, x fastest).
+ACCH_DEV void tile_origin(const Phys &P, int lb, int &bx0, int &by0) {
+  const int ntx = (P.nx + TX - 1) / TX;
+  const int ty = lb / ntx;
+  bx0 = (lb - ty * ntx) * TX;
+  by0 = ty * TY;
+}
+
+// Batched launches: lam_b / shift_st (may be null) are per instance; the state
+// vectors are offset by the instance's xoff.
+__global__ __launch_bounds__(TX *TY) void k_residual2d(Phys P0, Batch bt, const double *__restrict__ X,
+                                                        const double *__restrict__ Sdir, double lam0,
+                                                        const double *__restrict__ lam_b,
+                                                        const GmresState *shift_st, const double *__restrict__ Xn,
                                                         double inv_dt, double *__restrict__ Xt,
                                                         double *__restrict__ F, RedBuf red) {
   __shared__ double su1[LY2][LX2], sv1[LY2][LX2], su0[LY2][LX2], sv0[LY2][LX2];
   __shared__ double smu[LY1][LX1], sc[LY1][LX1], spm[LY1][LX1];
+  const Loc L = locate(bt, kFamTile);
+  if (!L.on) return;
+  const Phys P = bt.map[kFamTile] ? bt.inst[L.b].P : P0;
+  const long xo = bt.map[kFamTile] ? bt.inst[L.b].xoff : 0;
+  X += xo;
+  Xn += xo;
+  F += xo;
+  if (Sdir) Sdir += xo;
+  if (Xt) Xt += xo;
+  const double lam = lam_b ? lam_b[L.b] : lam0;
+  const double *shift = shift_st ? &shift_st[L.b].shift : nullptr;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-  const int bx0 = blockIdx.x * TX, by0 = blockIdx.y * TY;
+  int bx0, by0;
+  tile_origin(P, L.lb, bx0, by0);
   const long n = (long)P.nx * P.ny;
   load_tile(P, X, Sdir, lam, shift, Xn, bx0, by0, tid, su1, sv1, su0, sv0);
   __syncthreads();
@@ -99,16 +122,20 @@ __global__ __launch_bounds__(TX *TY) void k_residual2d(Phys P, const double *__r
     const double p = u1 + v1, q = u1 - v1;
     acc[1] = (p > 0.0 && p < 1.0 && q > 0.0 && q < 1.0) ? 0.0 : 1.0;
   }
-  block_partial<2>(acc, red.partials, tid, TX * TY, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  block_partial<2>(acc, red.partials, tid, TX * TY, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
 // Discrete energy (eqs. relations, freeenergy) with the exact Phi, and sum u.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_energy2d(Phys P, const double *__restrict__ X, RedBuf red) {
+__global__ __launch_bounds__(256) void k_energy2d(Phys P0, Batch bt, const double *__restrict__ X, RedBuf red) {
+  const Loc L = locate(bt, kFamCell);
+  if (!L.on) return;
+  const Phys P = bt.map[kFamCell] ? bt.inst[L.b].P : P0;
+  if (bt.map[kFamCell]) X += bt.inst[L.b].xoff;
   const long n = (long)P.nx * P.ny;
   double acc[2] = {0.0, 0.0};
-  for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
+  for (long g = L.lb * 256L + threadIdx.x; g < n; g += (long)L.nb * 256) {
     const int gy = (int)(g / P.nx), gx = (int)(g - (long)gy * P.nx);
     const double u = X[g], v = X[n + g];
     double e = 0.5 * P.alpha * u * (1.0 - u) - 0.5 * P.beta * v * v + P.theta * (Phi(u + v) + Phi(u - v));
@@ -133,13 +160,22 @@ __global__ __launch_bounds__(256) void k_energy2d(Phys P, const double *__restri
 // ---------------------------------------------------------------------------
 // Analytic Jacobian, 24 slot arrays J[slot][cell] (slot table in include/acch.h).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TX *TY) void k_jacobian2d(Phys P, const double *__restrict__ X,
+__global__ __launch_bounds__(TX *TY) void k_jacobian2d(Phys P0, Batch bt, const double *__restrict__ X,
                                                         const double *__restrict__ Xn, double inv_dt,
                                                         double *__restrict__ J) {
   __shared__ double su1[LY2][LX2], sv1[LY2][LX2], su0[LY2][LX2], sv0[LY2][LX2];
   __shared__ double smu[LY1][LX1], sc[LY1][LX1], scu[LY1][LX1], scv[LY1][LX1], sAm[LY1][LX1], sav[LY1][LX1];
+  const Loc L = locate(bt, kFamTile);
+  if (!L.on) return;
+  const Phys P = bt.map[kFamTile] ? bt.inst[L.b].P : P0;
+  if (bt.map[kFamTile]) {
+    X += bt.inst[L.b].xoff;
+    Xn += bt.inst[L.b].xoff;
+    J += bt.inst[L.b].joff;
+  }
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-  const int bx0 = blockIdx.x * TX, by0 = blockIdx.y * TY;
+  int bx0, by0;
+  tile_origin(P, L.lb, bx0, by0);
   const long n = (long)P.nx * P.ny;
   load_tile(P, X, nullptr, 0.0, nullptr, Xn, bx0, by0, tid, su1, sv1, su0, sv0);
   __syncthreads();
@@ -322,10 +358,18 @@ ACCH_DEV void matvec_cell(const Phys &P, const double *__restrict__ J, const dou
 
 // y = J x (TR = false) or J^T x (TR = true).
 template <bool TR>
-__global__ __launch_bounds__(256) void k_spmv2d(Phys P, const double *__restrict__ J, const double *__restrict__ x,
-                                                 double *__restrict__ y) {
+__global__ __launch_bounds__(256) void k_spmv2d(Phys P0, Batch bt, const double *__restrict__ J,
+                                                 const double *__restrict__ x, double *__restrict__ y) {
+  const Loc L = locate(bt, kFamCell);
+  if (!L.on) return;
+  const Phys P = bt.map[kFamCell] ? bt.inst[L.b].P : P0;
+  if (bt.map[kFamCell]) {
+    J += bt.inst[L.b].joff;
+    x += bt.inst[L.b].xoff;
+    y += bt.inst[L.b].xoff;
+  }
   const long n = (long)P.nx * P.ny;
-  for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
+  for (long g = L.lb * 256L + threadIdx.x; g < n; g += (long)L.nb * 256) {
     const int gy = (int)(g / P.nx), gx = (int)(g - (long)gy * P.nx);
     double yu, yv;
     matvec_cell<TR>(P, J, x, n, gx, gy, yu, yv);
@@ -340,10 +384,17 @@ __global__ __launch_bounds__(256) void k_spmv2d(Phys P, const double *__restrict
 // every basis load of a cell is issued before the first is used.  Skipped when the
 // cycle is finished.
 template <int J, bool TR>
-__global__ __launch_bounds__(256) void k_spmv_dots2d(Phys P, const double *__restrict__ Jm,
+__global__ __launch_bounds__(256) void k_spmv_dots2d(Phys P0, Batch bt, const double *__restrict__ Jm,
                                                       const double *__restrict__ Z, double *__restrict__ V,
                                                       long vstride, GmresState *st, RedBuf red) {
-  if (st->done) return;
+  const Loc L = locate(bt, kFamCell);
+  if (!L.on || st[L.b].done) return;
+  const Phys P = bt.map[kFamCell] ? bt.inst[L.b].P : P0;
+  if (bt.map[kFamCell]) {
+    Jm += bt.inst[L.b].joff;
+    Z += bt.inst[L.b].xoff;
+    V += bt.inst[L.b].xoff;
+  }
   constexpr int NV = pow2_at_least(J + 1);
   const long n = (long)P.nx * P.ny;
   const double *z = Z + (long)J * vstride;
@@ -351,7 +402,7 @@ __global__ __launch_bounds__(256) void k_spmv_dots2d(Phys P, const double *__res
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-  for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
+  for (long g = L.lb * 256L + threadIdx.x; g < n; g += (long)L.nb * 256) {
     const int gy = (int)(g / P.nx), gx = (int)(g - (long)gy * P.nx);
     double bu[J + 1], bv[J + 1];
 #pragma unroll
@@ -374,8 +425,6 @@ __global__ __launch_bounds__(256) void k_spmv_dots2d(Phys P, const double *__res
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-static inline dim3 tile_grid(const Phys &P) { return dim3((P.nx + TX - 1) / TX, (P.ny + TY - 1) / TY); }
-
 int reduce_blocks(long n) {
   long b = (n + 255) / 256;
   if (b > kRedBlocks) b = kRedBlocks;
@@ -383,59 +432,75 @@ int reduce_blocks(long n) {
   return (int)b;
 }
 
-hipError_t launch_residual2d(const Phys &P, const double *X, const double *Sdir, double lam, const double *shift,
-                             const double *Xn, double dt, double *Xt, double *F, const RedBuf &red,
-                             hipStream_t s) {
-  const dim3 grid = tile_grid(P);
-  hipLaunchKernelGGL(k_residual2d, grid, dim3(TX, TY), 0, s, P, X, Sdir, lam, shift, Xn, 1.0 / dt, Xt, F, red);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_finalize(kFinPlain, 2, red, (int)(grid.x * grid.y), nullptr, FinalizeArgs{}, s);
+void family_blocks(const Phys &P, int nsub, int (&nb)[kFamilies]) {
+  const long n = (long)P.nx * P.ny;
+  nb[kFamTile] = ((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY);
+  nb[kFamCell] = reduce_blocks(n);
+  nb[kFamElem] = reduce_blocks(2 * n);
+  nb[kFamSub] = nsub;
 }
 
-hipError_t launch_energy2d(const Phys &P, const double *X, const RedBuf &red, hipStream_t s) {
-  const int nb = reduce_blocks((long)P.nx * P.ny);
-  hipLaunchKernelGGL(k_energy2d, dim3(nb), dim3(256), 0, s, P, X, red);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_finalize(kFinPlain, 2, red, nb, nullptr, FinalizeArgs{}, s);
+BatchLaunch single_launch(const Phys &P, int nsub) {
+  BatchLaunch bl{};
+  bl.P0 = P;
+  bl.count = 1;
+  bl.ncell = (long)P.nx * P.ny;
+  family_blocks(P, nsub, bl.grid);
+  return bl;
 }
 
-hipError_t launch_jacobian2d(const Phys &P, const double *X, const double *Xn, double dt, double *J,
+hipError_t launch_residual2d(const BatchLaunch &bl, const double *X, const double *Sdir, double lam0,
+                             const double *lam_b, const GmresState *shift_st, const double *Xn, double dt, double *Xt,
+                             double *F, const RedBuf &red, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual2d, dim3(bl.grid[kFamTile]), dim3(TX, TY), 0, s, bl.P0, bl.bt, X, Sdir, lam0, lam_b,
+                     shift_st, Xn, 1.0 / dt, Xt, F, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(kFinPlain, 2, red, bl, kFamTile, nullptr, FinalizeArgs{}, s);
+}
+
+hipError_t launch_energy2d(const BatchLaunch &bl, const double *X, const RedBuf &red, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy2d, dim3(bl.grid[kFamCell]), dim3(256), 0, s, bl.P0, bl.bt, X, red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finalize(kFinPlain, 2, red, bl, kFamCell, nullptr, FinalizeArgs{}, s);
+}
+
+hipError_t launch_jacobian2d(const BatchLaunch &bl, const double *X, const double *Xn, double dt, double *J,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_jacobian2d, tile_grid(P), dim3(TX, TY), 0, s, P, X, Xn, 1.0 / dt, J);
+  hipLaunchKernelGGL(k_jacobian2d, dim3(bl.grid[kFamTile]), dim3(TX, TY), 0, s, bl.P0, bl.bt, X, Xn, 1.0 / dt, J);
   return hipGetLastError();
 }
 
-hipError_t launch_spmv2d(const Phys &P, const double *J, const double *x, double *y, int transpose, hipStream_t s) {
-  const long n = (long)P.nx * P.ny;
-  const dim3 grid((int)((n + 255) / 256));
+hipError_t launch_spmv2d(const BatchLaunch &bl, const double *J, const double *x, double *y, int transpose,
+                         hipStream_t s) {
+  const dim3 grid(bl.grid[kFamCell]);
   if (transpose)
-    hipLaunchKernelGGL(k_spmv2d<true>, grid, dim3(256), 0, s, P, J, x, y);
+    hipLaunchKernelGGL(k_spmv2d<true>, grid, dim3(256), 0, s, bl.P0, bl.bt, J, x, y);
   else
-    hipLaunchKernelGGL(k_spmv2d<false>, grid, dim3(256), 0, s, P, J, x, y);
+    hipLaunchKernelGGL(k_spmv2d<false>, grid, dim3(256), 0, s, bl.P0, bl.bt, J, x, y);
   return hipGetLastError();
 }
 
 template <int J, bool TR>
-static hipError_t spmv_dots_at(int j, const Phys &P, const double *Jm, const double *Z, double *V, long vstride,
-                               GmresState *st, const RedBuf &red, int nb, hipStream_t s) {
+static hipError_t spmv_dots_at(int j, const BatchLaunch &bl, const double *Jm, const double *Z, double *V,
+                               long vstride, GmresState *st, const RedBuf &red, hipStream_t s) {
   if (j == J) {
-    hipLaunchKernelGGL((k_spmv_dots2d<J, TR>), dim3(nb), dim3(256), 0, s, P, Jm, Z, V, vstride, st, red);
+    hipLaunchKernelGGL((k_spmv_dots2d<J, TR>), dim3(bl.grid[kFamCell]), dim3(256), 0, s, bl.P0, bl.bt, Jm, Z, V,
+                       vstride, st, red);
     return hipGetLastError();
   }
-  if constexpr (J + 1 < kMaxRestart) return spmv_dots_at<J + 1, TR>(j, P, Jm, Z, V, vstride, st, red, nb, s);
+  if constexpr (J + 1 < kMaxRestart) return spmv_dots_at<J + 1, TR>(j, bl, Jm, Z, V, vstride, st, red, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_spmv_dots2d(const Phys &P, const double *J, const double *Z, double *V, long vstride, int j,
+hipError_t launch_spmv_dots2d(const BatchLaunch &bl, const double *J, const double *Z, double *V, long vstride, int j,
                               int transpose, GmresState *st, const RedBuf &red, hipStream_t s) {
   if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
-  const int nb = reduce_blocks((long)P.nx * P.ny);
-  hipError_t e = transpose ? spmv_dots_at<0, true>(j, P, J, Z, V, vstride, st, red, nb, s)
-                           : spmv_dots_at<0, false>(j, P, J, Z, V, vstride, st, red, nb, s);
+  hipError_t e = transpose ? spmv_dots_at<0, true>(j, bl, J, Z, V, vstride, st, red, s)
+                           : spmv_dots_at<0, false>(j, bl, J, Z, V, vstride, st, red, s);
   if (e != hipSuccess) return e;
-  return launch_finalize_dots(j, red, nb, st, s);
+  return launch_finalize_dots(j, red, bl, st, s);
 }
 
 }  // namespace acch
