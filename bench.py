@@ -46,6 +46,14 @@ WORKLOADS = {
                              "with FP32 subdomain ILU(0) factors/solves, left-RAS 16x16 overlap 2, shift 0.02, "
                              "GMRES(30), tol 1e-8"),
 }
+# 96 independent periodic instances of uneven size (N in {96,128,192,256}), theta and
+# gamma drawn per instance, 10 steps at dt = 1e-3, all instances in one batched solve
+BATCH = dict(name="batch96", count=96, base_seed=1000, steps=10, overlap=2, boxes=(32, 48, 64),
+             common=dict(dt_fixed=1e-3, overlap=2, ilu_shift=0.02, newton_rtol=1e-8, newton_atol=1e-13,
+                         gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30),
+             text="batch96: 96 independent 2D periodic instances, N uniform in {96,128,192,256}, theta~U(0.08,0.12), "
+                  "gamma~U(5e-4,2e-3), 10 fixed steps dt=1e-3, one batched NKS per step (left-RAS ILU(0) shift 0.02, "
+                  "overlap 2, autotuned boxes, GMRES(30) cycles replayed from HIP graphs), tol 1e-8")
 WORKLOAD = WORKLOADS["periodic512"]
 
 
@@ -110,6 +118,126 @@ def run_gpu(steps: int, warmup: int, timing: bool, w=None):
                 E0=E0, E1=E1, M0=M0, M1=M1, ncell=u0.size)
 
 
+def batch_inputs():
+    from acch_inputs import batched_instances
+    insts = batched_instances(BATCH["count"], BATCH["base_seed"])
+    fields = [w.initial() for w in insts]
+    params = [dict(bc="periodic", theta=w.theta, gamma=w.gamma) for w in insts]
+    return fields, params
+
+
+def run_batch(steps: int, warmup: int, with_sequential: bool = True):
+    """The batched workload: autotune the box size, then time `steps` batched steps in
+    FP64 and in mixed precision (fresh batches from the initial data), the batched
+    preconditioner launch with HIP events on the batch stream, and the same instances
+    solved one after another by the single-instance solver (FP64)."""
+    import numpy as np
+    import torch
+    from paper_2007_04560_amd import BatchSolver, Solver
+    from paper_2007_04560_amd.batch import autotune, with_boxes
+
+    fields, params = batch_inputs()
+    common = BATCH["common"]
+    best, tune = autotune(fields, params, boxes=BATCH["boxes"], steps=1, **common)
+    shapes = [u.shape for u, _ in fields]
+    sub_params = with_boxes(shapes, params, best, BATCH["overlap"])
+    dof = np.array([2 * u.size for u, _ in fields])
+    out = {"box": best, "autotune_s_per_step": {str(k): round(v, 4) for k, v in tune.items()}}
+    for prec in ("fp64", "mixed"):
+        if warmup > 0:
+            with BatchSolver(fields, sub_params, precision=prec, **common) as b:
+                b.step(warmup)
+        b = BatchSolver(fields, sub_params, precision=prec, **common)
+        b.stream.synchronize()
+        t0 = time.perf_counter()
+        nit, git = b.step(steps)
+        b.stream.synchronize()
+        el = time.perf_counter() - t0
+        r = {"elapsed": el, "newton": int(nit.sum()), "gmres": int(git.sum()),
+             "dof_newton": float((dof * nit).sum()), "counters": b.counters()}
+        if prec == "fp64":
+            info = b.info()
+            x = torch.randn(2 * info["ncell"], dtype=torch.float64, device=b.device)
+            z = b.precondition(x)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20
+            with torch.cuda.stream(b.stream):
+                e0.record()
+                for _ in range(reps):
+                    b.precondition(x, z)
+                e1.record()
+            e1.synchronize()
+            r["ras_avg_s"] = e0.elapsed_time(e1) / reps * 1e-3
+            r["info"] = info
+        b.close()
+        out[prec] = r
+    if with_sequential:
+        t_seq = 0.0
+        n_seq = 0
+        for (u, v), p in zip(fields, sub_params):
+            kw = dict(common)
+            kw.update(p)
+            with Solver(u, v, **kw) as s:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                recs = s.step(steps)
+                torch.cuda.synchronize()
+                t_seq += time.perf_counter() - t0
+                n_seq += sum(int(x["newton_its"]) for x in recs)
+        out["sequential"] = {"elapsed": t_seq, "newton": n_seq}
+    out["dof_total"] = int(dof.sum())
+    out["sub_params"] = sub_params
+    out["shapes"] = shapes
+    return out
+
+
+def batch_line(args):
+    from paper_2007_04560_amd.batch import parts_for
+    r = run_batch(args.steps, args.warmup, with_sequential=not args.no_sequential)
+    f = r["fp64"]
+    value = f["dof_newton"] / f["elapsed"]
+    # algorithmic bytes of one batched RAS launch: per instance omega*16 + omega*24*8 + 16 per owned cell
+    d = BATCH["overlap"]
+    bytes_launch = 0.0
+    for (ny, nx), p in zip(r["shapes"], r["sub_params"]):
+        kx, ky = p["sub"]
+        box_cells = (nx + 2 * d * kx) * (ny + 2 * d * ky)
+        bytes_launch += box_cells * (16 + 24 * 8) + 16 * nx * ny
+    achieved = bytes_launch / f["ras_avg_s"] / 1e9
+    line = {
+        "metric": "dof*Newton-steps/s at 1e-8 tol",
+        "value": round(value, 1),
+        "unit": "dof*Newton/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f["elapsed"] / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": BATCH["text"], "instances": BATCH["count"], "dof": r["dof_total"],
+                   "box": r["box"], "autotune_s_per_step": r["autotune_s_per_step"],
+                   "newton_its": f["newton"], "gmres_its": f["gmres"],
+                   "batched_fp64_s": round(f["elapsed"], 4),
+                   "batched_mixed_s": round(r["mixed"]["elapsed"], 4),
+                   "mixed_value": round(r["mixed"]["dof_newton"] / r["mixed"]["elapsed"], 1),
+                   "counters_fp64": f["counters"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_ras_apply2d (all subdomains of all instances)",
+                     "avg_us": round(f["ras_avg_s"] * 1e6, 2), "bytes_per_launch": int(bytes_launch)},
+    }
+    if "sequential" in r:
+        sq = r["sequential"]
+        line["config"]["sequential_fp64_s"] = round(sq["elapsed"], 4)
+        line["config"]["speedup_batched_vs_sequential"] = round(sq["elapsed"] / f["elapsed"], 2)
+        line["config"]["speedup_mixed_vs_sequential"] = round(sq["elapsed"] / r["mixed"]["elapsed"], 2)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def cpu_baseline(budget_s: float = 20.0):
     """The FP64 oracle (NumPy residual/Jacobian, SuperLU direct Newton solves, same dt
     controller) on a bounded sample: the same workload's physics, controller and
@@ -145,9 +273,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP-event timers")
-    ap.add_argument("--workload", default="periodic512", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="periodic512", choices=sorted(WORKLOADS) + ["batch96"])
+    ap.add_argument("--no-sequential", action="store_true", help="batch96: skip the one-by-one FP64 comparison")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     args = ap.parse_args()
+    if args.workload == "batch96":
+        if args.gpus != 1:
+            print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
+            return 2
+        if args.steps is None:
+            args.steps = BATCH["steps"]
+        return batch_line(args)
     w = dict(WORKLOADS[args.workload])
     if args.precision:
         w["precision"] = args.precision

@@ -249,8 +249,9 @@ int acch_adjoint_step(acch_ctx *c, const double *X1, const double *X0, double dt
  * iterations, line searches and GMRES cycles run in lockstep with per-instance
  * masks, so every instance follows the operation sequence of its own
  * single-instance run.  The Arnoldi steps of a GMRES cycle are recorded once into
- * HIP graphs and replayed (ACCH_BATCH_OPT_GRAPH, default on; the stream of
- * instance 0 must then be a created stream, not the null stream).  Instance 0 also
+ * HIP graphs and replayed (ACCH_BATCH_OPT_GRAPH, default on, recorded at the first
+ * step or when the option is switched on; the stream of instance 0 must then be a
+ * created stream, not the null stream).  Instance 0 also
  * supplies the tolerances, restart limits, ilu_shift, mass projection, workspace
  * (acch_batch_workspace_bytes) and stream. */
 typedef struct acch_batch acch_batch;
@@ -272,6 +273,16 @@ int acch_batch_energy(acch_batch *b, double *energy, double *mass);
 
 /* Copy instance i's state to host arrays of its ncell doubles each. */
 int acch_batch_get_fields(acch_batch *b, int i, double *u, double *v);
+
+/* z = M^{-1} r for every instance at once (one launch over all subdomains) with the
+ * factors of the last step's first Newton iteration; r, z are batched device
+ * vectors (instance i's u then v at element offset xoff[i], see acch_batch_info).
+ * Asynchronous on the batch stream. */
+int acch_batch_precondition(acch_batch *b, const double *r, double *z);
+
+/* Total cells, subdomains, padded box size and the element offset of each instance
+ * in batched vectors (xoff: host array of count longs, may be NULL). */
+int acch_batch_info(acch_batch *b, long *ncell, int *nsub, int *box_w, int *box_h, long *xoff);
 
 int acch_batch_set_option(acch_batch *b, int option, long value);
 

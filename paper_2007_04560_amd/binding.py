@@ -27,6 +27,7 @@ EXPORTED = [
     "acch_apply_jacobian_transpose", "acch_precondition_transpose", "acch_energy_gradient", "acch_adjoint_step",
     "acch_batch_workspace_bytes", "acch_batch_create", "acch_batch_step", "acch_batch_energy",
     "acch_batch_get_fields", "acch_batch_set_option", "acch_batch_counters", "acch_batch_destroy",
+    "acch_batch_precondition", "acch_batch_info",
 ]
 KERNEL_KINDS = ["residual", "jacobian", "factor", "ras", "spmv_dots", "orth", "gmres_start", "gmres_update",
                 "energy", "spmv", "other"]
@@ -120,6 +121,9 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "acch_batch_counters": (ctypes.c_int, [ctx, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long),
                                                ctypes.POINTER(ctypes.c_long)]),
         "acch_batch_destroy": (ctypes.c_int, [ctx]),
+        "acch_batch_precondition": (ctypes.c_int, [ctx, vp, vp]),
+        "acch_batch_info": (ctypes.c_int, [ctx, ctypes.POINTER(ctypes.c_long), ip, ip, ip,
+                                           ctypes.POINTER(ctypes.c_long)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -417,8 +421,7 @@ class BatchSolver:
         # the workspace tensor was made on the current stream: finish before the batch stream uses it
         torch.cuda.current_stream(self.device).synchronize()
         _check(self.lib, self.lib.acch_batch_create(arr, self.count, pu, pv, ctypes.byref(self.ctx)))
-        if not graph:
-            self.set_graph(False)
+        self.set_graph(graph)   # records the cycle graphs now when on
 
     def close(self):
         if getattr(self, "ctx", None) and self.ctx.value:
@@ -458,6 +461,23 @@ class BatchSolver:
         v = np.empty(self.shapes[i])
         _check(self.lib, self.lib.acch_batch_get_fields(self.ctx, i, u.ctypes.data, v.ctypes.data))
         return u, v
+
+    def info(self):
+        n, ns, bw, bh = ctypes.c_long(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        xo = (ctypes.c_long * self.count)()
+        _check(self.lib, self.lib.acch_batch_info(self.ctx, ctypes.byref(n), ctypes.byref(ns), ctypes.byref(bw),
+                                                  ctypes.byref(bh), xo))
+        return {"ncell": n.value, "nsub": ns.value, "box_w": bw.value, "box_h": bh.value, "xoff": list(xo[:])}
+
+    def vector(self):
+        return self.torch.empty(2 * self.info()["ncell"], dtype=self.torch.float64, device=self.device)
+
+    def precondition(self, r, z=None):
+        """z = M^{-1} r for all instances (batched device vectors), asynchronous on
+        the batch stream."""
+        z = self.vector() if z is None else z
+        _check(self.lib, self.lib.acch_batch_precondition(self.ctx, _ptr(r), _ptr(z)))
+        return z
 
     def counters(self):
         a, g, s = ctypes.c_long(), ctypes.c_long(), ctypes.c_long()

@@ -175,6 +175,7 @@ struct acch_batch {
   double t = 0.0;
   int use_graph = 1;
   bool graphs_ready = false;
+  bool factored = false;
   std::vector<hipGraphExec_t> graphs;   // chunk c holds Arnoldi steps [c kChunk, (c+1) kChunk)
   long launches = 0, syncs = 0, graph_launches = 0;
 };
@@ -355,9 +356,11 @@ int nks_batch(acch_batch *b, BStats &stats) {
     rc = upload_mask(b, 0);
     if (rc) return rc;
     BLAUNCH(b, launch_jacobian2d(b->newton, b->X, b->Xn, p.dt_fixed, b->J, b->stream));
-    if (it == 1 || !p.ilu_reuse)
+    if (it == 1 || !p.ilu_reuse) {
       BLAUNCH(b, launch_ilu_factor2d(b->newton, b->pl.G, b->d_subs, b->d_lvl, b->J, p.ilu_shift, b->fac,
                                      p.precision == ACCH_PREC_MIXED, b->stream));
+      b->factored = true;
+    }
     rc = gmres_batch(b, stats.gmres);
     if (rc) return rc;
     // line searches of the active instances, in lockstep rounds
@@ -566,10 +569,30 @@ extern "C" int acch_batch_get_fields(acch_batch *b, int i, double *u, double *v)
   return bsync(b);
 }
 
+extern "C" int acch_batch_precondition(acch_batch *b, const double *r, double *z) {
+  if (!b || !r || !z) return fail(ACCH_EINVAL, "bad arguments");
+  if (!b->factored) return fail(ACCH_EINVAL, "no factorisation yet: take a step first");
+  BLAUNCH(b, launch_ras_apply2d(b->all, b->pl.G, b->d_subs, b->d_lvl, b->fac, b->ybuf, r, z, b->dump, nullptr, 0,
+                                b->p.precision == ACCH_PREC_MIXED, b->stream));
+  return ACCH_OK;
+}
+
+extern "C" int acch_batch_info(acch_batch *b, long *ncell, int *nsub, int *box_w, int *box_h, long *xoff) {
+  if (!b) return fail(ACCH_EINVAL, "null batch");
+  if (ncell) *ncell = b->pl.ncell;
+  if (nsub) *nsub = b->pl.G.nsub;
+  if (box_w) *box_w = b->pl.G.bw;
+  if (box_h) *box_h = b->pl.G.bh;
+  if (xoff)
+    for (int i = 0; i < b->pl.count; ++i) xoff[i] = b->pl.inst[i].xoff;
+  return ACCH_OK;
+}
+
 extern "C" int acch_batch_set_option(acch_batch *b, int option, long value) {
   if (!b) return fail(ACCH_EINVAL, "null batch");
   if (option == ACCH_BATCH_OPT_GRAPH) {
     b->use_graph = value != 0;
+    if (b->use_graph && !b->graphs_ready) return record_graphs(b);
     return ACCH_OK;
   }
   return fail(ACCH_EINVAL, "unknown batch option");

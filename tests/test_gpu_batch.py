@@ -60,6 +60,27 @@ def test_batch_matches_single_instance_runs(graph, precision):
         assert (c["graph_launches"] > 0) == graph
 
 
+def test_batched_preconditioner_equals_each_instance():
+    """One launch over all subdomains of all instances = each instance's own M^{-1}."""
+    fields, params = instances()
+    with BatchSolver(fields, params, **COMMON) as b:
+        b.step(1)
+        info = b.info()
+        r = np.random.default_rng(11).standard_normal(2 * info["ncell"])
+        z = b.precondition(torch.as_tensor(r).cuda())
+        b.stream.synchronize()
+        z = z.cpu().numpy()
+    for i, ((u, v), p) in enumerate(zip(fields, params)):
+        kw = dict(COMMON)
+        kw.update(p)
+        n2 = 2 * u.size
+        xo = info["xoff"][i]
+        with Solver(u, v, **kw) as s:
+            s.step(1)
+            zi = s.precondition(torch.as_tensor(r[xo:xo + n2]).cuda()).cpu().numpy()
+        assert np.max(np.abs(z[xo:xo + n2] - zi)) <= 1e-13 * np.max(np.abs(zi)), i
+
+
 def test_batch_matches_oracle():
     fields, params = instances()
     fields, params = fields[:2], params[:2]
