@@ -275,8 +275,19 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP-event timers")
     ap.add_argument("--workload", default="periodic512", choices=sorted(WORKLOADS) + ["batch96"])
     ap.add_argument("--no-sequential", action="store_true", help="batch96: skip the one-by-one FP64 comparison")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 64 MiB FP64 tensor 3 times (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(64 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copied 64 MiB FP64 three times"}), flush=True)
+        return 0
     if args.workload == "batch96":
         if args.gpus != 1:
             print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
