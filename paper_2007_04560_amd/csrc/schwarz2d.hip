@@ -326,21 +326,36 @@ ACCH_DEV void neighbour_fetch(int w, int lane, int wave, FT o1u, FT o1v, FT a3u,
 template <typename FT, int NCH>
 struct Stage {
   typename ChunkOf<FT>::T c[NCH];
-  FT a, b;      // U sweep: y_u, y_v
-  double ra, rb;  // L sweep: r_u, r_v as loaded (masked and scaled only when used)
-  bool real;    // L sweep: the cell is a real cell of the domain
-  int idx;      // wavefront-ordered cell index (dump slot ncb if the lane has no cell)
-  bool act;     // the lane has a cell on this wavefront
-  int g;        // U sweep: global cell to write, or -1 (not owned / not a real cell)
+  typename ChunkOf<FT>::Pair y;   // L sweep: R r of the cell; U sweep: y of the cell
+  unsigned idx;                    // wavefront-ordered cell index (dump slot ncb if the lane has no cell)
+  bool act;                        // the lane has a cell on this wavefront
 };
 
+// Threads of a Schwarz block: the sweeps run on NW waves; with one sweep wave the
+// block has three more, which only share the gather / scatter passes.
+template <int NW>
+constexpr int ras_threads() {
+  return NW == 1 ? 256 : 64 * NW;
+}
+
+// Global cell of box cell (i, j) for the box si (periodic wrap), -1 if padding or
+// outside a Neumann domain; own: the cell is in the owned rectangle.
+ACCH_DEV long box_cell(const SubInfo &si, int i, int j, int nx, int ny, int periodic, bool &own) {
+  own = false;
+  const long g = box_to_global(si, i, j, nx, ny, periodic);
+  own = g >= 0 && i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1;
+  return g;
+}
+
 template <typename FT, int NW, int D>
-__global__ __launch_bounds__(64 * NW) void k_ras_apply2d(Phys P0, Batch bt, BoxGeom G,
-                                                         const SubInfo *__restrict__ subs,
-                                                         const int *__restrict__ lvl, const void *__restrict__ fac_,
-                                                         void *__restrict__ ybuf_, const double *__restrict__ r,
-                                                         double *__restrict__ z, double *__restrict__ dump,
-                                                         const GmresState *st, long vstride) {
+__global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batch bt, BoxGeom G,
+                                                                   const SubInfo *__restrict__ subs,
+                                                                   const int *__restrict__ lvl,
+                                                                   const void *__restrict__ fac_,
+                                                                   void *__restrict__ ybuf_,
+                                                                   const double *__restrict__ r,
+                                                                   double *__restrict__ z, double *__restrict__ dump,
+                                                                   const GmresState *st, long vstride) {
   const Loc Lc = locate(bt, kFamSub);
   if (!Lc.on) return;
   const Phys &Pi = bt.map[kFamSub] ? bt.inst[Lc.b].P : P0;
@@ -369,137 +384,146 @@ __global__ __launch_bounds__(64 * NW) void k_ras_apply2d(Phys P0, Batch bt, BoxG
   constexpr int U0C = 11 / per;                // first chunk of slots 11..23
   constexpr int NUC = NCH - U0C;
   constexpr int TT = 64 * NW;
+  constexpr int TB = ras_threads<NW>();
   __shared__ FT xch[2][NW][4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const SubInfo si = subs[blockIdx.x];
   const long n = (long)nx * ny;
-  const int ncb = G.nlev * G.bh;   // padded wavefront-major cell slots
+  const unsigned ncb = (unsigned)G.nlev * G.bh;   // padded wavefront-major cell slots
   const T *Fk = (const T *)fac_ + (long)blockIdx.x * NCH * ncb;
   P2 *yk = (P2 *)ybuf_ + (long)blockIdx.x * (ncb + 1);   // entry ncb is this box's dump slot
   const FT zero = (FT)0;
   const int nlev = G.nlev;
-  const int nround = (nlev + D - 1) / D * D;
+  const int nbox = G.bw * G.bh;
 
-  // ---- forward sweep: L y = R_k r -------------------------------------------
-  // Closed-form cell of this thread on wavefront w (no branches): row j = t + TT q with
-  // q = floor((w - 2t) / (2 TT)), column i = w - 2j; real cell and ownership by compares.
-  const int pnx = periodic ? nx : 0, pny = periodic ? ny : 0;
-  auto cell_of = [&](int w, int &idx, bool &act, int &g, bool &own) {
-    const int wc = w < 0 ? 0 : (w < nlev ? w : nlev - 1);
-    const int d = wc - 2 * t;
-    const int q = d < 0 ? 0 : (d >> (7 + (NW == 2 ? 1 : (NW == 4 ? 2 : 0))));
-    const int j = t + TT * q;
-    const int i = wc - 2 * j;
-    act = (w >= 0) && (w < nlev) && (d >= 0) && (i < G.bw) && (j < G.bh);
-    idx = act ? wc * G.bh + j : ncb;
-    int gx = si.ox + i, gy = si.oy + j;
-    const bool inside = (unsigned)gx < (unsigned)nx && (unsigned)gy < (unsigned)ny;
-    gx = gx < 0 ? gx + pnx : (gx >= nx ? gx - pnx : gx);
-    gy = gy < 0 ? gy + pny : (gy >= ny ? gy - pny : gy);
-    const bool real = act && i < si.ex && j < si.ey && (periodic || inside);
-    g = real ? gy * nx + gx : -1;
-    own = real && i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1;
-  };
-  auto prefetch_L = [&](Stage<FT, NLC> &s, int w) {
-    int g;
+  // ---- gather: yk[slot of (i,j)] = R_k r (scaled), zero on padding / outside cells
+  for (int e = t; e < nbox; e += TB) {
+    const int j = e / G.bw, i = e - j * G.bw;
     bool own;
-    cell_of(w, s.idx, s.act, g, own);
-    const int li = s.act ? s.idx : 0;
+    const long g = box_cell(si, i, j, nx, ny, periodic, own);
+    const long gs = g >= 0 ? g : 0;
+    const double ru = r[gs], rv = r[n + gs];
+    P2 v;
+    v.x = g >= 0 ? (FT)(sc * ru) : zero;
+    v.y = g >= 0 ? (FT)(sc * rv) : zero;
+    yk[(unsigned)(i + 2 * j) * G.bh + j] = v;
+  }
+  __syncthreads();
+
+  if (t < TT) {
+    const int nround = (nlev + D - 1) / D * D;
+    // Closed-form cell of this thread on wavefront w (no branches): row j = t + TT q
+    // with q = floor((w - 2t) / (2 TT)), column i = w - 2j.
+    auto cell_of = [&](int w, unsigned &idx, bool &act) {
+      const int wc = w < 0 ? 0 : (w < nlev ? w : nlev - 1);
+      const int d = wc - 2 * t;
+      const int q = d < 0 ? 0 : (d >> (7 + (NW == 2 ? 1 : (NW == 4 ? 2 : 0))));
+      const int j = t + TT * q;
+      const int i = wc - 2 * j;
+      act = (w >= 0) && (w < nlev) && (d >= 0) && (i < G.bw) && (j < G.bh);
+      idx = act ? (unsigned)wc * G.bh + j : ncb;
+    };
+    // Loads as a uniform base plus a 32-bit byte offset (one offset for all chunks of
+    // a cell; a box's factors are far below 4 GiB).
+    const char *fbase = (const char *)Fk;
+    const char *ybase = (const char *)yk;
+    auto prefetch = [&](auto &s, int w, int c0) {
+      cell_of(w, s.idx, s.act);
+      const unsigned lo = (s.act ? s.idx : 0u) * (unsigned)sizeof(T);
 #pragma unroll
-    for (int q = 0; q < NLC; ++q) s.c[q] = Fk[(long)q * ncb + li];
-    const int gs = g >= 0 ? g : 0;
-    s.ra = r[gs];
-    s.rb = r[n + gs];
-    s.real = g >= 0;
-  };
-  Stage<FT, NLC> ring[D];
+      for (int q = 0; q < (int)(sizeof(s.c) / sizeof(s.c[0])); ++q)
+        s.c[q] = *(const T *)(fbase + (size_t)((unsigned)(c0 + q) * ncb * (unsigned)sizeof(T)) + lo);
+      s.y = *(const P2 *)(ybase + s.idx * (unsigned)sizeof(P2));
+    };
+    // ---- forward sweep: L y = R_k r (in place in yk) -------------------------
+    Stage<FT, NLC> ring[D];
 #pragma unroll
-  for (int k = 0; k < D; ++k) prefetch_L(ring[k], k);
-  FT o1u = zero, o1v = zero, o2u = zero, o2v = zero;
-  FT a1u = zero, a1v = zero, a2u = zero, a2v = zero, a3u = zero, a3v = zero;
-  for (int w0 = 0; w0 < nround; w0 += D) {
+    for (int k = 0; k < D; ++k) prefetch(ring[k], k, 0);
+    FT o1u = zero, o1v = zero, o2u = zero, o2v = zero;
+    FT a1u = zero, a1v = zero, a2u = zero, a2v = zero, a3u = zero, a3v = zero;
+    for (int w0 = 0; w0 < nround; w0 += D) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const int w = w0 + k;
-      FT Au, Av, Mu, Mv;
-      neighbour_fetch<-1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
-      Stage<FT, NLC> &s = ring[k];
-      // values of earlier wavefronts first; o1 (own, w-1) and A (neighbour, w-1) last
-      FT acc = slot<1, 0, FT>(s.c) * o2u;
-      acc = fma(slot<3, 0, FT>(s.c), a1u, acc);
-      acc = fma(slot<4, 0, FT>(s.c), a2u, acc);
-      acc = fma(slot<7, 0, FT>(s.c), a1v, acc);
-      acc = fma(slot<5, 0, FT>(s.c), Mu, acc);
-      acc = fma(slot<0, 0, FT>(s.c), o1u, acc);
-      acc = fma(slot<6, 0, FT>(s.c), o1v, acc);
-      acc = fma(slot<2, 0, FT>(s.c), Au, acc);
-      const FT ru = s.real ? (FT)(sc * s.ra) : zero;
-      const FT rv = s.real ? (FT)(sc * s.rb) : zero;
-      FT yu = ru - acc;
-      FT accv = slot<9, 0, FT>(s.c) * a1v;
-      accv = fma(slot<8, 0, FT>(s.c), o1v, accv);
-      accv = fma(slot<10, 0, FT>(s.c), yu, accv);
-      FT yv = rv - accv;
-      yu = s.act ? yu : zero;
-      yv = s.act ? yv : zero;
-      P2 y2;
-      y2.x = yu;
-      y2.y = yv;
-      yk[s.idx] = y2;
-      a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
-      o2u = o1u; o2v = o1v; o1u = yu; o1v = yv;
-      prefetch_L(s, w + D);
+      for (int k = 0; k < D; ++k) {
+        const int w = w0 + k;
+        FT Au, Av, Mu, Mv;
+        neighbour_fetch<-1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
+        Stage<FT, NLC> &s = ring[k];
+        // values of earlier wavefronts first; o1 (own, w-1) and A (neighbour, w-1) last
+        FT acc = slot<1, 0, FT>(s.c) * o2u;
+        acc = fma(slot<3, 0, FT>(s.c), a1u, acc);
+        acc = fma(slot<4, 0, FT>(s.c), a2u, acc);
+        acc = fma(slot<7, 0, FT>(s.c), a1v, acc);
+        acc = fma(slot<5, 0, FT>(s.c), Mu, acc);
+        acc = fma(slot<0, 0, FT>(s.c), o1u, acc);
+        acc = fma(slot<6, 0, FT>(s.c), o1v, acc);
+        acc = fma(slot<2, 0, FT>(s.c), Au, acc);
+        FT yu = s.y.x - acc;
+        FT accv = slot<9, 0, FT>(s.c) * a1v;
+        accv = fma(slot<8, 0, FT>(s.c), o1v, accv);
+        accv = fma(slot<10, 0, FT>(s.c), yu, accv);
+        FT yv = s.y.y - accv;
+        yu = s.act ? yu : zero;
+        yv = s.act ? yv : zero;
+        P2 y2;
+        y2.x = yu;
+        y2.y = yv;
+        yk[s.idx] = y2;
+        a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
+        o2u = o1u; o2v = o1v; o1u = yu; o1v = yv;
+        prefetch(s, w + D, 0);
+      }
+    }
+    // ---- backward sweep: U x = y (in place in yk) ----------------------------
+    Stage<FT, NUC> ringu[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) prefetch(ringu[k], nlev - 1 - k, U0C);
+    o1u = o1v = o2u = o2v = zero;
+    a1u = a1v = a2u = a2v = a3u = a3v = zero;
+    for (int w0 = nlev - 1; w0 > nlev - 1 - nround; w0 -= D) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const int w = w0 - k;
+        FT Au, Av, Mu, Mv;
+        neighbour_fetch<1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
+        Stage<FT, NUC> &s = ringu[k];
+        FT accv = slot<23, U0C, FT>(s.c) * a1v;
+        accv = fma(slot<22, U0C, FT>(s.c), o1v, accv);
+        FT xv = (s.y.y - accv) * slot<21, U0C, FT>(s.c);
+        FT acc = slot<13, U0C, FT>(s.c) * o2u;
+        acc = fma(slot<15, U0C, FT>(s.c), a1u, acc);
+        acc = fma(slot<16, U0C, FT>(s.c), a2u, acc);
+        acc = fma(slot<20, U0C, FT>(s.c), a1v, acc);
+        acc = fma(slot<17, U0C, FT>(s.c), Mu, acc);
+        acc = fma(slot<12, U0C, FT>(s.c), o1u, acc);
+        acc = fma(slot<19, U0C, FT>(s.c), o1v, acc);
+        acc = fma(slot<14, U0C, FT>(s.c), Au, acc);
+        acc = fma(slot<18, U0C, FT>(s.c), xv, acc);
+        FT xu = (s.y.x - acc) * slot<11, U0C, FT>(s.c);
+        xu = s.act ? xu : zero;
+        xv = s.act ? xv : zero;
+        P2 x2;
+        x2.x = xu;
+        x2.y = xv;
+        yk[s.idx] = x2;
+        a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
+        o2u = o1u; o2v = o1v; o1u = xu; o1v = xv;
+        prefetch(s, w - D, U0C);
+      }
     }
   }
-  // ---- backward sweep: U x = y, write the owned part ------------------------
-  auto prefetch_U = [&](Stage<FT, NUC> &s, int w) {
-    int g;
+  __syncthreads();
+  // ---- scatter: z = (R_k^0)^T x on the owned cells ---------------------------
+  for (int e = t; e < nbox; e += TB) {
+    const int j = e / G.bw, i = e - j * G.bw;
     bool own;
-    cell_of(w, s.idx, s.act, g, own);
-    const int li = s.act ? s.idx : 0;
-#pragma unroll
-    for (int q = 0; q < NUC; ++q) s.c[q] = Fk[(long)(U0C + q) * ncb + li];
-    const P2 y2 = yk[s.idx];
-    s.a = y2.x;
-    s.b = y2.y;
-    s.g = own ? g : -1;
-  };
-  Stage<FT, NUC> ringu[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) prefetch_U(ringu[k], nlev - 1 - k);
-  o1u = o1v = o2u = o2v = zero;
-  a1u = a1v = a2u = a2v = a3u = a3v = zero;
-  for (int w0 = nlev - 1; w0 > nlev - 1 - nround; w0 -= D) {
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      const int w = w0 - k;
-      FT Au, Av, Mu, Mv;
-      neighbour_fetch<1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
-      Stage<FT, NUC> &s = ringu[k];
-      FT accv = slot<23, U0C, FT>(s.c) * a1v;
-      accv = fma(slot<22, U0C, FT>(s.c), o1v, accv);
-      FT xv = (s.b - accv) * slot<21, U0C, FT>(s.c);
-      FT acc = slot<13, U0C, FT>(s.c) * o2u;
-      acc = fma(slot<15, U0C, FT>(s.c), a1u, acc);
-      acc = fma(slot<16, U0C, FT>(s.c), a2u, acc);
-      acc = fma(slot<20, U0C, FT>(s.c), a1v, acc);
-      acc = fma(slot<17, U0C, FT>(s.c), Mu, acc);
-      acc = fma(slot<12, U0C, FT>(s.c), o1u, acc);
-      acc = fma(slot<19, U0C, FT>(s.c), o1v, acc);
-      acc = fma(slot<14, U0C, FT>(s.c), Au, acc);
-      acc = fma(slot<18, U0C, FT>(s.c), xv, acc);
-      FT xu = (s.a - acc) * slot<11, U0C, FT>(s.c);
-      xu = s.act ? xu : zero;
-      xv = s.act ? xv : zero;
-      double *pu = s.g >= 0 ? z + s.g : dump;
-      double *pv = s.g >= 0 ? z + n + s.g : dump + 1;
-      *pu = (double)xu;
-      *pv = (double)xv;
-      a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
-      o2u = o1u; o2v = o1v; o1u = xu; o1v = xv;
-      prefetch_U(s, w - D);
+    const long g = box_cell(si, i, j, nx, ny, periodic, own);
+    if (own) {
+      const P2 x2 = yk[(unsigned)(i + 2 * j) * G.bh + j];
+      z[g] = (double)x2.x;
+      z[n + g] = (double)x2.y;
     }
   }
+  (void)dump;
 }
 
 // Factors (wavefront order, FT) -> FP64 [sub][slot][j][i].
@@ -542,8 +566,8 @@ template <typename FT, int NW, int D>
 hipError_t apply_d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl, const void *fac,
                    void *ybuf, const double *r, double *z, double *dump, const GmresState *st, long vstride,
                    hipStream_t s) {
-  hipLaunchKernelGGL((k_ras_apply2d<FT, NW, D>), dim3(bl.grid[kFamSub]), dim3(64 * NW), 0, s, bl.P0, bl.bt, G, subs,
-                     lvl, fac, ybuf, r, z, dump, st, vstride);
+  hipLaunchKernelGGL((k_ras_apply2d<FT, NW, D>), dim3(bl.grid[kFamSub]), dim3(ras_threads<NW>()), 0, s, bl.P0, bl.bt,
+                     G, subs, lvl, fac, ybuf, r, z, dump, st, vstride);
   return hipGetLastError();
 }
 
