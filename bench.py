@@ -70,7 +70,7 @@ def spmv_dots_bytes_per_cell(j_avg: float) -> float:
     return 24 * 8 + 16 + 16 + 16 * (j_avg + 1)
 
 
-def measured_traffic(kernel: str = "void k_ras_apply2d<double, 1, 8>"):
+def measured_traffic(kernel: str = "void k_ras_apply2d<double, 1, 4>"):
     """HBM bytes per launch of the RAS kernel from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE runs (profiles/traffic_periodic512.json, scaled by a plain-copy
     calibration), or None when the kernel source changed since the counters were taken."""

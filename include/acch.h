@@ -200,7 +200,7 @@ int acch_timing(acch_ctx *c, int enable);
 int acch_kernel_stats(acch_ctx *c, int kind, double *total_ms, long *count);
 
 /* Tuning options (process-wide): ACCH_OPT_RAS_PREFETCH = wavefronts of factors the
- * triangular-solve kernel loads ahead of their use (2, 4, 8 or 16; default 8).
+ * triangular-solve kernel loads ahead of their use (2, 4, 8 or 16; default 4).
  * c may be NULL. */
 enum { ACCH_OPT_RAS_PREFETCH = 0 };
 int acch_set_option(acch_ctx *c, int option, long value);

@@ -18,8 +18,8 @@ namespace {
 // ---------------------------------------------------------------------------
 // M^{-T} r: per box, restrict r to the owned cells, solve U^T y = r (forward over
 // the wavefronts), then L^T x = y (backward); the whole box is then added into z.
-// The factor layout is the one written by the factorisation kernel: slot S of box
-// cell (i, j) sits in 16-byte chunk S / per at padded wavefront index (i + 2j) bh + j.
+// The factor layout is the one written by the factorisation kernel: the 24 slots of
+// box cell (i, j) are contiguous at padded wavefront index (i + 2j) bh + j.
 // Slots: 0-7 u-row L at u(-1,0) u(-2,0) u(1,-1) u(0,-1) u(-1,-1) u(0,-2) v(-1,0)
 // v(0,-1); 8-10 v-row L at v(-1,0) v(0,-1) u(0,0); 11 1/U_uu; 12-17 u-row U at
 // u(1,0) u(2,0) u(-1,1) u(0,1) u(1,1) u(0,2); 18-20 u-row U at v(0,0) v(1,0) v(0,1);
@@ -32,9 +32,8 @@ struct TCoef {
   int bh;
   template <int S>
   ACCH_DEV double at(int i, int j) const {
-    constexpr int per = 16 / (int)sizeof(FT);
     const long idx = (long)(i + 2 * j) * bh + j;
-    return (double)F[((long)(S / per) * ncb + idx) * per + (S % per)];
+    return (double)F[idx * kNSlot2D + S];
   }
 };
 

@@ -223,9 +223,8 @@ __global__ __launch_bounds__(64 * NW) void k_ilu_factor2d(Phys P0, Batch bt, Box
       const double s[kNSlot2D] = {a[6],  a[5],       a[4],  a[2],  a[1],  a[0],  a[7],  a[3],
                                   b[1],  b[0],       b[2],  1.0 / a[8], a[10], a[12], a[13], a[14],
                                   a[16], a[17],      a[9],  a[11], a[15], 1.0 / b[3], b[4], b[5]};
-      constexpr int per = 16 / (int)sizeof(FT);   // chunked layout of the solve kernel
 #pragma unroll
-      for (int k = 0; k < kNSlot2D; ++k) Fk[((long)(k / per) * ncb + idx) * per + (k % per)] = (FT)s[k];
+      for (int k = 0; k < kNSlot2D; ++k) Fk[(long)idx * kNSlot2D + k] = (FT)s[k];
     }
     __syncthreads();
   }
@@ -234,9 +233,9 @@ __global__ __launch_bounds__(64 * NW) void k_ilu_factor2d(Phys P0, Batch bt, Box
 // ---------------------------------------------------------------------------
 // z = M^{-1} r, left-restricted Schwarz (restricted extension) with ILU(0) solves.
 // ---------------------------------------------------------------------------
-// Factor storage: per subdomain, the 24 slots of a cell are packed into 16-byte
-// chunks (2 FP64 or 4 FP32 values), chunk-major over the wavefront-ordered cells, so
-// each wavefront's chunk loads coalesce and a sweep needs 6-7 wide loads per cell.
+// Factor storage: per subdomain, the 24 slots of a cell are contiguous (12 16-byte
+// chunks in FP64, 6 in FP32) and the cells follow the padded wavefront order, so a
+// sweep reads a cell's half of the slots with one address and 16-byte loads.
 template <typename FT>
 struct ChunkOf;
 template <>
@@ -332,10 +331,11 @@ struct Stage {
 };
 
 // Threads of a Schwarz block: the sweeps run on NW waves; with one sweep wave the
-// block has three more, which only share the gather / scatter passes.
+// block has seven more, which only share the gather / scatter passes (whose
+// latency-bound loads then need few rounds).
 template <int NW>
 constexpr int ras_threads() {
-  return NW == 1 ? 256 : 64 * NW;
+  return NW == 1 ? 512 : 64 * NW;
 }
 
 // Global cell of box cell (i, j) for the box si (periodic wrap), -1 if padding or
@@ -396,17 +396,33 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
   const int nlev = G.nlev;
   const int nbox = G.bw * G.bh;
 
-  // ---- gather: yk[slot of (i,j)] = R_k r (scaled), zero on padding / outside cells
-  for (int e = t; e < nbox; e += TB) {
-    const int j = e / G.bw, i = e - j * G.bw;
-    bool own;
-    const long g = box_cell(si, i, j, nx, ny, periodic, own);
-    const long gs = g >= 0 ? g : 0;
-    const double ru = r[gs], rv = r[n + gs];
-    P2 v;
-    v.x = g >= 0 ? (FT)(sc * ru) : zero;
-    v.y = g >= 0 ? (FT)(sc * rv) : zero;
-    yk[(unsigned)(i + 2 * j) * G.bh + j] = v;
+  // ---- gather: yk[slot of (i,j)] = R_k r (scaled), zero on padding / outside cells;
+  // GU cells per thread and round, all loads first
+  constexpr int GU = 4;
+  for (int e0 = t; e0 < nbox; e0 += TB * GU) {
+    double ru[GU], rv[GU];
+    long gq[GU];
+    unsigned sq[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int e = e0 + u * TB;
+      const int ec = e < nbox ? e : 0;
+      const int j = ec / G.bw, i = ec - j * G.bw;
+      bool own;
+      gq[u] = e < nbox ? box_cell(si, i, j, nx, ny, periodic, own) : -2;
+      sq[u] = (unsigned)(i + 2 * j) * G.bh + j;
+      const long gs = gq[u] >= 0 ? gq[u] : 0;
+      ru[u] = r[gs];
+      rv[u] = r[n + gs];
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      if (gq[u] == -2) continue;
+      P2 v;
+      v.x = gq[u] >= 0 ? (FT)(sc * ru[u]) : zero;
+      v.y = gq[u] >= 0 ? (FT)(sc * rv[u]) : zero;
+      yk[sq[u]] = v;
+    }
   }
   __syncthreads();
 
@@ -423,17 +439,13 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
       act = (w >= 0) && (w < nlev) && (d >= 0) && (i < G.bw) && (j < G.bh);
       idx = act ? (unsigned)wc * G.bh + j : ncb;
     };
-    // Loads as a uniform base plus a 32-bit byte offset (one offset for all chunks of
-    // a cell; a box's factors are far below 4 GiB).
-    const char *fbase = (const char *)Fk;
-    const char *ybase = (const char *)yk;
+    // The chunks of a cell are contiguous: one address per cell, immediate offsets.
     auto prefetch = [&](auto &s, int w, int c0) {
       cell_of(w, s.idx, s.act);
-      const unsigned lo = (s.act ? s.idx : 0u) * (unsigned)sizeof(T);
+      const T *fc = Fk + (size_t)(s.act ? s.idx : 0u) * NCH + c0;
 #pragma unroll
-      for (int q = 0; q < (int)(sizeof(s.c) / sizeof(s.c[0])); ++q)
-        s.c[q] = *(const T *)(fbase + (size_t)((unsigned)(c0 + q) * ncb * (unsigned)sizeof(T)) + lo);
-      s.y = *(const P2 *)(ybase + s.idx * (unsigned)sizeof(P2));
+      for (int q = 0; q < (int)(sizeof(s.c) / sizeof(s.c[0])); ++q) s.c[q] = fc[q];
+      s.y = yk[s.idx];
     };
     // ---- forward sweep: L y = R_k r (in place in yk) -------------------------
     Stage<FT, NLC> ring[D];
@@ -512,15 +524,25 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
     }
   }
   __syncthreads();
-  // ---- scatter: z = (R_k^0)^T x on the owned cells ---------------------------
-  for (int e = t; e < nbox; e += TB) {
-    const int j = e / G.bw, i = e - j * G.bw;
-    bool own;
-    const long g = box_cell(si, i, j, nx, ny, periodic, own);
-    if (own) {
-      const P2 x2 = yk[(unsigned)(i + 2 * j) * G.bh + j];
-      z[g] = (double)x2.x;
-      z[n + g] = (double)x2.y;
+  // ---- scatter: z = (R_k^0)^T x on the owned cells, GU cells per round --------
+  for (int e0 = t; e0 < nbox; e0 += TB * GU) {
+    P2 xq[GU];
+    long gq[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int e = e0 + u * TB;
+      const int ec = e < nbox ? e : 0;
+      const int j = ec / G.bw, i = ec - j * G.bw;
+      bool own;
+      const long g = box_cell(si, i, j, nx, ny, periodic, own);
+      gq[u] = (e < nbox && own) ? g : -1;
+      xq[u] = yk[(unsigned)(i + 2 * j) * G.bh + j];
+    }
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      if (gq[u] < 0) continue;
+      z[gq[u]] = (double)xq[u].x;
+      z[n + gq[u]] = (double)xq[u].y;
     }
   }
   (void)dump;
@@ -538,10 +560,9 @@ __global__ void k_export_factors2d(BoxGeom G, const int *__restrict__ lvl, const
     const int w = i + 2 * j;
     const long ncbp = (long)G.nlev * G.bh;
     const long idx = (long)w * G.bh + j;
-    constexpr int per = 16 / (int)sizeof(FT);
     const long sub = ss / kNSlot2D;
     const int k = (int)(ss - sub * kNSlot2D);
-    out[e] = (double)fac[sub * kNSlot2D * ncbp + ((long)(k / per) * ncbp + idx) * per + (k % per)];
+    out[e] = (double)fac[sub * kNSlot2D * ncbp + idx * kNSlot2D + k];
   }
 }
 
@@ -560,7 +581,7 @@ hipError_t factor_impl(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *s
 }
 
 // Wavefronts loaded ahead of their use in the solves (selectable for tuning).
-int g_ras_prefetch = 8;
+int g_ras_prefetch = 4;
 
 template <typename FT, int NW, int D>
 hipError_t apply_d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl, const void *fac,
@@ -577,15 +598,15 @@ hipError_t apply_impl(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *su
                       hipStream_t s) {
   switch (g_ras_prefetch) {
     case 2: return apply_d<FT, NW, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
-    case 4: return apply_d<FT, NW, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    case 8: return apply_d<FT, NW, 8>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
     case 16: return apply_d<FT, NW, 16>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
-    default: return apply_d<FT, NW, 8>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    default: return apply_d<FT, NW, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
   }
 }
 
 }  // namespace
 
-void set_ras_prefetch(int d) { g_ras_prefetch = (d == 2 || d == 4 || d == 16) ? d : 8; }
+void set_ras_prefetch(int d) { g_ras_prefetch = (d == 2 || d == 8 || d == 16) ? d : 4; }
 int get_ras_prefetch() { return g_ras_prefetch; }
 
 int schwarz_waves(const BoxGeom &G) {
