@@ -66,7 +66,7 @@ typedef struct {
   double gmres_rtol, gmres_atol;          /* xi_r, xi_a; 0 -> 1e-8, 1e-14             */
   int gmres_restart;                      /* 0 -> 30 (maximum 30)                     */
   int gmres_max_restarts;                 /* 0 -> 10                                  */
-  int ras_type;                           /* ACCH_RAS_* (left only in this build)     */
+  int ras_type;                           /* ACCH_RAS_LEFT / _RIGHT / ACCH_AS_CLASSICAL */
   int sub[3];                             /* subdomains per direction                 */
   int overlap;                            /* delta, cell layers                       */
   int ilu_reuse;                          /* 1: factor once per step attempt (default) */

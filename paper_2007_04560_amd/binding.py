@@ -140,6 +140,7 @@ def _check(lib, rc: int):
 
 
 _BC = {"periodic": 0, "neumann": 1}
+_SCHWARZ = {"left": 0, "right": 1, "classical": 2}
 _PREC = {"fp64": 0, "mixed": 1}
 _MOB = {"midpoint": 0, "average": 1, "explicit": 2}
 
@@ -149,7 +150,7 @@ def make_params(shape: Sequence[int], *, bc="periodic", L=(1.0, 1.0), alpha=1.2,
                 newton_rtol=1e-8, newton_atol=1e-13, newton_max_it=50, gmres_rtol=1e-8, gmres_atol=1e-14,
                 gmres_restart=30, gmres_max_restarts=10, sub=(2, 2), overlap=1, ilu_reuse=True,
                 precision="fp64", mobility="midpoint", xd_norm="plain", mass_projection=True,
-                log_energy=True, ilu_shift=0.0) -> Params:
+                log_energy=True, ilu_shift=0.0, schwarz="left") -> Params:
     """acch_params for a 2D field of shape (ny, nx)."""
     ny, nx = int(shape[0]), int(shape[1])
     p = Params()
@@ -164,7 +165,7 @@ def make_params(shape: Sequence[int], *, bc="periodic", L=(1.0, 1.0), alpha=1.2,
     p.newton_rtol, p.newton_atol, p.newton_max_it = newton_rtol, newton_atol, newton_max_it
     p.gmres_rtol, p.gmres_atol = gmres_rtol, gmres_atol
     p.gmres_restart, p.gmres_max_restarts = gmres_restart, gmres_max_restarts
-    p.ras_type = 0
+    p.ras_type = _SCHWARZ[schwarz]
     p.sub[0], p.sub[1], p.sub[2] = int(sub[0]), int(sub[1]), 1
     p.overlap = overlap
     p.ilu_reuse = int(bool(ilu_reuse))

@@ -8,6 +8,7 @@
 //     stencil (no B is assembled),
 //   - the gradient of the discrete energy (eq. freeenergy).
 // J^T x itself is the slot-transposed product in the stencil file.
+#include "../../include/acch.h"
 #include "boxes.h"
 #include "kernels.h"
 #include "physics.h"
@@ -39,8 +40,9 @@ struct TCoef {
 
 template <typename FT, int NW, bool INLDS>
 __global__ __launch_bounds__(64 * NW) void k_ras_t_sweep2d(BoxGeom G, const SubInfo *__restrict__ subs, int nx,
-                                                           int ny, int periodic, const FT *__restrict__ fac,
-                                                           const double *__restrict__ r, double *__restrict__ box,
+                                                           int ny, int periodic, int kind,
+                                                           const FT *__restrict__ fac, const double *__restrict__ r,
+                                                           double *__restrict__ box, double *__restrict__ z,
                                                            const GmresState *st, long vstride) {
   constexpr int T = 64 * NW;
   extern __shared__ double lds_vals[];
@@ -63,8 +65,9 @@ __global__ __launch_bounds__(64 * NW) void k_ras_t_sweep2d(BoxGeom G, const SubI
       const int i = w - 2 * j;
       const long g = box_to_global(si, i, j, nx, ny, periodic);
       const bool own = g >= 0 && i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1;
-      double a = own ? sc * ru[g] : 0.0;
-      double b = own ? sc * rv[g] : 0.0;
+      const bool in = kind == ACCH_RAS_LEFT ? own : g >= 0;   // the transpose of the extension
+      double a = in ? sc * ru[g] : 0.0;
+      double b = in ? sc * rv[g] : 0.0;
       const int e = j * bw + i;
       if (i >= 1) a -= C.template at<12>(i - 1, j) * vu[e - 1];
       if (i >= 2) a -= C.template at<13>(i - 2, j) * vu[e - 2];
@@ -102,7 +105,18 @@ __global__ __launch_bounds__(64 * NW) void k_ras_t_sweep2d(BoxGeom G, const SubI
     }
     __syncthreads();
   }
-  if constexpr (INLDS) {
+  if (kind == ACCH_RAS_RIGHT) {
+    // the transpose of the owned-cell restriction: each owned cell written once
+    double *zu = z + (long)jj * vstride, *zv = zu + n;
+    for (int e = t; e < nb; e += T) {
+      const int j = e / bw, i = e - j * bw;
+      const long g = box_to_global(si, i, j, nx, ny, periodic);
+      if (g >= 0 && i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1) {
+        zu[g] = vu[e];
+        zv[g] = vv[e];
+      }
+    }
+  } else if constexpr (INLDS) {
     for (int e = t; e < nb; e += T) {
       gvals[e] = vu[e];
       gvals[nb + e] = vv[e];
@@ -111,8 +125,7 @@ __global__ __launch_bounds__(64 * NW) void k_ras_t_sweep2d(BoxGeom G, const SubI
 }
 
 // z = sum over the boxes that contain a cell of their values there, in a fixed
-// order.  Boxes that can contain a cell belong to its owner subdomain or to a
-// neighbour of it (the overlap is at most one subdomain wide).
+// order (for_boxes_of).
 __global__ __launch_bounds__(256) void k_ras_t_gather2d(BoxGeom G, const SubInfo *__restrict__ subs, int nx, int ny,
                                                          int periodic, int px, int py, const int *__restrict__ own_x,
                                                          const int *__restrict__ own_y,
@@ -125,35 +138,12 @@ __global__ __launch_bounds__(256) void k_ras_t_gather2d(BoxGeom G, const SubInfo
   const int nb = G.bw * G.bh;
   for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
     const int gy = (int)(g / nx), gx = (int)(g - (long)gy * nx);
-    int cx[3], cy[3], ncx = 0, ncy = 0;
-    for (int d = -1; d <= 1; ++d) {
-      int sx = own_x[gx] + d, sy = own_y[gy] + d;
-      if (periodic) {
-        sx = (sx + px) % px;
-        sy = (sy + py) % py;
-      }
-      bool newx = sx >= 0 && sx < px, newy = sy >= 0 && sy < py;
-      for (int q = 0; q < ncx; ++q) newx = newx && cx[q] != sx;
-      for (int q = 0; q < ncy; ++q) newy = newy && cy[q] != sy;
-      if (newx) cx[ncx++] = sx;
-      if (newy) cy[ncy++] = sy;
-    }
     double su = 0.0, sv = 0.0;
-    for (int b = 0; b < ncy; ++b)
-      for (int a = 0; a < ncx; ++a) {
-        const int k = cy[b] * px + cx[a];
-        const SubInfo si = subs[k];
-        int lx = gx - si.ox, ly = gy - si.oy;
-        if (periodic) {
-          lx = ((lx % nx) + nx) % nx;
-          ly = ((ly % ny) + ny) % ny;
-        }
-        if (lx >= 0 && lx < si.ex && ly >= 0 && ly < si.ey) {
-          const double *bk = box + (long)k * 2 * nb;
-          su += bk[ly * G.bw + lx];
-          sv += bk[nb + ly * G.bw + lx];
-        }
-      }
+    for_boxes_of(subs, nx, ny, periodic, px, py, own_x, own_y, gx, gy, [&](int k, int lx, int ly) {
+      const double *bk = box + (long)k * 2 * nb;
+      su += bk[ly * G.bw + lx];
+      sv += bk[nb + ly * G.bw + lx];
+    });
     zu[g] = su;
     zv[g] = sv;
   }
@@ -294,8 +284,8 @@ constexpr size_t kLdsDefault = 64 * 1024;
 constexpr size_t kLdsMax = 160 * 1024;
 
 template <typename FT, int NW>
-hipError_t ras_t_impl(const BoxGeom &G, const SubInfo *subs, int nx, int ny, int periodic, const void *fac,
-                      double *box, const double *r, const GmresState *st, long vstride, hipStream_t s) {
+hipError_t ras_t_impl(const BoxGeom &G, const SubInfo *subs, int nx, int ny, int periodic, int kind, const void *fac,
+                      double *box, const double *r, double *z, const GmresState *st, long vstride, hipStream_t s) {
   const size_t lds = (size_t)2 * G.bw * G.bh * sizeof(double);
   static size_t lds_allowed = kLdsDefault;   // per instantiation
   bool inlds = lds <= lds_allowed;
@@ -308,31 +298,34 @@ hipError_t ras_t_impl(const BoxGeom &G, const SubInfo *subs, int nx, int ny, int
   (void)hipGetLastError();   // a refused attribute leaves the global-memory variant
   if (inlds)
     hipLaunchKernelGGL((k_ras_t_sweep2d<FT, NW, true>), dim3(G.nsub), dim3(64 * NW), lds, s, G, subs, nx, ny,
-                       periodic, (const FT *)fac, r, box, st, vstride);
+                       periodic, kind, (const FT *)fac, r, box, z, st, vstride);
   else
     hipLaunchKernelGGL((k_ras_t_sweep2d<FT, NW, false>), dim3(G.nsub), dim3(64 * NW), 0, s, G, subs, nx, ny,
-                       periodic, (const FT *)fac, r, box, st, vstride);
+                       periodic, kind, (const FT *)fac, r, box, z, st, vstride);
   return hipGetLastError();
 }
 
 template <typename FT>
-hipError_t ras_t_waves(int nw, const BoxGeom &G, const SubInfo *subs, int nx, int ny, int periodic, const void *fac,
-                       double *box, const double *r, const GmresState *st, long vstride, hipStream_t s) {
-  if (nw == 1) return ras_t_impl<FT, 1>(G, subs, nx, ny, periodic, fac, box, r, st, vstride, s);
-  if (nw == 2) return ras_t_impl<FT, 2>(G, subs, nx, ny, periodic, fac, box, r, st, vstride, s);
-  if (nw == 4) return ras_t_impl<FT, 4>(G, subs, nx, ny, periodic, fac, box, r, st, vstride, s);
+hipError_t ras_t_waves(int nw, const BoxGeom &G, const SubInfo *subs, int nx, int ny, int periodic, int kind,
+                       const void *fac, double *box, const double *r, double *z, const GmresState *st, long vstride,
+                       hipStream_t s) {
+  if (nw == 1) return ras_t_impl<FT, 1>(G, subs, nx, ny, periodic, kind, fac, box, r, z, st, vstride, s);
+  if (nw == 2) return ras_t_impl<FT, 2>(G, subs, nx, ny, periodic, kind, fac, box, r, z, st, vstride, s);
+  if (nw == 4) return ras_t_impl<FT, 4>(G, subs, nx, ny, periodic, kind, fac, box, r, z, st, vstride, s);
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 hipError_t launch_ras_t_apply2d(const BoxGeom &G, const SubInfo *subs, int nx, int ny, int periodic, int px, int py,
-                                const int *own_x, const int *own_y, const void *fac, double *box, const double *r,
-                                double *z, const GmresState *st, long vstride, int fp32, hipStream_t s) {
+                                const int *own_x, const int *own_y, int kind, const void *fac, double *box,
+                                const double *r, double *z, const GmresState *st, long vstride, int fp32,
+                                hipStream_t s) {
   const int nw = schwarz_waves(G);
-  hipError_t e = fp32 ? ras_t_waves<float>(nw, G, subs, nx, ny, periodic, fac, box, r, st, vstride, s)
-                      : ras_t_waves<double>(nw, G, subs, nx, ny, periodic, fac, box, r, st, vstride, s);
+  hipError_t e = fp32 ? ras_t_waves<float>(nw, G, subs, nx, ny, periodic, kind, fac, box, r, z, st, vstride, s)
+                      : ras_t_waves<double>(nw, G, subs, nx, ny, periodic, kind, fac, box, r, z, st, vstride, s);
   if (e != hipSuccess) return e;
+  if (kind == ACCH_RAS_RIGHT) return hipSuccess;
   const int nb = reduce_blocks((long)nx * ny);
   hipLaunchKernelGGL(k_ras_t_gather2d, dim3(nb), dim3(256), 0, s, G, subs, nx, ny, periodic, px, py, own_x, own_y,
                      box, z, st, vstride);

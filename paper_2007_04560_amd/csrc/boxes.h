@@ -30,4 +30,37 @@ ACCH_DEV long box_to_global(const SubInfo &si, int i, int j, int nx, int ny, int
   return (long)gy * nx + gx;
 }
 
+// Calls f(k, lx, ly) for every box k that holds grid cell (gx, gy), with the cell's
+// box coordinates, in a fixed order.  Such boxes belong to the cell's owner
+// subdomain (own_x / own_y: owner index of each grid column / row) or to one of its
+// neighbours, since the overlap is at most one subdomain wide.
+template <class Fn>
+ACCH_DEV void for_boxes_of(const SubInfo *subs, int nx, int ny, int periodic, int px, int py, const int *own_x,
+                           const int *own_y, int gx, int gy, Fn &&f) {
+  int cx[3], cy[3], ncx = 0, ncy = 0;
+  for (int d = -1; d <= 1; ++d) {
+    int sx = own_x[gx] + d, sy = own_y[gy] + d;
+    if (periodic) {
+      sx = (sx + px) % px;
+      sy = (sy + py) % py;
+    }
+    bool newx = sx >= 0 && sx < px, newy = sy >= 0 && sy < py;
+    for (int q = 0; q < ncx; ++q) newx = newx && cx[q] != sx;
+    for (int q = 0; q < ncy; ++q) newy = newy && cy[q] != sy;
+    if (newx) cx[ncx++] = sx;
+    if (newy) cy[ncy++] = sy;
+  }
+  for (int b = 0; b < ncy; ++b)
+    for (int a = 0; a < ncx; ++a) {
+      const int k = cy[b] * px + cx[a];
+      const SubInfo si = subs[k];
+      int lx = gx - si.ox, ly = gy - si.oy;
+      if (periodic) {
+        lx = ((lx % nx) + nx) % nx;
+        ly = ((ly % ny) + ny) % ny;
+      }
+      if (lx >= 0 && lx < si.ex && ly >= 0 && ly < si.ey) f(k, lx, ly);
+    }
+}
+
 }  // namespace acch

@@ -53,9 +53,17 @@ hipError_t launch_spmv_dots2d(const BatchLaunch &bl, const double *J, const doub
 // schwarz2d.hip (subs: every subdomain of the launch, in block order)
 hipError_t launch_ilu_factor2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
                                const double *J, double shift, void *fac, int fp32, hipStream_t s);
+// Schwarz variant (ACCH_RAS_LEFT / ACCH_RAS_RIGHT / ACCH_AS_CLASSICAL); the last two
+// add whole boxes and need the owner maps (single-instance launches only).
+struct RasVariant {
+  int kind = 0;
+  const int *own_x = nullptr, *own_y = nullptr;
+  int px = 0, py = 0;
+};
 hipError_t launch_ras_apply2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
                               const void *fac, void *ybuf, const double *r, double *z, double *dump,
-                              const GmresState *st, long vstride, int fp32, hipStream_t s);
+                              const GmresState *st, long vstride, int fp32, hipStream_t s,
+                              const RasVariant &rv = RasVariant{});
 hipError_t launch_export_factors2d(const BoxGeom &G, const int *lvl, const void *fac, int fp32, double *out,
                                    hipStream_t s);
 
@@ -79,8 +87,9 @@ hipError_t launch_copy2(const BatchLaunch &bl, double *d1, const double *s1, dou
 // factors); box is a scratch of nsub * 2 * bw * bh doubles; own_x / own_y give the
 // owner subdomain index of each grid column / row.
 hipError_t launch_ras_t_apply2d(const BoxGeom &G, const SubInfo *subs, int nx, int ny, int periodic, int px, int py,
-                                const int *own_x, const int *own_y, const void *fac, double *box, const double *r,
-                                double *z, const GmresState *st, long vstride, int fp32, hipStream_t s);
+                                const int *own_x, const int *own_y, int kind, const void *fac, double *box,
+                                const double *r, double *z, const GmresState *st, long vstride, int fp32,
+                                hipStream_t s);
 // out = (dF/dU^n)^T (lam_scale lam) at (X1; X0, dt); bar is a 2n scratch; red.out[0..3]
 // receives (lam_scale lam) . dF/dp for p = alpha, beta, theta, gamma.
 hipError_t launch_adjoint_prev2d(const Phys &P, const double *X1, const double *X0, double dt, const double *lam,

@@ -13,6 +13,7 @@
 // one wavefront are contiguous, so a wavefront's loads coalesce).
 #include <utility>
 
+#include "../../include/acch.h"
 #include "boxes.h"
 #include "kernels.h"
 
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
                                                                    void *__restrict__ ybuf_,
                                                                    const double *__restrict__ r,
                                                                    double *__restrict__ z, double *__restrict__ dump,
-                                                                   const GmresState *st, long vstride) {
+                                                                   const GmresState *st, long vstride, int kind) {
   const Loc Lc = locate(bt, kFamSub);
   if (!Lc.on) return;
   const Phys &Pi = bt.map[kFamSub] ? bt.inst[Lc.b].P : P0;
@@ -410,6 +411,7 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
       const int j = ec / G.bw, i = ec - j * G.bw;
       bool own;
       gq[u] = e < nbox ? box_cell(si, i, j, nx, ny, periodic, own) : -2;
+      if (kind == ACCH_RAS_RIGHT && gq[u] >= 0 && !own) gq[u] = -1;   // restricted restriction
       sq[u] = (unsigned)(i + 2 * j) * G.bh + j;
       const long gs = gq[u] >= 0 ? gq[u] : 0;
       ru[u] = r[gs];
@@ -524,7 +526,9 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
     }
   }
   __syncthreads();
-  // ---- scatter: z = (R_k^0)^T x on the owned cells, GU cells per round --------
+  // ---- scatter: z = (R_k^0)^T x on the owned cells, GU cells per round (the
+  // other variants add whole boxes in k_ras_sum2d) -----------------------------
+  if (kind != ACCH_RAS_LEFT) return;
   for (int e0 = t; e0 < nbox; e0 += TB * GU) {
     P2 xq[GU];
     long gq[GU];
@@ -546,6 +550,34 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
     }
   }
   (void)dump;
+}
+
+// z = sum of the box values (in the wavefront-ordered box buffers) of every box
+// holding the cell: the extension (R_k^delta)^T of the right-restricted and the
+// classical variants.
+template <typename FT>
+__global__ __launch_bounds__(256) void k_ras_sum2d(BoxGeom G, const SubInfo *__restrict__ subs, int nx, int ny,
+                                                    int periodic, int px, int py, const int *__restrict__ own_x,
+                                                    const int *__restrict__ own_y, const void *__restrict__ ybuf_,
+                                                    double *__restrict__ z, const GmresState *st, long vstride) {
+  if (st && st->done) return;
+  const int jj = st ? st->j : 0;
+  const long n = (long)nx * ny;
+  double *zu = z + (long)jj * vstride, *zv = zu + n;
+  using P2 = typename ChunkOf<FT>::Pair;
+  const long ncb = (long)G.nlev * G.bh;
+  const P2 *yb = (const P2 *)ybuf_;
+  for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
+    const int gy = (int)(g / nx), gx = (int)(g - (long)gy * nx);
+    double su = 0.0, sv = 0.0;
+    for_boxes_of(subs, nx, ny, periodic, px, py, own_x, own_y, gx, gy, [&](int k, int lx, int ly) {
+      const P2 x2 = yb[(long)k * (ncb + 1) + (long)(lx + 2 * ly) * G.bh + ly];
+      su += (double)x2.x;
+      sv += (double)x2.y;
+    });
+    zu[g] = su;
+    zv[g] = sv;
+  }
 }
 
 // Factors (wavefront order, FT) -> FP64 [sub][slot][j][i].
@@ -586,21 +618,21 @@ int g_ras_prefetch = 4;
 template <typename FT, int NW, int D>
 hipError_t apply_d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl, const void *fac,
                    void *ybuf, const double *r, double *z, double *dump, const GmresState *st, long vstride,
-                   hipStream_t s) {
+                   int kind, hipStream_t s) {
   hipLaunchKernelGGL((k_ras_apply2d<FT, NW, D>), dim3(bl.grid[kFamSub]), dim3(ras_threads<NW>()), 0, s, bl.P0, bl.bt,
-                     G, subs, lvl, fac, ybuf, r, z, dump, st, vstride);
+                     G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind);
   return hipGetLastError();
 }
 
 template <typename FT, int NW>
 hipError_t apply_impl(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl, const void *fac,
                       void *ybuf, const double *r, double *z, double *dump, const GmresState *st, long vstride,
-                      hipStream_t s) {
+                      int kind, hipStream_t s) {
   switch (g_ras_prefetch) {
-    case 2: return apply_d<FT, NW, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
-    case 8: return apply_d<FT, NW, 8>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
-    case 16: return apply_d<FT, NW, 16>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
-    default: return apply_d<FT, NW, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    case 2: return apply_d<FT, NW, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    case 8: return apply_d<FT, NW, 8>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    case 16: return apply_d<FT, NW, 16>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    default: return apply_d<FT, NW, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
   }
 }
 
@@ -634,18 +666,30 @@ hipError_t launch_ilu_factor2d(const BatchLaunch &bl, const BoxGeom &G, const Su
 
 hipError_t launch_ras_apply2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
                               const void *fac, void *ybuf, const double *r, double *z, double *dump,
-                              const GmresState *st, long vstride, int fp32, hipStream_t s) {
+                              const GmresState *st, long vstride, int fp32, hipStream_t s, const RasVariant &rv) {
   const int nw = schwarz_waves(G);
+  const int kind = rv.kind;
+  if (kind != ACCH_RAS_LEFT && (bl.bt.map[kFamSub] != nullptr || !rv.own_x)) return hipErrorInvalidValue;
+  hipError_t e = hipErrorInvalidValue;
   if (fp32) {
-    if (nw == 1) return apply_impl<float, 1>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
-    if (nw == 2) return apply_impl<float, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
-    if (nw == 4) return apply_impl<float, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 1) e = apply_impl<float, 1>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    if (nw == 2) e = apply_impl<float, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    if (nw == 4) e = apply_impl<float, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
   } else {
-    if (nw == 1) return apply_impl<double, 1>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
-    if (nw == 2) return apply_impl<double, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
-    if (nw == 4) return apply_impl<double, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, s);
+    if (nw == 1) e = apply_impl<double, 1>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    if (nw == 2) e = apply_impl<double, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    if (nw == 4) e = apply_impl<double, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
   }
-  return hipErrorInvalidValue;
+  if (e != hipSuccess || kind == ACCH_RAS_LEFT) return e;
+  const Phys &P = bl.P0;
+  const int nb = reduce_blocks((long)P.nx * P.ny);
+  if (fp32)
+    hipLaunchKernelGGL(k_ras_sum2d<float>, dim3(nb), dim3(256), 0, s, G, subs, P.nx, P.ny, P.periodic, rv.px, rv.py,
+                       rv.own_x, rv.own_y, ybuf, z, st, vstride);
+  else
+    hipLaunchKernelGGL(k_ras_sum2d<double>, dim3(nb), dim3(256), 0, s, G, subs, P.nx, P.ny, P.periodic, rv.px, rv.py,
+                       rv.own_x, rv.own_y, ybuf, z, st, vstride);
+  return hipGetLastError();
 }
 
 hipError_t launch_export_factors2d(const BoxGeom &G, const int *lvl, const void *fac, int fp32, double *out,

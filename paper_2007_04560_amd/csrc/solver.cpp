@@ -75,6 +75,7 @@ struct acch_ctx {
   long launches = 0, syncs = 0;
   KernelTimer timer;
   BatchLaunch bl{};   // single-instance launch shapes
+  RasVariant ras{};   // Schwarz variant and owner maps
 };
 
 // ---------------------------------------------------------------------------
@@ -107,7 +108,8 @@ int acch::validate_params(const acch_params &p) {
     return fail(ACCH_EINVAL, "alpha, beta, theta, gamma, rho must be positive");
   if (p.S < 1 || p.S > kMaxS) return fail(ACCH_EINVAL, "S out of range");
   if (p.gmres_restart < 1 || p.gmres_restart > kMaxRestart) return fail(ACCH_EINVAL, "gmres_restart must be 1..30");
-  if (p.ras_type != ACCH_RAS_LEFT) return fail(ACCH_EUNSUPPORTED, "only the left-restricted Schwarz variant is built");
+  if (p.ras_type != ACCH_RAS_LEFT && p.ras_type != ACCH_RAS_RIGHT && p.ras_type != ACCH_AS_CLASSICAL)
+    return fail(ACCH_EINVAL, "ras_type");
   if (p.precision != ACCH_PREC_FP64 && p.precision != ACCH_PREC_MIXED) return fail(ACCH_EINVAL, "precision");
   if (p.mobility_mode < 0 || p.mobility_mode > 2) return fail(ACCH_EINVAL, "mobility_mode");
   if (p.overlap < 0) return fail(ACCH_EINVAL, "overlap");
@@ -310,8 +312,9 @@ int factor(acch_ctx *c) {
 
 int precondition_t(acch_ctx *c, const double *r, double *z, const GmresState *st, long vs) {
   LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_t_apply2d(c->geo.G, c->d_subs, c->P.nx, c->P.ny, c->P.periodic, c->p.sub[0],
-                                                   c->p.sub[1], c->d_own, c->d_own + c->P.nx, c->fac, c->tbox, r, z,
-                                                   st, vs, c->p.precision == ACCH_PREC_MIXED, c->stream));
+                                                   c->p.sub[1], c->d_own, c->d_own + c->P.nx, c->p.ras_type, c->fac,
+                                                   c->tbox, r, z, st, vs, c->p.precision == ACCH_PREC_MIXED,
+                                                   c->stream));
   return ACCH_OK;
 }
 
@@ -343,7 +346,7 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int 
         } else {
           LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->bl, c->geo.G, c->d_subs, c->d_lvl,
                                                          c->fac, c->ybuf, c->V, c->Z, c->dump, c->st, vs, fp32,
-                                                         c->stream));
+                                                         c->stream, c->ras));
         }
         LAUNCHK(c, ACCH_KERNEL_SPMV_DOTS,
                 launch_spmv_dots2d(c->bl, c->J, c->Z, c->V, vs, launched, transpose, c->st, c->red, c->stream));
@@ -467,6 +470,10 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
     delete c;
     return rc;
   }
+  if (p.ras_type != ACCH_RAS_LEFT && p.overlap > c->geo.min_part) {
+    delete c;
+    return fail(ACCH_EUNSUPPORTED, "right-restricted / classical Schwarz needs overlap <= the smallest subdomain width");
+  }
   make_layout(p, c->geo, c->lay);
   if (!p.workspace || p.workspace_bytes < c->lay.total) {
     delete c;
@@ -502,6 +509,8 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->d_subs = (SubInfo *)(c->ws + L.off_subs);
   c->d_lvl = (int *)(c->ws + L.off_lvl);
   c->d_own = (int *)(c->ws + L.off_own);
+  c->ras.own_x = c->d_own;
+  c->ras.own_y = c->d_own + p.n[0];
   c->st = (GmresState *)(c->ws + L.off_state);
   c->red.partials = (double *)(c->ws + L.off_part);
   c->red.counter = (unsigned *)(c->ws + L.off_cnt);
@@ -522,6 +531,9 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->P.mob = p.mobility_mode;
   c->eta = p.eta0;
   c->bl = single_launch(c->P, c->geo.G.nsub);
+  c->ras.kind = p.ras_type;
+  c->ras.px = p.sub[0];
+  c->ras.py = p.sub[1];
   if (hipHostMalloc((void **)&c->host, sizeof(GmresState) + sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(ACCH_EDEVICE, "hipHostMalloc failed");
@@ -819,7 +831,7 @@ extern "C" int acch_precondition(acch_ctx *c, const double *r, double *z) {
   if (!c || !r || !z) return fail(ACCH_EINVAL, "bad arguments");
   if (!c->factored) return fail(ACCH_EINVAL, "no factorisation: call acch_factor first");
   LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->bl, c->geo.G, c->d_subs, c->d_lvl, c->fac, c->ybuf, r, z,
-                               c->dump, nullptr, 0, c->p.precision == ACCH_PREC_MIXED, c->stream));
+                               c->dump, nullptr, 0, c->p.precision == ACCH_PREC_MIXED, c->stream, c->ras));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;
 }
