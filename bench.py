@@ -238,6 +238,65 @@ def batch_line(args):
     return 0
 
 
+def adjoint_line(args):
+    """Gradient of the final energy after `steps` accepted steps of the 512x512 workload
+    with respect to (u0, v0, alpha, beta, theta, gamma), checkpoints every 5 steps: the
+    forward run, then the backward pass (segment recomputation + transposed solves)."""
+    import numpy as np
+    import torch
+    from acch_inputs import random_ic
+    from paper_2007_04560_amd import Solver
+    from paper_2007_04560_amd.adjoint import final_energy
+    w = WORKLOAD
+    u0, v0 = random_ic(w["shape"], w["seed"])
+    kw = dict(bc=w["bc"], sub=w["sub"], overlap=w["overlap"], adaptive=w["adaptive"], dt_min=w["dt_min"],
+              dt_max=w["dt_max"], eta0=w["eta0"], newton_rtol=w["newton_rtol"], newton_atol=w["newton_atol"],
+              gmres_rtol=w["gmres_rtol"], gmres_atol=w["gmres_atol"], gmres_restart=w["gmres_restart"],
+              ilu_shift=w["ilu_shift"])
+    steps = args.steps
+    params = torch.tensor([1.2, 1.2, 0.1, 1e-3], dtype=torch.float64, requires_grad=True)
+    tu = torch.tensor(u0, requires_grad=True)
+    tv = torch.tensor(v0, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E = final_energy(tu, tv, params, steps, checkpoint_every=5, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    E.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    # the transposed Schwarz apply, timed with HIP events on the library's stream
+    s = Solver(u0, v0, **kw)
+    X = s.vector(np.concatenate([u0.ravel(), v0.ravel()]))
+    s.jacobian(X, X, 1e-3)
+    s.factor()
+    r = torch.randn(2 * u0.size, dtype=torch.float64, device="cuda")
+    s.timing(True)
+    for _ in range(20):
+        s.precondition_transpose(r)
+    ras_ms, ras_n = s.kernel_stats()["ras"]
+    info = s.info()
+    s.close()
+    avg_s = ras_ms / ras_n * 1e-3
+    owned = u0.size / info["nsub"]
+    bytes_launch = ras_bytes_per_cell(info["box_w"] * info["box_h"], owned) * u0.size
+    achieved = bytes_launch / avg_s / 1e9
+    line = {"metric": "gradient time of the final energy (forward + adjoint)", "value": round(t2 - t0, 4),
+            "unit": "s", "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": round((t2 - t0) / steps * 1e3, 3),
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"adjoint of periodic512: dE/d(u0, v0, alpha, beta, theta, gamma) after {steps} "
+                                   "adaptive steps, dt frozen, checkpoints every 5 steps",
+                       "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+                       "energy": float(E.detach()), "grad_params": [float(x) for x in params.grad],
+                       "grad_v0_norm": float(tv.grad.norm())},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "k_ras_t_sweep2d + k_ras_t_gather2d (transposed Schwarz)",
+                         "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": int(bytes_launch)}}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def cpu_baseline(budget_s: float = 20.0):
     """The FP64 oracle (NumPy residual/Jacobian, SuperLU direct Newton solves, same dt
     controller) on a bounded sample: the same workload's physics, controller and
@@ -273,7 +332,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP-event timers")
-    ap.add_argument("--workload", default="periodic512", choices=sorted(WORKLOADS) + ["batch96"])
+    ap.add_argument("--workload", default="periodic512", choices=sorted(WORKLOADS) + ["batch96", "adjoint512"])
     ap.add_argument("--no-sequential", action="store_true", help="batch96: skip the one-by-one FP64 comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 64 MiB FP64 tensor 3 times (reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -288,6 +347,13 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copied 64 MiB FP64 three times"}), flush=True)
         return 0
+    if args.workload == "adjoint512":
+        if args.gpus != 1:
+            print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
+            return 2
+        if args.steps is None:
+            args.steps = 20
+        return adjoint_line(args)
     if args.workload == "batch96":
         if args.gpus != 1:
             print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
