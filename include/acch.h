@@ -53,7 +53,7 @@ enum { ACCH_PREC_FP64 = 0, ACCH_PREC_MIXED = 1 };
 enum { ACCH_MOB_MIDPOINT = 0, ACCH_MOB_AVERAGE = 1, ACCH_MOB_EXPLICIT = 2 };
 
 typedef struct {
-  int dim;              /* 2 (3 reserved)                                            */
+  int dim;              /* 2 or 3 (3D: left-restricted Schwarz, single instances)    */
   int n[3];             /* cells per direction (x, y, z)                              */
   double L[3];          /* domain lengths; 0 means 1.0                                */
   int bc;               /* ACCH_BC_*                                                  */
@@ -141,6 +141,13 @@ int acch_residual(acch_ctx *c, const double *X, const double *Xn, double dt, dou
  *   u-row/v-col: 13:(0,0) 14:(-1,0) 15:(1,0) 16:(0,-1) 17:(0,1)
  *   v-row/v-col: 18:(0,0) 19:(-1,0) 20:(1,0) 21:(0,-1) 22:(0,1)
  *   v-row/u-col: 23:(0,0)
+ * In 3D, 40 slots per cell (offsets (dx,dy,dz)):
+ *   u-row/u-col 0:(0,0,0) 1..6: (-1,0,0) (1,0,0) (0,-1,0) (0,1,0) (0,0,-1) (0,0,1)
+ *     7..12: (-2,0,0) (2,0,0) (0,-2,0) (0,2,0) (0,0,-2) (0,0,2)
+ *     13..24: (-1,-1,0) (1,-1,0) (-1,1,0) (1,1,0) (-1,0,-1) (1,0,-1) (-1,0,1) (1,0,1)
+ *             (0,-1,-1) (0,1,-1) (0,-1,1) (0,1,1)
+ *   u-row/v-col 25..31, v-row/v-col 32..38: the cell then its 6 faces in the order above
+ *   v-row/u-col 39: the cell
  * Entries whose neighbour lies outside a Neumann domain are zero. */
 int acch_jacobian(acch_ctx *c, const double *X, const double *Xn, double dt);
 

@@ -151,12 +151,19 @@ def make_params(shape: Sequence[int], *, bc="periodic", L=(1.0, 1.0), alpha=1.2,
                 gmres_restart=30, gmres_max_restarts=10, sub=(2, 2), overlap=1, ilu_reuse=True,
                 precision="fp64", mobility="midpoint", xd_norm="plain", mass_projection=True,
                 log_energy=True, ilu_shift=0.0, schwarz="left") -> Params:
-    """acch_params for a 2D field of shape (ny, nx)."""
-    ny, nx = int(shape[0]), int(shape[1])
+    """acch_params for a 2D field of shape (ny, nx) or a 3D field of shape (nz, ny, nx);
+    L and sub are given in x, y[, z] order."""
     p = Params()
-    p.dim = 2
-    p.n[0], p.n[1], p.n[2] = nx, ny, 1
-    p.L[0], p.L[1], p.L[2] = float(L[0]), float(L[1]), 1.0
+    if len(shape) == 3:
+        nz, ny, nx = int(shape[0]), int(shape[1]), int(shape[2])
+        p.dim = 3
+    else:
+        ny, nx = int(shape[0]), int(shape[1])
+        nz = 1
+        p.dim = 2
+    p.n[0], p.n[1], p.n[2] = nx, ny, nz
+    p.L[0], p.L[1] = float(L[0]), float(L[1])
+    p.L[2] = float(L[2]) if len(L) > 2 else 1.0
     p.bc = _BC[bc]
     p.alpha, p.beta, p.theta, p.gamma, p.rho = alpha, beta, theta, gamma, rho
     p.S = S
@@ -166,7 +173,7 @@ def make_params(shape: Sequence[int], *, bc="periodic", L=(1.0, 1.0), alpha=1.2,
     p.gmres_rtol, p.gmres_atol = gmres_rtol, gmres_atol
     p.gmres_restart, p.gmres_max_restarts = gmres_restart, gmres_max_restarts
     p.ras_type = _SCHWARZ[schwarz]
-    p.sub[0], p.sub[1], p.sub[2] = int(sub[0]), int(sub[1]), 1
+    p.sub[0], p.sub[1], p.sub[2] = int(sub[0]), int(sub[1]), int(sub[2]) if len(sub) > 2 else 1
     p.overlap = overlap
     p.ilu_reuse = int(bool(ilu_reuse))
     p.precision = _PREC[precision]
@@ -194,8 +201,8 @@ class Solver:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
         v0 = np.ascontiguousarray(v0, dtype=np.float64)
-        if u0.shape != v0.shape or u0.ndim != 2:
-            raise ValueError("u0 and v0 must be 2D arrays of one shape (ny, nx)")
+        if u0.shape != v0.shape or u0.ndim not in (2, 3):
+            raise ValueError("u0 and v0 must be arrays of one shape, (ny, nx) or (nz, ny, nx)")
         self.shape = u0.shape
         self.ncell = int(u0.size)
         self.params = make_params(self.shape, **kw)
@@ -367,11 +374,13 @@ class Solver:
         return out
 
     def export_jacobian(self):
-        ny, nx = self.shape
-        return self._export(EXPORT_JACOBIAN, np.float64).reshape(24, ny, nx)
+        nslot = 40 if len(self.shape) == 3 else 24
+        return self._export(EXPORT_JACOBIAN, np.float64).reshape((nslot,) + tuple(self.shape))
 
     def export_factors(self):
         i = self.info()
+        if len(self.shape) == 3:
+            return self._export(EXPORT_FACTORS, np.float64).reshape(i["nsub"], 40, -1)
         return self._export(EXPORT_FACTORS, np.float64).reshape(i["nsub"], 24, i["box_h"], i["box_w"])
 
     def export_boxes(self):

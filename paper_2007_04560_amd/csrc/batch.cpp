@@ -53,6 +53,7 @@ int make_plan(const acch_params *ps, int count, Plan &pl) {
     acch_params_default(&p);
     int rc = validate_params(p);
     if (rc) return fail(rc, "instance " + std::to_string(b) + ": " + acch_last_error());
+    if (p.dim != 2) return fail(ACCH_EUNSUPPORTED, "batches are 2D");
     if (p.adaptive) return fail(ACCH_EUNSUPPORTED, "batches step at a common fixed dt (adaptive = 0)");
     if (p.ras_type != ACCH_RAS_LEFT) return fail(ACCH_EUNSUPPORTED, "batches use the left-restricted Schwarz variant");
     if (p.overlap != p0.overlap || p.precision != p0.precision || p.dt_fixed != p0.dt_fixed)
@@ -87,6 +88,8 @@ int make_plan(const acch_params *ps, int count, Plan &pl) {
     P.rho = p.rho;
     P.S = p.S;
     P.mob = p.mobility_mode;
+    P.nz = 1;
+    P.wz = 0.0;
     const long n = (long)P.nx * P.ny;
     I.xoff = xoff;
     I.joff = joff;

@@ -19,6 +19,8 @@ struct Phys {
   double alpha, beta, theta, gamma, rho;
   int S;
   int mob;                // 0 midpoint, 1 average, 2 explicit
+  int nz;                 // 1 in 2D
+  double wz;              // 1/hz^2 (3D)
 };
 
 // Scratch of the two-kernel reductions: per-block partial sums and final values.
@@ -33,6 +35,7 @@ struct RedBuf {
 // (i + 2j) * bh + j of nlev * bh slots, so a wavefront's cells are contiguous.
 struct BoxGeom {
   int bw, bh;             // padded box width/height (cells)
+  int bd;                 // padded box depth (1 in 2D)
   int nlev;               // levels of the i + 2j wavefront: bw + 2(bh-1)
   int ncb;                // bw * bh (cells of a box; storage is padded to nlev * bh slots)
   int nsub;
@@ -44,6 +47,7 @@ struct SubInfo {
   int ox, oy;             // global coordinates of box cell (0,0), may be negative
   int ex, ey;             // real box extent (<= bw, bh); cells beyond are padding
   int own_x0, own_x1, own_y0, own_y1;
+  int oz, ez, own_z0, own_z1;   // third direction (0, 1, 0, 1 in 2D)
 };
 
 // Device-resident state of one restarted GMRES cycle (flexible, right preconditioned).

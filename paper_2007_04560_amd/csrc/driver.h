@@ -46,6 +46,7 @@ struct Geometry {
   BoxGeom G{};
   std::vector<SubInfo> subs;
   std::vector<int> lvl;  // nlev + 1 prefix counts
+  std::vector<int> cells;  // 3D: box cells (i + bw (j + bh k)) in level order
   std::vector<int> own;  // owner subdomain of each grid column (nx), then of each row (ny)
   int min_part = 0;      // smallest owned width / height
   int tile_blocks = 0;

@@ -98,4 +98,30 @@ hipError_t launch_adjoint_prev2d(const Phys &P, const double *X1, const double *
 hipError_t launch_energy_grad2d(const Phys &P, const double *X, double vol, double *g, const RedBuf &red,
                                 hipStream_t s);
 
+// stencil3d.hip / schwarz3d.hip (single instance; cells listed per level in `cells`)
+hipError_t launch_residual3d(const BatchLaunch &bl, const double *X, const double *Sdir, double lam,
+                             const GmresState *shift_st, const double *Xn, double dt, double *Xt, double *F,
+                             const RedBuf &red, hipStream_t s);
+hipError_t launch_energy3d(const BatchLaunch &bl, const double *X, const RedBuf &red, hipStream_t s);
+hipError_t launch_jacobian3d(const BatchLaunch &bl, const double *X, const double *Xn, double dt, double *J,
+                             hipStream_t s);
+hipError_t launch_spmv3d(const BatchLaunch &bl, const double *J, const double *x, double *y, int transpose,
+                         hipStream_t s);
+hipError_t launch_spmv_dots3d(const BatchLaunch &bl, const double *J, const double *Z, double *V, long vstride, int j,
+                              int transpose, GmresState *st, const RedBuf &red, hipStream_t s);
+hipError_t launch_adjoint_prev3d(const Phys &P, const double *X1, const double *X0, double dt, const double *lam,
+                                 double lam_scale, double *bar, double *out, const RedBuf &red, hipStream_t s);
+hipError_t launch_energy_grad3d(const Phys &P, const double *X, double vol, double *g, const RedBuf &red,
+                                hipStream_t s);
+hipError_t launch_ilu_factor3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
+                               const double *J, double shift, void *fac, int fp32, hipStream_t s);
+hipError_t launch_ras_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
+                              const void *fac, void *ybuf, const double *r, double *z, const GmresState *st,
+                              long vstride, int fp32, hipStream_t s);
+hipError_t launch_ras_t_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl,
+                                const int *cells, int px, int py, int pz, const int *own, const void *fac, void *ybuf,
+                                const double *r, double *z, const GmresState *st, long vstride, int fp32,
+                                hipStream_t s);
+hipError_t launch_export_factors3d(const BoxGeom &G, const void *fac, int fp32, double *out, hipStream_t s);
+
 }  // namespace acch

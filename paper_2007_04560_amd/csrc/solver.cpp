@@ -16,6 +16,7 @@
 #include "../../include/acch.h"
 #include "driver.h"
 #include "kernels.h"
+#include "stencil3d.h"
 
 using namespace acch;
 
@@ -76,6 +77,7 @@ struct acch_ctx {
   KernelTimer timer;
   BatchLaunch bl{};   // single-instance launch shapes
   RasVariant ras{};   // Schwarz variant and owner maps
+  bool d3 = false;    // 3D grid
 };
 
 // ---------------------------------------------------------------------------
@@ -99,11 +101,16 @@ extern "C" void acch_params_default(acch_params *p) {
 }
 
 int acch::validate_params(const acch_params &p) {
-  if (p.dim != 2) return fail(ACCH_EUNSUPPORTED, "only dim = 2 is implemented");
-  if (p.n[0] < 2 || p.n[1] < 2) return fail(ACCH_EINVAL, "need at least 2 cells per direction");
+  if (p.dim != 2 && p.dim != 3) return fail(ACCH_EUNSUPPORTED, "dim must be 2 or 3");
+  const int nd = p.dim;
+  for (int d = 0; d < nd; ++d)
+    if (p.n[d] < 2) return fail(ACCH_EINVAL, "need at least 2 cells per direction");
   if (p.bc != ACCH_BC_PERIODIC && p.bc != ACCH_BC_NEUMANN) return fail(ACCH_EINVAL, "bc");
-  if (p.bc == ACCH_BC_PERIODIC && (p.n[0] < 5 || p.n[1] < 5))
-    return fail(ACCH_EINVAL, "periodic grids need at least 5 cells per direction");
+  for (int d = 0; d < nd; ++d)
+    if (p.bc == ACCH_BC_PERIODIC && p.n[d] < 5)
+      return fail(ACCH_EINVAL, "periodic grids need at least 5 cells per direction");
+  if (nd == 3 && p.ras_type != ACCH_RAS_LEFT)
+    return fail(ACCH_EUNSUPPORTED, "3D runs use the left-restricted Schwarz variant");
   if (!(p.alpha > 0 && p.beta > 0 && p.theta > 0 && p.gamma > 0 && p.rho > 0))
     return fail(ACCH_EINVAL, "alpha, beta, theta, gamma, rho must be positive");
   if (p.S < 1 || p.S > kMaxS) return fail(ACCH_EINVAL, "S out of range");
@@ -119,7 +126,7 @@ int acch::validate_params(const acch_params &p) {
   } else if (!(p.dt_fixed > 0)) {
     return fail(ACCH_EINVAL, "dt_fixed");
   }
-  for (int d = 0; d < 2; ++d) {
+  for (int d = 0; d < nd; ++d) {
     if (p.sub[d] < 1 || p.sub[d] > p.n[d]) return fail(ACCH_EINVAL, "sub");
     if (p.bc == ACCH_BC_PERIODIC) {
       if (p.sub[d] < 2) return fail(ACCH_EINVAL, "periodic directions need at least 2 subdomains");
@@ -130,7 +137,67 @@ int acch::validate_params(const acch_params &p) {
   return ACCH_OK;
 }
 
+// 3D: boxes in x, y, z; levels w = i + 2j + 3k listed cell by cell.
+static int build_geometry3(const acch_params &p, Geometry &geo) {
+  const int nx = p.n[0], ny = p.n[1], nz = p.n[2], d = p.overlap;
+  geo.ncell = (long)nx * ny * nz;
+  std::vector<int> s3[3], l3[3];
+  for (int a = 0; a < 3; ++a) split(p.n[a], p.sub[a], s3[a], l3[a]);
+  int b3[3] = {0, 0, 0};
+  for (int a = 0; a < 3; ++a)
+    for (int v : l3[a]) b3[a] = std::max(b3[a], v + 2 * d);
+  BoxGeom &G = geo.G;
+  G.bw = b3[0];
+  G.bh = b3[1];
+  G.bd = b3[2];
+  G.nlev = (G.bw - 1) + 2 * (G.bh - 1) + 3 * (G.bd - 1) + 1;
+  G.ncb = G.bw * G.bh * G.bd;
+  G.nsub = p.sub[0] * p.sub[1] * p.sub[2];
+  geo.subs.clear();
+  for (int bz = 0; bz < p.sub[2]; ++bz)
+    for (int by = 0; by < p.sub[1]; ++by)
+      for (int bx = 0; bx < p.sub[0]; ++bx) {
+        SubInfo s{};
+        s.ox = s3[0][bx] - d;
+        s.oy = s3[1][by] - d;
+        s.oz = s3[2][bz] - d;
+        s.ex = l3[0][bx] + 2 * d;
+        s.ey = l3[1][by] + 2 * d;
+        s.ez = l3[2][bz] + 2 * d;
+        s.own_x0 = s.own_y0 = s.own_z0 = d;
+        s.own_x1 = d + l3[0][bx];
+        s.own_y1 = d + l3[1][by];
+        s.own_z1 = d + l3[2][bz];
+        geo.subs.push_back(s);
+      }
+  geo.own.assign(nx + ny + nz, 0);
+  int base = 0;
+  geo.min_part = 1 << 30;
+  for (int a = 0; a < 3; ++a) {
+    for (int k = 0; k < p.sub[a]; ++k) {
+      for (int x = s3[a][k]; x < s3[a][k] + l3[a][k]; ++x) geo.own[base + x] = k;
+      geo.min_part = std::min(geo.min_part, l3[a][k]);
+    }
+    base += p.n[a];
+  }
+  // cells of the padded box grouped by level w = i + 2j + 3k
+  geo.lvl.assign(G.nlev + 1, 0);
+  geo.cells.assign(G.ncb, 0);
+  std::vector<int> count(G.nlev, 0);
+  for (int k = 0; k < G.bd; ++k)
+    for (int j = 0; j < G.bh; ++j)
+      for (int i = 0; i < G.bw; ++i) count[i + 2 * j + 3 * k]++;
+  for (int w = 0; w < G.nlev; ++w) geo.lvl[w + 1] = geo.lvl[w] + count[w];
+  std::vector<int> fill(geo.lvl.begin(), geo.lvl.end() - 1);
+  for (int k = 0; k < G.bd; ++k)
+    for (int j = 0; j < G.bh; ++j)
+      for (int i = 0; i < G.bw; ++i) geo.cells[fill[i + 2 * j + 3 * k]++] = i + G.bw * (j + G.bh * k);
+  geo.tile_blocks = 0;
+  return ACCH_OK;
+}
+
 int acch::build_geometry(const acch_params &p, Geometry &geo) {
+  if (p.dim == 3) return build_geometry3(p, geo);
   const int nx = p.n[0], ny = p.n[1], d = p.overlap;
   geo.ncell = (long)nx * ny;
   std::vector<int> sx, lx, sy, ly;
@@ -141,6 +208,7 @@ int acch::build_geometry(const acch_params &p, Geometry &geo) {
   for (int v : ly) bh = std::max(bh, v + 2 * d);
   geo.G.bw = bw;
   geo.G.bh = bh;
+  geo.G.bd = 1;
   geo.G.nlev = bw + 2 * (bh - 1);
   geo.G.ncb = bw * bh;
   geo.G.nsub = p.sub[0] * p.sub[1];
@@ -157,6 +225,10 @@ int acch::build_geometry(const acch_params &p, Geometry &geo) {
       s.own_x1 = d + lx[bx];
       s.own_y0 = d;
       s.own_y1 = d + ly[by];
+      s.oz = 0;
+      s.ez = 1;
+      s.own_z0 = 0;
+      s.own_z1 = 1;
       geo.subs.push_back(s);
     }
   geo.own.assign(nx + ny, 0);
@@ -195,15 +267,20 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_Ft = take(n2);
   L.off_S = take(n2);
   L.off_W = take(n2);
-  L.off_J = take((size_t)kNSlot2D * geo.ncell * sizeof(double));
+  const bool d3 = p.dim == 3;
+  const int nslot = d3 ? kNSlot3D : kNSlot2D;
+  L.off_J = take((size_t)nslot * geo.ncell * sizeof(double));
   L.off_V = take((size_t)(m + 1) * n2);
   L.off_Z = take((size_t)m * n2);
-  const size_t slots = (size_t)geo.G.nlev * geo.G.bh;   // padded wavefront-major cells per box
-  L.off_fac = take((size_t)geo.G.nsub * kNSlot2D * slots * fsz);
-  L.off_y = take((size_t)geo.G.nsub * 2 * (slots + 1) * fsz);   // + one dump slot per box
+  // 2D: padded wavefront-major cells per box; 3D: box cells
+  const size_t slots = d3 ? (size_t)geo.G.ncb : (size_t)geo.G.nlev * geo.G.bh;
+  L.off_fac = take((size_t)geo.G.nsub * nslot * slots * fsz);
+  // 2D: FT pairs + one dump slot per box; 3D: FP64 pairs
+  L.off_y = d3 ? take((size_t)geo.G.nsub * slots * 2 * sizeof(double))
+               : take((size_t)geo.G.nsub * 2 * (slots + 1) * fsz);
   L.off_dump = take(64 * sizeof(double));
   L.off_subs = take(geo.subs.size() * sizeof(SubInfo));
-  L.off_lvl = take(geo.lvl.size() * sizeof(int));
+  L.off_lvl = take((geo.lvl.size() + geo.cells.size()) * sizeof(int));
   L.off_state = take(sizeof(GmresState));
   const size_t nparts = std::max<size_t>((size_t)(kMaxRestart + 1) * kRedBlocks, 2 * (size_t)geo.tile_blocks);
   L.off_part = take(nparts * sizeof(double));
@@ -292,10 +369,56 @@ void timer_end(acch_ctx *c, int slot) {
   } while (0)
 #define LAUNCH(c, expr) LAUNCHK(c, ACCH_KERNEL_OTHER, expr)
 
+// Kernel launches by dimension.
+const int *level_cells(acch_ctx *c) { return c->d_lvl + c->geo.lvl.size(); }
+int fp32_of(acch_ctx *c) { return c->p.precision == ACCH_PREC_MIXED; }
+
+hipError_t run_residual(acch_ctx *c, const double *X, const double *Sdir, double lam, const GmresState *shift,
+                        const double *Xn, double dt, double *Xt, double *F) {
+  return c->d3 ? launch_residual3d(c->bl, X, Sdir, lam, shift, Xn, dt, Xt, F, c->red, c->stream)
+               : launch_residual2d(c->bl, X, Sdir, lam, nullptr, shift, Xn, dt, Xt, F, c->red, c->stream);
+}
+hipError_t run_jacobian(acch_ctx *c, const double *X, const double *Xn, double dt) {
+  return c->d3 ? launch_jacobian3d(c->bl, X, Xn, dt, c->J, c->stream)
+               : launch_jacobian2d(c->bl, X, Xn, dt, c->J, c->stream);
+}
+hipError_t run_spmv(acch_ctx *c, const double *x, double *y, int transpose) {
+  return c->d3 ? launch_spmv3d(c->bl, c->J, x, y, transpose, c->stream)
+               : launch_spmv2d(c->bl, c->J, x, y, transpose, c->stream);
+}
+hipError_t run_spmv_dots(acch_ctx *c, long vs, int j, int transpose) {
+  return c->d3 ? launch_spmv_dots3d(c->bl, c->J, c->Z, c->V, vs, j, transpose, c->st, c->red, c->stream)
+               : launch_spmv_dots2d(c->bl, c->J, c->Z, c->V, vs, j, transpose, c->st, c->red, c->stream);
+}
+hipError_t run_energy(acch_ctx *c, const double *X) {
+  return c->d3 ? launch_energy3d(c->bl, X, c->red, c->stream) : launch_energy2d(c->bl, X, c->red, c->stream);
+}
+hipError_t run_factor(acch_ctx *c) {
+  if (c->d3)
+    return launch_ilu_factor3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->J, c->p.ilu_shift, c->fac,
+                               fp32_of(c), c->stream);
+  return launch_ilu_factor2d(c->bl, c->geo.G, c->d_subs, c->d_lvl, c->J, c->p.ilu_shift, c->fac, fp32_of(c),
+                             c->stream);
+}
+hipError_t run_ras(acch_ctx *c, const double *r, double *z, const GmresState *st, long vs) {
+  if (c->d3)
+    return launch_ras_apply3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->fac, c->ybuf, r, z, st, vs,
+                              fp32_of(c), c->stream);
+  return launch_ras_apply2d(c->bl, c->geo.G, c->d_subs, c->d_lvl, c->fac, c->ybuf, r, z, c->dump, st, vs, fp32_of(c),
+                            c->stream, c->ras);
+}
+hipError_t run_ras_t(acch_ctx *c, const double *r, double *z, const GmresState *st, long vs) {
+  if (c->d3)
+    return launch_ras_t_apply3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->p.sub[0], c->p.sub[1],
+                                c->p.sub[2], c->d_own, c->fac, c->ybuf, r, z, st, vs, fp32_of(c), c->stream);
+  return launch_ras_t_apply2d(c->geo.G, c->d_subs, c->P.nx, c->P.ny, c->P.periodic, c->p.sub[0], c->p.sub[1],
+                              c->d_own, c->d_own + c->P.nx, c->p.ras_type, c->fac, c->tbox, r, z, st, vs, fp32_of(c),
+                              c->stream);
+}
+
 int residual_eval(acch_ctx *c, const double *X, const double *Sdir, double lam, const GmresState *shift,
                   const double *Xn, double dt, double *Xt, double *F, double &f2, double &bad) {
-  LAUNCHK(c, ACCH_KERNEL_RESIDUAL,
-          launch_residual2d(c->bl, X, Sdir, lam, nullptr, shift, Xn, dt, Xt, F, c->red, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_RESIDUAL, run_residual(c, X, Sdir, lam, shift, Xn, dt, Xt, F));
   int rc = sync_read(c, c->red.out, c->host->vals, 2 * sizeof(double));
   if (rc) return rc;
   f2 = c->host->vals[0];
@@ -304,17 +427,13 @@ int residual_eval(acch_ctx *c, const double *X, const double *Sdir, double lam, 
 }
 
 int factor(acch_ctx *c) {
-  LAUNCHK(c, ACCH_KERNEL_FACTOR, launch_ilu_factor2d(c->bl, c->geo.G, c->d_subs, c->d_lvl, c->J,
-                                c->p.ilu_shift, c->fac, c->p.precision == ACCH_PREC_MIXED, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_FACTOR, run_factor(c));
   c->factored = true;
   return ACCH_OK;
 }
 
 int precondition_t(acch_ctx *c, const double *r, double *z, const GmresState *st, long vs) {
-  LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_t_apply2d(c->geo.G, c->d_subs, c->P.nx, c->P.ny, c->P.periodic, c->p.sub[0],
-                                                   c->p.sub[1], c->d_own, c->d_own + c->P.nx, c->p.ras_type, c->fac,
-                                                   c->tbox, r, z, st, vs, c->p.precision == ACCH_PREC_MIXED,
-                                                   c->stream));
+  LAUNCHK(c, ACCH_KERNEL_RAS, run_ras_t(c, r, z, st, vs));
   return ACCH_OK;
 }
 
@@ -325,7 +444,6 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int 
   const long n2 = 2 * c->geo.ncell;
   const long vs = n2;
   const int m = c->p.gmres_restart;
-  const int fp32 = c->p.precision == ACCH_PREC_MIXED;
   const int project = transpose ? 0 : c->p.mass_projection;
   LAUNCH(c, launch_reset_state(c->bl, c->st, c->stream));
   its = 0;
@@ -333,7 +451,7 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int 
   const size_t tail = offsetof(GmresState, beta);
   GmresState hs{};
   for (int cycle = 0; cycle < c->p.gmres_max_restarts; ++cycle) {
-    if (cycle > 0) LAUNCHK(c, ACCH_KERNEL_SPMV, launch_spmv2d(c->bl, c->J, S, c->W, transpose, c->stream));
+    if (cycle > 0) LAUNCHK(c, ACCH_KERNEL_SPMV, run_spmv(c, S, c->W, transpose));
     LAUNCHK(c, ACCH_KERNEL_GMRES_START, launch_gmres_start(c->bl, F, cycle > 0 ? c->W : nullptr, c->V, c->st, m, c->p.gmres_rtol,
                                  c->p.gmres_atol, c->red, c->stream));
     int launched = 0;
@@ -344,12 +462,9 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int 
           int rc = precondition_t(c, c->V, c->Z, c->st, vs);
           if (rc) return rc;
         } else {
-          LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->bl, c->geo.G, c->d_subs, c->d_lvl,
-                                                         c->fac, c->ybuf, c->V, c->Z, c->dump, c->st, vs, fp32,
-                                                         c->stream, c->ras));
+          LAUNCHK(c, ACCH_KERNEL_RAS, run_ras(c, c->V, c->Z, c->st, vs));
         }
-        LAUNCHK(c, ACCH_KERNEL_SPMV_DOTS,
-                launch_spmv_dots2d(c->bl, c->J, c->Z, c->V, vs, launched, transpose, c->st, c->red, c->stream));
+        LAUNCHK(c, ACCH_KERNEL_SPMV_DOTS, run_spmv_dots(c, vs, launched, transpose));
         LAUNCHK(c, ACCH_KERNEL_ORTH, launch_gmres_orth(c->bl, c->V, vs, launched, c->st, c->red, c->stream));
       }
       LAUNCHK(c, ACCH_KERNEL_GMRES_UPDATE, launch_gmres_update(c->bl, S, c->Z, vs, c->st, cycle > 0, project, c->red, c->stream));
@@ -408,7 +523,7 @@ int nks_solve(acch_ctx *c, double dt, SolveStats &stats) {
   const double tol = std::max(c->p.newton_rtol * fnorm, c->p.newton_atol);
   if (fnorm <= tol) return ACCH_OK;
   for (int it = 1; it <= c->p.newton_max_it; ++it) {
-    LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->bl, c->X, c->Xn, dt, c->J, c->stream));
+    LAUNCHK(c, ACCH_KERNEL_JACOBIAN, run_jacobian(c, c->X, c->Xn, dt));
     if (it == 1 || !c->p.ilu_reuse) {
       rc = factor(c);
       if (rc) return rc;
@@ -433,7 +548,7 @@ int nks_solve(acch_ctx *c, double dt, SolveStats &stats) {
 }
 
 int energy_mass(acch_ctx *c, const double *X, double &E, double &M) {
-  LAUNCHK(c, ACCH_KERNEL_ENERGY, launch_energy2d(c->bl, X, c->red, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_ENERGY, run_energy(c, X));
   int rc = sync_read(c, c->red.out, c->host->vals, 2 * sizeof(double));
   if (rc) return rc;
   E = c->host->vals[0] * c->hvol;
@@ -517,11 +632,15 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->red.out = (double *)(c->ws + L.off_out);
   c->P.nx = p.n[0];
   c->P.ny = p.n[1];
+  c->P.nz = p.dim == 3 ? p.n[2] : 1;
   c->P.periodic = p.bc == ACCH_BC_PERIODIC;
   const double hx = p.L[0] / p.n[0], hy = p.L[1] / p.n[1];
+  const double hz = p.dim == 3 ? p.L[2] / p.n[2] : 1.0;
   c->P.wx = 1.0 / (hx * hx);
   c->P.wy = 1.0 / (hy * hy);
-  c->hvol = hx * hy;
+  c->P.wz = p.dim == 3 ? 1.0 / (hz * hz) : 0.0;
+  c->hvol = hx * hy * hz;
+  c->d3 = p.dim == 3;
   c->P.alpha = p.alpha;
   c->P.beta = p.beta;
   c->P.theta = p.theta;
@@ -550,6 +669,9 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
                      c->stream) != hipSuccess ||
       hipMemcpyAsync(c->d_lvl, c->geo.lvl.data(), c->geo.lvl.size() * sizeof(int), hipMemcpyHostToDevice,
                      c->stream) != hipSuccess ||
+      (!c->geo.cells.empty() &&
+       hipMemcpyAsync(c->d_lvl + c->geo.lvl.size(), c->geo.cells.data(), c->geo.cells.size() * sizeof(int),
+                      hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
       hipMemcpyAsync(c->d_own, c->geo.own.data(), c->geo.own.size() * sizeof(int), hipMemcpyHostToDevice,
                      c->stream) != hipSuccess ||
       hipMemsetAsync(c->red.counter, 0, 64, c->stream) != hipSuccess ||
@@ -751,21 +873,21 @@ extern "C" int acch_residual(acch_ctx *c, const double *X, const double *Xn, dou
 
 extern "C" int acch_jacobian(acch_ctx *c, const double *X, const double *Xn, double dt) {
   if (!c || !X || !Xn || !(dt > 0)) return fail(ACCH_EINVAL, "bad arguments");
-  LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->bl, X, Xn, dt, c->J, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_JACOBIAN, run_jacobian(c, X, Xn, dt));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;
 }
 
 extern "C" int acch_apply_jacobian(acch_ctx *c, const double *x, double *y) {
   if (!c || !x || !y) return fail(ACCH_EINVAL, "bad arguments");
-  LAUNCH(c, launch_spmv2d(c->bl, c->J, x, y, 0, c->stream));
+  LAUNCH(c, run_spmv(c, x, y, 0));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;
 }
 
 extern "C" int acch_apply_jacobian_transpose(acch_ctx *c, const double *x, double *y) {
   if (!c || !x || !y) return fail(ACCH_EINVAL, "bad arguments");
-  LAUNCHK(c, ACCH_KERNEL_SPMV, launch_spmv2d(c->bl, c->J, x, y, 1, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_SPMV, run_spmv(c, x, y, 1));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;
 }
@@ -789,7 +911,9 @@ extern "C" int acch_precondition_transpose(acch_ctx *c, const double *r, double 
 
 extern "C" int acch_energy_gradient(acch_ctx *c, const double *X, double *g, double *dparams) {
   if (!c || !g || !dparams) return fail(ACCH_EINVAL, "bad arguments");
-  LAUNCHK(c, ACCH_KERNEL_ENERGY, launch_energy_grad2d(c->P, X ? X : c->Xn, c->hvol, g, c->red, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_ENERGY,
+          c->d3 ? launch_energy_grad3d(c->P, X ? X : c->Xn, c->hvol, g, c->red, c->stream)
+                : launch_energy_grad2d(c->P, X ? X : c->Xn, c->hvol, g, c->red, c->stream));
   int rc = sync_read(c, c->red.out, c->host->vals, 4 * sizeof(double));
   if (rc) return rc;
   for (int k = 0; k < 4; ++k) dparams[k] = c->host->vals[k];
@@ -802,7 +926,7 @@ extern "C" int acch_adjoint_step(acch_ctx *c, const double *X1, const double *X0
   if (!(dt > 0.0)) return fail(ACCH_EINVAL, "dt must be positive");
   int rc = adjoint_ready(c);
   if (rc) return rc;
-  LAUNCHK(c, ACCH_KERNEL_JACOBIAN, launch_jacobian2d(c->bl, X1, X0, dt, c->J, c->stream));
+  LAUNCHK(c, ACCH_KERNEL_JACOBIAN, run_jacobian(c, X1, X0, dt));
   rc = factor(c);
   if (rc) return rc;
   int its = 0;
@@ -812,7 +936,8 @@ extern "C" int acch_adjoint_step(acch_ctx *c, const double *X1, const double *X0
   if (resid) *resid = res;
   if (rc) return rc;
   // g_prev = (dF/dX0)^T S and red.out = S . dF/dp, i.e. -lambda . dF/dp
-  LAUNCH(c, launch_adjoint_prev2d(c->P, X1, X0, dt, c->S, 1.0, c->W, g_prev, c->red, c->stream));
+  LAUNCH(c, c->d3 ? launch_adjoint_prev3d(c->P, X1, X0, dt, c->S, 1.0, c->W, g_prev, c->red, c->stream)
+                  : launch_adjoint_prev2d(c->P, X1, X0, dt, c->S, 1.0, c->W, g_prev, c->red, c->stream));
   rc = sync_read(c, c->red.out, c->host->vals, 4 * sizeof(double));
   if (rc) return rc;
   for (int k = 0; k < 4; ++k) dparams[k] += c->host->vals[k];
@@ -830,8 +955,7 @@ extern "C" int acch_factor(acch_ctx *c) {
 extern "C" int acch_precondition(acch_ctx *c, const double *r, double *z) {
   if (!c || !r || !z) return fail(ACCH_EINVAL, "bad arguments");
   if (!c->factored) return fail(ACCH_EINVAL, "no factorisation: call acch_factor first");
-  LAUNCHK(c, ACCH_KERNEL_RAS, launch_ras_apply2d(c->bl, c->geo.G, c->d_subs, c->d_lvl, c->fac, c->ybuf, r, z,
-                               c->dump, nullptr, 0, c->p.precision == ACCH_PREC_MIXED, c->stream, c->ras));
+  LAUNCHK(c, ACCH_KERNEL_RAS, run_ras(c, r, z, nullptr, 0));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return ACCH_OK;
 }
@@ -851,8 +975,9 @@ extern "C" int acch_export(acch_ctx *c, int which, void *out, size_t *bytes) {
   if (!c || !bytes) return fail(ACCH_EINVAL, "bad arguments");
   const BoxGeom &G = c->geo.G;
   size_t need = 0;
-  if (which == ACCH_EXPORT_JACOBIAN) need = (size_t)kNSlot2D * c->geo.ncell * sizeof(double);
-  else if (which == ACCH_EXPORT_FACTORS) need = (size_t)G.nsub * kNSlot2D * G.ncb * sizeof(double);
+  const int nslot = c->d3 ? kNSlot3D : kNSlot2D;
+  if (which == ACCH_EXPORT_JACOBIAN) need = (size_t)nslot * c->geo.ncell * sizeof(double);
+  else if (which == ACCH_EXPORT_FACTORS) need = (size_t)G.nsub * nslot * G.ncb * sizeof(double);
   else if (which == ACCH_EXPORT_BOXES) need = (size_t)G.nsub * 4 * sizeof(int);
   else return fail(ACCH_EINVAL, "unknown export");
   if (!out) {
@@ -864,8 +989,11 @@ extern "C" int acch_export(acch_ctx *c, int which, void *out, size_t *bytes) {
     HIP_TRY(hipMemcpyAsync(out, c->J, need, hipMemcpyDeviceToDevice, c->stream));
   } else if (which == ACCH_EXPORT_FACTORS) {
     if (!c->factored) return fail(ACCH_EINVAL, "no factorisation");
-    LAUNCH(c, launch_export_factors2d(G, c->d_lvl, c->fac, c->p.precision == ACCH_PREC_MIXED, (double *)out,
-                                      c->stream));
+    if (c->d3)
+      LAUNCH(c, launch_export_factors3d(G, c->fac, c->p.precision == ACCH_PREC_MIXED, (double *)out, c->stream));
+    else
+      LAUNCH(c, launch_export_factors2d(G, c->d_lvl, c->fac, c->p.precision == ACCH_PREC_MIXED, (double *)out,
+                                        c->stream));
   } else {
     std::vector<int> b;
     for (const SubInfo &s : c->geo.subs) {

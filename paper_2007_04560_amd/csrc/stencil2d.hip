@@ -433,7 +433,7 @@ int reduce_blocks(long n) {
 }
 
 void family_blocks(const Phys &P, int nsub, int (&nb)[kFamilies]) {
-  const long n = (long)P.nx * P.ny;
+  const long n = (long)P.nx * P.ny * (P.nz > 0 ? P.nz : 1);
   nb[kFamTile] = ((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY);
   nb[kFamCell] = reduce_blocks(n);
   nb[kFamElem] = reduce_blocks(2 * n);
@@ -444,7 +444,7 @@ BatchLaunch single_launch(const Phys &P, int nsub) {
   BatchLaunch bl{};
   bl.P0 = P;
   bl.count = 1;
-  bl.ncell = (long)P.nx * P.ny;
+  bl.ncell = (long)P.nx * P.ny * (P.nz > 0 ? P.nz : 1);
   family_blocks(P, nsub, bl.grid);
   return bl;
 }
