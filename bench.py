@@ -45,6 +45,13 @@ WORKLOADS = {
                         text="neumann2048: 2D Neumann 2048x2048, 50 adaptive steps dt in [1e-4,1e-1], FP64 NKS "
                              "with FP32 subdomain ILU(0) factors/solves, left-RAS 16x16 overlap 2, shift 0.02, "
                              "GMRES(30), tol 1e-8"),
+    # the 3D Neumann configuration
+    "neumann128_3d": dict(name="neumann128_3d", shape=(128, 128, 128), bc="neumann", sub=(4, 4, 4), overlap=1,
+                          adaptive=True, dt_min=1e-4, dt_max=2.0, eta0=100.0, newton_rtol=1e-8, newton_atol=1e-13,
+                          gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30, ilu_shift=0.02, precision="fp64",
+                          seed=0, steps=20,
+                          text="neumann128_3d: 3D Neumann 128^3, 20 adaptive steps dt in [1e-4,2] (eta0 = 100), FP64 "
+                               "NKS, left-RAS 4x4x4 overlap 1, ILU(0) shift 0.02, GMRES(30), tol 1e-8"),
 }
 # 96 independent periodic instances of uneven size (N in {96,128,192,256}), theta and
 # gamma drawn per instance, 10 steps at dt = 1e-3, all instances in one batched solve
@@ -238,16 +245,17 @@ def batch_line(args):
     return 0
 
 
-def adjoint_line(args):
-    """Gradient of the final energy after `steps` accepted steps of the 512x512 workload
-    with respect to (u0, v0, alpha, beta, theta, gamma), checkpoints every 5 steps: the
-    forward run, then the backward pass (segment recomputation + transposed solves)."""
+def adjoint_line(args, w=None):
+    """Gradient of the final energy after `steps` accepted steps of a workload (512x512
+    periodic or the 128^3 Neumann one) with respect to (u0, v0, alpha, beta, theta,
+    gamma), checkpoints every 5 steps: the forward run, then the backward pass
+    (segment recomputation + transposed solves)."""
     import numpy as np
     import torch
     from acch_inputs import random_ic
     from paper_2007_04560_amd import Solver
     from paper_2007_04560_amd.adjoint import final_energy
-    w = WORKLOAD
+    w = w or WORKLOAD
     u0, v0 = random_ic(w["shape"], w["seed"])
     kw = dict(bc=w["bc"], sub=w["sub"], overlap=w["overlap"], adaptive=w["adaptive"], dt_min=w["dt_min"],
               dt_max=w["dt_max"], eta0=w["eta0"], newton_rtol=w["newton_rtol"], newton_atol=w["newton_atol"],
@@ -279,19 +287,25 @@ def adjoint_line(args):
     s.close()
     avg_s = ras_ms / ras_n * 1e-3
     owned = u0.size / info["nsub"]
-    bytes_launch = ras_bytes_per_cell(info["box_w"] * info["box_h"], owned) * u0.size
+    if u0.ndim == 3:
+        box = 1.0
+        for n_a, p_a in zip(reversed(w["shape"]), w["sub"]):
+            box *= n_a / p_a + 2 * w["overlap"]
+        bytes_launch = ras_bytes_per_cell(box, owned, nslot=40) * u0.size
+    else:
+        bytes_launch = ras_bytes_per_cell(info["box_w"] * info["box_h"], owned) * u0.size
     achieved = bytes_launch / avg_s / 1e9
     line = {"metric": "gradient time of the final energy (forward + adjoint)", "value": round(t2 - t0, 4),
             "unit": "s", "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": round((t2 - t0) / steps * 1e3, 3),
             "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": f"adjoint of periodic512: dE/d(u0, v0, alpha, beta, theta, gamma) after {steps} "
+            "config": {"workload": f"adjoint of {w['name']}: dE/d(u0, v0, alpha, beta, theta, gamma) after {steps} "
                                    "adaptive steps, dt frozen, checkpoints every 5 steps",
                        "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
                        "energy": float(E.detach()), "grad_params": [float(x) for x in params.grad],
                        "grad_v0_norm": float(tv.grad.norm())},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                         "kernel": "k_ras_t_sweep2d + k_ras_t_gather2d (transposed Schwarz)",
+                         "kernel": "transposed Schwarz (sweep + gather)",
                          "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": int(bytes_launch)}}
     print(json.dumps(line), flush=True)
     return 0
@@ -332,7 +346,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP-event timers")
-    ap.add_argument("--workload", default="periodic512", choices=sorted(WORKLOADS) + ["batch96", "adjoint512"])
+    ap.add_argument("--workload", default="periodic512",
+                    choices=sorted(WORKLOADS) + ["batch96", "adjoint512", "adjoint3d128"])
     ap.add_argument("--no-sequential", action="store_true", help="batch96: skip the one-by-one FP64 comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 64 MiB FP64 tensor 3 times (reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -347,13 +362,13 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copied 64 MiB FP64 three times"}), flush=True)
         return 0
-    if args.workload == "adjoint512":
+    if args.workload in ("adjoint512", "adjoint3d128"):
         if args.gpus != 1:
             print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
             return 2
         if args.steps is None:
             args.steps = 20
-        return adjoint_line(args)
+        return adjoint_line(args, WORKLOADS["periodic512" if args.workload == "adjoint512" else "neumann128_3d"])
     if args.workload == "batch96":
         if args.gpus != 1:
             print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
@@ -381,15 +396,21 @@ def main():
     dof = 2 * r["ncell"]
     value = dof * newton_its / r["elapsed"]
     info = r["info"]
-    box = info["box_w"] * info["box_h"]
+    if len(w["shape"]) == 3:   # boxes of (n/p + 2 overlap)^3 cells, 40 slots per cell
+        box = 1.0
+        for n_a, p_a in zip(reversed(w["shape"]), w["sub"]):
+            box *= n_a / p_a + 2 * w["overlap"]
+    else:
+        box = info["box_w"] * info["box_h"]
     owned = r["ncell"] / info["nsub"]
+    nslot = 40 if len(w["shape"]) == 3 else 24
     roofline = None
     stats = r["stats"]
     if stats and stats["ras"][1] > 0:
         ras_ms, ras_n = stats["ras"]
         avg_s = ras_ms / ras_n * 1e-3
         sp = 4 if w["precision"] == "mixed" else 8
-        bytes_launch = ras_bytes_per_cell(box, owned, sp=sp) * r["ncell"]
+        bytes_launch = ras_bytes_per_cell(box, owned, nslot=nslot, sp=sp) * r["ncell"]
         achieved = bytes_launch / avg_s / 1e9
         dom = max(stats, key=lambda k: stats[k][0])
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
