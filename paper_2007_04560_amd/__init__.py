@@ -4,7 +4,7 @@ The per-time-step Newton–Krylov–Schwarz solve of scheme (2.20) runs in the H
 library libacch.so (include/acch.h); this package only builds and binds it.
 """
 from .binding import (AcchError, BatchSolver, Params, Solver, StepInfo, load_library, make_params,  # noqa: F401
-                      LIB_PATH, EXPORTED)
+                      set_option, LIB_PATH, EXPORTED)
 
-__all__ = ["AcchError", "BatchSolver", "Params", "Solver", "StepInfo", "load_library", "make_params", "LIB_PATH",
-           "EXPORTED"]
+__all__ = ["AcchError", "BatchSolver", "Params", "Solver", "StepInfo", "load_library", "make_params", "set_option",
+           "LIB_PATH", "EXPORTED"]

@@ -139,6 +139,17 @@ def _check(lib, rc: int):
         raise AcchError(rc, f"{lib.acch_strerror(rc).decode()}: {lib.acch_last_error().decode()}")
 
 
+_OPTIONS = {"ras_prefetch": 0, "ras3d_window": 1}
+
+
+def set_option(name: str, value: int):
+    """Process-wide tuning option of the library (acch_set_option): "ras_prefetch"
+    (2D triangular-solve prefetch depth) or "ras3d_window" (1: keep the recent levels
+    of a 3D box in LDS when it fits, 0: whole box in device memory)."""
+    lib = load_library()
+    _check(lib, lib.acch_set_option(None, _OPTIONS[name], int(value)))
+
+
 _BC = {"periodic": 0, "neumann": 1}
 _SCHWARZ = {"left": 0, "right": 1, "classical": 2}
 _PREC = {"fp64": 0, "mixed": 1}

@@ -39,6 +39,7 @@ struct BoxGeom {
   int nlev;               // levels of the i + 2j wavefront: bw + 2(bh-1)
   int ncb;                // bw * bh (cells of a box; storage is padded to nlev * bh slots)
   int nsub;
+  int wmax;               // 3D: most cells on one level
 };
 
 // One subdomain: unwrapped box origin, its real extent inside the padded box and

@@ -46,7 +46,8 @@ struct Geometry {
   BoxGeom G{};
   std::vector<SubInfo> subs;
   std::vector<int> lvl;  // nlev + 1 prefix counts
-  std::vector<int> cells;  // 3D: box cells (i + bw (j + bh k)) in level order
+  std::vector<int> cells;  // 3D: box cells (i | j << 10 | k << 20) in level order, then
+                           // the windowed apply's column lists (when G.wmax > 0)
   std::vector<int> own;  // owner subdomain of each grid column (nx), then of each row (ny)
   int min_part = 0;      // smallest owned width / height
   int tile_blocks = 0;

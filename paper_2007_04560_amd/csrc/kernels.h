@@ -34,6 +34,12 @@ hipError_t launch_finalize_dots(int j, const RedBuf &red, const BatchLaunch &bl,
 int schwarz_waves(const BoxGeom &G);
 void set_ras_prefetch(int d);
 int get_ras_prefetch();
+void set_ras3d_window(bool on);
+// 3D windowed Schwarz apply: threads per box and box columns (j, k) per thread.  The
+// host lists each thread's columns after the level-ordered cells, in order and then
+// in reverse ([2][kWin3DCols][kWin3DThreads], -1 unused; wmax = 0: no list).
+constexpr int kWin3DThreads = 512;
+constexpr int kWin3DCols = 8;
 
 // stencil2d.hip.  lam_b (per instance, may be null: lam0) and shift_st (the mass
 // shift of each instance's GMRES state, may be null) describe the trial state.

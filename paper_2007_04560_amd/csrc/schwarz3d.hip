@@ -6,8 +6,10 @@
 // 25-point set, v on the 7-point star; v-row: v on the star, u at the cell).  Every
 // earlier neighbour in that order lies on an earlier level w = i + 2j + 3k, so the
 // factorisation and the sweeps walk the levels in order, one workgroup per box and
-// a host-built list of each level's cells; values of a box live in a global box
-// buffer (a box of 34^3 cells does not fit in LDS) and a barrier separates levels.
+// a host-built list of each level's cells, a barrier separating levels.  The
+// general kernels keep a box's values in a device-memory box buffer (a box of 34^3
+// cells does not fit in LDS); the windowed apply keeps only the levels a sweep still
+// reads in LDS (see k_ras_apply3d_win).
 //
 // Factor storage: 40 values per box cell (box-local index i + bw (j + bh k)): the
 // u-row's 32 pattern entries in column order (15 multipliers of L, then U with the
@@ -116,6 +118,21 @@ ACCH_DEV bool owned3(const SubInfo &si, int i, int j, int k) {
   return i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1 && k >= si.own_z0 && k < si.own_z1;
 }
 
+// Index of box cell (i+dx, j+dy, k+dz), or `self` when it lies outside the box (the
+// caller masks the term), so every load of a sweep is unconditional and the loads of
+// a cell can all be in flight together.
+ACCH_DEV int nb_or(const Box3 &B, int i, int j, int k, int dx, int dy, int dz, int self, bool &in) {
+  in = B.in(i + dx, j + dy, k + dz);
+  return in ? B.at(i + dx, j + dy, k + dz) : self;
+}
+
+// Level lists hold box coordinates packed as i | j << 10 | k << 20.
+ACCH_DEV void unpack(int c, int &i, int &j, int &k) {
+  i = c & 1023;
+  j = (c >> 10) & 1023;
+  k = c >> 20;
+}
+
 ACCH_DEV void decode(int e, const Box3 &B, int &i, int &j, int &k) {
   i = e % B.bw;
   const int r = e / B.bw;
@@ -155,18 +172,19 @@ ACCH_DEV void load_urow(const FT *rec, int first, double (&prow)[NE]) {
   for (int e = 0; e < NE; ++e) prow[e] = (double)rec[first + e];
 }
 
+// A pivot column outside the box reads the record of box cell 0, whatever it holds,
+// and masks it to zero, so the loads carry no branch.
 template <int P, typename FT>
 ACCH_DEV void pivot_u(double (&a)[kUN], const FT *fk, const Box3 &B, int i, int j, int k) {
   constexpr Col3 pc = ucol3(P);
-  const int qi = i + pc.dx, qj = j + pc.dy, qk = k + pc.dz;
-  if (!B.in(qi, qj, qk)) {
-    a[P] = 0.0;
-    return;
-  }
-  const FT *rec = fk + (long)B.at(qi, qj, qk) * kNSlot3D;
+  bool in;
+  const int q = nb_or(B, i, j, k, pc.dx, pc.dy, pc.dz, 0, in);
+  const FT *rec = fk + (long)q * kNSlot3D;
   constexpr int ne = (pc.t == 0) ? kUN - kUD : kVN - kVD;
   double prow[ne];
   load_urow<FT, ne>(rec, pc.t == 0 ? kFA + kUD : kFB + kVD, prow);
+#pragma unroll
+  for (int e = 0; e < ne; ++e) prow[e] = in ? prow[e] : 0.0;
   const double l = a[P] * prow[0];
   a[P] = l;
   elim3_u_row<P>(a, l, prow, std::make_integer_sequence<int, ne - 1>{});
@@ -175,14 +193,13 @@ ACCH_DEV void pivot_u(double (&a)[kUN], const FT *fk, const Box3 &B, int i, int 
 template <int P, typename FT>
 ACCH_DEV void pivot_v(double (&b)[kVN], const FT *fk, const Box3 &B, int i, int j, int k) {
   constexpr Col3 pc = vcol3(P);
-  const int qi = i + pc.dx, qj = j + pc.dy, qk = k + pc.dz;
-  if (!B.in(qi, qj, qk)) {
-    b[P] = 0.0;
-    return;
-  }
-  const FT *rec = fk + (long)B.at(qi, qj, qk) * kNSlot3D;
+  bool in;
+  const int q = nb_or(B, i, j, k, pc.dx, pc.dy, pc.dz, 0, in);
+  const FT *rec = fk + (long)q * kNSlot3D;
   double prow[kVN - kVD];
   load_urow<FT, kVN - kVD>(rec, kFB + kVD, prow);
+#pragma unroll
+  for (int e = 0; e < kVN - kVD; ++e) prow[e] = in ? prow[e] : 0.0;
   const double l = b[P] * prow[0];
   b[P] = l;
   elim3_v_row<P>(b, l, prow, std::make_integer_sequence<int, kVN - kVD - 1>{});
@@ -210,9 +227,9 @@ __global__ __launch_bounds__(256) void k_ilu_factor3d(Phys P, BoxGeom G, const S
   FT *fk = fac + (long)blockIdx.x * G.ncb * kNSlot3D;
   for (int w = 0; w < G.nlev; ++w) {
     for (int q = lvl[w] + threadIdx.x; q < lvl[w + 1]; q += blockDim.x) {
-      const int e = cells[q];
       int i, j, k;
-      decode(e, B, i, j, k);
+      unpack(cells[q], i, j, k);
+      const int e = B.at(i, j, k);
       const long g = box3_to_global(si, i, j, k, P);
       double a[kUN], b[kVN];
       if (g >= 0) {
@@ -285,29 +302,30 @@ __global__ __launch_bounds__(256) void k_ras_apply3d(Phys P, BoxGeom G, const Su
     yb[e] = g >= 0 ? make_double2(sc * r[g], sc * r[n + g]) : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  auto val = [&](int i, int j, int k, int t) -> double {
-    const double2 v = yb[B.at(i, j, k)];
-    return t == 0 ? v.x : v.y;
-  };
   // L y = R r
   for (int w = 0; w < G.nlev; ++w) {
     for (int q = lvl[w] + threadIdx.x; q < lvl[w + 1]; q += blockDim.x) {
-      const int e = cells[q];
       int i, j, k;
-      decode(e, B, i, j, k);
+      unpack(cells[q], i, j, k);
+      const int e = B.at(i, j, k);
       const FT *rec = fk + (long)e * kNSlot3D;
-      double yu = yb[e].x, yv = yb[e].y;
+      const double2 y0 = yb[e];
+      double yu = y0.x, yv = y0.y;
 #pragma unroll
       for (int c = 0; c < kUL; ++c) {
         const Col3 cc = ucol3(c);
-        const int ii = i + cc.dx, jj = j + cc.dy, kk = k + cc.dz;
-        if (B.in(ii, jj, kk)) yu -= (double)rec[kFA + c] * val(ii, jj, kk, cc.t);
+        bool in;
+        const double2 v = yb[nb_or(B, i, j, k, cc.dx, cc.dy, cc.dz, e, in)];
+        const double l = in ? (double)rec[kFA + c] : 0.0;
+        yu = fma(-l, cc.t == 0 ? v.x : v.y, yu);
       }
 #pragma unroll
       for (int c = 0; c < kVL - 1; ++c) {
         const Col3 cc = vcol3(c);
-        const int ii = i + cc.dx, jj = j + cc.dy, kk = k + cc.dz;
-        if (B.in(ii, jj, kk)) yv -= (double)rec[kFB + c] * val(ii, jj, kk, cc.t);
+        bool in;
+        const double2 v = yb[nb_or(B, i, j, k, cc.dx, cc.dy, cc.dz, e, in)];
+        const double l = in ? (double)rec[kFB + c] : 0.0;
+        yv = fma(-l, cc.t == 0 ? v.x : v.y, yv);
       }
       yv -= (double)rec[kFB + kVL - 1] * yu;
       yb[e] = make_double2(yu, yv);
@@ -317,24 +335,29 @@ __global__ __launch_bounds__(256) void k_ras_apply3d(Phys P, BoxGeom G, const Su
   // U x = y
   for (int w = G.nlev - 1; w >= 0; --w) {
     for (int q = lvl[w] + threadIdx.x; q < lvl[w + 1]; q += blockDim.x) {
-      const int e = cells[q];
       int i, j, k;
-      decode(e, B, i, j, k);
+      unpack(cells[q], i, j, k);
+      const int e = B.at(i, j, k);
       const FT *rec = fk + (long)e * kNSlot3D;
-      double xv = yb[e].y;
+      const double2 y0 = yb[e];
+      double xv = y0.y;
 #pragma unroll
       for (int c = kVD + 1; c < kVN; ++c) {
         const Col3 cc = vcol3(c);
-        const int ii = i + cc.dx, jj = j + cc.dy, kk = k + cc.dz;
-        if (B.in(ii, jj, kk)) xv -= (double)rec[kFB + c] * val(ii, jj, kk, cc.t);
+        bool in;
+        const double2 v = yb[nb_or(B, i, j, k, cc.dx, cc.dy, cc.dz, e, in)];
+        const double u = in ? (double)rec[kFB + c] : 0.0;
+        xv = fma(-u, cc.t == 0 ? v.x : v.y, xv);
       }
       xv *= (double)rec[kFB + kVD];
-      double xu = yb[e].x - (double)rec[kFA + kUD + 1] * xv;   // column (0,0,0,v)
+      double xu = y0.x - (double)rec[kFA + kUD + 1] * xv;   // column (0,0,0,v)
 #pragma unroll
       for (int c = kUD + 2; c < kUN; ++c) {
         const Col3 cc = ucol3(c);
-        const int ii = i + cc.dx, jj = j + cc.dy, kk = k + cc.dz;
-        if (B.in(ii, jj, kk)) xu -= (double)rec[kFA + c] * val(ii, jj, kk, cc.t);
+        bool in;
+        const double2 v = yb[nb_or(B, i, j, k, cc.dx, cc.dy, cc.dz, e, in)];
+        const double u = in ? (double)rec[kFA + c] : 0.0;
+        xu = fma(-u, cc.t == 0 ? v.x : v.y, xu);
       }
       xu *= (double)rec[kFA + kUD];
       yb[e] = make_double2(xu, xv);
@@ -348,6 +371,210 @@ __global__ __launch_bounds__(256) void k_ras_apply3d(Phys P, BoxGeom G, const Su
     if (g >= 0 && owned3(si, i, j, k)) {
       z[g] = yb[e].x;
       z[n + g] = yb[e].y;
+    }
+  }
+}
+
+// ---- z = M^{-1} r through a rolling LDS window (left-restricted) ------------------
+// A sweep at level w reads neighbours at most 6 levels away (offset (0,0,-2) forward,
+// (0,0,+2) backward), and the cells of one level differ in (j, k).  LDS slot
+// (i mod 8, j, k) therefore holds every value a level reads: a cell's slot is next
+// written 8 levels later, by (i + 8, j, k) forward or (i - 8, j, k) backward.  The
+// window starts zeroed and only ever holds finite values, and a factor entry of a
+// column outside the box is exactly zero (factorisation above), so a neighbour read
+// needs no mask, only an address kept inside the window.
+//
+// Threads own box columns (j, k) (host-built lists, columns of one thread busy on
+// disjoint level ranges), so a thread finds its cell of a level from a column cursor
+// and walks a column's cells in storage order.  The operands of a level (right-hand
+// side or forward result, factor entries) are loaded two levels ahead, and the
+// barrier between levels waits for LDS only, so those loads stay in flight across it.
+// Every device-memory access of the sweeps is unconditional, so the count of
+// outstanding accesses is the same on every path and the compiler waits for exactly
+// the level it needs: an idle thread loads the operands of box cell (0,0,0) and
+// writes to a spare pair after the box buffers.  The forward result goes to the box
+// buffer, where the backward sweep reads it ahead.
+constexpr int kWinSpan = 8;   // window depth in i: more than the 6 levels a sweep reaches back
+
+struct WinCell {
+  int i, j, k;
+  bool act;   // the thread has a cell on this level
+};
+struct WinFwd {
+  WinCell c;
+  bool dom;              // inside the domain (else a decoupled identity row with rhs 0)
+  double ru, rv;         // right-hand side as loaded
+  double lu[kUL];        // u-row multipliers
+  double lv[kVL];        // v-row multipliers, the last one for column (0,0,0,u)
+};
+struct WinBwd {
+  WinCell c;
+  double yu, yv;             // forward-sweep result
+  double uu[kUN - kUD];      // u-row: inverted diagonal, then U
+  double uv[kVN - kVD];      // v-row: inverted diagonal, then U
+};
+
+// Barrier for values exchanged through LDS only: device-memory loads issued before it
+// stay in flight (__syncthreads would also wait for them).
+ACCH_DEV void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// A thread's columns, packed j | k << 10 (-1: none), the current one first.
+struct ColCursor {
+  int col[kWin3DCols];
+  ACCH_DEV static int first_level(int c) { return c < 0 ? (1 << 29) : 2 * (c & 1023) + 3 * (c >> 10); }
+  // Cell of level w (levels visited one by one, upward if `up`, else downward).
+  ACCH_DEV WinCell at(int w, int bw, bool up) {
+    const int o = first_level(col[0]);
+    const bool next = up ? w >= o + bw : w < o;
+#pragma unroll
+    for (int m = 0; m + 1 < kWin3DCols; ++m) col[m] = next ? col[m + 1] : col[m];
+    col[kWin3DCols - 1] = next ? -1 : col[kWin3DCols - 1];
+    const int c = col[0], o2 = first_level(c), i = w - o2;
+    const bool act = c >= 0 && i >= 0 && i < bw;
+    return act ? WinCell{i, c & 1023, c >> 10, true} : WinCell{0, 0, 0, false};
+  }
+};
+
+template <typename FT>
+__global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
+    Phys P, BoxGeom G, const SubInfo *__restrict__ subs, const int *__restrict__ wcols, const FT *__restrict__ fac,
+    double2 *__restrict__ ybuf, const double *__restrict__ r, double *__restrict__ z, const GmresState *st,
+    long vstride) {
+  extern __shared__ double2 win[];   // kWinSpan * bh * bd values
+  double sc = 1.0;
+  if (st) {
+    if (st->done) return;
+    const int jj = st->j;
+    r += (long)jj * vstride;
+    z += (long)jj * vstride;
+    sc = st->inv_norm[jj];
+  }
+  const SubInfo si = subs[blockIdx.x];
+  const Box3 B{G.bw, G.bh, G.bd};
+  const long n = (long)P.nx * P.ny * P.nz;
+  const FT *fk = fac + (long)blockIdx.x * G.ncb * kNSlot3D;
+  double2 *yb = ybuf + (long)blockIdx.x * G.ncb;
+  double *spare = (double *)(ybuf + (long)G.nsub * G.ncb);
+  const int plane = G.bh * G.bd;
+  const unsigned last_slot = (unsigned)(kWinSpan * plane - 1);
+  const int top = G.nlev - 1;
+  for (int e = threadIdx.x; e <= (int)last_slot; e += kWin3DThreads) win[e] = make_double2(0.0, 0.0);
+  ColCursor cur;
+#pragma unroll
+  for (int m = 0; m < kWin3DCols; ++m) cur.col[m] = wcols[m * kWin3DThreads + threadIdx.x];
+  __syncthreads();
+
+  auto record = [&](const WinCell &c) -> const FT * {
+    return (const FT *)__builtin_assume_aligned(fk + (long)B.at(c.i, c.j, c.k) * kNSlot3D, 32);
+  };
+  // value pair of the neighbour at offset cc of cell c (any finite pair outside the box)
+  auto nb = [&](const WinCell &c, const Col3 cc) -> double2 {
+    const int s = ((c.i + cc.dx) & (kWinSpan - 1)) * plane + (c.j + cc.dy) * G.bd + (c.k + cc.dz);
+    return win[min((unsigned)s, last_slot)];
+  };
+  auto fetch_fwd = [&](int w, WinFwd &d) {
+    d.c = cur.at(w, G.bw, true);
+    const long g = box3_to_global(si, d.c.i, d.c.j, d.c.k, P);
+    d.dom = g >= 0;
+    const long gs = g >= 0 ? g : 0;
+    d.ru = r[gs];
+    d.rv = r[n + gs];
+    const FT *rec = record(d.c);
+#pragma unroll
+    for (int q = 0; q < kUL; ++q) d.lu[q] = (double)rec[kFA + q];
+#pragma unroll
+    for (int q = 0; q < kVL; ++q) d.lv[q] = (double)rec[kFB + q];
+  };
+  auto fetch_bwd = [&](int w, WinBwd &d) {
+    d.c = cur.at(w, G.bw, false);
+    const double2 y = yb[B.at(d.c.i, d.c.j, d.c.k)];
+    d.yu = y.x;
+    d.yv = y.y;
+    const FT *rec = record(d.c);
+#pragma unroll
+    for (int q = 0; q < kUN - kUD; ++q) d.uu[q] = (double)rec[kFA + kUD + q];
+#pragma unroll
+    for (int q = 0; q < kVN - kVD; ++q) d.uv[q] = (double)rec[kFB + kVD + q];
+  };
+  auto slot = [&](const WinCell &c) { return (c.i & (kWinSpan - 1)) * plane + c.j * G.bd + c.k; };
+
+  // The three operand sets rotate by name (the loops are unrolled by three): copying
+  // a set still being loaded would wait for its loads.
+  // L y = R r
+  {
+    auto level = [&](const WinFwd &d, WinFwd &fill, int wfill) {
+      fetch_fwd(wfill, fill);
+      const WinCell &c = d.c;
+      double yu = d.dom ? sc * d.ru : 0.0, yv = d.dom ? sc * d.rv : 0.0;
+#pragma unroll
+      for (int q = 0; q < kUL; ++q) {
+        const Col3 cc = ucol3(q);
+        const double2 v = nb(c, cc);
+        yu = fma(-d.lu[q], cc.t == 0 ? v.x : v.y, yu);
+      }
+#pragma unroll
+      for (int q = 0; q < kVL - 1; ++q) {
+        const Col3 cc = vcol3(q);
+        const double2 v = nb(c, cc);
+        yv = fma(-d.lv[q], cc.t == 0 ? v.x : v.y, yv);
+      }
+      yv = fma(-d.lv[kVL - 1], yu, yv);
+      const double2 y = make_double2(yu, yv);
+      if (c.act) win[slot(c)] = y;
+      *(double2 *)(c.act ? (double *)(yb + B.at(c.i, c.j, c.k)) : spare) = y;
+      lds_barrier();
+    };
+    WinFwd s0, s1, s2;
+    fetch_fwd(0, s0);
+    fetch_fwd(1, s1);
+    for (int w = 0; w <= top; w += 3) {
+      level(s0, s2, w + 2);
+      level(s1, s0, w + 3);
+      level(s2, s1, w + 4);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kWin3DCols; ++m) cur.col[m] = wcols[(kWin3DCols + m) * kWin3DThreads + threadIdx.x];
+  __syncthreads();   // the forward results in the box buffer are read below
+  // U x = y, owned cells straight to z
+  {
+    auto level = [&](const WinBwd &d, WinBwd &fill, int wfill) {
+      fetch_bwd(wfill, fill);
+      const WinCell &c = d.c;
+      double xv = d.yv;
+#pragma unroll
+      for (int q = kVD + 1; q < kVN; ++q) {
+        const Col3 cc = vcol3(q);
+        const double2 v = nb(c, cc);
+        xv = fma(-d.uv[q - kVD], cc.t == 0 ? v.x : v.y, xv);
+      }
+      xv *= d.uv[0];
+      double xu = fma(-d.uu[1], xv, d.yu);   // column (0,0,0,v)
+#pragma unroll
+      for (int q = kUD + 2; q < kUN; ++q) {
+        const Col3 cc = ucol3(q);
+        const double2 v = nb(c, cc);
+        xu = fma(-d.uu[q - kUD], cc.t == 0 ? v.x : v.y, xu);
+      }
+      xu *= d.uu[0];
+      if (c.act) win[slot(c)] = make_double2(xu, xv);
+      const long g = box3_to_global(si, c.i, c.j, c.k, P);
+      const bool out = c.act && g >= 0 && owned3(si, c.i, c.j, c.k);
+      *(out ? z + g : spare) = xu;
+      *(out ? z + n + g : spare + 1) = xv;
+      lds_barrier();
+    };
+    WinBwd t0, t1, t2;
+    fetch_bwd(top, t0);
+    fetch_bwd(top - 1, t1);
+    for (int w = top; w >= 0; w -= 3) {
+      level(t0, t2, w - 2);
+      level(t1, t0, w - 3);
+      level(t2, t1, w - 4);
     }
   }
 }
@@ -380,44 +607,44 @@ __global__ __launch_bounds__(256) void k_ras_t_sweep3d(Phys P, BoxGeom G, const 
     yb[e] = own ? make_double2(sc * r[g], sc * r[n + g]) : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  auto coef = [&](int i, int j, int k, int slot) -> double {
-    return (double)fk[(long)B.at(i, j, k) * kNSlot3D + slot];
-  };
-  auto val = [&](int i, int j, int k, int t) -> double {
-    const double2 v = yb[B.at(i, j, k)];
-    return t == 0 ? v.x : v.y;
-  };
+  auto coefq = [&](int q, int slot) -> double { return (double)fk[(long)q * kNSlot3D + slot]; };
   // U^T y = R r: column p receives the U entries of the earlier rows q = p - o
   for (int w = 0; w < G.nlev; ++w) {
     for (int q = lvl[w] + threadIdx.x; q < lvl[w + 1]; q += blockDim.x) {
-      const int e = cells[q];
       int i, j, k;
-      decode(e, B, i, j, k);
-      double yu = yb[e].x, yv = yb[e].y;
+      unpack(cells[q], i, j, k);
+      const int e = B.at(i, j, k);
+      const double2 y0 = yb[e];
+      double yu = y0.x, yv = y0.y;
 #pragma unroll
       for (int c = kUD + 1; c < kUN; ++c) {   // u-rows q with a u column at p
         const Col3 cc = ucol3(c);
         if (cc.t != 0) continue;
-        const int ii = i - cc.dx, jj = j - cc.dy, kk = k - cc.dz;
-        if (B.in(ii, jj, kk)) yu -= coef(ii, jj, kk, kFA + c) * val(ii, jj, kk, 0);
+        bool in;
+        const int nq = nb_or(B, i, j, k, -cc.dx, -cc.dy, -cc.dz, e, in);
+        const double u = in ? coefq(nq, kFA + c) : 0.0;
+        yu = fma(-u, yb[nq].x, yu);
       }
-      yu *= coef(i, j, k, kFA + kUD);
+      yu *= coefq(e, kFA + kUD);
 #pragma unroll
       for (int c = kUD + 1; c < kUN; ++c) {   // u-rows q with a v column at p (q = p for (0,0,0,v))
         const Col3 cc = ucol3(c);
         if (cc.t != 1) continue;
-        const int ii = i - cc.dx, jj = j - cc.dy, kk = k - cc.dz;
-        if (!B.in(ii, jj, kk)) continue;
-        const double yq = (cc.dx == 0 && cc.dy == 0 && cc.dz == 0) ? yu : val(ii, jj, kk, 0);
-        yv -= coef(ii, jj, kk, kFA + c) * yq;
+        bool in;
+        const int nq = nb_or(B, i, j, k, -cc.dx, -cc.dy, -cc.dz, e, in);
+        const double u = in ? coefq(nq, kFA + c) : 0.0;
+        const double yq = (cc.dx == 0 && cc.dy == 0 && cc.dz == 0) ? yu : yb[nq].x;
+        yv = fma(-u, yq, yv);
       }
 #pragma unroll
       for (int c = kVD + 1; c < kVN; ++c) {   // v-rows q with a v column at p
         const Col3 cc = vcol3(c);
-        const int ii = i - cc.dx, jj = j - cc.dy, kk = k - cc.dz;
-        if (B.in(ii, jj, kk)) yv -= coef(ii, jj, kk, kFB + c) * val(ii, jj, kk, 1);
+        bool in;
+        const int nq = nb_or(B, i, j, k, -cc.dx, -cc.dy, -cc.dz, e, in);
+        const double u = in ? coefq(nq, kFB + c) : 0.0;
+        yv = fma(-u, yb[nq].y, yv);
       }
-      yv *= coef(i, j, k, kFB + kVD);
+      yv *= coefq(e, kFB + kVD);
       yb[e] = make_double2(yu, yv);
     }
     __syncthreads();
@@ -425,31 +652,38 @@ __global__ __launch_bounds__(256) void k_ras_t_sweep3d(Phys P, BoxGeom G, const 
   // L^T x = y (unit diagonal): column p receives the L entries of the later rows
   for (int w = G.nlev - 1; w >= 0; --w) {
     for (int q = lvl[w] + threadIdx.x; q < lvl[w + 1]; q += blockDim.x) {
-      const int e = cells[q];
       int i, j, k;
-      decode(e, B, i, j, k);
-      double xu = yb[e].x, xv = yb[e].y;
+      unpack(cells[q], i, j, k);
+      const int e = B.at(i, j, k);
+      const double2 y0 = yb[e];
+      double xu = y0.x, xv = y0.y;
 #pragma unroll
       for (int c = 0; c < kUL; ++c) {   // u-rows q with a v column at p
         const Col3 cc = ucol3(c);
         if (cc.t != 1) continue;
-        const int ii = i - cc.dx, jj = j - cc.dy, kk = k - cc.dz;
-        if (B.in(ii, jj, kk)) xv -= coef(ii, jj, kk, kFA + c) * val(ii, jj, kk, 0);
+        bool in;
+        const int nq = nb_or(B, i, j, k, -cc.dx, -cc.dy, -cc.dz, e, in);
+        const double l = in ? coefq(nq, kFA + c) : 0.0;
+        xv = fma(-l, yb[nq].x, xv);
       }
 #pragma unroll
       for (int c = 0; c < kVL - 1; ++c) {   // v-rows q with a v column at p
         const Col3 cc = vcol3(c);
-        const int ii = i - cc.dx, jj = j - cc.dy, kk = k - cc.dz;
-        if (B.in(ii, jj, kk)) xv -= coef(ii, jj, kk, kFB + c) * val(ii, jj, kk, 1);
+        bool in;
+        const int nq = nb_or(B, i, j, k, -cc.dx, -cc.dy, -cc.dz, e, in);
+        const double l = in ? coefq(nq, kFB + c) : 0.0;
+        xv = fma(-l, yb[nq].y, xv);
       }
 #pragma unroll
       for (int c = 0; c < kUL; ++c) {   // u-rows q with a u column at p
         const Col3 cc = ucol3(c);
         if (cc.t != 0) continue;
-        const int ii = i - cc.dx, jj = j - cc.dy, kk = k - cc.dz;
-        if (B.in(ii, jj, kk)) xu -= coef(ii, jj, kk, kFA + c) * val(ii, jj, kk, 0);
+        bool in;
+        const int nq = nb_or(B, i, j, k, -cc.dx, -cc.dy, -cc.dz, e, in);
+        const double l = in ? coefq(nq, kFA + c) : 0.0;
+        xu = fma(-l, yb[nq].x, xu);
       }
-      xu -= coef(i, j, k, kFB + kVL - 1) * xv;   // the v-row of this cell, column (0,0,0,u)
+      xu -= coefq(e, kFB + kVL - 1) * xv;   // the v-row of this cell, column (0,0,0,u)
       yb[e] = make_double2(xu, xv);
     }
     __syncthreads();
@@ -528,9 +762,42 @@ hipError_t launch_ilu_factor3d(const Phys &P, const BoxGeom &G, const SubInfo *s
   return hipGetLastError();
 }
 
+namespace {
+bool g_ras3d_window = true;
+constexpr size_t kLdsDefault3 = 64 * 1024;
+constexpr size_t kLdsMax3 = 160 * 1024;   // LDS per CU on gfx950
+
+// Launches the windowed apply when the box allows it; false: use the general kernel.
+template <typename FT>
+bool ras_apply3d_win(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
+                     const void *fac, void *ybuf, const double *r, double *z, const GmresState *st, long vstride,
+                     hipStream_t s) {
+  const size_t lds = (size_t)kWinSpan * G.bh * G.bd * sizeof(double2);
+  if (!g_ras3d_window || G.wmax <= 0 || G.wmax > kWin3DThreads || lds > kLdsMax3) return false;
+  static size_t allowed = kLdsDefault3;   // per instantiation
+  if (lds > allowed) {
+    if (hipFuncSetAttribute((const void *)k_ras_apply3d_win<FT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kLdsMax3) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    allowed = kLdsMax3;
+  }
+  (void)lvl;
+  hipLaunchKernelGGL(k_ras_apply3d_win<FT>, dim3(G.nsub), dim3(kWin3DThreads), lds, s, P, G, subs, cells + G.ncb,
+                     (const FT *)fac, (double2 *)ybuf, r, z, st, vstride);
+  return true;
+}
+}  // namespace
+
+void set_ras3d_window(bool on) { g_ras3d_window = on; }
+
 hipError_t launch_ras_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
                               const void *fac, void *ybuf, const double *r, double *z, const GmresState *st,
                               long vstride, int fp32, hipStream_t s) {
+  if (fp32 ? ras_apply3d_win<float>(P, G, subs, lvl, cells, fac, ybuf, r, z, st, vstride, s)
+           : ras_apply3d_win<double>(P, G, subs, lvl, cells, fac, ybuf, r, z, st, vstride, s))
+    return hipGetLastError();
   if (fp32)
     hipLaunchKernelGGL(k_ras_apply3d<float>, dim3(G.nsub), dim3(256), 0, s, P, G, subs, lvl, cells,
                        (const float *)fac, (double2 *)ybuf, r, z, st, vstride);

@@ -146,6 +146,7 @@ static int build_geometry3(const acch_params &p, Geometry &geo) {
   int b3[3] = {0, 0, 0};
   for (int a = 0; a < 3; ++a)
     for (int v : l3[a]) b3[a] = std::max(b3[a], v + 2 * d);
+  if (std::max(b3[0], std::max(b3[1], b3[2])) > 1023) return fail(ACCH_EINVAL, "subdomain box longer than 1023 cells");
   BoxGeom &G = geo.G;
   G.bw = b3[0];
   G.bh = b3[1];
@@ -180,7 +181,7 @@ static int build_geometry3(const acch_params &p, Geometry &geo) {
     }
     base += p.n[a];
   }
-  // cells of the padded box grouped by level w = i + 2j + 3k
+  // cells of the padded box grouped by level w = i + 2j + 3k, as i | j << 10 | k << 20
   geo.lvl.assign(G.nlev + 1, 0);
   geo.cells.assign(G.ncb, 0);
   std::vector<int> count(G.nlev, 0);
@@ -191,7 +192,49 @@ static int build_geometry3(const acch_params &p, Geometry &geo) {
   std::vector<int> fill(geo.lvl.begin(), geo.lvl.end() - 1);
   for (int k = 0; k < G.bd; ++k)
     for (int j = 0; j < G.bh; ++j)
-      for (int i = 0; i < G.bw; ++i) geo.cells[fill[i + 2 * j + 3 * k]++] = i + G.bw * (j + G.bh * k);
+      for (int i = 0; i < G.bw; ++i) geo.cells[fill[i + 2 * j + 3 * k]++] = i | j << 10 | k << 20;
+  // Columns (j, k) of the box for the windowed apply: column (j, k) holds the cell of
+  // level w at i = w - (2j + 3k), so it is busy on bw consecutive levels.  Columns in
+  // order of their first level go to the thread that became free first (equal
+  // lengths: a queue), which needs as many threads as the largest level.
+  {
+    std::vector<std::pair<int, int>> col;   // (first level, packed j | k << 10)
+    for (int k = 0; k < G.bd; ++k)
+      for (int j = 0; j < G.bh; ++j) col.push_back({2 * j + 3 * k, j | k << 10});
+    std::stable_sort(col.begin(), col.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    std::vector<std::vector<int>> per;   // columns of each thread
+    std::vector<int> free_at;            // level from which a thread is free
+    size_t head = 0;                     // queue of threads in order of free_at
+    std::vector<int> queue;
+    for (const auto &c : col) {
+      int t;
+      if (head < queue.size() && free_at[queue[head]] <= c.first) {
+        t = queue[head++];
+      } else {
+        t = (int)per.size();
+        per.emplace_back();
+        free_at.push_back(0);
+      }
+      per[t].push_back(c.second);
+      free_at[t] = c.first + G.bw;
+      queue.push_back(t);
+    }
+    bool fits = (int)per.size() <= kWin3DThreads;
+    for (const auto &v : per) fits = fits && (int)v.size() <= kWin3DCols;
+    if (fits) {
+      G.wmax = (int)per.size();
+      const size_t base = geo.cells.size();
+      // each thread's columns in order (forward sweep), then in reverse (backward)
+      geo.cells.resize(base + (size_t)2 * kWin3DCols * kWin3DThreads, -1);
+      for (size_t t = 0; t < per.size(); ++t)
+        for (size_t m = 0; m < per[t].size(); ++m) {
+          geo.cells[base + m * kWin3DThreads + t] = per[t][m];
+          geo.cells[base + (kWin3DCols + m) * kWin3DThreads + t] = per[t][per[t].size() - 1 - m];
+        }
+    } else {
+      G.wmax = 0;
+    }
+  }
   geo.tile_blocks = 0;
   return ACCH_OK;
 }
@@ -276,7 +319,8 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   const size_t slots = d3 ? (size_t)geo.G.ncb : (size_t)geo.G.nlev * geo.G.bh;
   L.off_fac = take((size_t)geo.G.nsub * nslot * slots * fsz);
   // 2D: FT pairs + one dump slot per box; 3D: FP64 pairs
-  L.off_y = d3 ? take((size_t)geo.G.nsub * slots * 2 * sizeof(double))
+  // (3D: one more pair, where the windowed apply's idle threads write)
+  L.off_y = d3 ? take(((size_t)geo.G.nsub * slots + 1) * 2 * sizeof(double))
                : take((size_t)geo.G.nsub * 2 * (slots + 1) * fsz);
   L.off_dump = take(64 * sizeof(double));
   L.off_subs = take(geo.subs.size() * sizeof(SubInfo));
@@ -721,6 +765,10 @@ extern "C" int acch_set_option(acch_ctx *c, int option, long value) {
   (void)c;
   if (option == ACCH_OPT_RAS_PREFETCH) {
     set_ras_prefetch((int)value);
+    return ACCH_OK;
+  }
+  if (option == ACCH_OPT_RAS3D_WINDOW) {
+    set_ras3d_window(value != 0);
     return ACCH_OK;
   }
   return fail(ACCH_EINVAL, "unknown option");

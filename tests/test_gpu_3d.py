@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from paper_2007_04560_amd import Solver  # noqa: E402
+from paper_2007_04560_amd import Solver, set_option  # noqa: E402
 
 L3 = (1.0, 0.9, 1.1)
 CASES = [((9, 10, 11), "periodic", (2, 2, 2), 1), ((8, 10, 12), "neumann", (2, 2, 3), 1),
@@ -65,9 +65,17 @@ def test_jacobian_3d_products_match_oracle(shape, bc, sub, ov, mob):
     assert rel(s.apply_jacobian_transpose(dev(x)).cpu().numpy(), Jo.T @ x) <= 1e-12
 
 
+@pytest.fixture(params=[1, 0], ids=["window", "boxbuffer"])
+def window(request):
+    """Both forms of the 3D apply: LDS window and whole box in device memory."""
+    set_option("ras3d_window", request.param)
+    yield request.param
+    set_option("ras3d_window", 1)
+
+
 @pytest.mark.parametrize("shape,bc,sub,ov", CASES)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_schwarz_3d_matches_oracle(shape, bc, sub, ov, precision):
+def test_schwarz_3d_matches_oracle(shape, bc, sub, ov, precision, window):
     u1, v1, u0, v0 = perturbed_pair(shape, 73, amp=0.03)
     P = Problem(bc=bc, lengths=L3)
     s = solver(u0, v0, bc, sub, ov, ilu_shift=0.02, precision=precision)
@@ -101,7 +109,7 @@ def test_transpose_3d_is_the_transpose_of_the_oracle_operator():
 
 
 @pytest.mark.parametrize("bc", ["neumann", "periodic"])
-def test_steps_3d_match_oracle(bc):
+def test_steps_3d_match_oracle(bc, window):
     shape = (8, 9, 10) if bc == "neumann" else (9, 9, 10)
     sub = (2, 2, 2)
     u0, v0 = random_ic(shape, 75)
@@ -168,3 +176,18 @@ def test_final_energy_gradient_3d_matches_central_differences():
     eps = 1e-5
     fd = (energy(u0, v0 + eps * d, p0) - energy(u0, v0 - eps * d, p0)) / (2 * eps)
     assert abs(float((tv.grad * torch.tensor(d)).sum()) - fd) <= 1e-6 * abs(fd)
+
+
+def test_window_and_box_buffer_applies_agree_at_full_box_size(window):
+    """A 34^3 box (32^3 with overlap 1, the box of the 128^3 run's 4x4x4 split): both
+    applies agree with each other on the same factors, to rounding."""
+    shape = (32, 32, 32)
+    u1, v1, u0, v0 = perturbed_pair(shape, 78, amp=0.03)
+    s = solver(u0, v0, "neumann", (1, 1, 1), 1, ilu_shift=0.02)
+    s.jacobian(dev(vec(u1, v1)), dev(vec(u0, v0)), 2e-3)
+    s.factor()
+    r = dev(np.random.default_rng(13).standard_normal(2 * u1.size))
+    z = s.precondition(r).cpu().numpy()
+    set_option("ras3d_window", 1 - window)
+    z2 = s.precondition(r).cpu().numpy()
+    assert rel(z, z2) <= 1e-12
