@@ -40,6 +40,19 @@ void set_ras3d_window(bool on);
 // in reverse ([2][kWin3DCols][kWin3DThreads], -1 unused; wmax = 0: no list).
 constexpr int kWin3DThreads = 512;
 constexpr int kWin3DCols = 8;
+constexpr int kWin3DSlots = 40;   // factor values per cell (3D)
+// Threads of the windowed apply = row width of its level-major arrays (0: no window).
+inline int win3d_row(const BoxGeom &G) { return G.wmax > 0 ? (G.wmax + 63) / 64 * 64 : 0; }
+// Level-major factor copy of the windowed apply: [sub][level][slot][row] (elements).
+inline size_t win3d_fac_elems(const BoxGeom &G) {
+  return (size_t)G.nsub * G.nlev * kWin3DSlots * win3d_row(G);
+}
+// 3D box-buffer pairs: cell-ordered boxes of the general apply, or the level-major
+// rows of the windowed one, whichever is larger; one spare pair follows.
+inline size_t box3_ypairs(const BoxGeom &G) {
+  const size_t a = (size_t)G.nsub * G.ncb, b = (size_t)G.nsub * G.nlev * win3d_row(G);
+  return a > b ? a : b;
+}
 
 // stencil2d.hip.  lam_b (per instance, may be null: lam0) and shift_st (the mass
 // shift of each instance's GMRES state, may be null) describe the trial state.
@@ -119,11 +132,12 @@ hipError_t launch_adjoint_prev3d(const Phys &P, const double *X1, const double *
                                  double lam_scale, double *bar, double *out, const RedBuf &red, hipStream_t s);
 hipError_t launch_energy_grad3d(const Phys &P, const double *X, double vol, double *g, const RedBuf &red,
                                 hipStream_t s);
+// wfac (may be null): also fill the level-major copy of the windowed apply
 hipError_t launch_ilu_factor3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
-                               const double *J, double shift, void *fac, int fp32, hipStream_t s);
+                               const double *J, double shift, void *fac, void *wfac, int fp32, hipStream_t s);
 hipError_t launch_ras_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
-                              const void *fac, void *ybuf, const double *r, double *z, const GmresState *st,
-                              long vstride, int fp32, hipStream_t s);
+                              const void *fac, const void *wfac, void *ybuf, const double *r, double *z,
+                              const GmresState *st, long vstride, int fp32, hipStream_t s);
 hipError_t launch_ras_t_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl,
                                 const int *cells, int px, int py, int pz, const int *own, const void *fac, void *ybuf,
                                 const double *r, double *z, const GmresState *st, long vstride, int fp32,

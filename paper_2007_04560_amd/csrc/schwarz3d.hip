@@ -385,16 +385,19 @@ __global__ __launch_bounds__(256) void k_ras_apply3d(Phys P, BoxGeom G, const Su
 // needs no mask, only an address kept inside the window.
 //
 // Threads own box columns (j, k) (host-built lists, columns of one thread busy on
-// disjoint level ranges), so a thread finds its cell of a level from a column cursor
-// and walks a column's cells in storage order.  The operands of a level (right-hand
-// side or forward result, factor entries) are loaded two levels ahead, and the
-// barrier between levels waits for LDS only, so those loads stay in flight across it.
-// Every device-memory access of the sweeps is unconditional, so the count of
-// outstanding accesses is the same on every path and the compiler waits for exactly
-// the level it needs: an idle thread loads the operands of box cell (0,0,0) and
-// writes to a spare pair after the box buffers.  The forward result goes to the box
-// buffer, where the backward sweep reads it ahead.
+// disjoint level ranges), so a thread finds its cell of a level from a column cursor.
+// Factor entries and forward results sit in level-major arrays (the entry of thread t
+// on level w at w * W + t; the factorisation fills the factor copy), so a wave's
+// accesses to them are contiguous.  The operands of a level (right-hand side or
+// forward result, factor entries) are loaded two levels ahead, and the barrier
+// between levels waits for LDS only, so those loads stay in flight across it.  Every
+// device-memory access of the sweeps is unconditional, so the count of outstanding
+// accesses is the same on every path and the compiler waits for exactly the level it
+// needs: an idle thread's buffer accesses fall past the end of the buffer (no memory
+// access), its right-hand-side load reads cell 0 and its z values go to a spare pair
+// after the box buffers.
 constexpr int kWinSpan = 8;   // window depth in i: more than the 6 levels a sweep reaches back
+static_assert(kWin3DSlots == kNSlot3D, "level-major factor copy holds whole records");
 
 struct WinCell {
   int i, j, k;
@@ -439,11 +442,25 @@ struct ColCursor {
   }
 };
 
+// Buffer resource over `bytes` bytes (raw, stride 0): a load at an offset past the end
+// returns zero and a store there is dropped, without a memory access.
+ACCH_DEV __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+constexpr unsigned kPastEnd = 0x80000000u;   // offset of an idle lane's access
+
+ACCH_DEV double buf_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const double *) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+ACCH_DEV double buf_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const float *) {
+  return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+
 template <typename FT>
 __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
-    Phys P, BoxGeom G, const SubInfo *__restrict__ subs, const int *__restrict__ wcols, const FT *__restrict__ fac,
-    double2 *__restrict__ ybuf, const double *__restrict__ r, double *__restrict__ z, const GmresState *st,
-    long vstride) {
+    Phys P, BoxGeom G, const SubInfo *__restrict__ subs, const int *__restrict__ wcols, const FT *__restrict__ wfac,
+    double2 *__restrict__ ybuf, double *__restrict__ spare, const double *__restrict__ r, double *__restrict__ z,
+    const GmresState *st, long vstride) {
   extern __shared__ double2 win[];   // kWinSpan * bh * bd values
   double sc = 1.0;
   if (st) {
@@ -456,9 +473,14 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
   const SubInfo si = subs[blockIdx.x];
   const Box3 B{G.bw, G.bh, G.bd};
   const long n = (long)P.nx * P.ny * P.nz;
-  const FT *fk = fac + (long)blockIdx.x * G.ncb * kNSlot3D;
-  double2 *yb = ybuf + (long)blockIdx.x * G.ncb;
-  double *spare = (double *)(ybuf + (long)G.nsub * G.ncb);
+  const int W = blockDim.x;   // row width of the level-major arrays
+  const unsigned tid = threadIdx.x;
+  // this box's level-major factors [level][slot][W] and forward results [level][W]
+  const long fbox = (long)G.nlev * kNSlot3D * W;
+  const __amdgpu_buffer_rsrc_t rsF = buffer_rsrc(wfac + blockIdx.x * fbox, (unsigned)(fbox * sizeof(FT)));
+  const __amdgpu_buffer_rsrc_t rsY =
+      buffer_rsrc(ybuf + (long)blockIdx.x * G.nlev * W, (unsigned)((long)G.nlev * W * sizeof(double2)));
+  const unsigned slot_bytes = (unsigned)W * sizeof(FT);
   const int plane = G.bh * G.bd;
   const unsigned last_slot = (unsigned)(kWinSpan * plane - 1);
   const int top = G.nlev - 1;
@@ -468,8 +490,12 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
   for (int m = 0; m < kWin3DCols; ++m) cur.col[m] = wcols[m * kWin3DThreads + threadIdx.x];
   __syncthreads();
 
-  auto record = [&](const WinCell &c) -> const FT * {
-    return (const FT *)__builtin_assume_aligned(fk + (long)B.at(c.i, c.j, c.k) * kNSlot3D, 32);
+  // byte offset of this thread's entry of level w, slot 0 (past the end when idle)
+  auto foff = [&](const WinCell &c, int w) -> unsigned {
+    return c.act ? ((unsigned)w * kNSlot3D * W + tid) * (unsigned)sizeof(FT) : kPastEnd;
+  };
+  auto yoff = [&](const WinCell &c, int w) -> unsigned {
+    return c.act ? ((unsigned)w * W + tid) * (unsigned)sizeof(double2) : kPastEnd;
   };
   // value pair of the neighbour at offset cc of cell c (any finite pair outside the box)
   auto nb = [&](const WinCell &c, const Col3 cc) -> double2 {
@@ -483,22 +509,22 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
     const long gs = g >= 0 ? g : 0;
     d.ru = r[gs];
     d.rv = r[n + gs];
-    const FT *rec = record(d.c);
+    const unsigned o = foff(d.c, w);
 #pragma unroll
-    for (int q = 0; q < kUL; ++q) d.lu[q] = (double)rec[kFA + q];
+    for (int q = 0; q < kUL; ++q) d.lu[q] = buf_load(rsF, o, (kFA + q) * slot_bytes, wfac);
 #pragma unroll
-    for (int q = 0; q < kVL; ++q) d.lv[q] = (double)rec[kFB + q];
+    for (int q = 0; q < kVL; ++q) d.lv[q] = buf_load(rsF, o, (kFB + q) * slot_bytes, wfac);
   };
   auto fetch_bwd = [&](int w, WinBwd &d) {
     d.c = cur.at(w, G.bw, false);
-    const double2 y = yb[B.at(d.c.i, d.c.j, d.c.k)];
-    d.yu = y.x;
-    d.yv = y.y;
-    const FT *rec = record(d.c);
+    const auto y = __builtin_amdgcn_raw_buffer_load_b128(rsY, yoff(d.c, w), 0, 0);
+    d.yu = __builtin_bit_cast(double, __builtin_shufflevector(y, y, 0, 1));
+    d.yv = __builtin_bit_cast(double, __builtin_shufflevector(y, y, 2, 3));
+    const unsigned o = foff(d.c, w);
 #pragma unroll
-    for (int q = 0; q < kUN - kUD; ++q) d.uu[q] = (double)rec[kFA + kUD + q];
+    for (int q = 0; q < kUN - kUD; ++q) d.uu[q] = buf_load(rsF, o, (kFA + kUD + q) * slot_bytes, wfac);
 #pragma unroll
-    for (int q = 0; q < kVN - kVD; ++q) d.uv[q] = (double)rec[kFB + kVD + q];
+    for (int q = 0; q < kVN - kVD; ++q) d.uv[q] = buf_load(rsF, o, (kFB + kVD + q) * slot_bytes, wfac);
   };
   auto slot = [&](const WinCell &c) { return (c.i & (kWinSpan - 1)) * plane + c.j * G.bd + c.k; };
 
@@ -508,6 +534,7 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
   {
     auto level = [&](const WinFwd &d, WinFwd &fill, int wfill) {
       fetch_fwd(wfill, fill);
+      const int w = wfill - 2;
       const WinCell &c = d.c;
       double yu = d.dom ? sc * d.ru : 0.0, yv = d.dom ? sc * d.rv : 0.0;
 #pragma unroll
@@ -523,9 +550,10 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
         yv = fma(-d.lv[q], cc.t == 0 ? v.x : v.y, yv);
       }
       yv = fma(-d.lv[kVL - 1], yu, yv);
-      const double2 y = make_double2(yu, yv);
-      if (c.act) win[slot(c)] = y;
-      *(double2 *)(c.act ? (double *)(yb + B.at(c.i, c.j, c.k)) : spare) = y;
+      if (c.act) win[slot(c)] = make_double2(yu, yv);
+      const auto bu = __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, yu);
+      const auto bv = __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, yv);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_shufflevector(bu, bv, 0, 1, 2, 3), rsY, yoff(c, w), 0, 0);
       lds_barrier();
     };
     WinFwd s0, s1, s2;
@@ -736,6 +764,26 @@ __global__ __launch_bounds__(256) void k_ras_t_gather3d(Phys P, BoxGeom G, const
   }
 }
 
+// Level-major copy of the factors for the windowed apply: block (w, sub), thread t
+// copies the record of its cell on level w (if any) to [sub][w][slot][t].
+template <typename FT>
+__global__ __launch_bounds__(kWin3DThreads) void k_pack_window3d(BoxGeom G, const int *__restrict__ wcols,
+                                                                 const FT *__restrict__ fac, FT *__restrict__ wfac) {
+  const int w = blockIdx.x, sub = blockIdx.y, W = blockDim.x, t = threadIdx.x;
+  int e = -1;
+#pragma unroll
+  for (int m = 0; m < kWin3DCols; ++m) {
+    const int c = wcols[m * kWin3DThreads + t];
+    const int j = c & 1023, k = c >> 10, i = w - 2 * j - 3 * k;
+    if (c >= 0 && i >= 0 && i < G.bw) e = i + G.bw * (j + G.bh * k);
+  }
+  if (e < 0) return;
+  const FT *rec = fac + ((long)sub * G.ncb + e) * kNSlot3D;
+  FT *dst = wfac + (((long)sub * G.nlev + w) * kNSlot3D) * W + t;
+#pragma unroll
+  for (int q = 0; q < kNSlot3D; ++q) dst[(long)q * W] = rec[q];
+}
+
 // Factors of box cells -> FP64 [sub][slot][cell] (the 40-slot record of each cell).
 template <typename FT>
 __global__ void k_export_factors3d(BoxGeom G, const FT *__restrict__ fac, double *__restrict__ out) {
@@ -752,13 +800,22 @@ __global__ void k_export_factors3d(BoxGeom G, const FT *__restrict__ fac, double
 }  // namespace
 
 hipError_t launch_ilu_factor3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
-                               const double *J, double shift, void *fac, int fp32, hipStream_t s) {
+                               const double *J, double shift, void *fac, void *wfac, int fp32, hipStream_t s) {
   if (fp32)
     hipLaunchKernelGGL(k_ilu_factor3d<float>, dim3(G.nsub), dim3(256), 0, s, P, G, subs, lvl, cells, J, shift,
                        (float *)fac);
   else
     hipLaunchKernelGGL(k_ilu_factor3d<double>, dim3(G.nsub), dim3(256), 0, s, P, G, subs, lvl, cells, J, shift,
                        (double *)fac);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !wfac || G.wmax <= 0) return e;
+  const dim3 grid(G.nlev, G.nsub);
+  if (fp32)
+    hipLaunchKernelGGL(k_pack_window3d<float>, grid, dim3(win3d_row(G)), 0, s, G, cells + G.ncb,
+                       (const float *)fac, (float *)wfac);
+  else
+    hipLaunchKernelGGL(k_pack_window3d<double>, grid, dim3(win3d_row(G)), 0, s, G, cells + G.ncb,
+                       (const double *)fac, (double *)wfac);
   return hipGetLastError();
 }
 
@@ -769,11 +826,10 @@ constexpr size_t kLdsMax3 = 160 * 1024;   // LDS per CU on gfx950
 
 // Launches the windowed apply when the box allows it; false: use the general kernel.
 template <typename FT>
-bool ras_apply3d_win(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
-                     const void *fac, void *ybuf, const double *r, double *z, const GmresState *st, long vstride,
-                     hipStream_t s) {
+bool ras_apply3d_win(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *cells, const void *wfac,
+                     void *ybuf, const double *r, double *z, const GmresState *st, long vstride, hipStream_t s) {
   const size_t lds = (size_t)kWinSpan * G.bh * G.bd * sizeof(double2);
-  if (!g_ras3d_window || G.wmax <= 0 || G.wmax > kWin3DThreads || lds > kLdsMax3) return false;
+  if (!g_ras3d_window || !wfac || G.wmax <= 0 || G.wmax > kWin3DThreads || lds > kLdsMax3) return false;
   static size_t allowed = kLdsDefault3;   // per instantiation
   if (lds > allowed) {
     if (hipFuncSetAttribute((const void *)k_ras_apply3d_win<FT>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -783,9 +839,9 @@ bool ras_apply3d_win(const Phys &P, const BoxGeom &G, const SubInfo *subs, const
     }
     allowed = kLdsMax3;
   }
-  (void)lvl;
-  hipLaunchKernelGGL(k_ras_apply3d_win<FT>, dim3(G.nsub), dim3(kWin3DThreads), lds, s, P, G, subs, cells + G.ncb,
-                     (const FT *)fac, (double2 *)ybuf, r, z, st, vstride);
+  double *spare = (double *)((double2 *)ybuf + box3_ypairs(G));
+  hipLaunchKernelGGL(k_ras_apply3d_win<FT>, dim3(G.nsub), dim3(win3d_row(G)), lds, s, P, G, subs, cells + G.ncb,
+                     (const FT *)wfac, (double2 *)ybuf, spare, r, z, st, vstride);
   return true;
 }
 }  // namespace
@@ -793,10 +849,10 @@ bool ras_apply3d_win(const Phys &P, const BoxGeom &G, const SubInfo *subs, const
 void set_ras3d_window(bool on) { g_ras3d_window = on; }
 
 hipError_t launch_ras_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
-                              const void *fac, void *ybuf, const double *r, double *z, const GmresState *st,
-                              long vstride, int fp32, hipStream_t s) {
-  if (fp32 ? ras_apply3d_win<float>(P, G, subs, lvl, cells, fac, ybuf, r, z, st, vstride, s)
-           : ras_apply3d_win<double>(P, G, subs, lvl, cells, fac, ybuf, r, z, st, vstride, s))
+                              const void *fac, const void *wfac, void *ybuf, const double *r, double *z,
+                              const GmresState *st, long vstride, int fp32, hipStream_t s) {
+  if (fp32 ? ras_apply3d_win<float>(P, G, subs, cells, wfac, ybuf, r, z, st, vstride, s)
+           : ras_apply3d_win<double>(P, G, subs, cells, wfac, ybuf, r, z, st, vstride, s))
     return hipGetLastError();
   if (fp32)
     hipLaunchKernelGGL(k_ras_apply3d<float>, dim3(G.nsub), dim3(256), 0, s, P, G, subs, lvl, cells,

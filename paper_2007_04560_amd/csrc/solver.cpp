@@ -33,7 +33,7 @@ namespace {
 
 struct Layout {
   size_t off_Xn, off_Xprev, off_X, off_Xt, off_F, off_Ft, off_S, off_W;
-  size_t off_J, off_V, off_Z, off_fac, off_y, off_dump, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
+  size_t off_J, off_V, off_Z, off_fac, off_wfac, off_y, off_dump, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
   size_t off_tbox, off_own;
   size_t total;
 };
@@ -60,7 +60,7 @@ struct acch_ctx {
   hipStream_t stream = nullptr;
   char *ws = nullptr;
   double *Xn, *Xprev, *X, *Xt, *F, *Ft, *S, *W, *J, *V, *Z;
-  void *fac, *ybuf;
+  void *fac, *wfac, *ybuf;   // wfac: level-major factor copy of the 3D windowed apply (or null)
   double *dump, *tbox;
   SubInfo *d_subs;
   int *d_lvl, *d_own;
@@ -320,8 +320,9 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_fac = take((size_t)geo.G.nsub * nslot * slots * fsz);
   // 2D: FT pairs + one dump slot per box; 3D: FP64 pairs
   // (3D: one more pair, where the windowed apply's idle threads write)
-  L.off_y = d3 ? take(((size_t)geo.G.nsub * slots + 1) * 2 * sizeof(double))
+  L.off_y = d3 ? take((box3_ypairs(geo.G) + 1) * 2 * sizeof(double))
                : take((size_t)geo.G.nsub * 2 * (slots + 1) * fsz);
+  L.off_wfac = take(d3 ? win3d_fac_elems(geo.G) * fsz : 0);
   L.off_dump = take(64 * sizeof(double));
   L.off_subs = take(geo.subs.size() * sizeof(SubInfo));
   L.off_lvl = take((geo.lvl.size() + geo.cells.size()) * sizeof(int));
@@ -440,14 +441,14 @@ hipError_t run_energy(acch_ctx *c, const double *X) {
 hipError_t run_factor(acch_ctx *c) {
   if (c->d3)
     return launch_ilu_factor3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->J, c->p.ilu_shift, c->fac,
-                               fp32_of(c), c->stream);
+                               c->wfac, fp32_of(c), c->stream);
   return launch_ilu_factor2d(c->bl, c->geo.G, c->d_subs, c->d_lvl, c->J, c->p.ilu_shift, c->fac, fp32_of(c),
                              c->stream);
 }
 hipError_t run_ras(acch_ctx *c, const double *r, double *z, const GmresState *st, long vs) {
   if (c->d3)
-    return launch_ras_apply3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->fac, c->ybuf, r, z, st, vs,
-                              fp32_of(c), c->stream);
+    return launch_ras_apply3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->fac, c->wfac, c->ybuf, r, z,
+                              st, vs, fp32_of(c), c->stream);
   return launch_ras_apply2d(c->bl, c->geo.G, c->d_subs, c->d_lvl, c->fac, c->ybuf, r, z, c->dump, st, vs, fp32_of(c),
                             c->stream, c->ras);
 }
@@ -662,6 +663,7 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->V = (double *)(c->ws + L.off_V);
   c->Z = (double *)(c->ws + L.off_Z);
   c->fac = c->ws + L.off_fac;
+  c->wfac = c->geo.G.wmax > 0 ? (void *)(c->ws + L.off_wfac) : nullptr;
   c->ybuf = c->ws + L.off_y;
   c->dump = (double *)(c->ws + L.off_dump);
   c->tbox = (double *)(c->ws + L.off_tbox);

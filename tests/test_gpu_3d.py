@@ -179,8 +179,8 @@ def test_final_energy_gradient_3d_matches_central_differences():
 
 
 def test_window_and_box_buffer_applies_agree_at_full_box_size(window):
-    """A 34^3 box (32^3 with overlap 1, the box of the 128^3 run's 4x4x4 split): both
-    applies agree with each other on the same factors, to rounding."""
+    """A 34^3 box (32^3 with overlap 1, as in a 4x4x4 split of 128^3), about the largest
+    the LDS window takes: both applies agree with each other on the same factors."""
     shape = (32, 32, 32)
     u1, v1, u0, v0 = perturbed_pair(shape, 78, amp=0.03)
     s = solver(u0, v0, "neumann", (1, 1, 1), 1, ilu_shift=0.02)
