@@ -403,17 +403,23 @@ struct WinCell {
   int i, j, k;
   bool act;   // the thread has a cell on this level
 };
+// Factor entries travel in pairs of consecutive slots (one 16-byte load in FP64): the
+// forward sweep reads pairs 0..7 (u-row multipliers, slot 15 unused) and 16..17
+// (v-row), the backward sweep pairs 7..15 (u-row U part, slot 14 unused) and 18..19.
+constexpr int kPairs = kNSlot3D / 2;
+constexpr int kFwdPairsU = 8, kBwdPair0U = 7, kBwdPairsU = 9;
+
 struct WinFwd {
   WinCell c;
-  bool dom;              // inside the domain (else a decoupled identity row with rhs 0)
-  double ru, rv;         // right-hand side as loaded
-  double lu[kUL];        // u-row multipliers
-  double lv[kVL];        // v-row multipliers, the last one for column (0,0,0,u)
+  bool dom;                  // inside the domain (else a decoupled identity row with rhs 0)
+  double ru, rv;             // right-hand side as loaded
+  double lu[2 * kFwdPairsU]; // u-row multipliers in 0..14
+  double lv[kVL];            // v-row multipliers, the last one for column (0,0,0,u)
 };
 struct WinBwd {
   WinCell c;
   double yu, yv;             // forward-sweep result
-  double uu[kUN - kUD];      // u-row: inverted diagonal, then U
+  double uu[2 * kBwdPairsU]; // u-row: slot 14 (unused), inverted diagonal, then U
   double uv[kVN - kVD];      // v-row: inverted diagonal, then U
 };
 
@@ -448,15 +454,29 @@ ACCH_DEV __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
 constexpr unsigned kPastEnd = 0x80000000u;   // offset of an idle lane's access
+typedef double double_pair __attribute__((ext_vector_type(2)));
+typedef unsigned word4 __attribute__((ext_vector_type(4)));
 
-ACCH_DEV double buf_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const double *) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+// one pair of factor entries
+ACCH_DEV void pair_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const double *, double &a,
+                        double &b) {
+  const double_pair d = __builtin_bit_cast(double_pair, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+  a = d.x;
+  b = d.y;
 }
-ACCH_DEV double buf_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const float *) {
-  return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+ACCH_DEV void pair_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const float *, double &a,
+                        double &b) {
+  // (bit-cast the whole vector: indexing the loaded vector's elements directly compiled
+  // to a single 32-bit load here)
+  typedef float float_pair __attribute__((ext_vector_type(2)));
+  const float_pair f = __builtin_bit_cast(float_pair, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+  a = (double)f.x;
+  b = (double)f.y;
 }
 
-template <typename FT>
+// Operands are loaded D levels ahead: D + 1 operand sets rotate by name through a
+// loop unrolled D + 1 times (copying a set still being loaded would wait for it).
+template <typename FT, int D>
 __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
     Phys P, BoxGeom G, const SubInfo *__restrict__ subs, const int *__restrict__ wcols, const FT *__restrict__ wfac,
     double2 *__restrict__ ybuf, double *__restrict__ spare, const double *__restrict__ r, double *__restrict__ z,
@@ -475,24 +495,25 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
   const long n = (long)P.nx * P.ny * P.nz;
   const int W = blockDim.x;   // row width of the level-major arrays
   const unsigned tid = threadIdx.x;
-  // this box's level-major factors [level][slot][W] and forward results [level][W]
+  // this box's level-major factor pairs [level][pair][W] and forward results [level][W]
   const long fbox = (long)G.nlev * kNSlot3D * W;
   const __amdgpu_buffer_rsrc_t rsF = buffer_rsrc(wfac + blockIdx.x * fbox, (unsigned)(fbox * sizeof(FT)));
   const __amdgpu_buffer_rsrc_t rsY =
       buffer_rsrc(ybuf + (long)blockIdx.x * G.nlev * W, (unsigned)((long)G.nlev * W * sizeof(double2)));
-  const unsigned slot_bytes = (unsigned)W * sizeof(FT);
+  // (uniform: kept in a scalar register, as the loads' scalar offsets need)
+  const unsigned pair_bytes = __builtin_amdgcn_readfirstlane((unsigned)W * 2 * sizeof(FT));
   const int plane = G.bh * G.bd;
   const unsigned last_slot = (unsigned)(kWinSpan * plane - 1);
   const int top = G.nlev - 1;
-  for (int e = threadIdx.x; e <= (int)last_slot; e += kWin3DThreads) win[e] = make_double2(0.0, 0.0);
+  for (int e = threadIdx.x; e <= (int)last_slot; e += W) win[e] = make_double2(0.0, 0.0);
   ColCursor cur;
 #pragma unroll
   for (int m = 0; m < kWin3DCols; ++m) cur.col[m] = wcols[m * kWin3DThreads + threadIdx.x];
   __syncthreads();
 
-  // byte offset of this thread's entry of level w, slot 0 (past the end when idle)
+  // byte offset of this thread's pair 0 on level w (past the end when idle)
   auto foff = [&](const WinCell &c, int w) -> unsigned {
-    return c.act ? ((unsigned)w * kNSlot3D * W + tid) * (unsigned)sizeof(FT) : kPastEnd;
+    return c.act ? ((unsigned)w * kPairs * W + tid) * (unsigned)(2 * sizeof(FT)) : kPastEnd;
   };
   auto yoff = [&](const WinCell &c, int w) -> unsigned {
     return c.act ? ((unsigned)w * W + tid) * (unsigned)sizeof(double2) : kPastEnd;
@@ -511,30 +532,30 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
     d.rv = r[n + gs];
     const unsigned o = foff(d.c, w);
 #pragma unroll
-    for (int q = 0; q < kUL; ++q) d.lu[q] = buf_load(rsF, o, (kFA + q) * slot_bytes, wfac);
+    for (int q = 0; q < kFwdPairsU; ++q) pair_load(rsF, o, q * pair_bytes, wfac, d.lu[2 * q], d.lu[2 * q + 1]);
 #pragma unroll
-    for (int q = 0; q < kVL; ++q) d.lv[q] = buf_load(rsF, o, (kFB + q) * slot_bytes, wfac);
+    for (int q = 0; q < kVL / 2; ++q)
+      pair_load(rsF, o, (kFB / 2 + q) * pair_bytes, wfac, d.lv[2 * q], d.lv[2 * q + 1]);
   };
   auto fetch_bwd = [&](int w, WinBwd &d) {
     d.c = cur.at(w, G.bw, false);
-    const auto y = __builtin_amdgcn_raw_buffer_load_b128(rsY, yoff(d.c, w), 0, 0);
-    d.yu = __builtin_bit_cast(double, __builtin_shufflevector(y, y, 0, 1));
-    d.yv = __builtin_bit_cast(double, __builtin_shufflevector(y, y, 2, 3));
+    const double_pair y =
+        __builtin_bit_cast(double_pair, __builtin_amdgcn_raw_buffer_load_b128(rsY, yoff(d.c, w), 0, 0));
+    d.yu = y.x;
+    d.yv = y.y;
     const unsigned o = foff(d.c, w);
 #pragma unroll
-    for (int q = 0; q < kUN - kUD; ++q) d.uu[q] = buf_load(rsF, o, (kFA + kUD + q) * slot_bytes, wfac);
+    for (int q = 0; q < kBwdPairsU; ++q)
+      pair_load(rsF, o, (kBwdPair0U + q) * pair_bytes, wfac, d.uu[2 * q], d.uu[2 * q + 1]);
 #pragma unroll
-    for (int q = 0; q < kVN - kVD; ++q) d.uv[q] = buf_load(rsF, o, (kFB + kVD + q) * slot_bytes, wfac);
+    for (int q = 0; q < (kVN - kVD) / 2; ++q)
+      pair_load(rsF, o, ((kFB + kVD) / 2 + q) * pair_bytes, wfac, d.uv[2 * q], d.uv[2 * q + 1]);
   };
   auto slot = [&](const WinCell &c) { return (c.i & (kWinSpan - 1)) * plane + c.j * G.bd + c.k; };
 
-  // The three operand sets rotate by name (the loops are unrolled by three): copying
-  // a set still being loaded would wait for its loads.
   // L y = R r
   {
-    auto level = [&](const WinFwd &d, WinFwd &fill, int wfill) {
-      fetch_fwd(wfill, fill);
-      const int w = wfill - 2;
+    auto level = [&](const WinFwd &d, int w) {
       const WinCell &c = d.c;
       double yu = d.dom ? sc * d.ru : 0.0, yv = d.dom ? sc * d.rv : 0.0;
 #pragma unroll
@@ -551,18 +572,19 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
       }
       yv = fma(-d.lv[kVL - 1], yu, yv);
       if (c.act) win[slot(c)] = make_double2(yu, yv);
-      const auto bu = __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, yu);
-      const auto bv = __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, yv);
-      __builtin_amdgcn_raw_buffer_store_b128(__builtin_shufflevector(bu, bv, 0, 1, 2, 3), rsY, yoff(c, w), 0, 0);
+      const double_pair y{yu, yv};
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(word4, y), rsY, yoff(c, w), 0, 0);
       lds_barrier();
     };
-    WinFwd s0, s1, s2;
-    fetch_fwd(0, s0);
-    fetch_fwd(1, s1);
-    for (int w = 0; w <= top; w += 3) {
-      level(s0, s2, w + 2);
-      level(s1, s0, w + 3);
-      level(s2, s1, w + 4);
+    WinFwd s[D + 1];
+#pragma unroll
+    for (int m = 0; m < D; ++m) fetch_fwd(m, s[m]);
+    for (int w = 0; w <= top; w += D + 1) {
+#pragma unroll
+      for (int m = 0; m <= D; ++m) {
+        fetch_fwd(w + m + D, s[(m + D) % (D + 1)]);
+        level(s[m], w + m);
+      }
     }
   }
 #pragma unroll
@@ -570,8 +592,7 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
   __syncthreads();   // the forward results in the box buffer are read below
   // U x = y, owned cells straight to z
   {
-    auto level = [&](const WinBwd &d, WinBwd &fill, int wfill) {
-      fetch_bwd(wfill, fill);
+    auto level = [&](const WinBwd &d) {
       const WinCell &c = d.c;
       double xv = d.yv;
 #pragma unroll
@@ -581,14 +602,14 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
         xv = fma(-d.uv[q - kVD], cc.t == 0 ? v.x : v.y, xv);
       }
       xv *= d.uv[0];
-      double xu = fma(-d.uu[1], xv, d.yu);   // column (0,0,0,v)
+      double xu = fma(-d.uu[2], xv, d.yu);   // column (0,0,0,v)
 #pragma unroll
       for (int q = kUD + 2; q < kUN; ++q) {
         const Col3 cc = ucol3(q);
         const double2 v = nb(c, cc);
-        xu = fma(-d.uu[q - kUD], cc.t == 0 ? v.x : v.y, xu);
+        xu = fma(-d.uu[q - kUD + 1], cc.t == 0 ? v.x : v.y, xu);
       }
-      xu *= d.uu[0];
+      xu *= d.uu[1];
       if (c.act) win[slot(c)] = make_double2(xu, xv);
       const long g = box3_to_global(si, c.i, c.j, c.k, P);
       const bool out = c.act && g >= 0 && owned3(si, c.i, c.j, c.k);
@@ -596,13 +617,15 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
       *(out ? z + n + g : spare + 1) = xv;
       lds_barrier();
     };
-    WinBwd t0, t1, t2;
-    fetch_bwd(top, t0);
-    fetch_bwd(top - 1, t1);
-    for (int w = top; w >= 0; w -= 3) {
-      level(t0, t2, w - 2);
-      level(t1, t0, w - 3);
-      level(t2, t1, w - 4);
+    WinBwd t[D + 1];
+#pragma unroll
+    for (int m = 0; m < D; ++m) fetch_bwd(top - m, t[m]);
+    for (int w = top; w >= 0; w -= D + 1) {
+#pragma unroll
+      for (int m = 0; m <= D; ++m) {
+        fetch_bwd(w - m - D, t[(m + D) % (D + 1)]);
+        level(t[m]);
+      }
     }
   }
 }
@@ -765,7 +788,7 @@ __global__ __launch_bounds__(256) void k_ras_t_gather3d(Phys P, BoxGeom G, const
 }
 
 // Level-major copy of the factors for the windowed apply: block (w, sub), thread t
-// copies the record of its cell on level w (if any) to [sub][w][slot][t].
+// copies the record of its cell on level w (if any) to [sub][w][slot pair][t][2].
 template <typename FT>
 __global__ __launch_bounds__(kWin3DThreads) void k_pack_window3d(BoxGeom G, const int *__restrict__ wcols,
                                                                  const FT *__restrict__ fac, FT *__restrict__ wfac) {
@@ -779,9 +802,9 @@ __global__ __launch_bounds__(kWin3DThreads) void k_pack_window3d(BoxGeom G, cons
   }
   if (e < 0) return;
   const FT *rec = fac + ((long)sub * G.ncb + e) * kNSlot3D;
-  FT *dst = wfac + (((long)sub * G.nlev + w) * kNSlot3D) * W + t;
+  FT *dst = wfac + (((long)sub * G.nlev + w) * kNSlot3D) * W + 2 * t;
 #pragma unroll
-  for (int q = 0; q < kNSlot3D; ++q) dst[(long)q * W] = rec[q];
+  for (int q = 0; q < kNSlot3D; ++q) dst[(long)(q / 2) * 2 * W + (q & 1)] = rec[q];
 }
 
 // Factors of box cells -> FP64 [sub][slot][cell] (the 40-slot record of each cell).
@@ -821,6 +844,7 @@ hipError_t launch_ilu_factor3d(const Phys &P, const BoxGeom &G, const SubInfo *s
 
 namespace {
 bool g_ras3d_window = true;
+constexpr int kWinDepth = 3;   // levels the windowed apply loads ahead
 constexpr size_t kLdsDefault3 = 64 * 1024;
 constexpr size_t kLdsMax3 = 160 * 1024;   // LDS per CU on gfx950
 
@@ -832,16 +856,16 @@ bool ras_apply3d_win(const Phys &P, const BoxGeom &G, const SubInfo *subs, const
   if (!g_ras3d_window || !wfac || G.wmax <= 0 || G.wmax > kWin3DThreads || lds > kLdsMax3) return false;
   static size_t allowed = kLdsDefault3;   // per instantiation
   if (lds > allowed) {
-    if (hipFuncSetAttribute((const void *)k_ras_apply3d_win<FT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)kLdsMax3) != hipSuccess) {
+    if (hipFuncSetAttribute((const void *)k_ras_apply3d_win<FT, kWinDepth>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax3) != hipSuccess) {
       (void)hipGetLastError();
       return false;
     }
     allowed = kLdsMax3;
   }
   double *spare = (double *)((double2 *)ybuf + box3_ypairs(G));
-  hipLaunchKernelGGL(k_ras_apply3d_win<FT>, dim3(G.nsub), dim3(win3d_row(G)), lds, s, P, G, subs, cells + G.ncb,
-                     (const FT *)wfac, (double2 *)ybuf, spare, r, z, st, vstride);
+  hipLaunchKernelGGL((k_ras_apply3d_win<FT, kWinDepth>), dim3(G.nsub), dim3(win3d_row(G)), lds, s, P, G, subs,
+                     cells + G.ncb, (const FT *)wfac, (double2 *)ybuf, spare, r, z, st, vstride);
   return true;
 }
 }  // namespace
