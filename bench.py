@@ -78,17 +78,28 @@ def spmv_dots_bytes_per_cell(j_avg: float) -> float:
     return 24 * 8 + 16 + 16 + 16 * (j_avg + 1)
 
 
-def measured_traffic(kernel: str = "void k_ras_apply2d<double, 1, 4>"):
-    """HBM bytes per launch of the RAS kernel from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (profiles/traffic_periodic512.json, scaled by a plain-copy
-    calibration), or None when the kernel source changed since the counters were taken."""
+# The dominant (Schwarz) kernel of each workload, as rocprofv3 names it, and its source.
+RAS_KERNELS = {
+    "periodic512": ("void k_ras_apply2d<double, 1, 4>", "schwarz2d.hip"),
+    "neumann128_3d": ("void k_ras_apply3d_win<double, 3>", "schwarz3d.hip"),
+}
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the workload's Schwarz kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (profiles/traffic_<workload>.json, scaled by a
+    plain-copy calibration), or None when the kernel's source changed since the counters
+    were taken (or none were taken)."""
     import hashlib
+    if workload not in RAS_KERNELS:
+        return None
+    kernel, source = RAS_KERNELS[workload]
     try:
-        prof = json.load(open(os.path.join(ROOT, "profiles", "traffic_periodic512.json")))
-        src = open(os.path.join(ROOT, "paper_2007_04560_amd", "csrc", "schwarz2d.hip"), "rb").read()
+        prof = json.load(open(os.path.join(ROOT, "profiles", f"traffic_{workload}.json")))
+        src = open(os.path.join(ROOT, "paper_2007_04560_amd", "csrc", source), "rb").read()
     except OSError:
         return None
-    if hashlib.sha256(src).hexdigest() != prof.get("schwarz2d_sha256"):
+    if hashlib.sha256(src).hexdigest() != prof.get("source_sha256"):
         return None
     k = prof["kernels"].get(kernel)
     return k["hbm_bytes_per_launch"] if k else None
@@ -422,8 +433,9 @@ def main():
         dom = max(stats, key=lambda k: stats[k][0])
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic() if w["name"] == "periodic512" and sp == 8 else None,
-                    "kernel": "k_ras_apply2d",
+                    "traffic": measured_traffic(w["name"]) if sp == 8 and w["sub"] == WORKLOADS[w["name"]]["sub"]
+                    else None,
+                    "kernel": "k_ras_apply3d_win" if len(w["shape"]) == 3 else "k_ras_apply2d",
                     "avg_us": round(avg_s * 1e6, 2), "launches": ras_n,
                     "bytes_per_launch": int(bytes_launch), "dominant_by_time": dom}
     line = {
