@@ -118,12 +118,13 @@ hipError_t launch_energy_grad2d(const Phys &P, const double *X, double vol, doub
                                 hipStream_t s);
 
 // stencil3d.hip / schwarz3d.hip (single instance; cells listed per level in `cells`)
+// Q: scratch of 3 (residual) / 8 (Jacobian) FP64 values per cell
 hipError_t launch_residual3d(const BatchLaunch &bl, const double *X, const double *Sdir, double lam,
                              const GmresState *shift_st, const double *Xn, double dt, double *Xt, double *F,
-                             const RedBuf &red, hipStream_t s);
+                             double *Q, const RedBuf &red, hipStream_t s);
 hipError_t launch_energy3d(const BatchLaunch &bl, const double *X, const RedBuf &red, hipStream_t s);
 hipError_t launch_jacobian3d(const BatchLaunch &bl, const double *X, const double *Xn, double dt, double *J,
-                             hipStream_t s);
+                             double *Q, hipStream_t s);
 hipError_t launch_spmv3d(const BatchLaunch &bl, const double *J, const double *x, double *y, int transpose,
                          hipStream_t s);
 hipError_t launch_spmv_dots3d(const BatchLaunch &bl, const double *J, const double *Z, double *V, long vstride, int j,

@@ -9,8 +9,8 @@
 // the bw + 2(bh - 1) wavefronts in order.  Thread t owns the box rows j = t (mod T);
 // a wavefront meets each row at most once because bw < 2T.
 //
-// Factors are stored per subdomain as 24 slot arrays in wavefront order (cells of
-// one wavefront are contiguous, so a wavefront's loads coalesce).
+// Factors are stored per subdomain cell by cell in the padded wavefront order, the
+// 24 slots of a cell contiguous (see the factor-storage note above k_ras_apply2d).
 #include <utility>
 
 #include "../../include/acch.h"

@@ -33,7 +33,7 @@ namespace {
 
 struct Layout {
   size_t off_Xn, off_Xprev, off_X, off_Xt, off_F, off_Ft, off_S, off_W;
-  size_t off_J, off_V, off_Z, off_fac, off_wfac, off_y, off_dump, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
+  size_t off_J, off_V, off_Z, off_fac, off_wfac, off_q3, off_y, off_dump, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
   size_t off_tbox, off_own;
   size_t total;
 };
@@ -61,6 +61,7 @@ struct acch_ctx {
   char *ws = nullptr;
   double *Xn, *Xprev, *X, *Xt, *F, *Ft, *S, *W, *J, *V, *Z;
   void *fac, *wfac, *ybuf;   // wfac: level-major factor copy of the 3D windowed apply (or null)
+  double *q3;                // 3D: cell quantities of the residual / Jacobian passes
   double *dump, *tbox;
   SubInfo *d_subs;
   int *d_lvl, *d_own;
@@ -323,6 +324,7 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_y = d3 ? take((box3_ypairs(geo.G) + 1) * 2 * sizeof(double))
                : take((size_t)geo.G.nsub * 2 * (slots + 1) * fsz);
   L.off_wfac = take(d3 ? win3d_fac_elems(geo.G) * fsz : 0);
+  L.off_q3 = take(d3 ? (size_t)8 * geo.ncell * sizeof(double) : 0);   // 3D cell quantities
   L.off_dump = take(64 * sizeof(double));
   L.off_subs = take(geo.subs.size() * sizeof(SubInfo));
   L.off_lvl = take((geo.lvl.size() + geo.cells.size()) * sizeof(int));
@@ -420,11 +422,11 @@ int fp32_of(acch_ctx *c) { return c->p.precision == ACCH_PREC_MIXED; }
 
 hipError_t run_residual(acch_ctx *c, const double *X, const double *Sdir, double lam, const GmresState *shift,
                         const double *Xn, double dt, double *Xt, double *F) {
-  return c->d3 ? launch_residual3d(c->bl, X, Sdir, lam, shift, Xn, dt, Xt, F, c->red, c->stream)
+  return c->d3 ? launch_residual3d(c->bl, X, Sdir, lam, shift, Xn, dt, Xt, F, c->q3, c->red, c->stream)
                : launch_residual2d(c->bl, X, Sdir, lam, nullptr, shift, Xn, dt, Xt, F, c->red, c->stream);
 }
 hipError_t run_jacobian(acch_ctx *c, const double *X, const double *Xn, double dt) {
-  return c->d3 ? launch_jacobian3d(c->bl, X, Xn, dt, c->J, c->stream)
+  return c->d3 ? launch_jacobian3d(c->bl, X, Xn, dt, c->J, c->q3, c->stream)
                : launch_jacobian2d(c->bl, X, Xn, dt, c->J, c->stream);
 }
 hipError_t run_spmv(acch_ctx *c, const double *x, double *y, int transpose) {
@@ -664,6 +666,7 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->Z = (double *)(c->ws + L.off_Z);
   c->fac = c->ws + L.off_fac;
   c->wfac = c->geo.G.wmax > 0 ? (void *)(c->ws + L.off_wfac) : nullptr;
+  c->q3 = (double *)(c->ws + L.off_q3);
   c->ybuf = c->ws + L.off_y;
   c->dump = (double *)(c->ws + L.off_dump);
   c->tbox = (double *)(c->ws + L.off_tbox);

@@ -1,8 +1,9 @@
 // 3D stencil kernels of scheme (2.20): residual, discrete energy and mass, the
 // analytic Jacobian in 40 slots per cell and its products, and the adjoint pieces
-// (B^T lambda, parameter terms, energy gradient).  The 3D path evaluates the cell
-// quantities directly from the fields (one thread per cell, neighbours through the
-// caches); the same formulas as the 2D tile kernels with a third face pair.
+// (B^T lambda, parameter terms, energy gradient).  The residual and the Jacobian first
+// store the cell quantities (mu, nu, c and their derivatives) of every cell, then a
+// second pass reads them at the face neighbours; the same formulas as the 2D tile
+// kernels with a third face pair.
 //
 // Slots (include/acch.h): u-row/u-col 0..24 on uu3, u-row/v-col 25..31 on star3,
 // v-row/v-col 32..38 on star3, v-row/u-col 39 at the cell.
@@ -101,24 +102,48 @@ ACCH_DEV C3 cell_of_index(const Phys &P, long g) {
   return c;
 }
 
+// mu, nu and c of every cell at the trial state, stored [mu | nu | c][cell], so that
+// the residual reads them at the neighbours instead of recomputing them there.
+__global__ __launch_bounds__(256) void k_cellq3d(Phys P, const double *__restrict__ X, const double *__restrict__ Sdir,
+                                                  double lam, const GmresState *shift_st,
+                                                  const double *__restrict__ Xn, double *__restrict__ Q) {
+  const long n = (long)P.nx * P.ny * P.nz;
+  const Trial T{X, Sdir, Xn, lam, shift_st ? shift_st->shift : 0.0, n};
+  for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
+    const Q3 q = cell_q3(T, P, cell_of_index(P, g));
+    Q[g] = q.mu;
+    Q[n + g] = q.nu;
+    Q[2 * n + g] = q.c;
+  }
+}
+
 // F (optionally at the trial state, which is also written to Xt), ||F||^2 and the
-// number of inadmissible cells.
+// number of inadmissible cells, from the cell quantities of k_cellq3d.
 __global__ __launch_bounds__(256) void k_residual3d(Phys P, const double *__restrict__ X,
                                                      const double *__restrict__ Sdir, double lam,
                                                      const GmresState *shift_st, const double *__restrict__ Xn,
-                                                     double inv_dt, double *__restrict__ Xt, double *__restrict__ F,
-                                                     RedBuf red) {
+                                                     double inv_dt, const double *__restrict__ Q,
+                                                     double *__restrict__ Xt, double *__restrict__ F, RedBuf red) {
   const long n = (long)P.nx * P.ny * P.nz;
   const Trial T{X, Sdir, Xn, lam, shift_st ? shift_st->shift : 0.0, n};
+  const double *Qmu = Q, *Qnu = Q + n, *Qc = Q + 2 * n;
   double acc[2] = {0.0, 0.0};
   for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
     const C3 c = cell_of_index(P, g);
-    const Q3 q = cell_q3(T, P, c);
+    Q3 q;
+    q.u1 = T.u1(g);
+    q.v1 = T.v1(g);
+    q.u0 = Xn[g];
+    q.v0 = Xn[n + g];
+    q.mu = Qmu[g];
+    q.nu = Qnu[g];
+    q.c = Qc[g];
     double div = 0.0;
     for (int f = 0; f < 6; ++f) {
       if (!face3(P, c.x, c.y, c.z, f)) continue;
-      const Q3 qn = cell_q3(T, P, step(c, f));
-      div += 0.5 * (q.c + qn.c) * (qn.mu - q.mu) * face_w(P, f);
+      const C3 cn = step(c, f);
+      const long h = gidx(P, cn.x, cn.y, cn.z);
+      div += 0.5 * (q.c + Qc[h]) * (Qmu[h] - q.mu) * face_w(P, f);
     }
     const double Fu = (q.u1 - q.u0) * inv_dt - div;
     const double Fv = (q.v1 - q.v0) * inv_dt + q.c * q.nu / P.rho;
@@ -186,14 +211,32 @@ ACCH_DEV D3 cell_d3(const double *X, const double *Xn, const Phys &P, long n, C3
   return d;
 }
 
-__global__ __launch_bounds__(256) void k_jacobian3d(Phys P, const double *__restrict__ X,
-                                                     const double *__restrict__ Xn, double inv_dt,
+constexpr int kD3 = 8;   // values of D3 per cell
+
+// D3 of every cell, stored [field][cell] in the order of the struct.
+__global__ __launch_bounds__(256) void k_celld3d(Phys P, const double *__restrict__ X, const double *__restrict__ Xn,
+                                                  double *__restrict__ Q) {
+  const long n = (long)P.nx * P.ny * P.nz;
+  for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
+    const D3 d = cell_d3(X, Xn, P, n, cell_of_index(P, g));
+    const double v[kD3] = {d.mu, d.c, d.cu, d.cv, d.Am, d.av, d.nu, d.Bnu};
+#pragma unroll
+    for (int k = 0; k < kD3; ++k) Q[k * n + g] = v[k];
+  }
+}
+
+ACCH_DEV D3 load_d3(const double *__restrict__ Q, long n, long g) {
+  return D3{Q[g], Q[n + g], Q[2 * n + g], Q[3 * n + g], Q[4 * n + g], Q[5 * n + g], Q[6 * n + g], Q[7 * n + g]};
+}
+
+// The 40 slots of every cell from the cell quantities of k_celld3d.
+__global__ __launch_bounds__(256) void k_jacobian3d(Phys P, const double *__restrict__ Q, double inv_dt,
                                                      double *__restrict__ J) {
   const long n = (long)P.nx * P.ny * P.nz;
   const double hg = 0.5 * P.gamma;
   for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
     const C3 c = cell_of_index(P, g);
-    const D3 k = cell_d3(X, Xn, P, n, c);
+    const D3 k = load_d3(Q, n, g);
     D3 nb[6];
     bool fe[6];
     double D[6], ct[6];
@@ -201,7 +244,8 @@ __global__ __launch_bounds__(256) void k_jacobian3d(Phys P, const double *__rest
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       fe[f] = face3(P, c.x, c.y, c.z, f);
-      nb[f] = cell_d3(X, Xn, P, n, step(c, f));
+      const C3 cn = step(c, f);
+      nb[f] = load_d3(Q, n, gidx(P, cn.x, cn.y, cn.z));
       D[f] = nb[f].mu - k.mu;
       ct[f] = 0.5 * (k.c + nb[f].c);
       if (fe[f]) {
@@ -439,9 +483,10 @@ int nblocks3(const Phys &P) { return reduce_blocks((long)P.nx * P.ny * P.nz); }
 
 hipError_t launch_residual3d(const BatchLaunch &bl, const double *X, const double *Sdir, double lam,
                              const GmresState *shift_st, const double *Xn, double dt, double *Xt, double *F,
-                             const RedBuf &red, hipStream_t s) {
+                             double *Q, const RedBuf &red, hipStream_t s) {
+  hipLaunchKernelGGL(k_cellq3d, dim3(nblocks3(bl.P0)), dim3(256), 0, s, bl.P0, X, Sdir, lam, shift_st, Xn, Q);
   hipLaunchKernelGGL(k_residual3d, dim3(bl.grid[kFamCell]), dim3(256), 0, s, bl.P0, X, Sdir, lam, shift_st, Xn,
-                     1.0 / dt, Xt, F, red);
+                     1.0 / dt, (const double *)Q, Xt, F, red);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_finalize(kFinPlain, 2, red, bl, kFamCell, nullptr, FinalizeArgs{}, s);
@@ -455,8 +500,9 @@ hipError_t launch_energy3d(const BatchLaunch &bl, const double *X, const RedBuf 
 }
 
 hipError_t launch_jacobian3d(const BatchLaunch &bl, const double *X, const double *Xn, double dt, double *J,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_jacobian3d, dim3(nblocks3(bl.P0)), dim3(256), 0, s, bl.P0, X, Xn, 1.0 / dt, J);
+                             double *Q, hipStream_t s) {
+  hipLaunchKernelGGL(k_celld3d, dim3(nblocks3(bl.P0)), dim3(256), 0, s, bl.P0, X, Xn, Q);
+  hipLaunchKernelGGL(k_jacobian3d, dim3(nblocks3(bl.P0)), dim3(256), 0, s, bl.P0, (const double *)Q, 1.0 / dt, J);
   return hipGetLastError();
 }
 
