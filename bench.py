@@ -85,21 +85,29 @@ RAS_KERNELS = {
 }
 
 
+def code_sha256(text: str) -> str:
+    """SHA-256 of a C++ source without its // comments, blank lines and indentation:
+    changes only when the code does."""
+    import hashlib
+    import re
+    lines = [re.sub(r"//.*$", "", line).strip() for line in text.splitlines()]
+    return hashlib.sha256("\n".join(line for line in lines if line).encode()).hexdigest()
+
+
 def measured_traffic(workload: str):
     """HBM bytes per launch of the workload's Schwarz kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs (profiles/traffic_<workload>.json, scaled by a
-    plain-copy calibration), or None when the kernel's source changed since the counters
-    were taken (or none were taken)."""
-    import hashlib
+    plain-copy calibration), or None when the kernel's source code changed since the
+    counters were taken (or none were taken)."""
     if workload not in RAS_KERNELS:
         return None
     kernel, source = RAS_KERNELS[workload]
     try:
         prof = json.load(open(os.path.join(ROOT, "profiles", f"traffic_{workload}.json")))
-        src = open(os.path.join(ROOT, "paper_2007_04560_amd", "csrc", source), "rb").read()
+        src = open(os.path.join(ROOT, "paper_2007_04560_amd", "csrc", source)).read()
     except OSError:
         return None
-    if hashlib.sha256(src).hexdigest() != prof.get("source_sha256"):
+    if code_sha256(src) != prof.get("source_code_sha256"):
         return None
     k = prof["kernels"].get(kernel)
     return k["hbm_bytes_per_launch"] if k else None
