@@ -216,44 +216,67 @@ ACCH_DEV void pivots_v(std::integer_sequence<int, Ps...>, double (&b)[kVN], cons
   (pivot_v<Ps>(b, fk, B, i, j, k), ...);
 }
 
+// A_k = R_k J R_k^T plus the shift on its diagonal, written as each box cell's record
+// in the factor storage (pattern order; entries coupling to cells outside the box or
+// the domain are zero, padding cells are decoupled identity rows).  One thread per box
+// cell in storage order, so the J reads of a wave are contiguous.
 template <typename FT>
-__global__ __launch_bounds__(256) void k_ilu_factor3d(Phys P, BoxGeom G, const SubInfo *__restrict__ subs,
-                                                      const int *__restrict__ lvl, const int *__restrict__ cells,
-                                                      const double *__restrict__ J, double shift,
-                                                      FT *__restrict__ fac) {
-  const SubInfo si = subs[blockIdx.x];
+__global__ __launch_bounds__(256) void k_extract3d(Phys P, BoxGeom G, const SubInfo *__restrict__ subs,
+                                                   const double *__restrict__ J, double shift, FT *__restrict__ fac) {
   const Box3 B{G.bw, G.bh, G.bd};
   const long n = (long)P.nx * P.ny * P.nz;
+  const long total = (long)G.nsub * G.ncb;
+  for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
+    const int sub = (int)(x / G.ncb), e = (int)(x - (long)sub * G.ncb);
+    const SubInfo si = subs[sub];
+    int i, j, k;
+    decode(e, B, i, j, k);
+    const long g = box3_to_global(si, i, j, k, P);
+    FT *rec = fac + x * kNSlot3D;
+    if (g >= 0) {
+#pragma unroll
+      for (int c = 0; c < kUN; ++c) {
+        const Col3 cc = ucol3(c);
+        const int ii = i + cc.dx, jj = j + cc.dy, kk = k + cc.dz;
+        const bool in = B.in(ii, jj, kk) && box3_to_global(si, ii, jj, kk, P) >= 0;
+        const double a = in ? J[(long)jslot3(0, cc) * n + g] : 0.0;
+        rec[kFA + c] = (FT)(c == kUD ? a * (1.0 + shift) : a);
+      }
+#pragma unroll
+      for (int c = 0; c < kVN; ++c) {
+        const Col3 cc = vcol3(c);
+        const int ii = i + cc.dx, jj = j + cc.dy, kk = k + cc.dz;
+        const bool in = B.in(ii, jj, kk) && box3_to_global(si, ii, jj, kk, P) >= 0;
+        const double b = in ? J[(long)jslot3(1, cc) * n + g] : 0.0;
+        rec[kFB + c] = (FT)(c == kVD ? b * (1.0 + shift) : b);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < kUN; ++c) rec[kFA + c] = (FT)(c == kUD ? 1.0 : 0.0);
+#pragma unroll
+      for (int c = 0; c < kVN; ++c) rec[kFB + c] = (FT)(c == kVD ? 1.0 : 0.0);
+    }
+  }
+}
+
+// ILU(0) of the extracted records in place, level by level.
+template <typename FT>
+__global__ __launch_bounds__(256) void k_ilu_factor3d(BoxGeom G, const int *__restrict__ lvl,
+                                                      const int *__restrict__ cells, FT *__restrict__ fac) {
+  const Box3 B{G.bw, G.bh, G.bd};
   FT *fk = fac + (long)blockIdx.x * G.ncb * kNSlot3D;
   for (int w = 0; w < G.nlev; ++w) {
     for (int q = lvl[w] + threadIdx.x; q < lvl[w + 1]; q += blockDim.x) {
       int i, j, k;
       unpack(cells[q], i, j, k);
       const int e = B.at(i, j, k);
-      const long g = box3_to_global(si, i, j, k, P);
       double a[kUN], b[kVN];
-      if (g >= 0) {
+      {
+        const FT *own = fk + (long)e * kNSlot3D;
 #pragma unroll
-        for (int c = 0; c < kUN; ++c) {
-          const Col3 cc = ucol3(c);
-          const int ii = i + cc.dx, jj = j + cc.dy, kk = k + cc.dz;
-          const bool in = B.in(ii, jj, kk) && box3_to_global(si, ii, jj, kk, P) >= 0;
-          a[c] = in ? J[(long)jslot3(0, cc) * n + g] : 0.0;
-        }
+        for (int c = 0; c < kUN; ++c) a[c] = (double)own[kFA + c];
 #pragma unroll
-        for (int c = 0; c < kVN; ++c) {
-          const Col3 cc = vcol3(c);
-          const int ii = i + cc.dx, jj = j + cc.dy, kk = k + cc.dz;
-          const bool in = B.in(ii, jj, kk) && box3_to_global(si, ii, jj, kk, P) >= 0;
-          b[c] = in ? J[(long)jslot3(1, cc) * n + g] : 0.0;
-        }
-        a[kUD] *= 1.0 + shift;
-        b[kVD] *= 1.0 + shift;
-      } else {  // padding / outside the domain: a decoupled identity row pair
-#pragma unroll
-        for (int c = 0; c < kUN; ++c) a[c] = c == kUD ? 1.0 : 0.0;
-#pragma unroll
-        for (int c = 0; c < kVN; ++c) b[c] = c == kVD ? 1.0 : 0.0;
+        for (int c = 0; c < kVN; ++c) b[c] = (double)own[kFB + c];
       }
       pivots_u(std::make_integer_sequence<int, kUL>{}, a, fk, B, i, j, k);
       a[kUD] = 1.0 / a[kUD];
@@ -824,12 +847,16 @@ __global__ void k_export_factors3d(BoxGeom G, const FT *__restrict__ fac, double
 
 hipError_t launch_ilu_factor3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
                                const double *J, double shift, void *fac, void *wfac, int fp32, hipStream_t s) {
-  if (fp32)
-    hipLaunchKernelGGL(k_ilu_factor3d<float>, dim3(G.nsub), dim3(256), 0, s, P, G, subs, lvl, cells, J, shift,
-                       (float *)fac);
-  else
-    hipLaunchKernelGGL(k_ilu_factor3d<double>, dim3(G.nsub), dim3(256), 0, s, P, G, subs, lvl, cells, J, shift,
-                       (double *)fac);
+  const long total = (long)G.nsub * G.ncb;
+  int nb = (int)((total + 255) / 256);
+  if (nb > 8192) nb = 8192;
+  if (fp32) {
+    hipLaunchKernelGGL(k_extract3d<float>, dim3(nb), dim3(256), 0, s, P, G, subs, J, shift, (float *)fac);
+    hipLaunchKernelGGL(k_ilu_factor3d<float>, dim3(G.nsub), dim3(256), 0, s, G, lvl, cells, (float *)fac);
+  } else {
+    hipLaunchKernelGGL(k_extract3d<double>, dim3(nb), dim3(256), 0, s, P, G, subs, J, shift, (double *)fac);
+    hipLaunchKernelGGL(k_ilu_factor3d<double>, dim3(G.nsub), dim3(256), 0, s, G, lvl, cells, (double *)fac);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !wfac || G.wmax <= 0) return e;
   const dim3 grid(G.nlev, G.nsub);
