@@ -139,10 +139,12 @@ hipError_t launch_ilu_factor3d(const Phys &P, const BoxGeom &G, const SubInfo *s
 hipError_t launch_ras_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
                               const void *fac, const void *wfac, void *ybuf, const double *r, double *z,
                               const GmresState *st, long vstride, int fp32, hipStream_t s);
+// wfact (may be null): transposed-record copy of the windowed form, filled from fac
+// unless *packed (set once filled); tbox: 2 ncb doubles per box
 hipError_t launch_ras_t_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl,
-                                const int *cells, int px, int py, int pz, const int *own, const void *fac, void *ybuf,
-                                const double *r, double *z, const GmresState *st, long vstride, int fp32,
-                                hipStream_t s);
+                                const int *cells, int px, int py, int pz, const int *own, const void *fac,
+                                void *wfact, bool *packed, void *ybuf, double *tbox, const double *r, double *z,
+                                const GmresState *st, long vstride, int fp32, hipStream_t s);
 hipError_t launch_export_factors3d(const BoxGeom &G, const void *fac, int fp32, double *out, hipStream_t s);
 
 }  // namespace acch

@@ -653,6 +653,259 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
   }
 }
 
+// ---- z = M^{-T} r through the LDS window (adjoint) --------------------------------
+// M^{-T} = sum_k (R_k^delta)^T (L_k U_k)^{-T} R_k^0: restrict r to the owned cells,
+// solve U^T y = R r (lower triangular: levels upward) and L^T x = y (levels
+// downward), then add every box's x into z (k_ras_t_gather3d).  Row p of U^T / L^T
+// holds the coefficients of column p of U / L, which sit in the rows of the cells
+// q = p - o for the pattern offsets o of those rows; a transposed record gathers them
+// per cell (k_pack_window3d_t), so the sweeps have the shape of the forward apply:
+// own-record loads, neighbour values from the window (q lies at most 6 levels away).
+//
+// Transposed record slots (value of row q at column p, zero when q is outside the box):
+//   0..11  U[u_q][u_p], q = p - o over the u-row's U columns of type u
+//   12     1 / U[u_p][u_p]
+//   13..16 U[u_q][v_p] over the u-row's U columns of type v (the first: q = p)
+//   17..19 U[v_q][v_p] over the v-row's U columns
+//   20     1 / U[v_p][v_p]
+//   21..32 L[u_q][u_p] over the u-row's L columns of type u
+//   33     L[v_p][u_p]
+//   34..36 L[u_q][v_p] over the u-row's L columns of type v
+//   37..39 L[v_q][v_p] over the v-row's L columns
+// The forward sweep reads pairs 0..10 (slot 21 unused), the backward pairs 10..19
+// (slot 20 unused).
+__host__ __device__ constexpr int nth_ucol(int lo, int hi, int t, int m) {
+  for (int c = lo; c < hi; ++c)
+    if (ucol3(c).t == t && m-- == 0) return c;
+  return -1;
+}
+constexpr int kTUU = 0, kTUI = 12, kTVU = 13, kTVV = 17, kTVI = 20, kTLUU = 21, kTLUV = 33, kTLVU = 34, kTLVV = 37;
+constexpr int kTFwdPairs = 11, kTBwdPair0 = 10, kTBwdPairs = 10;
+// pattern column of transposed slot m: (is_u_row_of_q, column index in that row)
+__host__ __device__ constexpr Col3 tcol(int m, bool &urow, int &slot) {
+  if (m < kTUI) { slot = kFA + nth_ucol(kUD + 1, kUN, 0, m - kTUU); urow = true; return ucol3(slot - kFA); }
+  if (m == kTUI) { slot = kFA + kUD; urow = true; return ucol3(kUD); }
+  if (m < kTVV) { slot = kFA + nth_ucol(kUD + 1, kUN, 1, m - kTVU); urow = true; return ucol3(slot - kFA); }
+  if (m < kTVI) { slot = kFB + kVD + 1 + (m - kTVV); urow = false; return vcol3(slot - kFB); }
+  if (m == kTVI) { slot = kFB + kVD; urow = false; return vcol3(kVD); }
+  if (m < kTLUV) { slot = kFA + nth_ucol(0, kUL, 0, m - kTLUU); urow = true; return ucol3(slot - kFA); }
+  if (m == kTLUV) { slot = kFB + kVL - 1; urow = false; return vcol3(kVL - 1); }
+  if (m < kTLVV) { slot = kFA + nth_ucol(0, kUL, 1, m - kTLVU); urow = true; return ucol3(slot - kFA); }
+  slot = kFB + (m - kTLVV);
+  urow = false;
+  return vcol3(m - kTLVV);
+}
+__host__ __device__ constexpr bool tcols_consistent() {
+  // 12 + 4 u-row U columns, 12 + 3 u-row L columns, the first v-type U column at p itself
+  bool ok = nth_ucol(kUD + 1, kUN, 0, 11) >= 0 && nth_ucol(kUD + 1, kUN, 0, 12) < 0 &&
+            nth_ucol(kUD + 1, kUN, 1, 3) >= 0 && nth_ucol(kUD + 1, kUN, 1, 4) < 0 &&
+            nth_ucol(0, kUL, 0, 11) >= 0 && nth_ucol(0, kUL, 0, 12) < 0 && nth_ucol(0, kUL, 1, 2) >= 0 &&
+            nth_ucol(0, kUL, 1, 3) < 0;
+  const Col3 own = ucol3(nth_ucol(kUD + 1, kUN, 1, 0));
+  return ok && own.dx == 0 && own.dy == 0 && own.dz == 0;
+}
+static_assert(tcols_consistent(), "transposed record layout");
+
+template <typename FT>
+__global__ __launch_bounds__(kWin3DThreads) void k_pack_window3d_t(BoxGeom G, const int *__restrict__ wcols,
+                                                                   const FT *__restrict__ fac,
+                                                                   FT *__restrict__ wfact) {
+  const int w = blockIdx.x, sub = blockIdx.y, W = blockDim.x, t = threadIdx.x;
+  int i = 0, j = 0, k = 0;
+  bool found = false;
+#pragma unroll
+  for (int m = 0; m < kWin3DCols; ++m) {
+    const int c = wcols[m * kWin3DThreads + t];
+    const int jj = c & 1023, kk = c >> 10, ii = w - 2 * jj - 3 * kk;
+    if (c >= 0 && ii >= 0 && ii < G.bw) {
+      i = ii;
+      j = jj;
+      k = kk;
+      found = true;
+    }
+  }
+  if (!found) return;
+  const Box3 B{G.bw, G.bh, G.bd};
+  const FT *fk = fac + (long)sub * G.ncb * kNSlot3D;
+  FT *dst = wfact + (((long)sub * G.nlev + w) * kNSlot3D) * W + 2 * t;
+#pragma unroll
+  for (int m = 0; m < kNSlot3D; ++m) {
+    bool urow = false;
+    int slot = 0;
+    const Col3 cc = tcol(m, urow, slot);
+    const int qi = i - cc.dx, qj = j - cc.dy, qk = k - cc.dz;   // the row holding column p
+    const FT v = B.in(qi, qj, qk) ? fk[(long)B.at(qi, qj, qk) * kNSlot3D + slot] : (FT)0;
+    dst[(long)(m / 2) * 2 * W + (m & 1)] = v;
+  }
+}
+
+template <typename FT, int D>
+__global__ __launch_bounds__(kWin3DThreads) void k_ras_t_apply3d_win(
+    Phys P, BoxGeom G, const SubInfo *__restrict__ subs, const int *__restrict__ wcols, const FT *__restrict__ wfact,
+    double2 *__restrict__ ybuf, double2 *__restrict__ tbox, const double *__restrict__ r, const GmresState *st,
+    long vstride) {
+  extern __shared__ double2 win[];   // kWinSpan * bh * bd values
+  double sc = 1.0;
+  if (st) {
+    if (st->done) return;
+    r += (long)st->j * vstride;
+    sc = st->inv_norm[st->j];
+  }
+  const SubInfo si = subs[blockIdx.x];
+  const Box3 B{G.bw, G.bh, G.bd};
+  const long n = (long)P.nx * P.ny * P.nz;
+  const int W = blockDim.x;
+  const unsigned tid = threadIdx.x;
+  const long fbox = (long)G.nlev * kNSlot3D * W;
+  const __amdgpu_buffer_rsrc_t rsF = buffer_rsrc(wfact + blockIdx.x * fbox, (unsigned)(fbox * sizeof(FT)));
+  const __amdgpu_buffer_rsrc_t rsY =
+      buffer_rsrc(ybuf + (long)blockIdx.x * G.nlev * W, (unsigned)((long)G.nlev * W * sizeof(double2)));
+  const __amdgpu_buffer_rsrc_t rsX =
+      buffer_rsrc(tbox + (long)blockIdx.x * G.ncb, (unsigned)((long)G.ncb * sizeof(double2)));
+  const unsigned pair_bytes = __builtin_amdgcn_readfirstlane((unsigned)W * 2 * sizeof(FT));
+  const int plane = G.bh * G.bd;
+  const unsigned last_slot = (unsigned)(kWinSpan * plane - 1);
+  const int top = G.nlev - 1;
+  for (int e = threadIdx.x; e <= (int)last_slot; e += W) win[e] = make_double2(0.0, 0.0);
+  ColCursor cur;
+#pragma unroll
+  for (int m = 0; m < kWin3DCols; ++m) cur.col[m] = wcols[m * kWin3DThreads + threadIdx.x];
+  __syncthreads();
+
+  auto foff = [&](const WinCell &c, int w) -> unsigned {
+    return c.act ? ((unsigned)w * kPairs * W + tid) * (unsigned)(2 * sizeof(FT)) : kPastEnd;
+  };
+  auto yoff = [&](const WinCell &c, int w) -> unsigned {
+    return c.act ? ((unsigned)w * W + tid) * (unsigned)sizeof(double2) : kPastEnd;
+  };
+  // value pair at cell c - o (the row q of a transposed entry; any finite pair outside the box)
+  auto nbm = [&](const WinCell &c, const Col3 o) -> double2 {
+    const int s = ((c.i - o.dx) & (kWinSpan - 1)) * plane + (c.j - o.dy) * G.bd + (c.k - o.dz);
+    return win[min((unsigned)s, last_slot)];
+  };
+  auto slot = [&](const WinCell &c) { return (c.i & (kWinSpan - 1)) * plane + c.j * G.bd + c.k; };
+  struct TF {
+    WinCell c;
+    bool own;
+    double ru, rv;
+    double e[2 * kTFwdPairs];
+  };
+  struct TB {
+    WinCell c;
+    double yu, yv;
+    double e[2 * kTBwdPairs];
+  };
+  auto fetch_f = [&](int w, TF &d) {
+    d.c = cur.at(w, G.bw, true);
+    const long g = box3_to_global(si, d.c.i, d.c.j, d.c.k, P);
+    d.own = g >= 0 && owned3(si, d.c.i, d.c.j, d.c.k);
+    const long gs = g >= 0 ? g : 0;
+    d.ru = r[gs];
+    d.rv = r[n + gs];
+    const unsigned o = foff(d.c, w);
+#pragma unroll
+    for (int q = 0; q < kTFwdPairs; ++q) pair_load(rsF, o, q * pair_bytes, wfact, d.e[2 * q], d.e[2 * q + 1]);
+  };
+  auto fetch_b = [&](int w, TB &d) {
+    d.c = cur.at(w, G.bw, false);
+    const double_pair y =
+        __builtin_bit_cast(double_pair, __builtin_amdgcn_raw_buffer_load_b128(rsY, yoff(d.c, w), 0, 0));
+    d.yu = y.x;
+    d.yv = y.y;
+    const unsigned o = foff(d.c, w);
+#pragma unroll
+    for (int q = 0; q < kTBwdPairs; ++q)
+      pair_load(rsF, o, (kTBwdPair0 + q) * pair_bytes, wfact, d.e[2 * q], d.e[2 * q + 1]);
+  };
+  // U^T y = R^0 r
+  {
+    auto level = [&](const TF &d, int w) {
+      const WinCell &c = d.c;
+      double yu = d.own ? sc * d.ru : 0.0, yv = d.own ? sc * d.rv : 0.0;
+#pragma unroll
+      for (int m = kTUU; m < kTUI; ++m) {
+        bool urow = false;
+        int sl = 0;
+        yu = fma(-d.e[m], nbm(c, tcol(m, urow, sl)).x, yu);
+      }
+      yu *= d.e[kTUI];
+      yv = fma(-d.e[kTVU], yu, yv);   // q = p
+#pragma unroll
+      for (int m = kTVU + 1; m < kTVV; ++m) {
+        bool urow = false;
+        int sl = 0;
+        yv = fma(-d.e[m], nbm(c, tcol(m, urow, sl)).x, yv);
+      }
+#pragma unroll
+      for (int m = kTVV; m < kTVI; ++m) {
+        bool urow = false;
+        int sl = 0;
+        yv = fma(-d.e[m], nbm(c, tcol(m, urow, sl)).y, yv);
+      }
+      yv *= d.e[kTVI];
+      if (c.act) win[slot(c)] = make_double2(yu, yv);
+      const double_pair y{yu, yv};
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(word4, y), rsY, yoff(c, w), 0, 0);
+      lds_barrier();
+    };
+    TF s[D + 1];
+#pragma unroll
+    for (int m = 0; m < D; ++m) fetch_f(m, s[m]);
+    for (int w = 0; w <= top; w += D + 1) {
+#pragma unroll
+      for (int m = 0; m <= D; ++m) {
+        fetch_f(w + m + D, s[(m + D) % (D + 1)]);
+        level(s[m], w + m);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kWin3DCols; ++m) cur.col[m] = wcols[(kWin3DCols + m) * kWin3DThreads + threadIdx.x];
+  __syncthreads();   // the forward results are read below
+  // L^T x = y; the whole box's x to tbox (cell order)
+  {
+    auto level = [&](const TB &d) {
+      const WinCell &c = d.c;
+      constexpr int o = kTBwdPair0 * 2;   // slot of d.e[0]
+      double xv = d.yv;
+#pragma unroll
+      for (int m = kTLVU; m < kTLVV; ++m) {
+        bool urow = false;
+        int sl = 0;
+        xv = fma(-d.e[m - o], nbm(c, tcol(m, urow, sl)).x, xv);
+      }
+#pragma unroll
+      for (int m = kTLVV; m < kNSlot3D; ++m) {
+        bool urow = false;
+        int sl = 0;
+        xv = fma(-d.e[m - o], nbm(c, tcol(m, urow, sl)).y, xv);
+      }
+      double xu = fma(-d.e[kTLUV - o], xv, d.yu);   // L[v_p][u_p]
+#pragma unroll
+      for (int m = kTLUU; m < kTLUV; ++m) {
+        bool urow = false;
+        int sl = 0;
+        xu = fma(-d.e[m - o], nbm(c, tcol(m, urow, sl)).x, xu);
+      }
+      if (c.act) win[slot(c)] = make_double2(xu, xv);
+      const double_pair x{xu, xv};
+      const unsigned xo = c.act ? (unsigned)B.at(c.i, c.j, c.k) * (unsigned)sizeof(double2) : kPastEnd;
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(word4, x), rsX, xo, 0, 0);
+      lds_barrier();
+    };
+    TB t[D + 1];
+#pragma unroll
+    for (int m = 0; m < D; ++m) fetch_b(top - m, t[m]);
+    for (int w = top; w >= 0; w -= D + 1) {
+#pragma unroll
+      for (int m = 0; m <= D; ++m) {
+        fetch_b(w - m - D, t[(m + D) % (D + 1)]);
+        level(t[m]);
+      }
+    }
+  }
+}
+
 // ---- z = M^{-T} r: restrict to owned cells, U^T then L^T sweeps (coefficients of
 // the neighbour rows), add whole boxes (k_ras_t_gather3d) ---------------------------
 template <typename FT>
@@ -914,10 +1167,48 @@ hipError_t launch_ras_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *su
   return hipGetLastError();
 }
 
+namespace {
+// Windowed transposed apply when the box allows it (packs the transposed records first
+// unless *packed); false: use the box-buffer kernels.
+template <typename FT>
+bool ras_t_apply3d_win(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *cells, int px, int py,
+                       int pz, const int *own, const void *fac, void *wfact, bool *packed, void *ybuf, double *tbox,
+                       const double *r, double *z, const GmresState *st, long vstride, hipStream_t s) {
+  const size_t lds = (size_t)kWinSpan * G.bh * G.bd * sizeof(double2);
+  if (!g_ras3d_window || !wfact || G.wmax <= 0 || G.wmax > kWin3DThreads || lds > kLdsMax3) return false;
+  static size_t allowed = kLdsDefault3;   // per instantiation
+  if (lds > allowed) {
+    if (hipFuncSetAttribute((const void *)k_ras_t_apply3d_win<FT, kWinDepth>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax3) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    allowed = kLdsMax3;
+  }
+  const int *wcols = cells + G.ncb;
+  if (!*packed) {
+    hipLaunchKernelGGL(k_pack_window3d_t<FT>, dim3(G.nlev, G.nsub), dim3(win3d_row(G)), 0, s, G, wcols,
+                       (const FT *)fac, (FT *)wfact);
+    *packed = true;
+  }
+  hipLaunchKernelGGL((k_ras_t_apply3d_win<FT, kWinDepth>), dim3(G.nsub), dim3(win3d_row(G)), lds, s, P, G, subs,
+                     wcols, (const FT *)wfact, (double2 *)ybuf, (double2 *)tbox, r, st, vstride);
+  const int nb = reduce_blocks((long)P.nx * P.ny * P.nz);
+  hipLaunchKernelGGL(k_ras_t_gather3d, dim3(nb), dim3(256), 0, s, P, G, subs, px, py, pz, own,
+                     (const double2 *)tbox, z, st, vstride);
+  return true;
+}
+}  // namespace
+
 hipError_t launch_ras_t_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl,
-                                const int *cells, int px, int py, int pz, const int *own, const void *fac, void *ybuf,
-                                const double *r, double *z, const GmresState *st, long vstride, int fp32,
-                                hipStream_t s) {
+                                const int *cells, int px, int py, int pz, const int *own, const void *fac,
+                                void *wfact, bool *packed, void *ybuf, double *tbox, const double *r, double *z,
+                                const GmresState *st, long vstride, int fp32, hipStream_t s) {
+  if (fp32 ? ras_t_apply3d_win<float>(P, G, subs, cells, px, py, pz, own, fac, wfact, packed, ybuf, tbox, r, z, st,
+                                      vstride, s)
+           : ras_t_apply3d_win<double>(P, G, subs, cells, px, py, pz, own, fac, wfact, packed, ybuf, tbox, r, z, st,
+                                       vstride, s))
+    return hipGetLastError();
   if (fp32)
     hipLaunchKernelGGL(k_ras_t_sweep3d<float>, dim3(G.nsub), dim3(256), 0, s, P, G, subs, lvl, cells,
                        (const float *)fac, (double2 *)ybuf, r, st, vstride);

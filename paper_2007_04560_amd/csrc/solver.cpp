@@ -33,7 +33,7 @@ namespace {
 
 struct Layout {
   size_t off_Xn, off_Xprev, off_X, off_Xt, off_F, off_Ft, off_S, off_W;
-  size_t off_J, off_V, off_Z, off_fac, off_wfac, off_q3, off_y, off_dump, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
+  size_t off_J, off_V, off_Z, off_fac, off_wfac, off_wfact, off_q3, off_y, off_dump, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
   size_t off_tbox, off_own;
   size_t total;
 };
@@ -62,6 +62,8 @@ struct acch_ctx {
   double *Xn, *Xprev, *X, *Xt, *F, *Ft, *S, *W, *J, *V, *Z;
   void *fac, *wfac, *ybuf;   // wfac: level-major factor copy of the 3D windowed apply (or null)
   double *q3;                // 3D: cell quantities of the residual / Jacobian passes
+  void *wfact = nullptr;     // 3D: transposed-record copy for the windowed M^{-T}
+  bool tpacked = false;      // wfact holds the current factorisation
   double *dump, *tbox;
   SubInfo *d_subs;
   int *d_lvl, *d_own;
@@ -324,6 +326,7 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_y = d3 ? take((box3_ypairs(geo.G) + 1) * 2 * sizeof(double))
                : take((size_t)geo.G.nsub * 2 * (slots + 1) * fsz);
   L.off_wfac = take(d3 ? win3d_fac_elems(geo.G) * fsz : 0);
+  L.off_wfact = take(d3 ? win3d_fac_elems(geo.G) * fsz : 0);   // transposed records (adjoint)
   L.off_q3 = take(d3 ? (size_t)8 * geo.ncell * sizeof(double) : 0);   // 3D cell quantities
   L.off_dump = take(64 * sizeof(double));
   L.off_subs = take(geo.subs.size() * sizeof(SubInfo));
@@ -441,6 +444,7 @@ hipError_t run_energy(acch_ctx *c, const double *X) {
   return c->d3 ? launch_energy3d(c->bl, X, c->red, c->stream) : launch_energy2d(c->bl, X, c->red, c->stream);
 }
 hipError_t run_factor(acch_ctx *c) {
+  c->tpacked = false;
   if (c->d3)
     return launch_ilu_factor3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->J, c->p.ilu_shift, c->fac,
                                c->wfac, fp32_of(c), c->stream);
@@ -457,7 +461,8 @@ hipError_t run_ras(acch_ctx *c, const double *r, double *z, const GmresState *st
 hipError_t run_ras_t(acch_ctx *c, const double *r, double *z, const GmresState *st, long vs) {
   if (c->d3)
     return launch_ras_t_apply3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->p.sub[0], c->p.sub[1],
-                                c->p.sub[2], c->d_own, c->fac, c->ybuf, r, z, st, vs, fp32_of(c), c->stream);
+                                c->p.sub[2], c->d_own, c->fac, c->wfact, &c->tpacked, c->ybuf, c->tbox, r, z, st, vs,
+                                fp32_of(c), c->stream);
   return launch_ras_t_apply2d(c->geo.G, c->d_subs, c->P.nx, c->P.ny, c->P.periodic, c->p.sub[0], c->p.sub[1],
                               c->d_own, c->d_own + c->P.nx, c->p.ras_type, c->fac, c->tbox, r, z, st, vs, fp32_of(c),
                               c->stream);
@@ -666,6 +671,7 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->Z = (double *)(c->ws + L.off_Z);
   c->fac = c->ws + L.off_fac;
   c->wfac = c->geo.G.wmax > 0 ? (void *)(c->ws + L.off_wfac) : nullptr;
+  c->wfact = c->geo.G.wmax > 0 ? (void *)(c->ws + L.off_wfact) : nullptr;
   c->q3 = (double *)(c->ws + L.off_q3);
   c->ybuf = c->ws + L.off_y;
   c->dump = (double *)(c->ws + L.off_dump);
