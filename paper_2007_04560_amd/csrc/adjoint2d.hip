@@ -2,152 +2,17 @@
 // fixed, 2D.  A step solves F(U^{n+1}; U^n) = 0, so for a loss L(U^N)
 //   A^T lambda = dL/dU^{n+1},  dL/dU^n = -B^T lambda,  dL/dp -= lambda . dF/dp,
 // with A = dF/dU^{n+1} (the Newton Jacobian J) and B = dF/dU^n.  This file holds
-//   - the transposed Schwarz preconditioner M^{-T} = sum_k (R_k^delta)^T (L_k U_k)^{-T} R_k^0
-//     (the exact transpose of the left-restricted operator, with the same factors),
 //   - B^T lambda and the parameter terms by reverse differentiation of the residual
 //     stencil (no B is assembled),
 //   - the gradient of the discrete energy (eq. freeenergy).
-// J^T x itself is the slot-transposed product in the stencil file.
+// J^T x itself is the slot-transposed product in the stencil file, and the transposed
+// Schwarz preconditioner runs in the Schwarz file (transposed records, same sweeps).
 #include "../../include/acch.h"
-#include "boxes.h"
 #include "kernels.h"
 #include "physics.h"
 
 namespace acch {
 namespace {
-
-// ---------------------------------------------------------------------------
-// M^{-T} r: per box, restrict r to the owned cells, solve U^T y = r (forward over
-// the wavefronts), then L^T x = y (backward); the whole box is then added into z.
-// The factor layout is the one written by the factorisation kernel: the 24 slots of
-// box cell (i, j) are contiguous at padded wavefront index (i + 2j) bh + j.
-// Slots: 0-7 u-row L at u(-1,0) u(-2,0) u(1,-1) u(0,-1) u(-1,-1) u(0,-2) v(-1,0)
-// v(0,-1); 8-10 v-row L at v(-1,0) v(0,-1) u(0,0); 11 1/U_uu; 12-17 u-row U at
-// u(1,0) u(2,0) u(-1,1) u(0,1) u(1,1) u(0,2); 18-20 u-row U at v(0,0) v(1,0) v(0,1);
-// 21 1/U_vv; 22-23 v-row U at v(1,0) v(0,1).
-// ---------------------------------------------------------------------------
-template <typename FT>
-struct TCoef {
-  const FT *F;
-  long ncb;
-  int bh;
-  template <int S>
-  ACCH_DEV double at(int i, int j) const {
-    const long idx = (long)(i + 2 * j) * bh + j;
-    return (double)F[idx * kNSlot2D + S];
-  }
-};
-
-template <typename FT, int NW, bool INLDS>
-__global__ __launch_bounds__(64 * NW) void k_ras_t_sweep2d(BoxGeom G, const SubInfo *__restrict__ subs, int nx,
-                                                           int ny, int periodic, int kind,
-                                                           const FT *__restrict__ fac, const double *__restrict__ r,
-                                                           double *__restrict__ box, double *__restrict__ z,
-                                                           const GmresState *st, long vstride) {
-  constexpr int T = 64 * NW;
-  extern __shared__ double lds_vals[];
-  if (st && st->done) return;
-  const int jj = st ? st->j : 0;
-  const double sc = st ? st->inv_norm[jj] : 1.0;
-  const long n = (long)nx * ny;
-  const double *ru = r + (long)jj * vstride, *rv = ru + n;
-  const int t = threadIdx.x;
-  const SubInfo si = subs[blockIdx.x];
-  const int bw = G.bw, bh = G.bh, nb = bw * bh;
-  const TCoef<FT> C{fac + (long)blockIdx.x * kNSlot2D * (long)G.nlev * bh, (long)G.nlev * bh, bh};
-  double *gvals = box + (long)blockIdx.x * 2 * nb;
-  double *vu = INLDS ? lds_vals : gvals;
-  double *vv = vu + nb;
-  // U^T y = R^0 r
-  for (int w = 0; w < G.nlev; ++w) {
-    const int j = row_on_level<T>(w, t, bw, bh);
-    if (j >= 0) {
-      const int i = w - 2 * j;
-      const long g = box_to_global(si, i, j, nx, ny, periodic);
-      const bool own = g >= 0 && i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1;
-      const bool in = kind == ACCH_RAS_LEFT ? own : g >= 0;   // the transpose of the extension
-      double a = in ? sc * ru[g] : 0.0;
-      double b = in ? sc * rv[g] : 0.0;
-      const int e = j * bw + i;
-      if (i >= 1) a -= C.template at<12>(i - 1, j) * vu[e - 1];
-      if (i >= 2) a -= C.template at<13>(i - 2, j) * vu[e - 2];
-      if (j >= 1 && i + 1 < bw) a -= C.template at<14>(i + 1, j - 1) * vu[e - bw + 1];
-      if (j >= 1) a -= C.template at<15>(i, j - 1) * vu[e - bw];
-      if (j >= 1 && i >= 1) a -= C.template at<16>(i - 1, j - 1) * vu[e - bw - 1];
-      if (j >= 2) a -= C.template at<17>(i, j - 2) * vu[e - 2 * bw];
-      const double yu = a * C.template at<11>(i, j);
-      b -= C.template at<18>(i, j) * yu;
-      if (i >= 1) b -= C.template at<19>(i - 1, j) * vu[e - 1] + C.template at<22>(i - 1, j) * vv[e - 1];
-      if (j >= 1) b -= C.template at<20>(i, j - 1) * vu[e - bw] + C.template at<23>(i, j - 1) * vv[e - bw];
-      vu[e] = yu;
-      vv[e] = b * C.template at<21>(i, j);
-    }
-    __syncthreads();
-  }
-  // L^T x = y (unit diagonal), v before u at each cell
-  for (int w = G.nlev - 1; w >= 0; --w) {
-    const int j = row_on_level<T>(w, t, bw, bh);
-    if (j >= 0) {
-      const int i = w - 2 * j;
-      const int e = j * bw + i;
-      double b = vv[e];
-      if (i + 1 < bw) b -= C.template at<6>(i + 1, j) * vu[e + 1] + C.template at<8>(i + 1, j) * vv[e + 1];
-      if (j + 1 < bh) b -= C.template at<7>(i, j + 1) * vu[e + bw] + C.template at<9>(i, j + 1) * vv[e + bw];
-      double a = vu[e] - C.template at<10>(i, j) * b;
-      if (i + 1 < bw) a -= C.template at<0>(i + 1, j) * vu[e + 1];
-      if (i + 2 < bw) a -= C.template at<1>(i + 2, j) * vu[e + 2];
-      if (j + 1 < bh && i >= 1) a -= C.template at<2>(i - 1, j + 1) * vu[e + bw - 1];
-      if (j + 1 < bh) a -= C.template at<3>(i, j + 1) * vu[e + bw];
-      if (j + 1 < bh && i + 1 < bw) a -= C.template at<4>(i + 1, j + 1) * vu[e + bw + 1];
-      if (j + 2 < bh) a -= C.template at<5>(i, j + 2) * vu[e + 2 * bw];
-      vu[e] = a;
-      vv[e] = b;
-    }
-    __syncthreads();
-  }
-  if (kind == ACCH_RAS_RIGHT) {
-    // the transpose of the owned-cell restriction: each owned cell written once
-    double *zu = z + (long)jj * vstride, *zv = zu + n;
-    for (int e = t; e < nb; e += T) {
-      const int j = e / bw, i = e - j * bw;
-      const long g = box_to_global(si, i, j, nx, ny, periodic);
-      if (g >= 0 && i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1) {
-        zu[g] = vu[e];
-        zv[g] = vv[e];
-      }
-    }
-  } else if constexpr (INLDS) {
-    for (int e = t; e < nb; e += T) {
-      gvals[e] = vu[e];
-      gvals[nb + e] = vv[e];
-    }
-  }
-}
-
-// z = sum over the boxes that contain a cell of their values there, in a fixed
-// order (for_boxes_of).
-__global__ __launch_bounds__(256) void k_ras_t_gather2d(BoxGeom G, const SubInfo *__restrict__ subs, int nx, int ny,
-                                                         int periodic, int px, int py, const int *__restrict__ own_x,
-                                                         const int *__restrict__ own_y,
-                                                         const double *__restrict__ box, double *__restrict__ z,
-                                                         const GmresState *st, long vstride) {
-  if (st && st->done) return;
-  const int jj = st ? st->j : 0;
-  const long n = (long)nx * ny;
-  double *zu = z + (long)jj * vstride, *zv = zu + n;
-  const int nb = G.bw * G.bh;
-  for (long g = blockIdx.x * 256L + threadIdx.x; g < n; g += (long)gridDim.x * 256) {
-    const int gy = (int)(g / nx), gx = (int)(g - (long)gy * nx);
-    double su = 0.0, sv = 0.0;
-    for_boxes_of(subs, nx, ny, periodic, px, py, own_x, own_y, gx, gy, [&](int k, int lx, int ly) {
-      const double *bk = box + (long)k * 2 * nb;
-      su += bk[ly * G.bw + lx];
-      sv += bk[nb + ly * G.bw + lx];
-    });
-    zu[g] = su;
-    zv[g] = sv;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // B^T lambda = (dF/dU^n)^T lambda and lambda . dF/dp by reverse differentiation
@@ -278,59 +143,7 @@ __global__ __launch_bounds__(256) void k_energy_grad2d(Phys P, const double *__r
   block_partial<4>(acc, red.partials, threadIdx.x, 256, blockIdx.x, gridDim.x);
 }
 
-// Box values stay in LDS when both fields of a box fit (gfx950 has 160 KB per CU;
-// above 64 KB the kernel has to be allowed the larger allocation first).
-constexpr size_t kLdsDefault = 64 * 1024;
-constexpr size_t kLdsMax = 160 * 1024;
-
-template <typename FT, int NW>
-hipError_t ras_t_impl(const BoxGeom &G, const SubInfo *subs, int nx, int ny, int periodic, int kind, const void *fac,
-                      double *box, const double *r, double *z, const GmresState *st, long vstride, hipStream_t s) {
-  const size_t lds = (size_t)2 * G.bw * G.bh * sizeof(double);
-  static size_t lds_allowed = kLdsDefault;   // per instantiation
-  bool inlds = lds <= lds_allowed;
-  if (!inlds && lds <= kLdsMax &&
-      hipFuncSetAttribute((const void *)k_ras_t_sweep2d<FT, NW, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)kLdsMax) == hipSuccess) {
-    lds_allowed = kLdsMax;
-    inlds = true;
-  }
-  (void)hipGetLastError();   // a refused attribute leaves the global-memory variant
-  if (inlds)
-    hipLaunchKernelGGL((k_ras_t_sweep2d<FT, NW, true>), dim3(G.nsub), dim3(64 * NW), lds, s, G, subs, nx, ny,
-                       periodic, kind, (const FT *)fac, r, box, z, st, vstride);
-  else
-    hipLaunchKernelGGL((k_ras_t_sweep2d<FT, NW, false>), dim3(G.nsub), dim3(64 * NW), 0, s, G, subs, nx, ny,
-                       periodic, kind, (const FT *)fac, r, box, z, st, vstride);
-  return hipGetLastError();
-}
-
-template <typename FT>
-hipError_t ras_t_waves(int nw, const BoxGeom &G, const SubInfo *subs, int nx, int ny, int periodic, int kind,
-                       const void *fac, double *box, const double *r, double *z, const GmresState *st, long vstride,
-                       hipStream_t s) {
-  if (nw == 1) return ras_t_impl<FT, 1>(G, subs, nx, ny, periodic, kind, fac, box, r, z, st, vstride, s);
-  if (nw == 2) return ras_t_impl<FT, 2>(G, subs, nx, ny, periodic, kind, fac, box, r, z, st, vstride, s);
-  if (nw == 4) return ras_t_impl<FT, 4>(G, subs, nx, ny, periodic, kind, fac, box, r, z, st, vstride, s);
-  return hipErrorInvalidValue;
-}
-
 }  // namespace
-
-hipError_t launch_ras_t_apply2d(const BoxGeom &G, const SubInfo *subs, int nx, int ny, int periodic, int px, int py,
-                                const int *own_x, const int *own_y, int kind, const void *fac, double *box,
-                                const double *r, double *z, const GmresState *st, long vstride, int fp32,
-                                hipStream_t s) {
-  const int nw = schwarz_waves(G);
-  hipError_t e = fp32 ? ras_t_waves<float>(nw, G, subs, nx, ny, periodic, kind, fac, box, r, z, st, vstride, s)
-                      : ras_t_waves<double>(nw, G, subs, nx, ny, periodic, kind, fac, box, r, z, st, vstride, s);
-  if (e != hipSuccess) return e;
-  if (kind == ACCH_RAS_RIGHT) return hipSuccess;
-  const int nb = reduce_blocks((long)nx * ny);
-  hipLaunchKernelGGL(k_ras_t_gather2d, dim3(nb), dim3(256), 0, s, G, subs, nx, ny, periodic, px, py, own_x, own_y,
-                     box, z, st, vstride);
-  return hipGetLastError();
-}
 
 hipError_t launch_adjoint_prev2d(const Phys &P, const double *X1, const double *X0, double dt, const double *lam,
                                  double lam_scale, double *bar, double *out, const RedBuf &red, hipStream_t s) {

@@ -101,14 +101,14 @@ hipError_t launch_reset_state(const BatchLaunch &bl, GmresState *st, hipStream_t
 hipError_t launch_copy2(const BatchLaunch &bl, double *d1, const double *s1, double *d2, const double *s2,
                         hipStream_t s);
 
+// z = M^{-T} r (the transpose of the variant rv.kind with the current factors, one
+// instance): fact holds the transposed records, filled from fac unless *packed (set
+// once filled); ybuf / dump as for launch_ras_apply2d.
+hipError_t launch_ras_t_apply2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
+                                const void *fac, void *fact, bool *packed, void *ybuf, const double *r, double *z,
+                                double *dump, const GmresState *st, long vstride, int fp32, hipStream_t s,
+                                const RasVariant &rv);
 // adjoint2d.hip
-// z = M^{-T} r (the transposed left-restricted Schwarz operator with the current
-// factors); box is a scratch of nsub * 2 * bw * bh doubles; own_x / own_y give the
-// owner subdomain index of each grid column / row.
-hipError_t launch_ras_t_apply2d(const BoxGeom &G, const SubInfo *subs, int nx, int ny, int periodic, int px, int py,
-                                const int *own_x, const int *own_y, int kind, const void *fac, double *box,
-                                const double *r, double *z, const GmresState *st, long vstride, int fp32,
-                                hipStream_t s);
 // out = (dF/dU^n)^T (lam_scale lam) at (X1; X0, dt); bar is a 2n scratch; red.out[0..3]
 // receives (lam_scale lam) . dF/dp for p = alpha, beta, theta, gamma.
 hipError_t launch_adjoint_prev2d(const Phys &P, const double *X1, const double *X0, double dt, const double *lam,

@@ -232,6 +232,48 @@ __global__ __launch_bounds__(64 * NW) void k_ilu_factor2d(Phys P0, Batch bt, Box
 }
 
 // ---------------------------------------------------------------------------
+// Transposed records (the adjoint's M^{-T}): slot m of cell p holds the coefficient of
+// column p in the row of cell q = p + (dx, dy) (zero when q is outside the box):
+//   0-5  U[u_q][u_p] for q at (-1,0) (-2,0) (1,-1) (0,-1) (-1,-1) (0,-2);  6  1/U[u_p][u_p]
+//   7-9  U[u_q][v_p] for q at (0,0) (-1,0) (0,-1);  10-11 U[v_q][v_p] for q at (-1,0) (0,-1)
+//   12   1/U[v_p][v_p]
+//   13-18 L[u_q][u_p] for q at (1,0) (2,0) (-1,1) (0,1) (1,1) (0,2);  19 L[v_p][u_p]
+//   20-21 L[u_q][v_p] for q at (1,0) (0,1);  22-23 L[v_q][v_p] for q at (1,0) (0,1)
+// The U^T sweep reads slots 0..12, the L^T sweep 13..23.
+// ---------------------------------------------------------------------------
+constexpr int kTFwd2D = 13;   // slots of the U^T sweep
+
+struct TSrc {
+  int dx, dy, slot;   // row cell q - p and the forward record slot holding the coefficient
+};
+__host__ __device__ constexpr TSrc tsrc2(int m) {
+  constexpr TSrc tab[kNSlot2D] = {{-1, 0, 12}, {-2, 0, 13}, {1, -1, 14}, {0, -1, 15}, {-1, -1, 16}, {0, -2, 17},
+                                  {0, 0, 11},  {0, 0, 18},  {-1, 0, 19}, {0, -1, 20}, {-1, 0, 22},  {0, -1, 23},
+                                  {0, 0, 21},  {1, 0, 0},   {2, 0, 1},   {-1, 1, 2},  {0, 1, 3},    {1, 1, 4},
+                                  {0, 2, 5},   {0, 0, 10},  {1, 0, 6},   {0, 1, 7},   {1, 0, 8},    {0, 1, 9}};
+  return tab[m];
+}
+
+template <typename FT>
+__global__ __launch_bounds__(256) void k_pack_t2d(BoxGeom G, const FT *__restrict__ fac, FT *__restrict__ fact) {
+  const long ncb = (long)G.nlev * G.bh;   // padded wavefront-major cell slots
+  const FT *Fk = fac + (long)blockIdx.x * kNSlot2D * ncb;
+  FT *Tk = fact + (long)blockIdx.x * kNSlot2D * ncb;
+  const int nbox = G.bw * G.bh;
+  for (int e = threadIdx.x; e < nbox; e += 256) {
+    const int j = e / G.bw, i = e - j * G.bw;
+    FT *dst = Tk + ((long)(i + 2 * j) * G.bh + j) * kNSlot2D;
+#pragma unroll
+    for (int m = 0; m < kNSlot2D; ++m) {
+      const TSrc q = tsrc2(m);
+      const int qi = i + q.dx, qj = j + q.dy;
+      const bool in = qi >= 0 && qi < G.bw && qj >= 0 && qj < G.bh;
+      dst[m] = in ? Fk[((long)(qi + 2 * qj) * G.bh + qj) * kNSlot2D + q.slot] : (FT)0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // z = M^{-1} r, left-restricted Schwarz (restricted extension) with ILU(0) solves.
 // ---------------------------------------------------------------------------
 // Factor storage: per subdomain, the 24 slots of a cell are contiguous (12 16-byte
@@ -348,7 +390,10 @@ ACCH_DEV long box_cell(const SubInfo &si, int i, int j, int nx, int ny, int peri
   return g;
 }
 
-template <typename FT, int NW, int D>
+// TRP: the transposed solves (U^T y = b, then L^T x = y) with transposed records
+// (k_pack_t2d); they read the same neighbour cells as the forward sweeps, since the
+// rows holding column p of U (of L) are the cells p - o for the U (L) offsets o.
+template <typename FT, int NW, int D, bool TRP>
 __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batch bt, BoxGeom G,
                                                                    const SubInfo *__restrict__ subs,
                                                                    const int *__restrict__ lvl,
@@ -381,8 +426,9 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
   using P2 = typename C::Pair;
   constexpr int per = C::per;
   constexpr int NCH = kNSlot2D / per;          // chunks per cell
-  constexpr int NLC = (11 + per - 1) / per;    // chunks holding slots 0..10
-  constexpr int U0C = 11 / per;                // first chunk of slots 11..23
+  constexpr int NL = TRP ? kTFwd2D : 11;        // slots the L (U^T) sweep reads
+  constexpr int NLC = (NL + per - 1) / per;    // chunks holding slots 0..NL-1
+  constexpr int U0C = NL / per;                // first chunk of slots NL..23
   constexpr int NUC = NCH - U0C;
   constexpr int TT = 64 * NW;
   constexpr int TB = ras_threads<NW>();
@@ -463,19 +509,36 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
         neighbour_fetch<-1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
         Stage<FT, NLC> &s = ring[k];
         // values of earlier wavefronts first; o1 (own, w-1) and A (neighbour, w-1) last
-        FT acc = slot<1, 0, FT>(s.c) * o2u;
-        acc = fma(slot<3, 0, FT>(s.c), a1u, acc);
-        acc = fma(slot<4, 0, FT>(s.c), a2u, acc);
-        acc = fma(slot<7, 0, FT>(s.c), a1v, acc);
-        acc = fma(slot<5, 0, FT>(s.c), Mu, acc);
-        acc = fma(slot<0, 0, FT>(s.c), o1u, acc);
-        acc = fma(slot<6, 0, FT>(s.c), o1v, acc);
-        acc = fma(slot<2, 0, FT>(s.c), Au, acc);
-        FT yu = s.y.x - acc;
-        FT accv = slot<9, 0, FT>(s.c) * a1v;
-        accv = fma(slot<8, 0, FT>(s.c), o1v, accv);
-        accv = fma(slot<10, 0, FT>(s.c), yu, accv);
-        FT yv = s.y.y - accv;
+        FT yu, yv;
+        if constexpr (!TRP) {
+          FT acc = slot<1, 0, FT>(s.c) * o2u;
+          acc = fma(slot<3, 0, FT>(s.c), a1u, acc);
+          acc = fma(slot<4, 0, FT>(s.c), a2u, acc);
+          acc = fma(slot<7, 0, FT>(s.c), a1v, acc);
+          acc = fma(slot<5, 0, FT>(s.c), Mu, acc);
+          acc = fma(slot<0, 0, FT>(s.c), o1u, acc);
+          acc = fma(slot<6, 0, FT>(s.c), o1v, acc);
+          acc = fma(slot<2, 0, FT>(s.c), Au, acc);
+          yu = s.y.x - acc;
+          FT accv = slot<9, 0, FT>(s.c) * a1v;
+          accv = fma(slot<8, 0, FT>(s.c), o1v, accv);
+          accv = fma(slot<10, 0, FT>(s.c), yu, accv);
+          yv = s.y.y - accv;
+        } else {   // U^T
+          FT acc = slot<1, 0, FT>(s.c) * o2u;
+          acc = fma(slot<3, 0, FT>(s.c), a1u, acc);
+          acc = fma(slot<4, 0, FT>(s.c), a2u, acc);
+          acc = fma(slot<5, 0, FT>(s.c), Mu, acc);
+          acc = fma(slot<0, 0, FT>(s.c), o1u, acc);
+          acc = fma(slot<2, 0, FT>(s.c), Au, acc);
+          yu = (s.y.x - acc) * slot<6, 0, FT>(s.c);
+          FT accv = slot<9, 0, FT>(s.c) * a1u;
+          accv = fma(slot<11, 0, FT>(s.c), a1v, accv);
+          accv = fma(slot<8, 0, FT>(s.c), o1u, accv);
+          accv = fma(slot<10, 0, FT>(s.c), o1v, accv);
+          accv = fma(slot<7, 0, FT>(s.c), yu, accv);
+          yv = (s.y.y - accv) * slot<12, 0, FT>(s.c);
+        }
         yu = s.act ? yu : zero;
         yv = s.act ? yv : zero;
         P2 y2;
@@ -500,19 +563,36 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
         FT Au, Av, Mu, Mv;
         neighbour_fetch<1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
         Stage<FT, NUC> &s = ringu[k];
-        FT accv = slot<23, U0C, FT>(s.c) * a1v;
-        accv = fma(slot<22, U0C, FT>(s.c), o1v, accv);
-        FT xv = (s.y.y - accv) * slot<21, U0C, FT>(s.c);
-        FT acc = slot<13, U0C, FT>(s.c) * o2u;
-        acc = fma(slot<15, U0C, FT>(s.c), a1u, acc);
-        acc = fma(slot<16, U0C, FT>(s.c), a2u, acc);
-        acc = fma(slot<20, U0C, FT>(s.c), a1v, acc);
-        acc = fma(slot<17, U0C, FT>(s.c), Mu, acc);
-        acc = fma(slot<12, U0C, FT>(s.c), o1u, acc);
-        acc = fma(slot<19, U0C, FT>(s.c), o1v, acc);
-        acc = fma(slot<14, U0C, FT>(s.c), Au, acc);
-        acc = fma(slot<18, U0C, FT>(s.c), xv, acc);
-        FT xu = (s.y.x - acc) * slot<11, U0C, FT>(s.c);
+        FT xu, xv;
+        if constexpr (!TRP) {
+          FT accv = slot<23, U0C, FT>(s.c) * a1v;
+          accv = fma(slot<22, U0C, FT>(s.c), o1v, accv);
+          xv = (s.y.y - accv) * slot<21, U0C, FT>(s.c);
+          FT acc = slot<13, U0C, FT>(s.c) * o2u;
+          acc = fma(slot<15, U0C, FT>(s.c), a1u, acc);
+          acc = fma(slot<16, U0C, FT>(s.c), a2u, acc);
+          acc = fma(slot<20, U0C, FT>(s.c), a1v, acc);
+          acc = fma(slot<17, U0C, FT>(s.c), Mu, acc);
+          acc = fma(slot<12, U0C, FT>(s.c), o1u, acc);
+          acc = fma(slot<19, U0C, FT>(s.c), o1v, acc);
+          acc = fma(slot<14, U0C, FT>(s.c), Au, acc);
+          acc = fma(slot<18, U0C, FT>(s.c), xv, acc);
+          xu = (s.y.x - acc) * slot<11, U0C, FT>(s.c);
+        } else {   // L^T (unit diagonal), v before u at each cell
+          FT accv = slot<21, U0C, FT>(s.c) * a1u;
+          accv = fma(slot<23, U0C, FT>(s.c), a1v, accv);
+          accv = fma(slot<20, U0C, FT>(s.c), o1u, accv);
+          accv = fma(slot<22, U0C, FT>(s.c), o1v, accv);
+          xv = s.y.y - accv;
+          FT acc = slot<14, U0C, FT>(s.c) * o2u;
+          acc = fma(slot<16, U0C, FT>(s.c), a1u, acc);
+          acc = fma(slot<17, U0C, FT>(s.c), a2u, acc);
+          acc = fma(slot<18, U0C, FT>(s.c), Mu, acc);
+          acc = fma(slot<13, U0C, FT>(s.c), o1u, acc);
+          acc = fma(slot<15, U0C, FT>(s.c), Au, acc);
+          acc = fma(slot<19, U0C, FT>(s.c), xv, acc);
+          xu = s.y.x - acc;
+        }
         xu = s.act ? xu : zero;
         xv = s.act ? xv : zero;
         P2 x2;
@@ -615,24 +695,24 @@ hipError_t factor_impl(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *s
 // Wavefronts loaded ahead of their use in the solves (selectable for tuning).
 int g_ras_prefetch = 4;
 
-template <typename FT, int NW, int D>
+template <typename FT, int NW, int D, bool TRP>
 hipError_t apply_d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl, const void *fac,
                    void *ybuf, const double *r, double *z, double *dump, const GmresState *st, long vstride,
                    int kind, hipStream_t s) {
-  hipLaunchKernelGGL((k_ras_apply2d<FT, NW, D>), dim3(bl.grid[kFamSub]), dim3(ras_threads<NW>()), 0, s, bl.P0, bl.bt,
-                     G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind);
+  hipLaunchKernelGGL((k_ras_apply2d<FT, NW, D, TRP>), dim3(bl.grid[kFamSub]), dim3(ras_threads<NW>()), 0, s, bl.P0,
+                     bl.bt, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind);
   return hipGetLastError();
 }
 
-template <typename FT, int NW>
+template <typename FT, int NW, bool TRP = false>
 hipError_t apply_impl(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl, const void *fac,
                       void *ybuf, const double *r, double *z, double *dump, const GmresState *st, long vstride,
                       int kind, hipStream_t s) {
   switch (g_ras_prefetch) {
-    case 2: return apply_d<FT, NW, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
-    case 8: return apply_d<FT, NW, 8>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
-    case 16: return apply_d<FT, NW, 16>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
-    default: return apply_d<FT, NW, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    case 2: return apply_d<FT, NW, 2, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    case 8: return apply_d<FT, NW, 8, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    case 16: return apply_d<FT, NW, 16, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    default: return apply_d<FT, NW, 4, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
   }
 }
 
@@ -679,6 +759,45 @@ hipError_t launch_ras_apply2d(const BatchLaunch &bl, const BoxGeom &G, const Sub
     if (nw == 1) e = apply_impl<double, 1>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
     if (nw == 2) e = apply_impl<double, 2>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
     if (nw == 4) e = apply_impl<double, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+  }
+  if (e != hipSuccess || kind == ACCH_RAS_LEFT) return e;
+  const Phys &P = bl.P0;
+  const int nb = reduce_blocks((long)P.nx * P.ny);
+  if (fp32)
+    hipLaunchKernelGGL(k_ras_sum2d<float>, dim3(nb), dim3(256), 0, s, G, subs, P.nx, P.ny, P.periodic, rv.px, rv.py,
+                       rv.own_x, rv.own_y, ybuf, z, st, vstride);
+  else
+    hipLaunchKernelGGL(k_ras_sum2d<double>, dim3(nb), dim3(256), 0, s, G, subs, P.nx, P.ny, P.periodic, rv.px, rv.py,
+                       rv.own_x, rv.own_y, ybuf, z, st, vstride);
+  return hipGetLastError();
+}
+
+// M^{-T} r for the three variants: M^{-T} of the left-restricted operator has the
+// shape of the right-restricted M^{-1} (owned-cell gather, whole boxes summed) and
+// vice versa, so the transposed solves run with the variant swapped.
+hipError_t launch_ras_t_apply2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
+                                const void *fac, void *fact, bool *packed, void *ybuf, const double *r, double *z,
+                                double *dump, const GmresState *st, long vstride, int fp32, hipStream_t s,
+                                const RasVariant &rv) {
+  const int nw = schwarz_waves(G);
+  if (bl.bt.map[kFamSub] != nullptr || !rv.own_x) return hipErrorInvalidValue;
+  if (!*packed) {
+    if (fp32)
+      hipLaunchKernelGGL(k_pack_t2d<float>, dim3(G.nsub), dim3(256), 0, s, G, (const float *)fac, (float *)fact);
+    else
+      hipLaunchKernelGGL(k_pack_t2d<double>, dim3(G.nsub), dim3(256), 0, s, G, (const double *)fac, (double *)fact);
+    *packed = true;
+  }
+  const int kind = rv.kind == ACCH_RAS_LEFT ? ACCH_RAS_RIGHT : (rv.kind == ACCH_RAS_RIGHT ? ACCH_RAS_LEFT : rv.kind);
+  hipError_t e = hipErrorInvalidValue;
+  if (fp32) {
+    if (nw == 1) e = apply_impl<float, 1, true>(bl, G, subs, lvl, fact, ybuf, r, z, dump, st, vstride, kind, s);
+    if (nw == 2) e = apply_impl<float, 2, true>(bl, G, subs, lvl, fact, ybuf, r, z, dump, st, vstride, kind, s);
+    if (nw == 4) e = apply_impl<float, 4, true>(bl, G, subs, lvl, fact, ybuf, r, z, dump, st, vstride, kind, s);
+  } else {
+    if (nw == 1) e = apply_impl<double, 1, true>(bl, G, subs, lvl, fact, ybuf, r, z, dump, st, vstride, kind, s);
+    if (nw == 2) e = apply_impl<double, 2, true>(bl, G, subs, lvl, fact, ybuf, r, z, dump, st, vstride, kind, s);
+    if (nw == 4) e = apply_impl<double, 4, true>(bl, G, subs, lvl, fact, ybuf, r, z, dump, st, vstride, kind, s);
   }
   if (e != hipSuccess || kind == ACCH_RAS_LEFT) return e;
   const Phys &P = bl.P0;

@@ -62,7 +62,7 @@ struct acch_ctx {
   double *Xn, *Xprev, *X, *Xt, *F, *Ft, *S, *W, *J, *V, *Z;
   void *fac, *wfac, *ybuf;   // wfac: level-major factor copy of the 3D windowed apply (or null)
   double *q3;                // 3D: cell quantities of the residual / Jacobian passes
-  void *wfact = nullptr;     // 3D: transposed-record copy for the windowed M^{-T}
+  void *wfact = nullptr;     // transposed records for M^{-T} (3D: level-major, windowed form)
   bool tpacked = false;      // wfact holds the current factorisation
   double *dump, *tbox;
   SubInfo *d_subs;
@@ -326,7 +326,8 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_y = d3 ? take((box3_ypairs(geo.G) + 1) * 2 * sizeof(double))
                : take((size_t)geo.G.nsub * 2 * (slots + 1) * fsz);
   L.off_wfac = take(d3 ? win3d_fac_elems(geo.G) * fsz : 0);
-  L.off_wfact = take(d3 ? win3d_fac_elems(geo.G) * fsz : 0);   // transposed records (adjoint)
+  // transposed records (adjoint): 3D level-major copy, 2D same layout as the factors
+  L.off_wfact = take(d3 ? win3d_fac_elems(geo.G) * fsz : (size_t)geo.G.nsub * nslot * slots * fsz);
   L.off_q3 = take(d3 ? (size_t)8 * geo.ncell * sizeof(double) : 0);   // 3D cell quantities
   L.off_dump = take(64 * sizeof(double));
   L.off_subs = take(geo.subs.size() * sizeof(SubInfo));
@@ -336,7 +337,7 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_part = take(nparts * sizeof(double));
   L.off_cnt = take(64);
   L.off_out = take(64 * sizeof(double));
-  L.off_tbox = take((size_t)geo.G.nsub * 2 * geo.G.ncb * sizeof(double));   // transposed Schwarz boxes
+  L.off_tbox = take(d3 ? (size_t)geo.G.nsub * 2 * geo.G.ncb * sizeof(double) : 0);   // 3D transposed boxes
   L.off_own = take(geo.own.size() * sizeof(int));
   L.total = o;
 }
@@ -463,9 +464,8 @@ hipError_t run_ras_t(acch_ctx *c, const double *r, double *z, const GmresState *
     return launch_ras_t_apply3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->p.sub[0], c->p.sub[1],
                                 c->p.sub[2], c->d_own, c->fac, c->wfact, &c->tpacked, c->ybuf, c->tbox, r, z, st, vs,
                                 fp32_of(c), c->stream);
-  return launch_ras_t_apply2d(c->geo.G, c->d_subs, c->P.nx, c->P.ny, c->P.periodic, c->p.sub[0], c->p.sub[1],
-                              c->d_own, c->d_own + c->P.nx, c->p.ras_type, c->fac, c->tbox, r, z, st, vs, fp32_of(c),
-                              c->stream);
+  return launch_ras_t_apply2d(c->bl, c->geo.G, c->d_subs, c->d_lvl, c->fac, c->wfact, &c->tpacked, c->ybuf, r, z,
+                              c->dump, st, vs, fp32_of(c), c->stream, c->ras);
 }
 
 int residual_eval(acch_ctx *c, const double *X, const double *Sdir, double lam, const GmresState *shift,
@@ -671,7 +671,7 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->Z = (double *)(c->ws + L.off_Z);
   c->fac = c->ws + L.off_fac;
   c->wfac = c->geo.G.wmax > 0 ? (void *)(c->ws + L.off_wfac) : nullptr;
-  c->wfact = c->geo.G.wmax > 0 ? (void *)(c->ws + L.off_wfact) : nullptr;
+  c->wfact = (p.dim == 2 || c->geo.G.wmax > 0) ? (void *)(c->ws + L.off_wfact) : nullptr;
   c->q3 = (double *)(c->ws + L.off_q3);
   c->ybuf = c->ws + L.off_y;
   c->dump = (double *)(c->ws + L.off_dump);

@@ -138,7 +138,7 @@ def test_final_energy_gradient_matches_oracle_adjoint():
     assert len(set(dts)) > 1   # the controller did change dt
     P = Problem(bc="periodic")
     Eo, gu, gv, gp = oadj.gradient(u0, v0, dts, P, NewtonOptions(rtol=1e-12, atol=1e-11))
-    assert abs(float(E) - Eo) <= 1e-10 * abs(Eo)
+    assert abs(float(E.detach()) - Eo) <= 1e-10 * abs(Eo)
     assert rel(tu.grad.numpy(), gu) <= 1e-7
     assert rel(tv.grad.numpy(), gv) <= 1e-7
     for k, name in enumerate(PARAMS):
