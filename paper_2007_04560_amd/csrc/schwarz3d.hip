@@ -218,35 +218,53 @@ ACCH_DEV void pivots_v(std::integer_sequence<int, Ps...>, double (&b)[kVN], cons
 
 // A_k = R_k J R_k^T plus the shift on its diagonal, written as each box cell's record
 // in the factor storage (pattern order; entries coupling to cells outside the box or
-// the domain are zero, padding cells are decoupled identity rows).  One thread per box
-// cell in storage order, so the J reads of a wave are contiguous.
+// the domain are zero, padding cells are decoupled identity rows).  A block takes 128
+// consecutive box cells: one thread per cell reads its Jacobian row (a wave's reads
+// of one slot are contiguous), the records go through LDS and leave as one contiguous
+// run.
+constexpr int kExtractCells = 128;
+
 template <typename FT>
-__global__ __launch_bounds__(256) void k_extract3d(Phys P, BoxGeom G, const SubInfo *__restrict__ subs,
-                                                   const double *__restrict__ J, double shift, FT *__restrict__ fac) {
-  const Box3 B{G.bw, G.bh, G.bd};
+__global__ __launch_bounds__(kExtractCells) void k_extract3d(Phys P, BoxGeom G, const SubInfo *__restrict__ subs,
+                                                             const double *__restrict__ J, double shift,
+                                                             FT *__restrict__ fac) {
+  __shared__ FT tile[kExtractCells * kNSlot3D];
   const long n = (long)P.nx * P.ny * P.nz;
   const long total = (long)G.nsub * G.ncb;
-  for (long x = blockIdx.x * 256L + threadIdx.x; x < total; x += (long)gridDim.x * 256) {
+  const long x0 = (long)blockIdx.x * kExtractCells;
+  const long x = x0 + threadIdx.x;
+  FT *rec = tile + threadIdx.x * kNSlot3D;
+  if (x < total) {
+    const Box3 B{G.bw, G.bh, G.bd};
     const int sub = (int)(x / G.ncb), e = (int)(x - (long)sub * G.ncb);
     const SubInfo si = subs[sub];
     int i, j, k;
     decode(e, B, i, j, k);
     const long g = box3_to_global(si, i, j, k, P);
-    FT *rec = fac + x * kNSlot3D;
+    // the neighbour at offset d along an axis is a real cell of the box and of the domain
+    auto axis_ok = [&](int c, int d, int ext, int org, int nn) {
+      const int cc = c + d;
+      return cc >= 0 && cc < ext && (P.periodic || (org + cc >= 0 && org + cc < nn));
+    };
+    bool okx[5], oky[5], okz[5];
+#pragma unroll
+    for (int d = -2; d <= 2; ++d) {
+      okx[d + 2] = axis_ok(i, d, si.ex, si.ox, P.nx);
+      oky[d + 2] = axis_ok(j, d, si.ey, si.oy, P.ny);
+      okz[d + 2] = axis_ok(k, d, si.ez, si.oz, P.nz);
+    }
     if (g >= 0) {
 #pragma unroll
       for (int c = 0; c < kUN; ++c) {
         const Col3 cc = ucol3(c);
-        const int ii = i + cc.dx, jj = j + cc.dy, kk = k + cc.dz;
-        const bool in = B.in(ii, jj, kk) && box3_to_global(si, ii, jj, kk, P) >= 0;
+        const bool in = okx[cc.dx + 2] && oky[cc.dy + 2] && okz[cc.dz + 2];
         const double a = in ? J[(long)jslot3(0, cc) * n + g] : 0.0;
         rec[kFA + c] = (FT)(c == kUD ? a * (1.0 + shift) : a);
       }
 #pragma unroll
       for (int c = 0; c < kVN; ++c) {
         const Col3 cc = vcol3(c);
-        const int ii = i + cc.dx, jj = j + cc.dy, kk = k + cc.dz;
-        const bool in = B.in(ii, jj, kk) && box3_to_global(si, ii, jj, kk, P) >= 0;
+        const bool in = okx[cc.dx + 2] && oky[cc.dy + 2] && okz[cc.dz + 2];
         const double b = in ? J[(long)jslot3(1, cc) * n + g] : 0.0;
         rec[kFB + c] = (FT)(c == kVD ? b * (1.0 + shift) : b);
       }
@@ -257,6 +275,10 @@ __global__ __launch_bounds__(256) void k_extract3d(Phys P, BoxGeom G, const SubI
       for (int c = 0; c < kVN; ++c) rec[kFB + c] = (FT)(c == kVD ? 1.0 : 0.0);
     }
   }
+  __syncthreads();
+  const long cells = total - x0 < kExtractCells ? total - x0 : kExtractCells;
+  FT *dst = fac + x0 * kNSlot3D;
+  for (long q = threadIdx.x; q < cells * kNSlot3D; q += kExtractCells) dst[q] = tile[q];
 }
 
 // ILU(0) of the extracted records in place, level by level.
@@ -1101,13 +1123,13 @@ __global__ void k_export_factors3d(BoxGeom G, const FT *__restrict__ fac, double
 hipError_t launch_ilu_factor3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
                                const double *J, double shift, void *fac, void *wfac, int fp32, hipStream_t s) {
   const long total = (long)G.nsub * G.ncb;
-  int nb = (int)((total + 255) / 256);
-  if (nb > 8192) nb = 8192;
+  const int nb = (int)((total + kExtractCells - 1) / kExtractCells);
   if (fp32) {
-    hipLaunchKernelGGL(k_extract3d<float>, dim3(nb), dim3(256), 0, s, P, G, subs, J, shift, (float *)fac);
+    hipLaunchKernelGGL(k_extract3d<float>, dim3(nb), dim3(kExtractCells), 0, s, P, G, subs, J, shift, (float *)fac);
     hipLaunchKernelGGL(k_ilu_factor3d<float>, dim3(G.nsub), dim3(256), 0, s, G, lvl, cells, (float *)fac);
   } else {
-    hipLaunchKernelGGL(k_extract3d<double>, dim3(nb), dim3(256), 0, s, P, G, subs, J, shift, (double *)fac);
+    hipLaunchKernelGGL(k_extract3d<double>, dim3(nb), dim3(kExtractCells), 0, s, P, G, subs, J, shift,
+                       (double *)fac);
     hipLaunchKernelGGL(k_ilu_factor3d<double>, dim3(G.nsub), dim3(256), 0, s, G, lvl, cells, (double *)fac);
   }
   hipError_t e = hipGetLastError();
