@@ -37,12 +37,13 @@ int get_ras_prefetch();
 void set_ras3d_window(bool on);
 // 3D windowed Schwarz apply: threads per box and box columns (j, k) per thread.  The
 // host lists each thread's columns after the level-ordered cells, in order and then
-// in reverse ([2][kWin3DCols][kWin3DThreads], -1 unused; wmax = 0: no list).
+// in reverse ([2][kWin3DCols][kWin3DThreads], -1 unused; wmax = 0: no list), then
+// the thread owning each column (bh * bd ints, index j + bh k).
 constexpr int kWin3DThreads = 512;
 constexpr int kWin3DCols = 8;
 constexpr int kWin3DSlots = 40;   // factor values per cell (3D)
 // Threads of the windowed apply = row width of its level-major arrays (0: no window).
-inline int win3d_row(const BoxGeom &G) { return G.wmax > 0 ? (G.wmax + 63) / 64 * 64 : 0; }
+__host__ __device__ inline int win3d_row(const BoxGeom &G) { return G.wmax > 0 ? (G.wmax + 63) / 64 * 64 : 0; }
 // Level-major factor copy of the windowed apply: [sub][level][slot][row] (elements).
 inline size_t win3d_fac_elems(const BoxGeom &G) {
   return (size_t)G.nsub * G.nlev * kWin3DSlots * win3d_row(G);

@@ -281,12 +281,16 @@ __global__ __launch_bounds__(kExtractCells) void k_extract3d(Phys P, BoxGeom G, 
   for (long q = threadIdx.x; q < cells * kNSlot3D; q += kExtractCells) dst[q] = tile[q];
 }
 
-// ILU(0) of the extracted records in place, level by level.
+// ILU(0) of the extracted records in place, level by level; with wfac, each record
+// also goes to the level-major pair copy of the windowed apply ([sub][w][pair][W][2],
+// at the thread owning the cell's column).
 template <typename FT>
 __global__ __launch_bounds__(256) void k_ilu_factor3d(BoxGeom G, const int *__restrict__ lvl,
-                                                      const int *__restrict__ cells, FT *__restrict__ fac) {
+                                                      const int *__restrict__ cells, const int *__restrict__ owner,
+                                                      FT *__restrict__ fac, FT *__restrict__ wfac) {
   const Box3 B{G.bw, G.bh, G.bd};
   FT *fk = fac + (long)blockIdx.x * G.ncb * kNSlot3D;
+  const int W = win3d_row(G);
   for (int w = 0; w < G.nlev; ++w) {
     for (int q = lvl[w] + threadIdx.x; q < lvl[w + 1]; q += blockDim.x) {
       int i, j, k;
@@ -315,6 +319,13 @@ __global__ __launch_bounds__(256) void k_ilu_factor3d(BoxGeom G, const int *__re
       for (int c = 0; c < kUN; ++c) rec[kFA + c] = (FT)a[c];
 #pragma unroll
       for (int c = 0; c < kVN; ++c) rec[kFB + c] = (FT)b[c];
+      if (wfac) {
+        FT *dst = wfac + (((long)blockIdx.x * G.nlev + w) * kNSlot3D) * W + 2 * owner[j + G.bh * k];
+#pragma unroll
+        for (int c = 0; c < kUN; ++c) dst[(long)((kFA + c) / 2) * 2 * W + ((kFA + c) & 1)] = (FT)a[c];
+#pragma unroll
+        for (int c = 0; c < kVN; ++c) dst[(long)((kFB + c) / 2) * 2 * W + ((kFB + c) & 1)] = (FT)b[c];
+      }
     }
     __syncthreads();
   }
@@ -536,7 +547,6 @@ __global__ __launch_bounds__(kWin3DThreads) void k_ras_apply3d_win(
     sc = st->inv_norm[jj];
   }
   const SubInfo si = subs[blockIdx.x];
-  const Box3 B{G.bw, G.bh, G.bd};
   const long n = (long)P.nx * P.ny * P.nz;
   const int W = blockDim.x;   // row width of the level-major arrays
   const unsigned tid = threadIdx.x;
@@ -1085,26 +1095,6 @@ __global__ __launch_bounds__(256) void k_ras_t_gather3d(Phys P, BoxGeom G, const
   }
 }
 
-// Level-major copy of the factors for the windowed apply: block (w, sub), thread t
-// copies the record of its cell on level w (if any) to [sub][w][slot pair][t][2].
-template <typename FT>
-__global__ __launch_bounds__(kWin3DThreads) void k_pack_window3d(BoxGeom G, const int *__restrict__ wcols,
-                                                                 const FT *__restrict__ fac, FT *__restrict__ wfac) {
-  const int w = blockIdx.x, sub = blockIdx.y, W = blockDim.x, t = threadIdx.x;
-  int e = -1;
-#pragma unroll
-  for (int m = 0; m < kWin3DCols; ++m) {
-    const int c = wcols[m * kWin3DThreads + t];
-    const int j = c & 1023, k = c >> 10, i = w - 2 * j - 3 * k;
-    if (c >= 0 && i >= 0 && i < G.bw) e = i + G.bw * (j + G.bh * k);
-  }
-  if (e < 0) return;
-  const FT *rec = fac + ((long)sub * G.ncb + e) * kNSlot3D;
-  FT *dst = wfac + (((long)sub * G.nlev + w) * kNSlot3D) * W + 2 * t;
-#pragma unroll
-  for (int q = 0; q < kNSlot3D; ++q) dst[(long)(q / 2) * 2 * W + (q & 1)] = rec[q];
-}
-
 // Factors of box cells -> FP64 [sub][slot][cell] (the 40-slot record of each cell).
 template <typename FT>
 __global__ void k_export_factors3d(BoxGeom G, const FT *__restrict__ fac, double *__restrict__ out) {
@@ -1124,23 +1114,18 @@ hipError_t launch_ilu_factor3d(const Phys &P, const BoxGeom &G, const SubInfo *s
                                const double *J, double shift, void *fac, void *wfac, int fp32, hipStream_t s) {
   const long total = (long)G.nsub * G.ncb;
   const int nb = (int)((total + kExtractCells - 1) / kExtractCells);
+  const bool win = wfac && G.wmax > 0;
+  const int *owner = win ? cells + G.ncb + 2 * kWin3DCols * kWin3DThreads : nullptr;
   if (fp32) {
     hipLaunchKernelGGL(k_extract3d<float>, dim3(nb), dim3(kExtractCells), 0, s, P, G, subs, J, shift, (float *)fac);
-    hipLaunchKernelGGL(k_ilu_factor3d<float>, dim3(G.nsub), dim3(256), 0, s, G, lvl, cells, (float *)fac);
+    hipLaunchKernelGGL(k_ilu_factor3d<float>, dim3(G.nsub), dim3(256), 0, s, G, lvl, cells, owner, (float *)fac,
+                       win ? (float *)wfac : nullptr);
   } else {
     hipLaunchKernelGGL(k_extract3d<double>, dim3(nb), dim3(kExtractCells), 0, s, P, G, subs, J, shift,
                        (double *)fac);
-    hipLaunchKernelGGL(k_ilu_factor3d<double>, dim3(G.nsub), dim3(256), 0, s, G, lvl, cells, (double *)fac);
+    hipLaunchKernelGGL(k_ilu_factor3d<double>, dim3(G.nsub), dim3(256), 0, s, G, lvl, cells, owner, (double *)fac,
+                       win ? (double *)wfac : nullptr);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !wfac || G.wmax <= 0) return e;
-  const dim3 grid(G.nlev, G.nsub);
-  if (fp32)
-    hipLaunchKernelGGL(k_pack_window3d<float>, grid, dim3(win3d_row(G)), 0, s, G, cells + G.ncb,
-                       (const float *)fac, (float *)wfac);
-  else
-    hipLaunchKernelGGL(k_pack_window3d<double>, grid, dim3(win3d_row(G)), 0, s, G, cells + G.ncb,
-                       (const double *)fac, (double *)wfac);
   return hipGetLastError();
 }
 

@@ -234,6 +234,11 @@ static int build_geometry3(const acch_params &p, Geometry &geo) {
           geo.cells[base + m * kWin3DThreads + t] = per[t][m];
           geo.cells[base + (kWin3DCols + m) * kWin3DThreads + t] = per[t][per[t].size() - 1 - m];
         }
+      // then the thread owning each column (j, k), at j + bh k
+      std::vector<int> owner((size_t)G.bh * G.bd, -1);
+      for (size_t t = 0; t < per.size(); ++t)
+        for (int c : per[t]) owner[(size_t)(c & 1023) + (size_t)G.bh * (c >> 10)] = (int)t;
+      geo.cells.insert(geo.cells.end(), owner.begin(), owner.end());
     } else {
       G.wmax = 0;
     }
