@@ -53,6 +53,16 @@ WORKLOADS = {
                           seed=0, steps=20,
                           text="neumann128_3d: 3D Neumann 128^3, 20 adaptive steps dt in [1e-4,2] (eta0 = 100), FP64 "
                                "NKS, left-RAS 8x8x8 overlap 1, ILU(0) shift 0.02, GMRES(30), tol 1e-8"),
+    # the paper's long adaptive 2D run (Section 4.2: alpha 4, beta 2, gamma 5e-3, theta 0.1,
+    # rho 1e-3, u0 = 0.55 + 0.05 U(-1,1), dt in [1e-4, 10], eta = 1e4), its first steps
+    "long128": dict(name="long128", shape=(128, 128), bc="periodic", sub=(4, 4), overlap=2,
+                    adaptive=True, dt_min=1e-4, dt_max=10.0, eta0=1e4, newton_rtol=1e-8, newton_atol=1e-13,
+                    gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30, ilu_shift=0.02, precision="fp64",
+                    seed=0, steps=2000, u_mean=0.55,
+                    phys=dict(alpha=4.0, beta=2.0, gamma=0.005, theta=0.1, rho=0.001),
+                    text="long128: the paper's long adaptive 2D run, 128x128 periodic, alpha 4, beta 2, gamma 5e-3, "
+                         "theta 0.1, rho 1e-3, u0 = 0.55 + 0.05 U(-1,1), dt in [1e-4,10] (eta0 = 1e4), first 2000 "
+                         "steps, FP64 NKS, left-RAS 4x4 overlap 2, ILU(0) shift 0.02, GMRES(30), tol 1e-8"),
 }
 # 96 independent periodic instances of uneven size (N in {96,128,192,256}), theta and
 # gamma drawn per instance, 10 steps at dt = 1e-3, all instances in one batched solve
@@ -120,11 +130,11 @@ def run_gpu(steps: int, warmup: int, timing: bool, w=None):
     from paper_2007_04560_amd import Solver
 
     w = w or WORKLOAD
-    u0, v0 = random_ic(w["shape"], w["seed"])
+    u0, v0 = random_ic(w["shape"], w["seed"], u_mean=w.get("u_mean", 0.5))
     kw = dict(bc=w["bc"], sub=w["sub"], overlap=w["overlap"], adaptive=w["adaptive"], dt_min=w["dt_min"],
               dt_max=w["dt_max"], eta0=w["eta0"], newton_rtol=w["newton_rtol"], newton_atol=w["newton_atol"],
               gmres_rtol=w["gmres_rtol"], gmres_atol=w["gmres_atol"], gmres_restart=w["gmres_restart"],
-              ilu_shift=w["ilu_shift"], precision=w["precision"])
+              ilu_shift=w["ilu_shift"], precision=w["precision"], **w.get("phys", {}))
     if warmup > 0:
         with Solver(u0, v0, **kw) as s:
             s.step(warmup)
@@ -467,10 +477,18 @@ def main():
                    "dt_last": recs[-1]["dt"] if recs else 0.0,
                    "energy_first_last": [r["E0"], r["E1"]],
                    "mass_drift_rel": abs(r["M1"] - r["M0"]) / r["M0"],
+                   "dt_range": [min(x["dt"] for x in recs), max(x["dt"] for x in recs)] if recs else None,
+                   "energy_max_rel_increase": max([0.0] + [(b["energy"] - a["energy"]) / abs(a["energy"])
+                                                          for a, b in zip(recs, recs[1:])]),
                    "launches": r["launches"], "host_syncs": r["syncs"],
                    "kernel_ms": {k: round(v[0], 3) for k, v in stats.items() if v[1]}},
         "roofline": roofline,
     }
+    if w["adaptive"] and recs:
+        # the same interval at the smallest step would take t_final / dt_min steps
+        fixed = recs[-1]["t"] / w["dt_min"]
+        line["config"]["fixed_dt_min_steps"] = round(fixed)
+        line["config"]["adaptive_step_saving"] = round(1.0 - len(recs) / fixed, 4)
     if not args.no_cpu_baseline and args.workload == "periodic512":
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
