@@ -37,7 +37,7 @@ enum {
   ACCH_EDOMAIN = 2,    /* a state outside the admissible set u+-v in (0,1)         */
   ACCH_EDIVERGED = 3,  /* Newton–Krylov–Schwarz failed at dt_min (or the fixed dt) */
   ACCH_EDEVICE = 4,    /* a HIP runtime error                                      */
-  ACCH_EUNSUPPORTED = 5/* a configuration this build does not implement            */
+  ACCH_EUNSUPPORTED = 5/* a configuration the library does not implement            */
 };
 
 enum { ACCH_BC_PERIODIC = 0, ACCH_BC_NEUMANN = 1 };
