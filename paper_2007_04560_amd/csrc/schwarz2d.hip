@@ -15,6 +15,7 @@
 
 #include "../../include/acch.h"
 #include "boxes.h"
+#include "bufio.h"
 #include "kernels.h"
 
 namespace acch {
@@ -319,7 +320,8 @@ ACCH_DEV FT slot(const T (&c)[N]) {
 template <int DIR>
 ACCH_DEV int rot_i(int x) {
   // wave_ror:1 / wave_rol:1; every lane has a source, so the old value is never used
-  return __builtin_amdgcn_update_dpp(x, x, DIR < 0 ? 0x13C : 0x134, 0xF, 0xF, false);
+  // (bound_ctrl set: the result register needs no copy of it)
+  return __builtin_amdgcn_update_dpp(0, x, DIR < 0 ? 0x13C : 0x134, 0xF, 0xF, true);
 }
 template <int DIR>
 ACCH_DEV double rot(double x) {
@@ -362,15 +364,13 @@ ACCH_DEV void neighbour_fetch(int w, int lane, int wave, FT o1u, FT o1v, FT a3u,
   }
 }
 
-// Per-thread data of one wavefront, loaded D wavefronts ahead of its use.  The loop
-// bodies are branch-free (inactive lanes load from a valid cell and store to a dump
-// slot), so the compiler can count the loads in flight exactly.
+// Per-thread data of one wavefront, loaded D wavefronts ahead of its use (branch-free
+// buffer accesses, see bufio.h).
 template <typename FT, int NCH>
 struct Stage {
   typename ChunkOf<FT>::T c[NCH];
   typename ChunkOf<FT>::Pair y;   // L sweep: R r of the cell; U sweep: y of the cell
-  unsigned idx;                    // wavefront-ordered cell index (dump slot ncb if the lane has no cell)
-  bool act;                        // the lane has a cell on this wavefront
+  unsigned fo, yo;                 // byte offsets of the cell's record and value (kPastEnd: no cell)
 };
 
 // Threads of a Schwarz block: the sweeps run on NW waves; with one sweep wave the
@@ -475,35 +475,43 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
   __syncthreads();
 
   if (t < TT) {
-    const int nround = (nlev + D - 1) / D * D;
-    // Closed-form cell of this thread on wavefront w (no branches): row j = t + TT q
-    // with q = floor((w - 2t) / (2 TT)), column i = w - 2j.
-    auto cell_of = [&](int w, unsigned &idx, bool &act) {
-      const int wc = w < 0 ? 0 : (w < nlev ? w : nlev - 1);
-      const int d = wc - 2 * t;
-      const int q = d < 0 ? 0 : (d >> (7 + (NW == 2 ? 1 : (NW == 4 ? 2 : 0))));
-      const int j = t + TT * q;
-      const int i = wc - 2 * j;
-      act = (w >= 0) && (w < nlev) && (d >= 0) && (i < G.bw) && (j < G.bh);
-      idx = act ? (unsigned)wc * G.bh + j : ncb;
-    };
-    // The chunks of a cell are contiguous: one address per cell, immediate offsets.
+    const int nround = (nlev + 2 * D) / (D + 1) * (D + 1);   // >= nlev + D wavefronts
+    constexpr unsigned REC = NCH * sizeof(T);   // bytes of a cell's record
+    constexpr unsigned YB = sizeof(P2);
+    const __amdgpu_buffer_rsrc_t rsF = buffer_rsrc(Fk, ncb * REC);
+    const __amdgpu_buffer_rsrc_t rsY = buffer_rsrc(yk, ncb * YB);
+    // Lane t holds box row t up to wavefront 2t + 2TT - 1 and row t + TT from there on
+    // (bw < 2TT: row t has left the wavefronts by then).  A row the box lacks is parked
+    // beyond every wavefront.  A lane without a cell loads zeros (zero factors and
+    // right-hand side give a zero result) and its store is dropped.
+    constexpr int kFar = 1 << 30;
+    const int j2A = t < G.bh ? 2 * t : kFar, j2B = t + TT < G.bh ? 2 * (t + TT) : kFar;
+    const unsigned frA = t * REC, frB = (t + TT) * REC, yrA = t * YB, yrB = (t + TT) * YB;
+    const int swB = 2 * t + 2 * TT;
     auto prefetch = [&](auto &s, int w, int c0) {
-      cell_of(w, s.idx, s.act);
-      const T *fc = Fk + (size_t)(s.act ? s.idx : 0u) * NCH + c0;
+      const bool b = w >= swB;
+      const bool act = (unsigned)(w - (b ? j2B : j2A)) < (unsigned)G.bw;
+      const unsigned wb = (unsigned)w * (unsigned)G.bh;
+      s.fo = act ? wb * REC + (b ? frB : frA) : kPastEnd;
+      s.yo = act ? wb * YB + (b ? yrB : yrA) : kPastEnd;
 #pragma unroll
-      for (int q = 0; q < (int)(sizeof(s.c) / sizeof(s.c[0])); ++q) s.c[q] = fc[q];
-      s.y = yk[s.idx];
+      for (int q = 0; q < (int)(sizeof(s.c) / sizeof(s.c[0])); ++q)
+        s.c[q] = load16(rsF, s.fo + (unsigned)((c0 + q) * sizeof(T)), 0, (const T *)nullptr);
+      s.y = load_pair(rsY, s.yo, (const P2 *)nullptr);
     };
     // ---- forward sweep: L y = R_k r (in place in yk) -------------------------
-    Stage<FT, NLC> ring[D];
+    // D + 1 operand sets rotate by name through a loop unrolled D + 1 times: each
+    // wavefront uses one set and loads wavefront w + D into the set used before it.
+    // The sweep starts D empty wavefronts early (zero operands, nothing to load), so
+    // every load is issued inside the loop and the waits there count exactly.
+    Stage<FT, NLC> ring[D + 1] = {};
 #pragma unroll
-    for (int k = 0; k < D; ++k) prefetch(ring[k], k, 0);
+    for (int k = 0; k <= D; ++k) ring[k].fo = ring[k].yo = kPastEnd;
     FT o1u = zero, o1v = zero, o2u = zero, o2v = zero;
     FT a1u = zero, a1v = zero, a2u = zero, a2v = zero, a3u = zero, a3v = zero;
-    for (int w0 = 0; w0 < nround; w0 += D) {
+    for (int w0 = -D; w0 < nround - D; w0 += D + 1) {
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
+      for (int k = 0; k <= D; ++k) {
         const int w = w0 + k;
         FT Au, Av, Mu, Mv;
         neighbour_fetch<-1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
@@ -539,26 +547,27 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
           accv = fma(slot<7, 0, FT>(s.c), yu, accv);
           yv = (s.y.y - accv) * slot<12, 0, FT>(s.c);
         }
-        yu = s.act ? yu : zero;
-        yv = s.act ? yv : zero;
         P2 y2;
         y2.x = yu;
         y2.y = yv;
-        yk[s.idx] = y2;
+        store_pair(rsY, s.yo, y2);
         a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
         o2u = o1u; o2v = o1v; o1u = yu; o1v = yv;
-        prefetch(s, w + D, 0);
+        prefetch(ring[(k + D) % (D + 1)], w + D, 0);
+        // nothing moves across wavefronts: hoisting later wavefronts' arithmetic above
+        // this point would make it wait for loads just issued
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     // ---- backward sweep: U x = y (in place in yk) ----------------------------
-    Stage<FT, NUC> ringu[D];
+    Stage<FT, NUC> ringu[D + 1] = {};
 #pragma unroll
-    for (int k = 0; k < D; ++k) prefetch(ringu[k], nlev - 1 - k, U0C);
+    for (int k = 0; k <= D; ++k) ringu[k].fo = ringu[k].yo = kPastEnd;
     o1u = o1v = o2u = o2v = zero;
     a1u = a1v = a2u = a2v = a3u = a3v = zero;
-    for (int w0 = nlev - 1; w0 > nlev - 1 - nround; w0 -= D) {
+    for (int w0 = nlev - 1 + D; w0 > nlev - 1 + D - nround; w0 -= D + 1) {
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
+      for (int k = 0; k <= D; ++k) {
         const int w = w0 - k;
         FT Au, Av, Mu, Mv;
         neighbour_fetch<1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
@@ -593,15 +602,14 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
           acc = fma(slot<19, U0C, FT>(s.c), xv, acc);
           xu = s.y.x - acc;
         }
-        xu = s.act ? xu : zero;
-        xv = s.act ? xv : zero;
         P2 x2;
         x2.x = xu;
         x2.y = xv;
-        yk[s.idx] = x2;
+        store_pair(rsY, s.yo, x2);
         a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
         o2u = o1u; o2v = o1v; o1u = xu; o1v = xv;
-        prefetch(s, w - D, U0C);
+        prefetch(ringu[(k + D) % (D + 1)], w - D, U0C);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   }

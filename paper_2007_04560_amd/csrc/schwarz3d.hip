@@ -18,6 +18,7 @@
 #include <utility>
 
 #include "../../include/acch.h"
+#include "bufio.h"
 #include "kernels.h"
 #include "stencil3d.h"
 
@@ -504,15 +505,6 @@ struct ColCursor {
   }
 };
 
-// Buffer resource over `bytes` bytes (raw, stride 0): a load at an offset past the end
-// returns zero and a store there is dropped, without a memory access.
-ACCH_DEV __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
-}
-constexpr unsigned kPastEnd = 0x80000000u;   // offset of an idle lane's access
-typedef double double_pair __attribute__((ext_vector_type(2)));
-typedef unsigned word4 __attribute__((ext_vector_type(4)));
-
 // one pair of factor entries
 ACCH_DEV void pair_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const double *, double &a,
                         double &b) {
@@ -522,9 +514,6 @@ ACCH_DEV void pair_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff,
 }
 ACCH_DEV void pair_load(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const float *, double &a,
                         double &b) {
-  // (bit-cast the whole vector: indexing the loaded vector's elements directly compiled
-  // to a single 32-bit load here)
-  typedef float float_pair __attribute__((ext_vector_type(2)));
   const float_pair f = __builtin_bit_cast(float_pair, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
   a = (double)f.x;
   b = (double)f.y;
