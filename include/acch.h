@@ -207,7 +207,7 @@ int acch_timing(acch_ctx *c, int enable);
 int acch_kernel_stats(acch_ctx *c, int kind, double *total_ms, long *count);
 
 /* Tuning options (process-wide): ACCH_OPT_RAS_PREFETCH = wavefronts of factors the
- * 2D triangular-solve kernel loads ahead of their use (2, 4, 8 or 16; default 4);
+ * 2D triangular-solve kernel loads ahead of their use (3, 4, 5 or 6; default 5);
  * ACCH_OPT_RAS3D_WINDOW = 1 (default) lets the 3D preconditioner keep the recent
  * levels of a box in LDS when the box allows it, 0 forces the variant that keeps
  * the whole box in device memory (same arithmetic).  c may be NULL. */

@@ -445,7 +445,7 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
 
   // ---- gather: yk[slot of (i,j)] = R_k r (scaled), zero on padding / outside cells;
   // GU cells per thread and round, all loads first
-  constexpr int GU = 4;
+  constexpr int GU = 10;   // one round for boxes up to 5120 cells with 512 threads
   for (int e0 = t; e0 < nbox; e0 += TB * GU) {
     double ru[GU], rv[GU];
     long gq[GU];
@@ -701,7 +701,7 @@ hipError_t factor_impl(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *s
 }
 
 // Wavefronts loaded ahead of their use in the solves (selectable for tuning).
-int g_ras_prefetch = 4;
+int g_ras_prefetch = 5;
 
 template <typename FT, int NW, int D, bool TRP>
 hipError_t apply_d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl, const void *fac,
@@ -717,16 +717,16 @@ hipError_t apply_impl(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *su
                       void *ybuf, const double *r, double *z, double *dump, const GmresState *st, long vstride,
                       int kind, hipStream_t s) {
   switch (g_ras_prefetch) {
-    case 2: return apply_d<FT, NW, 2, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
-    case 8: return apply_d<FT, NW, 8, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
-    case 16: return apply_d<FT, NW, 16, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
-    default: return apply_d<FT, NW, 4, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    case 3: return apply_d<FT, NW, 3, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    case 4: return apply_d<FT, NW, 4, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    case 6: return apply_d<FT, NW, 6, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
+    default: return apply_d<FT, NW, 5, TRP>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
   }
 }
 
 }  // namespace
 
-void set_ras_prefetch(int d) { g_ras_prefetch = (d == 2 || d == 8 || d == 16) ? d : 4; }
+void set_ras_prefetch(int d) { g_ras_prefetch = (d == 3 || d == 4 || d == 6) ? d : 5; }
 int get_ras_prefetch() { return g_ras_prefetch; }
 
 int schwarz_waves(const BoxGeom &G) {
