@@ -67,7 +67,7 @@ int make_plan(const acch_params *ps, int count, Plan &pl) {
   pl.G.bh = bh;
   pl.G.nlev = bw + 2 * (bh - 1);
   pl.G.ncb = bw * bh;
-  if (schwarz_waves(pl.G) == 0) return fail(ACCH_EINVAL, "subdomain box wider than 511 cells");
+  if (schwarz_waves(pl.G) == 0) return fail(ACCH_EINVAL, "subdomain box too large (at most 511 cells wide, 512 tall)");
   long xoff = 0, joff = 0;
   int blk[kFamilies] = {};
   for (int b = 0; b < count; ++b) {

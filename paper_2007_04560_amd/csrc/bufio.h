@@ -30,21 +30,21 @@ ACCH_DEV float4 load16(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, 
   const float_quad f = __builtin_bit_cast(float_quad, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
   return float4{f.x, f.y, f.z, f.w};
 }
-// one (u, v) pair of values
-ACCH_DEV double2 load_pair(__amdgpu_buffer_rsrc_t rs, unsigned voff, const double2 *) {
-  return load16(rs, voff, 0, (const double2 *)nullptr);
+// one (u, v) pair of values at voff + soff
+ACCH_DEV double2 load_pair(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const double2 *) {
+  return load16(rs, voff, soff, (const double2 *)nullptr);
 }
-ACCH_DEV float2 load_pair(__amdgpu_buffer_rsrc_t rs, unsigned voff, const float2 *) {
-  const float_pair f = __builtin_bit_cast(float_pair, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, 0, 0));
+ACCH_DEV float2 load_pair(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const float2 *) {
+  const float_pair f = __builtin_bit_cast(float_pair, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
   return float2{f.x, f.y};
 }
-ACCH_DEV void store_pair(__amdgpu_buffer_rsrc_t rs, unsigned voff, double2 v) {
+ACCH_DEV void store_pair(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, double2 v) {
   const double_pair d{v.x, v.y};
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(word4, d), rs, voff, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(word4, d), rs, voff, soff, 0);
 }
-ACCH_DEV void store_pair(__amdgpu_buffer_rsrc_t rs, unsigned voff, float2 v) {
+ACCH_DEV void store_pair(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, float2 v) {
   const float_pair f{v.x, v.y};
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(word2, f), rs, voff, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(word2, f), rs, voff, soff, 0);
 }
 
 }  // namespace acch

@@ -370,8 +370,17 @@ template <typename FT, int NCH>
 struct Stage {
   typename ChunkOf<FT>::T c[NCH];
   typename ChunkOf<FT>::Pair y;   // L sweep: R r of the cell; U sweep: y of the cell
-  unsigned fo, yo;                 // byte offsets of the cell's record and value (kPastEnd: no cell)
+  unsigned vf, vy;                 // per-lane byte offsets of the cell's record and value (kPastEnd: no cell)
+  unsigned sf, sy;                 // the wavefront's byte offsets (uniform)
 };
+
+// Waits until at most N vector-memory operations of this wave are outstanding (vmcnt
+// in bits 3:0 and 15:14; expcnt and lgkmcnt at their maxima, i.e. not waited for).
+template <int N>
+ACCH_DEV void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
 
 // Threads of a Schwarz block: the sweeps run on NW waves; with one sweep wave the
 // block has seven more, which only share the gather / scatter passes (whose
@@ -476,46 +485,59 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
 
   if (t < TT) {
     const int nround = (nlev + 2 * D) / (D + 1) * (D + 1);   // >= nlev + D wavefronts
+    const int niter = nround / (D + 1);
     constexpr unsigned REC = NCH * sizeof(T);   // bytes of a cell's record
     constexpr unsigned YB = sizeof(P2);
     const __amdgpu_buffer_rsrc_t rsF = buffer_rsrc(Fk, ncb * REC);
     const __amdgpu_buffer_rsrc_t rsY = buffer_rsrc(yk, ncb * YB);
-    // Lane t holds box row t up to wavefront 2t + 2TT - 1 and row t + TT from there on
-    // (bw < 2TT: row t has left the wavefronts by then).  A row the box lacks is parked
+    const unsigned wavF = (unsigned)G.bh * REC, wavY = (unsigned)G.bh * YB;   // bytes per wavefront
+    // Lane t holds box row jA = t, and from a switch level on row jB = t + TT if the box
+    // has it (bw < 2TT: row t has left the wavefronts before row t + TT enters them).
+    // The switch is uniform: any level in [lo, 2TT) works, lo = 2(bh - TT - 1) + bw,
+    // and the sweeps change rows between two loop iterations chosen inside it (the
+    // host picks NW so that the window holds one).  A row the box lacks is parked
     // beyond every wavefront.  A lane without a cell loads zeros (zero factors and
     // right-hand side give a zero result) and its store is dropped.
     constexpr int kFar = 1 << 30;
-    const int j2A = t < G.bh ? 2 * t : kFar, j2B = t + TT < G.bh ? 2 * (t + TT) : kFar;
-    const unsigned frA = t * REC, frB = (t + TT) * REC, yrA = t * YB, yrB = (t + TT) * YB;
-    const int swB = 2 * t + 2 * TT;
-    auto prefetch = [&](auto &s, int w, int c0) {
-      const bool b = w >= swB;
-      const bool act = (unsigned)(w - (b ? j2B : j2A)) < (unsigned)G.bw;
-      const unsigned wb = (unsigned)w * (unsigned)G.bh;
-      s.fo = act ? wb * REC + (b ? frB : frA) : kPastEnd;
-      s.yo = act ? wb * YB + (b ? yrB : yrA) : kPastEnd;
+    const bool hasB = t + TT < G.bh;
+    const int j2A = t < G.bh ? 2 * t : kFar, j2B = hasB ? 2 * (t + TT) : j2A;
+    const unsigned fA = t * REC, fB = hasB ? (t + TT) * REC : fA;
+    const unsigned yA = t * YB, yB = hasB ? (t + TT) * YB : yA;
+    const int lo = 2 * (G.bh - TT - 1) + G.bw;
+    // Per-lane offsets select the cell (kPastEnd: none); the wavefront's offset is
+    // uniform and goes in the scalar offset.
+    auto prefetch = [&](auto &s, int w, int c0, int j2, unsigned fl, unsigned yl) {
+      const bool act = (unsigned)(w - j2) < (unsigned)G.bw;
+      s.vf = act ? fl : kPastEnd;
+      s.vy = act ? yl : kPastEnd;
+      s.sf = (unsigned)w * wavF;
+      s.sy = (unsigned)w * wavY;
 #pragma unroll
       for (int q = 0; q < (int)(sizeof(s.c) / sizeof(s.c[0])); ++q)
-        s.c[q] = load16(rsF, s.fo + (unsigned)((c0 + q) * sizeof(T)), 0, (const T *)nullptr);
-      s.y = load_pair(rsY, s.yo, (const P2 *)nullptr);
+        s.c[q] = load16(rsF, s.vf + (unsigned)((c0 + q) * sizeof(T)), s.sf, (const T *)nullptr);
+      s.y = load_pair(rsY, s.vy, s.sy, (const P2 *)nullptr);
     };
     // ---- forward sweep: L y = R_k r (in place in yk) -------------------------
     // D + 1 operand sets rotate by name through a loop unrolled D + 1 times: each
     // wavefront uses one set and loads wavefront w + D into the set used before it.
     // The sweep starts D empty wavefronts early (zero operands, nothing to load), so
-    // every load is issued inside the loop and the waits there count exactly.
+    // every load is issued inside the loop; each wavefront waits once, for its own set
+    // (the D - 1 later sets and their stores may still be in flight).
+    constexpr int kWaitL = (D - 1) * (NLC + 2), kWaitU = (D - 1) * (NUC + 2);
     Stage<FT, NLC> ring[D + 1] = {};
 #pragma unroll
-    for (int k = 0; k <= D; ++k) ring[k].fo = ring[k].yo = kPastEnd;
+    for (int k = 0; k <= D; ++k) ring[k].vf = ring[k].vy = kPastEnd;
     FT o1u = zero, o1v = zero, o2u = zero, o2v = zero;
     FT a1u = zero, a1v = zero, a2u = zero, a2v = zero, a3u = zero, a3v = zero;
-    for (int w0 = -D; w0 < nround - D; w0 += D + 1) {
+    auto fwd_iter = [&](int w0, int j2, unsigned fl, unsigned yl) {
 #pragma unroll
       for (int k = 0; k <= D; ++k) {
         const int w = w0 + k;
+        wait_vm<kWaitL>();
+        __builtin_amdgcn_sched_barrier(0);   // the arithmetic stays after the one wait
         FT Au, Av, Mu, Mv;
         neighbour_fetch<-1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
-        Stage<FT, NLC> &s = ring[k];
+        const Stage<FT, NLC> &s = ring[k];
         // values of earlier wavefronts first; o1 (own, w-1) and A (neighbour, w-1) last
         FT yu, yv;
         if constexpr (!TRP) {
@@ -550,28 +572,36 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
         P2 y2;
         y2.x = yu;
         y2.y = yv;
-        store_pair(rsY, s.yo, y2);
+        store_pair(rsY, s.vy, s.sy, y2);
         a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
         o2u = o1u; o2v = o1v; o1u = yu; o1v = yv;
-        prefetch(ring[(k + D) % (D + 1)], w + D, 0);
+        prefetch(ring[(k + D) % (D + 1)], w + D, 0, j2, fl, yl);
         // nothing moves across wavefronts: hoisting later wavefronts' arithmetic above
         // this point would make it wait for loads just issued
         __builtin_amdgcn_sched_barrier(0);
       }
-    }
+    };
+    // Row A while the loads stay below 2TT; the last row-A iteration loads up to level
+    // w0 + 2D, and row B takes over from the first loaded level >= lo.
+    const int mA = G.bh > TT ? min(niter, 1 + max(0, (lo - 1) / (D + 1))) : niter;
+    int m = 0;
+    for (; m < mA; ++m) fwd_iter(-D + m * (D + 1), j2A, fA, yA);
+    for (; m < niter; ++m) fwd_iter(-D + m * (D + 1), j2B, fB, yB);
     // ---- backward sweep: U x = y (in place in yk) ----------------------------
     Stage<FT, NUC> ringu[D + 1] = {};
 #pragma unroll
-    for (int k = 0; k <= D; ++k) ringu[k].fo = ringu[k].yo = kPastEnd;
+    for (int k = 0; k <= D; ++k) ringu[k].vf = ringu[k].vy = kPastEnd;
     o1u = o1v = o2u = o2v = zero;
     a1u = a1v = a2u = a2v = a3u = a3v = zero;
-    for (int w0 = nlev - 1 + D; w0 > nlev - 1 + D - nround; w0 -= D + 1) {
+    auto bwd_iter = [&](int w0, int j2, unsigned fl, unsigned yl) {
 #pragma unroll
       for (int k = 0; k <= D; ++k) {
         const int w = w0 - k;
+        wait_vm<kWaitU>();
+        __builtin_amdgcn_sched_barrier(0);   // the arithmetic stays after the one wait
         FT Au, Av, Mu, Mv;
         neighbour_fetch<1, FT, NW>(w, lane, wave, o1u, o1v, a3u, a3v, Au, Av, Mu, Mv, xch);
-        Stage<FT, NUC> &s = ringu[k];
+        const Stage<FT, NUC> &s = ringu[k];
         FT xu, xv;
         if constexpr (!TRP) {
           FT accv = slot<23, U0C, FT>(s.c) * a1v;
@@ -605,13 +635,18 @@ __global__ __launch_bounds__(ras_threads<NW>()) void k_ras_apply2d(Phys P0, Batc
         P2 x2;
         x2.x = xu;
         x2.y = xv;
-        store_pair(rsY, s.yo, x2);
+        store_pair(rsY, s.vy, s.sy, x2);
         a3u = a2u; a3v = a2v; a2u = a1u; a2v = a1v; a1u = Au; a1v = Av;
         o2u = o1u; o2v = o1v; o1u = xu; o1v = xv;
-        prefetch(ringu[(k + D) % (D + 1)], w - D, U0C);
+        prefetch(ringu[(k + D) % (D + 1)], w - D, U0C, j2, fl, yl);
         __builtin_amdgcn_sched_barrier(0);
       }
-    }
+    };
+    // Row B while the loads stay at or above lo; the last row-B iteration loads down to
+    // level w0 - 2D.
+    const int m1 = G.bh > TT ? min(niter, 1 + max(0, (nlev - 1 - D - lo) / (D + 1))) : 0;
+    for (m = 0; m < m1; ++m) bwd_iter(nlev - 1 + D - m * (D + 1), j2B, fB, yB);
+    for (; m < niter; ++m) bwd_iter(nlev - 1 + D - m * (D + 1), j2A, fA, yA);
   }
   __syncthreads();
   // ---- scatter: z = (R_k^0)^T x on the owned cells, GU cells per round (the
@@ -729,8 +764,22 @@ hipError_t apply_impl(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *su
 void set_ras_prefetch(int d) { g_ras_prefetch = (d == 3 || d == 4 || d == 6) ? d : 5; }
 int get_ras_prefetch() { return g_ras_prefetch; }
 
+// Sweep waves of the Schwarz apply: bw < 2TT (a wavefront meets a lane's rows at most
+// once), and a box taller than TT rows needs a window of at least 8 levels for the
+// uniform switch of lanes from row t to row t + TT (2TT - lo >= 8, lo = 2(bh - TT - 1)
+// + bw), so that an iteration boundary of the unrolled sweep falls inside it.
+static int apply_waves(const BoxGeom &G) {
+  for (int nw = 1; nw <= 4; nw *= 2) {
+    const int tt = 64 * nw;
+    if (G.bw >= 2 * tt || G.bh > 2 * tt) continue;
+    if (G.bh <= tt || 2 * tt - (2 * (G.bh - tt - 1) + G.bw) >= 8) return nw;
+  }
+  return 0;
+}
+
 int schwarz_waves(const BoxGeom &G) {
   // bw < 2T keeps one active cell per thread per wavefront (and clean histories)
+  if (apply_waves(G) == 0) return 0;
   if (G.bw <= 127) return 1;
   if (G.bw <= 255) return 2;
   if (G.bw <= 511) return 4;
@@ -755,7 +804,7 @@ hipError_t launch_ilu_factor2d(const BatchLaunch &bl, const BoxGeom &G, const Su
 hipError_t launch_ras_apply2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
                               const void *fac, void *ybuf, const double *r, double *z, double *dump,
                               const GmresState *st, long vstride, int fp32, hipStream_t s, const RasVariant &rv) {
-  const int nw = schwarz_waves(G);
+  const int nw = apply_waves(G);
   const int kind = rv.kind;
   if (kind != ACCH_RAS_LEFT && (bl.bt.map[kFamSub] != nullptr || !rv.own_x)) return hipErrorInvalidValue;
   hipError_t e = hipErrorInvalidValue;
@@ -787,7 +836,7 @@ hipError_t launch_ras_t_apply2d(const BatchLaunch &bl, const BoxGeom &G, const S
                                 const void *fac, void *fact, bool *packed, void *ybuf, const double *r, double *z,
                                 double *dump, const GmresState *st, long vstride, int fp32, hipStream_t s,
                                 const RasVariant &rv) {
-  const int nw = schwarz_waves(G);
+  const int nw = apply_waves(G);
   if (bl.bt.map[kFamSub] != nullptr || !rv.own_x) return hipErrorInvalidValue;
   if (!*packed) {
     if (fp32)

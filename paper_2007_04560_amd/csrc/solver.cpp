@@ -263,7 +263,7 @@ int acch::build_geometry(const acch_params &p, Geometry &geo) {
   geo.G.nlev = bw + 2 * (bh - 1);
   geo.G.ncb = bw * bh;
   geo.G.nsub = p.sub[0] * p.sub[1];
-  if (schwarz_waves(geo.G) == 0) return fail(ACCH_EINVAL, "subdomain box wider than 511 cells");
+  if (schwarz_waves(geo.G) == 0) return fail(ACCH_EINVAL, "subdomain box too large (at most 511 cells wide, 512 tall)");
   geo.subs.clear();
   for (int by = 0; by < p.sub[1]; ++by)
     for (int bx = 0; bx < p.sub[0]; ++bx) {

@@ -323,6 +323,34 @@ def test_wide_boxes_use_two_waves_and_match_oracle():
     assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
 
 
+@pytest.mark.parametrize("shape,bc,sub,ov,rows", [((140, 60), "neumann", (1, 2), 2, 64),
+                                                   ((150, 60), "periodic", (2, 2), 2, 64),
+                                                   ((270, 40), "neumann", (1, 2), 2, 128)])
+def test_tall_boxes_switch_lane_rows_and_match_oracle(shape, bc, sub, ov, rows):
+    """Boxes taller than the sweep's lanes (64 per wave): lane t takes row t and later
+    row t + 64 NW, switching between two loop iterations of each sweep; M^{-1} against
+    the oracle, M^{-T} through the adjoint identity."""
+    u1, v1, u0, v0 = perturbed_pair(shape, 57, amp=0.03)
+    P = prob(bc)
+    dt = 5e-5   # a step size whose ILU(0) factors stay well scaled on these long boxes
+    s = solver(u0, v0, bc, sub=sub, overlap=ov, ilu_shift=0.02)
+    info = s.info()
+    assert rows < info["box_h"] <= 2 * rows
+    s.jacobian(dev(vec(u1, v1)), dev(vec(u0, v0)), dt)
+    s.factor()
+    Jo = jacobian.jacobian(u1, v1, u0, v0, dt, P)
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal(2 * u1.size)
+    z = s.precondition(dev(r)).cpu().numpy()
+    zo = schwarz.Schwarz(Jo, shape, (sub[1], sub[0]), ov, bc, kind="left", shift=0.02).apply(r)
+    assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
+    a = dev(rng.standard_normal(2 * u1.size))
+    b = dev(rng.standard_normal(2 * u1.size))
+    lhs = float(torch.dot(s.precondition_transpose(a), b))
+    rhs = float(torch.dot(a, s.precondition(b)))
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
+
+
 @pytest.mark.parametrize("shape,bc,sub,ov", [((64, 64), "periodic", (2, 2), 1), ((45, 100), "neumann", (3, 2), 2)])
 def test_mixed_precision_preconditioner_close_to_fp64(shape, bc, sub, ov):
     """FP32 factors and solves: the preconditioner output is the FP64 one to FP32 accuracy."""
