@@ -90,7 +90,7 @@ def spmv_dots_bytes_per_cell(j_avg: float) -> float:
 
 # The dominant (Schwarz) kernel of each workload, as rocprofv3 names it, and its source.
 RAS_KERNELS = {
-    "periodic512": ("void k_ras_apply2d<double, 1, 4, false>", "schwarz2d.hip"),
+    "periodic512": ("void k_ras_apply2d<double, 1, 5, false>", "schwarz2d.hip"),
     "neumann128_3d": ("void k_ras_apply3d_win<double, 3>", "schwarz3d.hip"),
 }
 
