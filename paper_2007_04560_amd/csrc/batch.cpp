@@ -144,8 +144,11 @@ void make_layout(const acch_params &p0, const Plan &pl, BLayout &L) {
   L.off_subs = take(pl.subs.size() * sizeof(SubInfo));
   L.off_lvl = take(pl.lvl.size() * sizeof(int));
   L.off_state = take((size_t)pl.count * sizeof(GmresState));
-  const size_t nparts = std::max<size_t>((size_t)(kMaxRestart + 1) * pl.grid[kFamCell],
-                                         std::max<size_t>(2 * (size_t)pl.grid[kFamTile], 4 * (size_t)pl.grid[kFamElem]));
+  // dot rows of the Arnoldi SpMV, then the Gram–Schmidt kernel's norm rows after them
+  const size_t nparts = std::max<size_t>((size_t)kMaxRestart * pl.grid[kFamCell] + pl.grid[kFamElem],
+                                         std::max<size_t>((size_t)(kMaxRestart + 1) * pl.grid[kFamCell],
+                                                          std::max<size_t>(2 * (size_t)pl.grid[kFamTile],
+                                                                           4 * (size_t)pl.grid[kFamElem])));
   L.off_part = take(nparts * sizeof(double));
   L.off_out = take((size_t)4 * pl.count * sizeof(double));
   L.off_inst = take((size_t)pl.count * sizeof(Inst));

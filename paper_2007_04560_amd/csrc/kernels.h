@@ -21,7 +21,7 @@ void family_blocks(const Phys &P, int nsub, int (&nb)[kFamilies]);
 
 // Second stage of the two-kernel reductions (krylov.hip): one block per instance,
 // out[4 b + k] for kFinPlain.
-enum { kFinPlain = 0, kFinStart = 1, kFinDots = 2, kFinOrth = 3, kFinUpdate = 4 };
+enum { kFinPlain = 0, kFinStart = 1, kFinOrth = 3, kFinUpdate = 4 };
 struct FinalizeArgs {
   int m, project;
   double rtol, atol;
@@ -29,8 +29,6 @@ struct FinalizeArgs {
 };
 hipError_t launch_finalize(int mode, int nv, const RedBuf &red, const BatchLaunch &bl, int fam, GmresState *st,
                            const FinalizeArgs &fa, hipStream_t s);
-// second stage of the Arnoldi dots of step j (0 <= j < kMaxRestart)
-hipError_t launch_finalize_dots(int j, const RedBuf &red, const BatchLaunch &bl, GmresState *st, hipStream_t s);
 int schwarz_waves(const BoxGeom &G);
 void set_ras_prefetch(int d);
 int get_ras_prefetch();
@@ -66,7 +64,8 @@ hipError_t launch_jacobian2d(const BatchLaunch &bl, const double *X, const doubl
 // y = J x, or J^T x when transpose
 hipError_t launch_spmv2d(const BatchLaunch &bl, const double *J, const double *x, double *y, int transpose,
                          hipStream_t s);
-// Arnoldi step j of the cycle (the device state's j must equal it unless the cycle is done)
+// Arnoldi step j of the cycle (the device state's j must equal it unless the cycle is done);
+// the block partials of the dots are summed by the Gram–Schmidt kernel of the step
 hipError_t launch_spmv_dots2d(const BatchLaunch &bl, const double *J, const double *Z, double *V, long vstride, int j,
                               int transpose, GmresState *st, const RedBuf &red, hipStream_t s);
 

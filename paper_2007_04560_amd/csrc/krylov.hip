@@ -70,19 +70,44 @@ ACCH_DEV void start_tail(GmresState *st, double sum, int m, double rtol, double 
   st->done = st->converged;
 }
 
-// W_{j+1} -= sum_{i<=j} h_ij v_i (classical Gram–Schmidt, one pass), then the norm,
-// the Givens update of the Hessenberg column and the convergence test.  One
-// instantiation per step j, like k_spmv_dots2d.
+// W_{j+1} -= sum_{i<=j} h_ij v_i (classical Gram–Schmidt, one pass), then the block
+// partials of ||W_{j+1}||^2 (red: their own rows of the partial buffer).  The dots of
+// the SpMV kernel are summed here, by every block for itself in block order (so all
+// blocks hold the same h_ij, and the same values as a separate one-block sum would
+// give); the instance's first block records the Hessenberg column for the serial tail.
+// One instantiation per step j, like k_spmv_dots2d.
 template <int J>
 __global__ __launch_bounds__(256) void k_gmres_orth(Batch bt, long n2s, double *__restrict__ V, long vstride,
-                                                     GmresState *st, RedBuf red) {
+                                                     GmresState *st, RedBuf red, const double *__restrict__ dots,
+                                                     int dstride) {
   const ElemLoc E = elem_loc(bt, n2s);
   if (!E.L.on) return;
   GmresState *sb = st + E.L.b;
   if (sb->done) return;
   V += E.xo;
+  const int db0 = bt.map[kFamElem] ? bt.inst[E.L.b].blk0[kFamCell] : 0;
+  const int dnb = bt.map[kFamElem] ? bt.inst[E.L.b].nblk[kFamCell] : dstride;
+  constexpr int NV = pow2_at_least(J + 1);
   __shared__ double coef[J + 1];
-  if (threadIdx.x <= J) coef[threadIdx.x] = sb->hcol[threadIdx.x] * sb->inv_norm[threadIdx.x];
+  {
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < dnb; b += 256) {
+      double p[J + 1];
+#pragma unroll
+      for (int k = 0; k <= J; ++k) p[k] = dots[(long)k * dstride + db0 + b];
+#pragma unroll
+      for (int k = 0; k <= J; ++k) acc[k] += p[k];
+    }
+    double tot;
+    block_multi_sum<NV>(acc, threadIdx.x, 256, J + 1, &tot);
+    if ((int)threadIdx.x <= J) {
+      const double h = tot * sb->inv_norm[threadIdx.x];   // h_ij
+      coef[threadIdx.x] = h * sb->inv_norm[threadIdx.x];
+      if (E.L.lb == 0) sb->hcol[threadIdx.x] = h;
+    }
+  }
   __syncthreads();
   double c[J + 1];
 #pragma unroll
@@ -256,29 +281,6 @@ ACCH_DEV FinRange fin_range(const Inst *inst, const int *active, int fam, int nb
   return R;
 }
 
-// h_ij = inv_norm_i * (sum of the block partials of dot i), i <= J.
-template <int J>
-__global__ __launch_bounds__(256) void k_finalize_dots(const double *__restrict__ partials, int stride,
-                                                        const Inst *inst, const int *active, GmresState *st) {
-  const FinRange R = fin_range(inst, active, kFamCell, stride);
-  GmresState *sb = st + R.b;
-  if (!R.on || sb->done) return;
-  constexpr int NV = pow2_at_least(J + 1);
-  double acc[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-  for (int b = threadIdx.x; b < R.nb; b += 256) {
-    double p[J + 1];
-#pragma unroll
-    for (int k = 0; k <= J; ++k) p[k] = partials[(long)k * stride + R.b0 + b];
-#pragma unroll
-    for (int k = 0; k <= J; ++k) acc[k] += p[k];
-  }
-  double tot;
-  block_multi_sum<NV>(acc, threadIdx.x, 256, J + 1, &tot);
-  if ((int)threadIdx.x <= J) sb->hcol[threadIdx.x] = tot * sb->inv_norm[threadIdx.x];
-}
-
 template <int MODE>
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partials, int stride, int fam,
                                                    const Inst *inst, const int *active, int nv,
@@ -378,30 +380,14 @@ hipError_t launch_finalize(int mode, int nv, const RedBuf &red, const BatchLaunc
 }
 
 template <int J>
-static hipError_t finalize_dots_at(int j, const RedBuf &red, const BatchLaunch &bl, GmresState *st, hipStream_t s) {
-  if (j == J) {
-    hipLaunchKernelGGL(k_finalize_dots<J>, dim3(bl.count), dim3(256), 0, s, red.partials, bl.grid[kFamCell],
-                       fin_inst(bl, kFamCell), bl.bt.active, st);
-    return hipGetLastError();
-  }
-  if constexpr (J + 1 < kMaxRestart) return finalize_dots_at<J + 1>(j, red, bl, st, s);
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_finalize_dots(int j, const RedBuf &red, const BatchLaunch &bl, GmresState *st, hipStream_t s) {
-  if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
-  return finalize_dots_at<0>(j, red, bl, st, s);
-}
-
-template <int J>
-static hipError_t orth_at(int j, const BatchLaunch &bl, double *V, long vstride, GmresState *st, const RedBuf &red,
-                          hipStream_t s) {
+static hipError_t orth_at(int j, const BatchLaunch &bl, double *V, long vstride, GmresState *st, const RedBuf &nred,
+                          const double *dots, hipStream_t s) {
   if (j == J) {
     hipLaunchKernelGGL(k_gmres_orth<J>, dim3(bl.grid[kFamElem]), dim3(256), 0, s, bl.bt, 2 * bl.ncell, V, vstride, st,
-                       red);
+                       nred, dots, bl.grid[kFamCell]);
     return hipGetLastError();
   }
-  if constexpr (J + 1 < kMaxRestart) return orth_at<J + 1>(j, bl, V, vstride, st, red, s);
+  if constexpr (J + 1 < kMaxRestart) return orth_at<J + 1>(j, bl, V, vstride, st, nred, dots, s);
   return hipErrorInvalidValue;
 }
 
@@ -420,9 +406,12 @@ hipError_t launch_gmres_start(const BatchLaunch &bl, const double *F, const doub
 hipError_t launch_gmres_orth(const BatchLaunch &bl, double *V, long vstride, int j, GmresState *st,
                              const RedBuf &red, hipStream_t s) {
   if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
-  hipError_t e = orth_at<0>(j, bl, V, vstride, st, red, s);
+  // the norm partials go after the dot rows, which the kernel is still reading
+  RedBuf nred = red;
+  nred.partials = red.partials + (long)kMaxRestart * bl.grid[kFamCell];
+  hipError_t e = orth_at<0>(j, bl, V, vstride, st, nred, red.partials, s);
   if (e != hipSuccess) return e;
-  return launch_finalize(kFinOrth, 1, red, bl, kFamElem, st, FinalizeArgs{}, s);
+  return launch_finalize(kFinOrth, 1, nred, bl, kFamElem, st, FinalizeArgs{}, s);
 }
 
 hipError_t launch_gmres_update(const BatchLaunch &bl, double *S, const double *Z, long vstride, GmresState *st,

@@ -499,8 +499,7 @@ hipError_t launch_spmv_dots2d(const BatchLaunch &bl, const double *J, const doub
   if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
   hipError_t e = transpose ? spmv_dots_at<0, true>(j, bl, J, Z, V, vstride, st, red, s)
                            : spmv_dots_at<0, false>(j, bl, J, Z, V, vstride, st, red, s);
-  if (e != hipSuccess) return e;
-  return launch_finalize_dots(j, red, bl, st, s);
+  return e;   // the dots are summed by the Gram–Schmidt kernel (k_gmres_orth)
 }
 
 }  // namespace acch

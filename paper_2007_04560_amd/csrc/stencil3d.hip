@@ -532,8 +532,7 @@ hipError_t launch_spmv_dots3d(const BatchLaunch &bl, const double *J, const doub
   if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
   hipError_t e = transpose ? dots3_at<0, true>(j, bl, J, Z, V, vstride, st, red, s)
                            : dots3_at<0, false>(j, bl, J, Z, V, vstride, st, red, s);
-  if (e != hipSuccess) return e;
-  return launch_finalize_dots(j, red, bl, st, s);
+  return e;   // the dots are summed by the Gram–Schmidt kernel (k_gmres_orth)
 }
 
 hipError_t launch_adjoint_prev3d(const Phys &P, const double *X1, const double *X0, double dt, const double *lam,
