@@ -198,8 +198,10 @@ enum {
 };
 
 /* Enable (1) or disable (0) per-kernel timing: HIP events recorded on the context's
- * stream around every launch, accumulated per kernel class.  Resets the totals and
- * the launch / synchronisation counters.  Synchronises the stream. */
+ * stream around every launch, accumulated per kernel class.  2: sampled timing of the
+ * Schwarz preconditioner only (events around one ACCH_KERNEL_RAS launch in 16, none
+ * elsewhere), for timing a run without the events' own cost on every launch.  Resets
+ * the totals and the launch / synchronisation counters.  Synchronises the stream. */
 int acch_timing(acch_ctx *c, int enable);
 
 /* Accumulated device time (ms, host double) and launch count of one kernel class

@@ -285,8 +285,9 @@ class Solver:
         _check(self.lib, self.lib.acch_get_time(self.ctx, ctypes.byref(t), ctypes.byref(dtp), ctypes.byref(eta)))
         return t.value, dtp.value, eta.value
 
-    def timing(self, enable: bool = True):
-        _check(self.lib, self.lib.acch_timing(self.ctx, int(bool(enable))))
+    def timing(self, enable=True):
+        """True / 1: time every launch; 2: sample the Schwarz launches only (acch_timing)."""
+        _check(self.lib, self.lib.acch_timing(self.ctx, 2 if enable == 2 else int(bool(enable))))
 
     def kernel_stats(self) -> Dict[str, Tuple[float, int]]:
         out = {}

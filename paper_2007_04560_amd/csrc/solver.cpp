@@ -42,7 +42,10 @@ struct Layout {
 // around each launch; harvested whenever the host synchronises anyway.
 struct KernelTimer {
   static constexpr int kPool = 2048;
+  static constexpr int kSample = 16;   // sampled mode: one Schwarz launch in kSample
   bool on = false;
+  bool sampled = false;
+  long seen = 0;
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
   std::vector<int> kind;
   int used = 0;
@@ -399,6 +402,7 @@ int sync_read(acch_ctx *c, const void *dev, void *host, size_t bytes) {
 int timer_begin(acch_ctx *c, int kind) {
   KernelTimer &T = c->timer;
   if (!T.on) return -1;
+  if (T.sampled && (kind != ACCH_KERNEL_RAS || T.seen++ % KernelTimer::kSample != 0)) return -1;
   if (T.used == KernelTimer::kPool) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     int rc = harvest_timer(c);
@@ -756,6 +760,8 @@ extern "C" int acch_timing(acch_ctx *c, int enable) {
     for (auto &e : T.ev) HIP_TRY(hipEventCreate(&e));
   }
   T.on = enable != 0;
+  T.sampled = enable == 2;
+  T.seen = 0;
   for (int k = 0; k < ACCH_KERNEL_KINDS; ++k) {
     T.total_ms[k] = 0.0;
     T.count[k] = 0;
