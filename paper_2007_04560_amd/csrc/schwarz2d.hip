@@ -140,28 +140,33 @@ __global__ __launch_bounds__(64 * NW) void k_ilu_factor2d(Phys P0, Batch bt, Box
   const long n = (long)nx * ny;
   const long ncb = (long)G.nlev * G.bh;
   FT *Fk = fac + (long)blockIdx.x * kNSlot2D * ncb;
+  // The box cells that hold a grid cell (box_to_global >= 0) form the rectangle
+  // [ilo, ihi) x [jlo, jhi): the real extent, cut to the domain for Neumann boxes.
+  int ilo = 0, jlo = 0, ihi = min(G.bw, si.ex), jhi = min(G.bh, si.ey);
+  if (!periodic) {
+    ilo = max(ilo, -si.ox);
+    jlo = max(jlo, -si.oy);
+    ihi = min(ihi, nx - si.ox);
+    jhi = min(jhi, ny - si.oy);
+  }
+  const unsigned iw = (unsigned)max(ihi - ilo, 0), jw = (unsigned)max(jhi - jlo, 0);
+  auto inside = [&](int ii, int jj) { return (unsigned)(ii - ilo) < iw && (unsigned)(jj - jlo) < jw; };
   for (int w = 0; w < G.nlev; ++w) {
     const int j = row_on_level<T>(w, t, G.bw, G.bh);
     if (j >= 0) {
       const int i = w - 2 * j;
-      const long g = box_to_global(si, i, j, nx, ny, periodic);
+      const long g = inside(i, j) ? box_to_global(si, i, j, nx, ny, periodic) : -1;
       double a[18], b[6];
       if (g >= 0) {
 #pragma unroll
         for (int k = 0; k < 18; ++k) {
           const Col c = ucol(k);
-          const int ii = i + c.dx, jj = j + c.dy;
-          const bool in = ii >= 0 && ii < G.bw && jj >= 0 && jj < G.bh &&
-                          box_to_global(si, ii, jj, nx, ny, periodic) >= 0;
-          a[k] = in ? J[(long)jslot(0, c) * n + g] : 0.0;
+          a[k] = inside(i + c.dx, j + c.dy) ? J[(long)jslot(0, c) * n + g] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
           const Col c = vcol(k);
-          const int ii = i + c.dx, jj = j + c.dy;
-          const bool in = ii >= 0 && ii < G.bw && jj >= 0 && jj < G.bh &&
-                          box_to_global(si, ii, jj, nx, ny, periodic) >= 0;
-          b[k] = in ? J[(long)jslot(1, c) * n + g] : 0.0;
+          b[k] = inside(i + c.dx, j + c.dy) ? J[(long)jslot(1, c) * n + g] : 0.0;
         }
         a[8] *= 1.0 + shift;  // ILU(0) of A_k + shift diag(A_k)
         b[3] *= 1.0 + shift;
