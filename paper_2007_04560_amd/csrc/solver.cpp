@@ -516,7 +516,11 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int 
     LAUNCHK(c, ACCH_KERNEL_GMRES_START, launch_gmres_start(c->bl, F, cycle > 0 ? c->W : nullptr, c->V, c->st, m, c->p.gmres_rtol,
                                  c->p.gmres_atol, c->red, c->stream));
     int launched = 0;
-    int chunk = cycle == 0 ? std::max(1, std::min(m, c->its_guess)) : std::max(1, m / 2);
+    // Steps enqueued before the first convergence check of the cycle: what the
+    // previous solve needed in this cycle, plus one (extra steps are no-ops once the
+    // cycle is done), or half a cycle beyond that solve's count; then two at a time.
+    const int rem = c->its_guess - cycle * m + 1;
+    int chunk = rem >= 1 ? std::min(m, rem) : std::max(1, m / 2);
     while (true) {
       for (int k = 0; k < chunk && launched < m; ++k, ++launched) {
         if (transpose) {
@@ -539,7 +543,7 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int 
     resid = hs.resid;
     if (!hs.done) return fail(ACCH_EDIVERGED, "GMRES cycle did not finish");
     if (hs.converged) {
-      c->its_guess = std::max(1, std::min(m, its));
+      c->its_guess = std::max(1, its);   // over all cycles
       return ACCH_OK;
     }
     if (!(resid == resid)) return fail(ACCH_EDIVERGED, "GMRES residual is not finite");
