@@ -55,14 +55,14 @@ WORKLOADS = {
                                "NKS, left-RAS 8x8x8 overlap 1, ILU(0) shift 0.02, GMRES(30), tol 1e-8"),
     # the paper's long adaptive 2D run (Section 4.2: alpha 4, beta 2, gamma 5e-3, theta 0.1,
     # rho 1e-3, u0 = 0.55 + 0.05 U(-1,1), dt in [1e-4, 10], eta = 1e4), its first steps
-    "long128": dict(name="long128", shape=(128, 128), bc="periodic", sub=(4, 4), overlap=2,
+    "long128": dict(name="long128", shape=(128, 128), bc="periodic", sub=(8, 8), overlap=1,
                     adaptive=True, dt_min=1e-4, dt_max=10.0, eta0=1e4, newton_rtol=1e-8, newton_atol=1e-13,
                     gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30, ilu_shift=0.02, precision="fp64",
                     seed=0, steps=2000, u_mean=0.55,
                     phys=dict(alpha=4.0, beta=2.0, gamma=0.005, theta=0.1, rho=0.001),
                     text="long128: the paper's long adaptive 2D run, 128x128 periodic, alpha 4, beta 2, gamma 5e-3, "
                          "theta 0.1, rho 1e-3, u0 = 0.55 + 0.05 U(-1,1), dt in [1e-4,10] (eta0 = 1e4), first 2000 "
-                         "steps, FP64 NKS, left-RAS 4x4 overlap 2, ILU(0) shift 0.02, GMRES(30), tol 1e-8"),
+                         "steps, FP64 NKS, left-RAS 8x8 overlap 1, ILU(0) shift 0.02, GMRES(30), tol 1e-8"),
 }
 # 96 independent periodic instances of uneven size (N in {96,128,192,256}), theta and
 # gamma drawn per instance, 10 steps at dt = 1e-3, all instances in one batched solve
