@@ -288,6 +288,28 @@ def test_periodic512_sampled_residual_and_root():
     assert scheme.energy(ug, vg, P) < scheme.energy(u0, v0, P)
 
 
+def test_timing_modes_count_launches():
+    """acch_timing: 1 times every launch of every class; 2 times one Schwarz launch in 16
+    and nothing else, and does not change the result."""
+    shape = (64, 64)
+    u0, v0 = random_ic(shape, 3)
+    out = {}
+    for mode in (1, 2):
+        s = solver(u0, v0, "periodic", sub=(2, 2), overlap=1, dt_fixed=1e-3)
+        s.timing(mode)
+        s.step(2)
+        st = s.kernel_stats()
+        out[mode] = (st, s.fields())
+        s.close()
+    full, sampled = out[1][0], out[2][0]
+    n_ras = full["ras"][1]
+    assert n_ras > 16 and full["spmv_dots"][1] > 0 and full["residual"][1] > 0
+    assert sampled["ras"][1] == (n_ras + 15) // 16 and sampled["ras"][0] > 0
+    assert all(v[1] == 0 for k, v in sampled.items() if k != "ras")
+    for a, b in zip(out[1][1], out[2][1]):
+        assert np.array_equal(a, b)
+
+
 def test_errors_are_reported():
     shape = (16, 16)
     u0, v0 = random_ic(shape, 1)
