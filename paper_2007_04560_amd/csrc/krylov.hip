@@ -128,29 +128,30 @@ __global__ __launch_bounds__(256) void k_gmres_orth(Batch bt, long n2s, double *
 }
 
 // The serial part of an Arnoldi step: Hessenberg column, Givens rotations, residual
-// estimate, stopping test and, at the end of a cycle, y.  The block first stages the
-// small GMRES arrays in LDS (one round trip), thread 0 works on LDS only, then the
-// block writes the results back.
+// estimate, stopping test and, at the end of a cycle, y.  The block stages the new
+// column, the rotations and g in LDS (one round trip), thread 0 works on LDS only,
+// then the block writes the results back; the earlier columns of H are read only for
+// the back substitution at the end of a cycle.
 ACCH_DEV void orth_tail(GmresState *st, double sum) {
   constexpr int M1 = kMaxRestart + 1;
-  __shared__ double sH[M1 * kMaxRestart];
+  __shared__ double sH[M1 * kMaxRestart];   // columns 0..j, for the back substitution
+  __shared__ double shc[M1];                // the new column j
   __shared__ double sc_[kMaxRestart], ss_[kMaxRestart], sg[M1], sy[kMaxRestart];
   __shared__ int s_done;
   const int tid = threadIdx.x;
   const int j = st->j;
-  for (int e = tid; e < (j + 1) * M1; e += blockDim.x) {
-    const int col = e / M1, row = e - col * M1;
-    sH[e] = (col < j) ? st->H[e] : (row <= j ? st->hcol[row] : 0.0);
+  if (tid <= j) {
+    shc[tid] = st->hcol[tid];
+    sg[tid] = st->g[tid];
   }
   if (tid < j) {
     sc_[tid] = st->cs[tid];
     ss_[tid] = st->sn[tid];
   }
-  if (tid <= j) sg[tid] = st->g[tid];
   __syncthreads();
   const double hn = sqrt(sum);
   if (tid == 0) {
-    double *h = sH + j * M1;
+    double *h = shc;
     for (int i = 0; i < j; ++i) {
       const double a = h[i], b = h[i + 1];
       h[i] = sc_[i] * a + ss_[i] * b;
@@ -178,14 +179,6 @@ ACCH_DEV void orth_tail(GmresState *st, double sum) {
     } else if (jn >= st->m || !(resid == resid)) {
       done = 1;
     }
-    if (done) {  // back substitution H(0:jn,0:jn) y = g
-      for (int i = jn - 1; i >= 0; --i) {
-        double a = sg[i];
-        for (int q = i + 1; q < jn; ++q) a -= sH[q * M1 + i] * sy[q];
-        const double d = sH[i * M1 + i];
-        sy[i] = d != 0.0 ? a / d : 0.0;
-      }
-    }
     st->resid = resid;
     st->inv_norm[jn] = breakdown ? 0.0 : 1.0 / hn;
     st->total_its += 1;
@@ -193,7 +186,23 @@ ACCH_DEV void orth_tail(GmresState *st, double sum) {
   }
   __syncthreads();
   const int jn = j + 1;
-  if (tid <= j) st->H[j * M1 + tid] = sH[j * M1 + tid];
+  if (s_done) {   // back substitution H(0:jn,0:jn) y = g
+    for (int e = tid; e < jn * M1; e += blockDim.x) {
+      const int col = e / M1, row = e - col * M1;
+      sH[e] = (col < j) ? st->H[e] : (row <= j ? shc[row] : 0.0);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int i = jn - 1; i >= 0; --i) {
+        double a = sg[i];
+        for (int q = i + 1; q < jn; ++q) a -= sH[q * M1 + i] * sy[q];
+        const double d = sH[i * M1 + i];
+        sy[i] = d != 0.0 ? a / d : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid <= j) st->H[j * M1 + tid] = shc[tid];
   if (tid == 0) {
     st->cs[j] = sc_[j];
     st->sn[j] = ss_[j];
