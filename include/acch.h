@@ -41,6 +41,9 @@ enum {
 };
 
 enum { ACCH_BC_PERIODIC = 0, ACCH_BC_NEUMANN = 1 };
+/* On/off switches of acch_params (ilu_reuse, mass_projection, log_energy): 0, the
+ * value of a zero-filled struct, selects the documented default, which is on. */
+enum { ACCH_OFF = -1, ACCH_SWITCH_DEFAULT = 0, ACCH_ON = 1 };
 /* Schwarz variant (Section 3.1): left-restricted (restricted extension, the paper's
  * choice), right-restricted (restricted restriction) or classical (eq. invM). */
 enum { ACCH_RAS_LEFT = 0, ACCH_RAS_RIGHT = 1, ACCH_AS_CLASSICAL = 2 };
@@ -69,14 +72,16 @@ typedef struct {
   int ras_type;                           /* ACCH_RAS_LEFT / _RIGHT / ACCH_AS_CLASSICAL */
   int sub[3];                             /* subdomains per direction                 */
   int overlap;                            /* delta, cell layers                       */
-  int ilu_reuse;                          /* 1: factor once per step attempt (default) */
+  int ilu_reuse;                          /* ACCH_ON (default): factor once per step
+                                             attempt; ACCH_OFF: at every Newton iteration */
   int precision;                          /* ACCH_PREC_*                              */
   int mobility_mode;                      /* ACCH_MOB_*                               */
   int xd_norm;                            /* 0: plain 2-norm of X^n - X^{n-1};
                                              1: cell-volume weighted                 */
-  int mass_projection;                    /* 1 (default): remove the mean of the u part
-                                             of each Newton direction              */
-  int log_energy;                         /* 1 (default): energy and mass per step     */
+  int mass_projection;                    /* ACCH_ON (default): remove the mean of the u
+                                             part of each Newton direction; ACCH_OFF */
+  int log_energy;                         /* ACCH_ON (default): energy and mass per step;
+                                             ACCH_OFF: NaN in the step records        */
   double ilu_shift;                       /* sigma >= 0: the subdomain ILU(0) factors
                                              A_k + sigma diag(A_k); 0 is plain ILU(0) */
   void *workspace;                        /* device buffer, >= acch_workspace_bytes    */

@@ -98,14 +98,23 @@ def line_search(residual_fn, X, S, F, n, opts: NewtonOptions):
 
 
 def solve_step(u0, v0, dt: float, prob: Problem, opts: Optional[NewtonOptions] = None,
-               X_init=None) -> NewtonResult:
-    """Solve F(U1; U0, dt) = 0 of scheme (2.20) from X_0 = U^n (or ``X_init``)."""
+               X_init=None, forcing=None) -> NewtonResult:
+    """Solve F(U1; U0, dt) = 0 of scheme (2.20) from X_0 = U^n (or ``X_init``).
+
+    ``forcing`` (a stacked [f_u, f_v] vector, default none) is subtracted from the
+    residual: the manufactured-solution test solves F(U1; U0, dt) = f with the
+    forcing of a chosen exact solution.  It does not depend on U1, so the Jacobian
+    is unchanged."""
     opts = opts or NewtonOptions()
     shape = u0.shape
     n = int(np.prod(shape))
     U0 = np.concatenate([u0.ravel(), v0.ravel()])
     X = U0.copy() if X_init is None else np.array(X_init, dtype=np.float64)
-    rfun = lambda Y: scheme.residual_vec(Y, U0, dt, prob, shape)
+    if forcing is None:
+        rfun = lambda Y: scheme.residual_vec(Y, U0, dt, prob, shape)
+    else:
+        fvec = np.asarray(forcing, dtype=np.float64)
+        rfun = lambda Y: scheme.residual_vec(Y, U0, dt, prob, shape) - fvec
     F = rfun(X)
     f_init = float(np.linalg.norm(F))
     res = NewtonResult(False, X, 0, [f_init], [])

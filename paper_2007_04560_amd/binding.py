@@ -186,12 +186,12 @@ def make_params(shape: Sequence[int], *, bc="periodic", L=(1.0, 1.0), alpha=1.2,
     p.ras_type = _SCHWARZ[schwarz]
     p.sub[0], p.sub[1], p.sub[2] = int(sub[0]), int(sub[1]), int(sub[2]) if len(sub) > 2 else 1
     p.overlap = overlap
-    p.ilu_reuse = int(bool(ilu_reuse))
+    p.ilu_reuse = 1 if ilu_reuse else -1
     p.precision = _PREC[precision]
     p.mobility_mode = _MOB[mobility]
     p.xd_norm = 0 if xd_norm == "plain" else 1
-    p.mass_projection = int(bool(mass_projection))
-    p.log_energy = int(bool(log_energy))
+    p.mass_projection = 1 if mass_projection else -1
+    p.log_energy = 1 if log_energy else -1
     p.ilu_shift = float(ilu_shift)
     return p
 

@@ -225,7 +225,7 @@ int enqueue_steps(acch_batch *b, int j0, int j1, int fp32, long vs) {
     BLAUNCH(b, launch_spmv_dots2d(b->cyc, b->J, b->Z, b->V, vs, j, 0, b->st, b->red, b->stream));
     BLAUNCH(b, launch_gmres_orth(b->cyc, b->V, vs, j, b->st, b->red, b->stream));
   }
-  BLAUNCH(b, launch_gmres_update(b->cyc, b->S, b->Z, vs, b->st, 1, b->p.mass_projection, b->red, b->stream));
+  BLAUNCH(b, launch_gmres_update(b->cyc, b->S, b->Z, vs, b->st, 1, b->p.mass_projection > 0, b->red, b->stream));
   return ACCH_OK;
 }
 
@@ -329,7 +329,7 @@ int gmres_batch(acch_batch *b, std::vector<int> &its) {
 // Residual of every instance selected by bl (trial state X + lam_i (S - shift_i e_u)
 // when Sdir is given); f2/bad per instance in h_out[4 i], h_out[4 i + 1].
 int residual_batch(acch_batch *b, const BatchLaunch &bl, const double *Sdir, double *Xt, double *F) {
-  const GmresState *shift = (Sdir && b->p.mass_projection) ? b->st : nullptr;
+  const GmresState *shift = (Sdir && b->p.mass_projection > 0) ? b->st : nullptr;
   BLAUNCH(b, launch_residual2d(bl, b->X, Sdir, 0.0, Sdir ? b->lam : nullptr, shift, b->Xn, b->p.dt_fixed, Xt, F,
                                b->red, b->stream));
   return read_out(b);
@@ -360,10 +360,13 @@ int nks_batch(acch_batch *b, BStats &stats) {
     }
     if (nact == 0) return ACCH_OK;
     if (it > p.newton_max_it) return fail(ACCH_EDIVERGED, "Newton iteration limit reached");
+    // counted before any early return, so a failed attempt's last iteration counts too
+    for (int i = 0; i < count; ++i)
+      if (b->h_mask[0][i]) stats.newton[i] = it;
     rc = upload_mask(b, 0);
     if (rc) return rc;
     BLAUNCH(b, launch_jacobian2d(b->newton, b->X, b->Xn, p.dt_fixed, b->J, b->stream));
-    if (it == 1 || !p.ilu_reuse) {
+    if (it == 1 || p.ilu_reuse < 0) {
       BLAUNCH(b, launch_ilu_factor2d(b->newton, b->pl.G, b->d_subs, b->d_lvl, b->J, p.ilu_shift, b->fac,
                                      p.precision == ACCH_PREC_MIXED, b->stream));
       b->factored = true;
@@ -398,7 +401,6 @@ int nks_batch(acch_batch *b, BStats &stats) {
     BLAUNCH(b, launch_copy2(b->newton, b->X, b->Xt, b->F, b->Ft, b->stream));
     for (int i = 0; i < count; ++i) {
       if (!b->h_mask[0][i]) continue;
-      stats.newton[i] = it;
       fnorm[i] = sqrt(ls[i].f2);
       if (!std::isfinite(fnorm[i])) return fail(ACCH_EDIVERGED, "instance " + std::to_string(i) + ": residual is not finite");
     }

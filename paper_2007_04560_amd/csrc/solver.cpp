@@ -104,6 +104,10 @@ extern "C" void acch_params_default(acch_params *p) {
   if (p->gmres_max_restarts == 0) p->gmres_max_restarts = 10;
   for (int d = 0; d < 3; ++d)
     if (p->sub[d] == 0) p->sub[d] = 1;
+  // switches: 0 (a zero-filled struct) means the documented default, on
+  if (p->ilu_reuse == 0) p->ilu_reuse = ACCH_ON;
+  if (p->mass_projection == 0) p->mass_projection = ACCH_ON;
+  if (p->log_energy == 0) p->log_energy = ACCH_ON;
 }
 
 int acch::validate_params(const acch_params &p) {
@@ -505,7 +509,7 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int 
   const long n2 = 2 * c->geo.ncell;
   const long vs = n2;
   const int m = c->p.gmres_restart;
-  const int project = transpose ? 0 : c->p.mass_projection;
+  const int project = transpose ? 0 : (c->p.mass_projection > 0);
   LAUNCH(c, launch_reset_state(c->bl, c->st, c->stream));
   its = 0;
   resid = 0.0;
@@ -557,7 +561,7 @@ int gmres(acch_ctx *c, const double *F, double *S, int &its, double &resid, int 
 int line_search(acch_ctx *c, double dt, double fnorm, double &f2_new, double &lam_out) {
   LineSearch ls;
   ls.start(fnorm);
-  const GmresState *shift = c->p.mass_projection ? c->st : nullptr;
+  const GmresState *shift = c->p.mass_projection > 0 ? c->st : nullptr;
   while (ls.state == LineSearch::kSearching) {
     double f2, bad;
     int rc = residual_eval(c, c->X, c->S, ls.lam, shift, c->Xn, dt, c->Xt, c->Ft, f2, bad);
@@ -588,8 +592,10 @@ int nks_solve(acch_ctx *c, double dt, SolveStats &stats) {
   const double tol = std::max(c->p.newton_rtol * fnorm, c->p.newton_atol);
   if (fnorm <= tol) return ACCH_OK;
   for (int it = 1; it <= c->p.newton_max_it; ++it) {
+    // counted before any early return, so a failed attempt's last iteration counts too
+    stats.newton = it;
     LAUNCHK(c, ACCH_KERNEL_JACOBIAN, run_jacobian(c, c->X, c->Xn, dt));
-    if (it == 1 || !c->p.ilu_reuse) {
+    if (it == 1 || c->p.ilu_reuse < 0) {
       rc = factor(c);
       if (rc) return rc;
     }
@@ -600,7 +606,6 @@ int nks_solve(acch_ctx *c, double dt, SolveStats &stats) {
     if (rc) return rc;
     double f2n, lam;
     rc = line_search(c, dt, fnorm, f2n, lam);
-    stats.newton = it;
     if (rc) return rc;
     std::swap(c->X, c->Xt);
     std::swap(c->F, c->Ft);
@@ -862,7 +867,7 @@ extern "C" int acch_step(acch_ctx *c, int nsteps, acch_step_info *info, int *acc
     rec.retries = retries;
     rec.status = ACCH_OK;
     rec.energy = rec.mass = NAN;
-    if (p.log_energy) {
+    if (p.log_energy > 0) {
       int rc = energy_mass(c, c->Xn, rec.energy, rec.mass);
       if (rc) return rc;
     }
@@ -887,7 +892,7 @@ extern "C" int acch_solve_step(acch_ctx *c, double dt, acch_step_info *info) {
     rec.newton_its = st.newton;
     rec.gmres_its = st.gmres;
     rec.energy = rec.mass = NAN;
-    if (c->p.log_energy) {
+    if (c->p.log_energy > 0) {
       rc = energy_mass(c, c->Xn, rec.energy, rec.mass);
       if (rc) return rc;
     }

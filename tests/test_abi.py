@@ -58,3 +58,21 @@ def test_workspace_and_validation(lib):
     # no workspace: rejected before any device work
     assert lib.acch_create(ctypes.byref(q), u, u, ctypes.byref(ctx)) == 1
     assert lib.acch_strerror(3) == b"Newton-Krylov-Schwarz diverged"
+
+
+def test_zero_filled_switches_mean_the_documented_defaults(lib):
+    """acch_params_default: a zero-filled struct gets ilu_reuse, mass_projection and
+    log_energy on (ACCH_ON = 1); an explicit ACCH_OFF (-1) is kept; repeated calls
+    change nothing."""
+    import paper_2007_04560_amd as pkg
+    p = pkg.Params()
+    lib.acch_params_default(ctypes.byref(p))
+    assert (p.ilu_reuse, p.mass_projection, p.log_energy) == (1, 1, 1)
+    assert (p.newton_rtol, p.gmres_restart, p.S) == (1e-8, 30, 10)
+    q = pkg.Params()
+    q.ilu_reuse, q.mass_projection, q.log_energy = -1, -1, -1
+    lib.acch_params_default(ctypes.byref(q))
+    lib.acch_params_default(ctypes.byref(q))
+    assert (q.ilu_reuse, q.mass_projection, q.log_energy) == (-1, -1, -1)
+    r = pkg.make_params((64, 64), ilu_reuse=False, mass_projection=True, log_energy=False)
+    assert (r.ilu_reuse, r.mass_projection, r.log_energy) == (-1, 1, -1)

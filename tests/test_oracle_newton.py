@@ -6,7 +6,9 @@ import numpy as np
 import pytest
 
 from acch_inputs import perturbed_pair, random_ic, smooth_ic_2d
-from oracle import controller, newton, scalar, scheme
+import scipy.sparse.linalg as spla
+
+from oracle import controller, jacobian, newton, scalar, scheme
 from oracle.params import Problem
 
 
@@ -98,39 +100,125 @@ def test_energy_law_identity(bc):
     assert -diss <= bound + 1e-12 * abs(diss)
 
 
+def _newton_direction(shape, seed, dt, prob):
+    u0, v0 = random_ic(shape, seed)
+    U0 = np.concatenate([u0.ravel(), v0.ravel()])
+    rfun = lambda Y: scheme.residual_vec(Y, U0, dt, prob, shape)
+    F = rfun(U0)
+    J = jacobian.jacobian(u0, v0, u0, v0, dt, prob)
+    S = spla.spsolve(J.tocsc(), -F)
+    return U0, F, S, rfun
+
+
 def test_line_search_backtracks_and_respects_admissibility():
-    """A full step that leaves the admissible set is halved; the accepted point
-    satisfies the sufficient-decrease test."""
+    """A step that leaves the admissible set at full length: lambda halves (without
+    evaluating F) until the trial is admissible, every evaluated trial is admissible,
+    each later lambda lies in [0.1, 0.5] times the previous one, and the accepted
+    point passes the sufficient-decrease test."""
     shape = (8, 8)
     prob = Problem(bc="periodic")
-    u0, v0 = random_ic(shape, 1)
-    U0 = np.concatenate([u0.ravel(), v0.ravel()])
-    n = u0.size
-    rfun = lambda Y: scheme.residual_vec(Y, U0, 0.01, prob, shape)
-    X = U0.copy()
-    F = rfun(X)
-    # a direction that pushes u far out of (0,1) at full length
-    S = np.zeros_like(X)
-    S[:n] = 4.0
-    S[n:] = 0.0
-    out = newton.line_search(rfun, X, S, F, n, newton.NewtonOptions())
-    if out is not None:
-        lam, Xt, Ft = out
-        assert lam <= 0.125
-        assert scheme.admissible(Xt[:n], Xt[n:])
-        assert 0.5 * Ft @ Ft <= 0.5 * F @ F * (1 - 2e-4 * lam) + 1e-300
+    X, F, SN, rfun = _newton_direction(shape, 1, 0.01, prob)
+    n = X.size // 2
+    S = 1024.0 * SN                       # far beyond the admissible set at lambda = 1
+    assert not scheme.admissible((X + S)[:n], (X + S)[n:])
+    m = 0                                 # first admissible power of two, found directly
+    while not scheme.admissible((X + S / 2 ** m)[:n], (X + S / 2 ** m)[n:]):
+        m += 1
+    assert m >= 2
+    k = int(np.argmax(np.abs(S)))
+    trials = []
 
+    def logged(Y):
+        assert scheme.admissible(Y[:n], Y[n:])
+        trials.append((Y[k] - X[k]) / S[k])
+        return rfun(Y)
 
-def test_line_search_quadratic_model():
-    """On f(X) = ||F||^2/2 with F(x) = atan-like overshoot, the first backtrack follows
-    the quadratic model clamped to [0.1, 0.5] lambda."""
-    F = lambda X: np.array([math.atan(X[0])])
-    X = np.array([2.0])
-    S = -np.array([math.atan(2.0) * (1 + 4.0)])   # the Newton step for atan at x = 2
-    out = newton.line_search(F, np.array([0.4, 0.0])[:1] * 0 + X, S, F(X), 0, newton.NewtonOptions())
+    out = newton.line_search(logged, X, S, F, n, newton.NewtonOptions())
     assert out is not None
     lam, Xt, Ft = out
-    assert abs(Ft[0]) < abs(F(X)[0])
+    assert trials[0] == pytest.approx(2.0 ** -m, rel=1e-12)
+    for a, b in zip(trials, trials[1:]):
+        assert 0.1 * a * (1 - 1e-12) <= b <= 0.5 * a * (1 + 1e-12)
+    assert lam == pytest.approx(trials[-1], rel=1e-12)
+    assert scheme.admissible(Xt[:n], Xt[n:])
+    assert 0.5 * Ft @ Ft <= 0.5 * F @ F * (1 - 2e-4 * lam)
+
+
+def _atan_trials(x0):
+    """Trial lambdas of the line search on F(x) = atan(x) along the Newton step
+    S = -atan(x0)(1 + x0^2), with the values f(lambda) = atan(x0 + lambda S)^2 / 2."""
+    F = lambda X: np.array([math.atan(X[0])])
+    X = np.array([x0])
+    S = np.array([-math.atan(x0) * (1.0 + x0 * x0)])
+    trials = []
+
+    def logged(Y):
+        trials.append(((Y[0] - x0) / S[0], 0.5 * math.atan(Y[0]) ** 2))
+        return F(Y)
+
+    out = newton.line_search(logged, X, S, F(X), 0, newton.NewtonOptions())
+    return out, trials, 0.5 * math.atan(x0) ** 2
+
+
+def test_line_search_quadratic_backtrack_on_atan():
+    """From x0 = 2 the full Newton step overshoots; the next trial is the minimiser of
+    the parabola through f(0), the Newton slope f'(0) = -2 f(0) and f(1), which passes.
+    The expected lambda was computed by hand from that parabola:
+    f(0) = atan(2)^2/2 = 0.61285..., f(1) = atan(2 - 5 atan 2)^2/2 = 0.83873...,
+    lambda = 2 f(0) / (2 (f(1) - f(0) + 2 f(0))) = 0.42221028..."""
+    out, trials, f0 = _atan_trials(2.0)
+    assert out is not None
+    assert [t for t, _ in trials][0] == 1.0
+    assert len(trials) == 2
+    lam = trials[1][0]
+    assert lam == pytest.approx(0.422210284908187, rel=1e-12)
+    # the same point as the stationary point of the interpolating parabola, found by
+    # fitting q(t) = f0 + g t + c t^2 to the data with a least-squares solve
+    g = -2.0 * f0
+    c = np.linalg.lstsq(np.array([[1.0]]), np.array([trials[0][1] - f0 - g]), rcond=None)[0][0]
+    assert lam == pytest.approx(-g / (2.0 * c), rel=1e-12)
+    assert out[0] == lam
+
+
+def test_line_search_upper_clamp_on_atan():
+    """Just inside Newton's 2-cycle of atan (x0 = 1.39173520..., the cycle point being
+    the root of 2x = atan(x)(1 + x^2), 1.39174520...) the full step lands almost on
+    -x0: f(1) is below f(0) by less than the Armijo margin, so the step fails, and the
+    parabola's minimiser f(0)/(f(0) + f(1)) = 0.50000294... is clamped to 0.5."""
+    out, trials, f0 = _atan_trials(1.3917352002707346)
+    assert out is not None
+    lams = [t for t, _ in trials]
+    assert lams[0] == 1.0 and f0 * (1 - 2e-4) < trials[0][1] < f0
+    assert lams[1] == 0.5
+    assert out[0] == 0.5
+
+
+def test_line_search_cubic_backtracks_on_atan():
+    """From x0 = 10 the quadratic trial fails too; the later trials minimise the cubic
+    f(0) + f'(0) t + b t^2 + a t^3 through the last two trials (a, b from a 2x2 solve,
+    the minimum taken where the cubic's second derivative is positive), each clamped to
+    [0.1, 0.5] times the previous lambda.  Hand-computed sequence:
+    1, 0.46956306999, 0.17085943160, 0.06468572070 (accepted)."""
+    out, trials, f0 = _atan_trials(10.0)
+    assert out is not None
+    lams = [t for t, _ in trials]
+    want = [1.0, 0.4695630699888559, 0.17085943160316305, 0.06468572069667183]
+    assert len(lams) == len(want)
+    for got, w in zip(lams, want):
+        assert got == pytest.approx(w, rel=1e-10)
+    g = -2.0 * f0
+    for i in range(2, len(trials)):
+        (l1, f1), (l2, f2) = trials[i - 2], trials[i - 1]
+        a, b = np.linalg.solve(np.array([[l1 ** 3, l1 ** 2], [l2 ** 3, l2 ** 2]]),
+                               np.array([f1 - f0 - g * l1, f2 - f0 - g * l2]))
+        roots = np.roots([3 * a, 2 * b, g])
+        mins = [r.real for r in roots if abs(r.imag) < 1e-14 and 6 * a * r.real + 2 * b > 0]
+        assert len(mins) == 1
+        expect = min(max(mins[0], 0.1 * l2), 0.5 * l2)
+        assert lams[i] == pytest.approx(expect, rel=1e-10)
+    assert out[0] == lams[-1]
+    f_acc = trials[-1][1]
+    assert f_acc <= f0 * (1 - 2e-4 * lams[-1])
 
 
 def test_controller_prediction_table():
