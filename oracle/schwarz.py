@@ -20,9 +20,15 @@ Readings where the paper is silent (shared with the HIP path):
   the box (u-row: u on the radius-2 diamond, v on the radius-1 star; v-row: v on
   the star and u at the cell), independent of numerically zero values.
 
+Subdomain solvers (Table 2): ILU(0), ILU(k) on the level-of-fill pattern, and the
+exact LU.
+
 Pins: textbook ILU(0) property (LU)_ij = A_ij on the pattern; ILU(0) equals the
 exact LU when the pattern admits no fill; one subdomain with zero overlap and an
-exact subdomain solve reproduces the global solve (tests).
+exact subdomain solve reproduces the global solve; ILU(k) levels equal the
+fill-path characterisation (shortest path through lower-numbered vertices) and
+(LU)_ij = A_ij on the level-k pattern; ILU(k) for k beyond the fill reaches the
+exact LU (tests).
 """
 from __future__ import annotations
 
@@ -31,6 +37,7 @@ from typing import Dict, List, Sequence, Tuple
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 
 def split(n: int, parts: int) -> List[Tuple[int, int]]:
@@ -146,6 +153,47 @@ def ilu0(rows: Dict[int, Dict[int, float]]):
 
     Returns a dict row -> {col: value} holding L (unit diagonal, entries col < row)
     and U (col >= row) in place, with (LU)_ij = A_ij for every (i, j) in the pattern."""
+    return ilu_on_pattern(rows)
+
+
+def fill_levels(rows: Dict[int, Dict[int, float]], k: int) -> Dict[int, Dict[int, int]]:
+    """Level-of-fill pattern of ILU(k) (Table 2's ILU(1), ILU(2)): every entry of A has
+    level 0; eliminating pivot p from row i creates or updates entry (i, j), j > p,
+    with level lev(i, p) + lev(p, j) + 1, the smallest such value kept; entries of
+    level above k are dropped.  Rows are processed in order, and the pivots of a row
+    in increasing column order, including fill created earlier in the same row."""
+    lev: Dict[int, Dict[int, int]] = {}
+    for i in range(len(rows)):
+        li = {j: 0 for j in rows[i]}
+        done = set()
+        while True:
+            pend = [p for p in li if p < i and p not in done]
+            if not pend:
+                break
+            p = min(pend)
+            done.add(p)
+            for j, lpj in lev[p].items():
+                if j <= p:
+                    continue
+                new = li[p] + lpj + 1
+                if new <= k and new < li.get(j, k + 1):
+                    li[j] = new
+        lev[i] = li
+    return lev
+
+
+def iluk(rows: Dict[int, Dict[int, float]], k: int):
+    """ILU(k): the IKJ elimination of ilu_on_pattern on the level-k pattern of
+    fill_levels (fill entries start at zero).  k = 0 is ILU(0)."""
+    lev = fill_levels(rows, k)
+    a = {i: {j: rows[i].get(j, 0.0) for j in lev[i]} for i in rows}
+    return ilu_on_pattern(a)
+
+
+def ilu_on_pattern(rows: Dict[int, Dict[int, float]]):
+    """Incomplete LU restricted to the pattern of ``rows`` (IKJ order): for each row i,
+    for each k < i in the pattern, l_ik = a_ik / u_kk and a_ij -= l_ik u_kj for the
+    j > k that are in row i's pattern; other updates are dropped."""
     a = {i: dict(r) for i, r in rows.items()}
     n = len(a)
     for i in range(n):
@@ -199,27 +247,47 @@ def to_dense(rows, n=None):
     return M
 
 
+def to_sparse(rows, n=None):
+    n = n or len(rows)
+    r, c, v = [], [], []
+    for i, row in rows.items():
+        for j, x in row.items():
+            r.append(i)
+            c.append(j)
+            v.append(x)
+    return sp.csc_matrix((v, (r, c)), shape=(n, n))
+
+
 class Schwarz:
-    """Additive Schwarz preconditioner M^{-1} with subdomain ILU(0) (or exact LU).
+    """Additive Schwarz preconditioner M^{-1} with a subdomain solver for inv(A_k).
 
     kind: "left" (restricted extension; the paper's choice), "right" (restricted
-    restriction) or "classical" (eq. invM)."""
+    restriction) or "classical" (eq. invM).  solver (Section 3.1 and Table 2):
+    "ilu0"; "iluk" with ``level`` = k (ILU(1), ILU(2)); "lu", the exact subdomain
+    solve (a sparse direct factorisation of A_k; the result does not depend on its
+    ordering).  ``exact=True`` is the same as solver="lu"."""
 
-    def __init__(self, J, shape, parts, overlap, bc, kind="left", exact=False, shift=0.0):
+    def __init__(self, J, shape, parts, overlap, bc, kind="left", exact=False, shift=0.0,
+                 solver="ilu0", level=0):
         self.shape = tuple(shape)
         self.ncell = int(np.prod(shape))
         self.kind = kind
         self.subs = decompose(self.shape, parts, overlap, bc)
         self.factors = []
-        self.exact = exact
+        self.solver = "lu" if exact else solver
+        self.exact = self.solver == "lu"
         for sub in self.subs:
             rows = subdomain_matrix(J, sub, self.shape)
             if shift:
                 rows = shifted(rows, shift)
-            if exact:
-                self.factors.append(np.linalg.inv(to_dense(rows)))
-            else:
+            if self.solver == "lu":
+                self.factors.append(spla.splu(to_sparse(rows)))
+            elif self.solver == "iluk":
+                self.factors.append(iluk(rows, level))
+            elif self.solver == "ilu0":
                 self.factors.append(ilu0(rows))
+            else:
+                raise ValueError(f"unknown subdomain solver {solver!r}")
 
     def apply(self, r):
         r = np.asarray(r, dtype=np.float64)
@@ -230,7 +298,7 @@ class Schwarz:
             rk = r[idx].copy()
             if self.kind == "right":
                 rk[~own] = 0.0
-            xk = fac @ rk if self.exact else ilu_solve(fac, rk)
+            xk = fac.solve(rk) if self.exact else ilu_solve(fac, rk)
             if self.kind == "left":
                 z[idx[own]] += xk[own]
             else:

@@ -114,3 +114,104 @@ def test_left_ras_writes_each_unknown_once():
     P = schwarz.Schwarz(I, shape, (2, 3), 2, "periodic", kind="left")
     r = np.random.default_rng(5).standard_normal(n)
     assert np.allclose(P.apply(r), r, rtol=0, atol=0)
+
+
+def _fill_path_levels(rows, k):
+    """Levels by the fill-path characterisation of ILU(k): entry (i, j) has level
+    (length of the shortest path i -> j in the graph of A whose interior vertices are
+    all numbered below min(i, j)) - 1, kept when <= k.  Breadth-first search per row."""
+    n = len(rows)
+    out = {}
+    for i in range(n):
+        li = {}
+        for j in range(n):
+            lim = min(i, j)
+            seen = {i: 0}
+            q = [i]
+            found = None
+            while q and found is None:
+                nq = []
+                for a in q:
+                    for b in rows[a]:
+                        if b == j:
+                            found = seen[a] + 1
+                            break
+                        if b < lim and b not in seen:
+                            seen[b] = seen[a] + 1
+                            nq.append(b)
+                    if found is not None:
+                        break
+                q = nq
+            if found is not None and found - 1 <= k:
+                li[j] = found - 1
+        out[i] = li
+    return out
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_iluk_levels_match_fill_paths(k):
+    """Symbolic ILU(k) levels = the fill-path characterisation (brute force)."""
+    shape = (6, 5)
+    J = _J(shape, "neumann")
+    sub = schwarz.decompose(shape, (1, 1), 0, "neumann")[0]
+    rows = schwarz.subdomain_matrix(J, sub, shape)
+    lev = schwarz.fill_levels(rows, k)
+    ref = _fill_path_levels(rows, k)
+    assert lev == ref
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_iluk_defining_property(k):
+    """(LU)_ij = A_ij for every (i, j) of the level-k pattern; outside the pattern L and U
+    are zero; fill occurs (the pattern grows with k)."""
+    shape = (12, 14)
+    J = _J(shape, "neumann")
+    sub = schwarz.decompose(shape, (2, 2), 1, "neumann")[1]
+    rows = schwarz.subdomain_matrix(J, sub, shape)
+    lev = schwarz.fill_levels(rows, k)
+    assert sum(len(r) for r in lev.values()) > sum(len(r) for r in rows.values())
+    F = schwarz.to_dense(schwarz.iluk(rows, k))
+    n = len(F)
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    A = schwarz.to_dense(rows)
+    LU = L @ U
+    mask = np.zeros((n, n), dtype=bool)
+    for i, r in lev.items():
+        for j in r:
+            mask[i, j] = True
+    assert np.all(F[~mask] == 0.0)
+    assert np.max(np.abs((LU - A)[mask])) <= 1e-12 * np.max(np.abs(A))
+
+
+def test_iluk_zero_is_ilu0_and_full_level_is_exact_lu():
+    shape = (10, 12)
+    J = _J(shape, "periodic", dt=1e-3)
+    sub = schwarz.decompose(shape, (2, 2), 1, "periodic")[0]
+    rows = schwarz.subdomain_matrix(J, sub, shape)
+    assert schwarz.iluk(rows, 0) == schwarz.ilu0(rows)
+    n = len(rows)
+    F = schwarz.to_dense(schwarz.iluk(rows, n))
+    L = np.tril(F, -1) + np.eye(n)
+    U = np.triu(F)
+    A = schwarz.to_dense(rows)
+    assert np.max(np.abs(L @ U - A)) <= 1e-12 * np.max(np.abs(A))
+
+
+@pytest.mark.parametrize("solver,level", [("iluk", 1), ("iluk", 2), ("lu", 0)])
+def test_subdomain_solvers_precondition_gmres(solver, level):
+    """Left-RAS with each Table 2 subdomain solver drives GMRES to the direct solution;
+    the exact subdomain LU solves A_k x = r_k to rounding."""
+    shape = (16, 18)
+    J = _J(shape, "neumann", dt=1e-3).tocsr()
+    P = schwarz.Schwarz(J, shape, (2, 2), 1, "neumann", kind="left", solver=solver, level=level)
+    b = np.random.default_rng(0).standard_normal(J.shape[0])
+    M = spla.LinearOperator(J.shape, matvec=P.apply)
+    x, info = spla.gmres(J, b, M=M, rtol=1e-12, atol=0.0, restart=60, maxiter=20)
+    assert info == 0
+    assert np.linalg.norm(x - spla.spsolve(J.tocsc(), b)) <= 1e-8 * np.linalg.norm(x)
+    if solver == "lu":
+        sub = P.subs[1]
+        A = schwarz.to_dense(schwarz.subdomain_matrix(J, sub, shape))
+        r = np.random.default_rng(1).standard_normal(len(A))
+        assert np.linalg.norm(A @ P.factors[1].solve(r) - r) <= 1e-12 * np.linalg.norm(r) * np.linalg.cond(A)
