@@ -47,6 +47,13 @@ enum { ACCH_OFF = -1, ACCH_SWITCH_DEFAULT = 0, ACCH_ON = 1 };
 /* Schwarz variant (Section 3.1): left-restricted (restricted extension, the paper's
  * choice), right-restricted (restricted restriction) or classical (eq. invM). */
 enum { ACCH_RAS_LEFT = 0, ACCH_RAS_RIGHT = 1, ACCH_AS_CLASSICAL = 2 };
+/* Subdomain solver for inv(A_k) (Section 3.1: "a sparse LU factorization or incomplete
+ * LU factorization"; the four solvers of Table 2): ILU(0) on the Jacobian stencil
+ * (default), ILU(k) on the level-of-fill pattern with k = acch_params.fill_level, or
+ * the exact LU.  ILU(k) and LU are 2D, single-instance, and need padded subdomain boxes
+ * (owned width + 2 overlap) of at most 55 cells in x: they store the band of A_k in
+ * the natural order (half bandwidth 4 box widths) and factor it without pivoting. */
+enum { ACCH_SUB_ILU0 = 0, ACCH_SUB_ILUK = 1, ACCH_SUB_LU = 2 };
 /* Precision of the subdomain ILU(0) factors and triangular solves; the residual,
  * Jacobian products, Arnoldi process, Newton update and diagnostics stay FP64. */
 enum { ACCH_PREC_FP64 = 0, ACCH_PREC_MIXED = 1 };
@@ -83,7 +90,10 @@ typedef struct {
   int log_energy;                         /* ACCH_ON (default): energy and mass per step;
                                              ACCH_OFF: NaN in the step records        */
   double ilu_shift;                       /* sigma >= 0: the subdomain ILU(0) factors
-                                             A_k + sigma diag(A_k); 0 is plain ILU(0) */
+                                             A_k + sigma diag(A_k); 0 is plain ILU(0)
+                                             (also ILU(k); the exact LU ignores it)    */
+  int subsolver;                          /* ACCH_SUB_* (0: ILU(0))                      */
+  int fill_level;                         /* k of ACCH_SUB_ILUK, 1..8                    */
   void *workspace;                        /* device buffer, >= acch_workspace_bytes    */
   size_t workspace_bytes;
   void *stream;                           /* hipStream_t                              */
@@ -159,8 +169,9 @@ int acch_jacobian(acch_ctx *c, const double *X, const double *Xn, double dt);
 /* y = J x with the context's Jacobian. */
 int acch_apply_jacobian(acch_ctx *c, const double *x, double *y);
 
-/* Extract the subdomain matrices A_k = R_k J R_k^T and factor them by ILU(0)
- * (of A_k + ilu_shift * diag(A_k)). */
+/* Extract the subdomain matrices A_k = R_k J R_k^T and factor them with the
+ * subdomain solver of acch_params.subsolver: ILU(0) or ILU(k) of A_k + ilu_shift *
+ * diag(A_k), or the exact LU of A_k. */
 int acch_factor(acch_ctx *c);
 
 /* z = M^{-1} r, the Schwarz preconditioner with the current factors. */
@@ -187,8 +198,13 @@ int acch_solve_step(acch_ctx *c, double dt, acch_step_info *info);
  *       16:u(1,1) 17:u(0,2) 18:v(0,0) 19:v(1,0) 20:v(0,1);
  *     U of the v-row: 21: 1/diag, 22:v(1,0) 23:v(0,1).
  *   ACCH_EXPORT_BOXES: int32 [sub][4] = box origin x, y (unwrapped) and box
- *     width, height (all boxes padded to the same width/height). */
-enum { ACCH_EXPORT_JACOBIAN = 0, ACCH_EXPORT_FACTORS = 1, ACCH_EXPORT_BOXES = 2 };
+ *     width, height (all boxes padded to the same width/height).
+ *   ACCH_EXPORT_BAND: the ILU(k) / exact-LU factors as FP64 [sub][R][d], R over the
+ *     2 bw bh unknowns of the padded box (cell (i, j) of the box: R = 2 (j bw + i) for
+ *     u, + 1 for v), d = 0 .. 8 bw for column R + d - 4 bw; L below the diagonal
+ *     (unit diagonal implied), U on and above it, with 1/u_RR stored on the diagonal.
+ *     Box cells outside the grid are identity rows. */
+enum { ACCH_EXPORT_JACOBIAN = 0, ACCH_EXPORT_FACTORS = 1, ACCH_EXPORT_BOXES = 2, ACCH_EXPORT_BAND = 3 };
 int acch_export(acch_ctx *c, int which, void *out, size_t *bytes);
 
 /* Number of cells and of subdomains, the padded box size, and the kernel-launch

@@ -32,6 +32,7 @@ exact LU (tests).
 """
 from __future__ import annotations
 
+import heapq
 from dataclasses import dataclass
 from typing import Dict, List, Sequence, Tuple
 
@@ -165,18 +166,21 @@ def fill_levels(rows: Dict[int, Dict[int, float]], k: int) -> Dict[int, Dict[int
     lev: Dict[int, Dict[int, int]] = {}
     for i in range(len(rows)):
         li = {j: 0 for j in rows[i]}
-        done = set()
-        while True:
-            pend = [p for p in li if p < i and p not in done]
-            if not pend:
-                break
-            p = min(pend)
-            done.add(p)
+        heap = [p for p in li if p < i]       # pivots of row i, smallest first
+        heapq.heapify(heap)
+        while heap:
+            p = heapq.heappop(heap)
             for j, lpj in lev[p].items():
                 if j <= p:
                     continue
                 new = li[p] + lpj + 1
-                if new <= k and new < li.get(j, k + 1):
+                if new > k:
+                    continue
+                if j not in li:
+                    li[j] = new
+                    if j < i:
+                        heapq.heappush(heap, j)
+                elif new < li[j]:
                     li[j] = new
         lev[i] = li
     return lev

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libacch.so")
 
 ACCH_OK, ACCH_EINVAL, ACCH_EDOMAIN, ACCH_EDIVERGED, ACCH_EDEVICE, ACCH_EUNSUPPORTED = range(6)
-EXPORT_JACOBIAN, EXPORT_FACTORS, EXPORT_BOXES = 0, 1, 2
+EXPORT_JACOBIAN, EXPORT_FACTORS, EXPORT_BOXES, EXPORT_BAND = 0, 1, 2, 3
 
 EXPORTED = [
     "acch_params_default", "acch_workspace_bytes", "acch_create", "acch_step", "acch_energy",
@@ -46,6 +46,7 @@ class Params(ctypes.Structure):
         ("sub", ctypes.c_int * 3), ("overlap", ctypes.c_int), ("ilu_reuse", ctypes.c_int),
         ("precision", ctypes.c_int), ("mobility_mode", ctypes.c_int), ("xd_norm", ctypes.c_int),
         ("mass_projection", ctypes.c_int), ("log_energy", ctypes.c_int), ("ilu_shift", ctypes.c_double),
+        ("subsolver", ctypes.c_int), ("fill_level", ctypes.c_int),
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p),
     ]
 
@@ -154,6 +155,7 @@ _BC = {"periodic": 0, "neumann": 1}
 _SCHWARZ = {"left": 0, "right": 1, "classical": 2}
 _PREC = {"fp64": 0, "mixed": 1}
 _MOB = {"midpoint": 0, "average": 1, "explicit": 2}
+_SUBSOLVER = {"ilu0": 0, "iluk": 1, "lu": 2}
 
 
 def make_params(shape: Sequence[int], *, bc="periodic", L=(1.0, 1.0), alpha=1.2, beta=1.2, theta=0.1,
@@ -161,7 +163,7 @@ def make_params(shape: Sequence[int], *, bc="periodic", L=(1.0, 1.0), alpha=1.2,
                 newton_rtol=1e-8, newton_atol=1e-13, newton_max_it=50, gmres_rtol=1e-8, gmres_atol=1e-14,
                 gmres_restart=30, gmres_max_restarts=10, sub=(2, 2), overlap=1, ilu_reuse=True,
                 precision="fp64", mobility="midpoint", xd_norm="plain", mass_projection=True,
-                log_energy=True, ilu_shift=0.0, schwarz="left") -> Params:
+                log_energy=True, ilu_shift=0.0, schwarz="left", subsolver="ilu0", fill_level=0) -> Params:
     """acch_params for a 2D field of shape (ny, nx) or a 3D field of shape (nz, ny, nx);
     L and sub are given in x, y[, z] order."""
     p = Params()
@@ -193,6 +195,8 @@ def make_params(shape: Sequence[int], *, bc="periodic", L=(1.0, 1.0), alpha=1.2,
     p.mass_projection = 1 if mass_projection else -1
     p.log_energy = 1 if log_energy else -1
     p.ilu_shift = float(ilu_shift)
+    p.subsolver = _SUBSOLVER[subsolver]
+    p.fill_level = int(fill_level)
     return p
 
 
@@ -397,6 +401,12 @@ class Solver:
 
     def export_boxes(self):
         return self._export(EXPORT_BOXES, np.int32).reshape(-1, 4)
+
+    def export_band(self):
+        """ILU(k) / exact-LU factors [sub][R][d] (include/acch.h, ACCH_EXPORT_BAND)."""
+        i = self.info()
+        n = 2 * i["box_w"] * i["box_h"]
+        return self._export(EXPORT_BAND, np.float64).reshape(i["nsub"], n, 8 * i["box_w"] + 1)
 
 
 class BatchSolver:

@@ -56,6 +56,7 @@ int make_plan(const acch_params *ps, int count, Plan &pl) {
     if (p.dim != 2) return fail(ACCH_EUNSUPPORTED, "batches are 2D");
     if (p.adaptive) return fail(ACCH_EUNSUPPORTED, "batches step at a common fixed dt (adaptive = 0)");
     if (p.ras_type != ACCH_RAS_LEFT) return fail(ACCH_EUNSUPPORTED, "batches use the left-restricted Schwarz variant");
+    if (p.subsolver != ACCH_SUB_ILU0) return fail(ACCH_EUNSUPPORTED, "batches use the ILU(0) subdomain solver");
     if (p.overlap != p0.overlap || p.precision != p0.precision || p.dt_fixed != p0.dt_fixed)
       return fail(ACCH_EINVAL, "instances must share overlap, precision and dt_fixed");
     rc = build_geometry(p, geos[b]);

@@ -1,6 +1,7 @@
 // Host-side launchers of the acch HIP kernels (one stream-ordered launch each).
 #pragma once
 
+#include "band.h"
 #include "common.h"
 
 namespace acch {
@@ -85,6 +86,22 @@ hipError_t launch_ras_apply2d(const BatchLaunch &bl, const BoxGeom &G, const Sub
                               const RasVariant &rv = RasVariant{});
 hipError_t launch_export_factors2d(const BoxGeom &G, const int *lvl, const void *fac, int fp32, double *out,
                                    hipStream_t s);
+// z = sum over the boxes holding each cell of their values in the box buffer (the
+// extension of the right-restricted and classical variants; single instance)
+hipError_t launch_ras_sum2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const void *ybuf, double *z,
+                            const GmresState *st, long vstride, int fp32, hipStream_t s, const RasVariant &rv);
+
+// bandlu2d.hip: the exact-LU / ILU(k) subdomain solvers in band storage (band.h),
+// single instance.  mask: the ILU(k) pattern, n * mwords words per box (null: exact LU).
+hipError_t launch_band_factor2d(const BatchLaunch &bl, const BandGeom &B, int nsub, const SubInfo *subs,
+                                const double *J, double shift, const unsigned *mask, void *band, int fp32,
+                                hipStream_t s);
+// z = M^{-1} r with the band factors; ybox: nchunk * 64 doubles per box; boxbuf: the
+// box buffer of the right-restricted / classical variants (layout of launch_ras_apply2d)
+hipError_t launch_band_apply2d(const BatchLaunch &bl, const BandGeom &B, const BoxGeom &G, const SubInfo *subs,
+                               const void *band, double *ybox, void *boxbuf, const double *r, double *z,
+                               const GmresState *st, long vstride, int fp32, hipStream_t s, const RasVariant &rv);
+hipError_t launch_band_export(const BandGeom &B, int nsub, const void *band, int fp32, double *out, hipStream_t s);
 
 // krylov.hip
 hipError_t launch_gmres_start(const BatchLaunch &bl, const double *F, const double *JS, double *V0, GmresState *st,

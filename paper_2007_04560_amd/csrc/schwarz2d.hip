@@ -823,15 +823,7 @@ hipError_t launch_ras_apply2d(const BatchLaunch &bl, const BoxGeom &G, const Sub
     if (nw == 4) e = apply_impl<double, 4>(bl, G, subs, lvl, fac, ybuf, r, z, dump, st, vstride, kind, s);
   }
   if (e != hipSuccess || kind == ACCH_RAS_LEFT) return e;
-  const Phys &P = bl.P0;
-  const int nb = reduce_blocks((long)P.nx * P.ny);
-  if (fp32)
-    hipLaunchKernelGGL(k_ras_sum2d<float>, dim3(nb), dim3(256), 0, s, G, subs, P.nx, P.ny, P.periodic, rv.px, rv.py,
-                       rv.own_x, rv.own_y, ybuf, z, st, vstride);
-  else
-    hipLaunchKernelGGL(k_ras_sum2d<double>, dim3(nb), dim3(256), 0, s, G, subs, P.nx, P.ny, P.periodic, rv.px, rv.py,
-                       rv.own_x, rv.own_y, ybuf, z, st, vstride);
-  return hipGetLastError();
+  return launch_ras_sum2d(bl, G, subs, ybuf, z, st, vstride, fp32, s, rv);
 }
 
 // M^{-T} r for the three variants: M^{-T} of the left-restricted operator has the
@@ -862,6 +854,11 @@ hipError_t launch_ras_t_apply2d(const BatchLaunch &bl, const BoxGeom &G, const S
     if (nw == 4) e = apply_impl<double, 4, true>(bl, G, subs, lvl, fact, ybuf, r, z, dump, st, vstride, kind, s);
   }
   if (e != hipSuccess || kind == ACCH_RAS_LEFT) return e;
+  return launch_ras_sum2d(bl, G, subs, ybuf, z, st, vstride, fp32, s, rv);
+}
+
+hipError_t launch_ras_sum2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const void *ybuf, double *z,
+                            const GmresState *st, long vstride, int fp32, hipStream_t s, const RasVariant &rv) {
   const Phys &P = bl.P0;
   const int nb = reduce_blocks((long)P.nx * P.ny);
   if (fp32)

@@ -9,6 +9,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -35,6 +37,7 @@ struct Layout {
   size_t off_Xn, off_Xprev, off_X, off_Xt, off_F, off_Ft, off_S, off_W;
   size_t off_J, off_V, off_Z, off_fac, off_wfac, off_wfact, off_q3, off_y, off_dump, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
   size_t off_tbox, off_own;
+  size_t off_band, off_bandy, off_mask;   // exact-LU / ILU(k) subdomain solvers (2D)
   size_t total;
 };
 
@@ -84,6 +87,11 @@ struct acch_ctx {
   BatchLaunch bl{};   // single-instance launch shapes
   RasVariant ras{};   // Schwarz variant and owner maps
   bool d3 = false;    // 3D grid
+  bool band = false;  // exact-LU / ILU(k) subdomain solver (band storage)
+  BandGeom bg{};
+  void *bandf = nullptr;        // band factors
+  double *bandy = nullptr;      // forward-sweep values of the band solve
+  unsigned *bandmask = nullptr; // ILU(k) pattern bits (null: exact LU)
 };
 
 // ---------------------------------------------------------------------------
@@ -131,6 +139,17 @@ int acch::validate_params(const acch_params &p) {
   if (p.mobility_mode < 0 || p.mobility_mode > 2) return fail(ACCH_EINVAL, "mobility_mode");
   if (p.overlap < 0) return fail(ACCH_EINVAL, "overlap");
   if (!(p.ilu_shift >= 0.0 && p.ilu_shift < 10.0)) return fail(ACCH_EINVAL, "ilu_shift must be in [0, 10)");
+  if (p.subsolver != ACCH_SUB_ILU0 && p.subsolver != ACCH_SUB_ILUK && p.subsolver != ACCH_SUB_LU)
+    return fail(ACCH_EINVAL, "subsolver");
+  if (p.subsolver == ACCH_SUB_ILUK && (p.fill_level < 1 || p.fill_level > 8))
+    return fail(ACCH_EINVAL, "fill_level must be 1..8 for ILU(k)");
+  if (p.subsolver != ACCH_SUB_ILU0) {
+    if (nd != 2) return fail(ACCH_EUNSUPPORTED, "ILU(k) and exact-LU subdomain solvers are 2D");
+    const int bw = (p.n[0] + p.sub[0] - 1) / p.sub[0] + 2 * p.overlap;
+    if (bw > kBandMaxWidth)
+      return fail(ACCH_EUNSUPPORTED, "ILU(k) / exact-LU subdomain boxes must be at most " +
+                                         std::to_string(kBandMaxWidth) + " cells wide (owned width + 2 overlap)");
+  }
   if (p.adaptive) {
     if (!(p.dt_min > 0 && p.dt_max >= p.dt_min && p.eta0 > 0)) return fail(ACCH_EINVAL, "dt_min, dt_max, eta0");
   } else if (!(p.dt_fixed > 0)) {
@@ -326,20 +345,21 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_S = take(n2);
   L.off_W = take(n2);
   const bool d3 = p.dim == 3;
+  const bool band = p.subsolver != ACCH_SUB_ILU0;
   const int nslot = d3 ? kNSlot3D : kNSlot2D;
   L.off_J = take((size_t)nslot * geo.ncell * sizeof(double));
   L.off_V = take((size_t)(m + 1) * n2);
   L.off_Z = take((size_t)m * n2);
   // 2D: padded wavefront-major cells per box; 3D: box cells
   const size_t slots = d3 ? (size_t)geo.G.ncb : (size_t)geo.G.nlev * geo.G.bh;
-  L.off_fac = take((size_t)geo.G.nsub * nslot * slots * fsz);
+  L.off_fac = take(band ? 0 : (size_t)geo.G.nsub * nslot * slots * fsz);
   // 2D: FT pairs + one dump slot per box; 3D: FP64 pairs
   // (3D: one more pair, where the windowed apply's idle threads write)
   L.off_y = d3 ? take((box3_ypairs(geo.G) + 1) * 2 * sizeof(double))
                : take((size_t)geo.G.nsub * 2 * (slots + 1) * fsz);
   L.off_wfac = take(d3 ? win3d_fac_elems(geo.G) * fsz : 0);
   // transposed records (adjoint): 3D level-major copy, 2D same layout as the factors
-  L.off_wfact = take(d3 ? win3d_fac_elems(geo.G) * fsz : (size_t)geo.G.nsub * nslot * slots * fsz);
+  L.off_wfact = take(d3 ? win3d_fac_elems(geo.G) * fsz : (band ? 0 : (size_t)geo.G.nsub * nslot * slots * fsz));
   L.off_q3 = take(d3 ? (size_t)8 * geo.ncell * sizeof(double) : 0);   // 3D cell quantities
   L.off_dump = take(64 * sizeof(double));
   L.off_subs = take(geo.subs.size() * sizeof(SubInfo));
@@ -351,6 +371,10 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_out = take(64 * sizeof(double));
   L.off_tbox = take(d3 ? (size_t)geo.G.nsub * 2 * geo.G.ncb * sizeof(double) : 0);   // 3D transposed boxes
   L.off_own = take(geo.own.size() * sizeof(int));
+  const BandGeom B = make_band_geom(geo.G.bw, geo.G.bh);
+  L.off_band = take(band ? (size_t)geo.G.nsub * B.box_elems * fsz : 0);
+  L.off_bandy = take(band ? (size_t)geo.G.nsub * B.nchunk * 64 * sizeof(double) : 0);
+  L.off_mask = take(p.subsolver == ACCH_SUB_ILUK ? (size_t)geo.G.nsub * B.n * B.mwords * sizeof(unsigned) : 0);
   L.total = o;
 }
 
@@ -375,6 +399,81 @@ static bool admissible_host(const double *u, const double *v, long n) {
     if (!(pp > 0.0 && pp < 1.0 && q > 0.0 && q < 1.0)) return false;
   }
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// ILU(k) pattern of a box matrix (band.h numbering): symbolic elimination with
+// levels of fill.  Entries of A_k have level 0; eliminating pivot p from row R gives
+// entry (R, C), C > p, the level lev(R, p) + lev(p, C) + 1 (the smallest over the
+// pivots); entries of level above k are dropped.  Rows are processed in order and the
+// pivots of a row in increasing column order, fill of the same row included.  Cells
+// of the padded box outside the rectangle [ilo, ihi) x [jlo, jhi) are identity rows.
+// Bit d of word d / 32 of row R is set for entry (R, R + d - kl).
+// ---------------------------------------------------------------------------
+static void iluk_pattern(const BandGeom &B, int ilo, int ihi, int jlo, int jhi, int k, unsigned *bits) {
+  static const int kSl[24][4] = {{0, 0, 0, 0},  {0, 0, -1, 0}, {0, 0, 1, 0},  {0, 0, 0, -1}, {0, 0, 0, 1},
+                                 {0, 0, -2, 0}, {0, 0, 2, 0},  {0, 0, 0, -2}, {0, 0, 0, 2},  {0, 0, -1, -1},
+                                 {0, 0, 1, -1}, {0, 0, -1, 1}, {0, 0, 1, 1},  {0, 1, 0, 0},  {0, 1, -1, 0},
+                                 {0, 1, 1, 0},  {0, 1, 0, -1}, {0, 1, 0, 1},  {1, 1, 0, 0},  {1, 1, -1, 0},
+                                 {1, 1, 1, 0},  {1, 1, 0, -1}, {1, 1, 0, 1},  {1, 0, 0, 0}};
+  const int n = B.n, bw = B.bw;
+  auto inside = [&](int i, int j) { return i >= ilo && i < ihi && j >= jlo && j < jhi; };
+  std::vector<std::vector<std::pair<int, int>>> upper(n);   // (column, level) right of the diagonal
+  std::vector<int> lev(n, -1), cols;
+  std::vector<char> queued(n, 0);
+  std::memset(bits, 0, sizeof(unsigned) * (size_t)n * B.mwords);
+  for (int R = 0; R < n; ++R) {
+    cols.clear();
+    const int c = R >> 1, t = R & 1, j = c / bw, i = c - j * bw;
+    auto add = [&](int C, int l) {
+      lev[C] = l;
+      cols.push_back(C);
+    };
+    if (inside(i, j)) {
+      for (const auto &q : kSl) {
+        if (q[0] != t || !inside(i + q[2], j + q[3])) continue;
+        add(2 * ((j + q[3]) * bw + i + q[2]) + q[1], 0);
+      }
+    } else {
+      add(R, 0);
+    }
+    // pivots of the row in increasing order (a min-heap; a column enters it once)
+    std::vector<int> heap;
+    for (int C : cols)
+      if (C < R) {
+        heap.push_back(C);
+        queued[C] = 1;
+      }
+    std::make_heap(heap.begin(), heap.end(), std::greater<int>());
+    while (!heap.empty()) {
+      std::pop_heap(heap.begin(), heap.end(), std::greater<int>());
+      const int p = heap.back();
+      heap.pop_back();
+      for (const auto &e : upper[p]) {
+        const int nl = lev[p] + e.second + 1;
+        if (nl > k) continue;
+        const int C = e.first;
+        if (lev[C] < 0) {
+          add(C, nl);
+          if (C < R && !queued[C]) {
+            heap.push_back(C);
+            std::push_heap(heap.begin(), heap.end(), std::greater<int>());
+            queued[C] = 1;
+          }
+        } else if (nl < lev[C]) {
+          lev[C] = nl;
+        }
+      }
+    }
+    for (int C : cols) {
+      const int d = C - R + B.kl;
+      bits[(size_t)R * B.mwords + (d >> 5)] |= 1u << (d & 31);
+      if (C > R) upper[R].push_back({C, lev[C]});
+      lev[C] = -1;
+      queued[C] = 0;
+    }
+    std::sort(upper[R].begin(), upper[R].end());
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -459,6 +558,10 @@ hipError_t run_energy(acch_ctx *c, const double *X) {
 }
 hipError_t run_factor(acch_ctx *c) {
   c->tpacked = false;
+  if (c->band)
+    return launch_band_factor2d(c->bl, c->bg, c->geo.G.nsub, c->d_subs, c->J,
+                                c->p.subsolver == ACCH_SUB_LU ? 0.0 : c->p.ilu_shift, c->bandmask, c->bandf,
+                                fp32_of(c), c->stream);
   if (c->d3)
     return launch_ilu_factor3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->J, c->p.ilu_shift, c->fac,
                                c->wfac, fp32_of(c), c->stream);
@@ -466,6 +569,9 @@ hipError_t run_factor(acch_ctx *c) {
                              c->stream);
 }
 hipError_t run_ras(acch_ctx *c, const double *r, double *z, const GmresState *st, long vs) {
+  if (c->band)
+    return launch_band_apply2d(c->bl, c->bg, c->geo.G, c->d_subs, c->bandf, c->bandy, c->ybuf, r, z, st, vs,
+                               fp32_of(c), c->stream, c->ras);
   if (c->d3)
     return launch_ras_apply3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->fac, c->wfac, c->ybuf, r, z,
                               st, vs, fp32_of(c), c->stream);
@@ -726,6 +832,42 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->ras.kind = p.ras_type;
   c->ras.px = p.sub[0];
   c->ras.py = p.sub[1];
+  c->band = p.subsolver != ACCH_SUB_ILU0;
+  std::vector<unsigned> maskh;
+  if (c->band) {
+    c->bg = make_band_geom(c->geo.G.bw, c->geo.G.bh);
+    c->bandf = c->ws + L.off_band;
+    c->bandy = (double *)(c->ws + L.off_bandy);
+    if (p.subsolver == ACCH_SUB_ILUK) {
+      c->bandmask = (unsigned *)(c->ws + L.off_mask);
+      // one pattern per distinct rectangle of grid cells inside the padded box
+      const size_t per = (size_t)c->bg.n * c->bg.mwords;
+      maskh.resize(per * c->geo.G.nsub);
+      std::vector<std::vector<int>> keys;
+      std::vector<size_t> first;
+      for (int b = 0; b < c->geo.G.nsub; ++b) {
+        const SubInfo &si = c->geo.subs[b];
+        int ilo = 0, jlo = 0, ihi = std::min(c->bg.bw, si.ex), jhi = std::min(c->bg.bh, si.ey);
+        if (p.bc != ACCH_BC_PERIODIC) {
+          ilo = std::max(ilo, -si.ox);
+          jlo = std::max(jlo, -si.oy);
+          ihi = std::min(ihi, p.n[0] - si.ox);
+          jhi = std::min(jhi, p.n[1] - si.oy);
+        }
+        const std::vector<int> key = {ilo, ihi, jlo, jhi};
+        size_t at = keys.size();
+        for (size_t q = 0; q < keys.size(); ++q)
+          if (keys[q] == key) at = q;
+        if (at == keys.size()) {
+          keys.push_back(key);
+          first.push_back((size_t)b);
+          iluk_pattern(c->bg, ilo, ihi, jlo, jhi, p.fill_level, maskh.data() + per * b);
+        } else {
+          std::memcpy(maskh.data() + per * b, maskh.data() + per * first[at], per * sizeof(unsigned));
+        }
+      }
+    }
+  }
   if (hipHostMalloc((void **)&c->host, sizeof(GmresState) + sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) {
     delete c;
     return fail(ACCH_EDEVICE, "hipHostMalloc failed");
@@ -749,6 +891,8 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
                      c->stream) != hipSuccess ||
       hipMemsetAsync(c->red.counter, 0, 64, c->stream) != hipSuccess ||
       hipMemsetAsync(c->st, 0, sizeof(GmresState), c->stream) != hipSuccess ||
+      (!maskh.empty() && hipMemcpyAsync(c->bandmask, maskh.data(), maskh.size() * sizeof(unsigned),
+                                        hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return cleanup(fail(ACCH_EDEVICE, "initial upload failed"));
   *out = c;
@@ -972,6 +1116,7 @@ extern "C" int acch_apply_jacobian_transpose(acch_ctx *c, const double *x, doubl
 }
 
 static int adjoint_ready(acch_ctx *c) {
+  if (c->band) return fail(ACCH_EUNSUPPORTED, "the transposed Schwarz operator uses the ILU(0) subdomain solver");
   if (c->p.overlap > c->geo.min_part)
     return fail(ACCH_EUNSUPPORTED, "transposed Schwarz operator needs overlap <= the smallest subdomain width");
   return ACCH_OK;
@@ -1058,6 +1203,7 @@ extern "C" int acch_export(acch_ctx *c, int which, void *out, size_t *bytes) {
   if (which == ACCH_EXPORT_JACOBIAN) need = (size_t)nslot * c->geo.ncell * sizeof(double);
   else if (which == ACCH_EXPORT_FACTORS) need = (size_t)G.nsub * nslot * G.ncb * sizeof(double);
   else if (which == ACCH_EXPORT_BOXES) need = (size_t)G.nsub * 4 * sizeof(int);
+  else if (which == ACCH_EXPORT_BAND && c->band) need = (size_t)G.nsub * c->bg.n * c->bg.nd * sizeof(double);
   else return fail(ACCH_EINVAL, "unknown export");
   if (!out) {
     *bytes = need;
@@ -1066,8 +1212,12 @@ extern "C" int acch_export(acch_ctx *c, int which, void *out, size_t *bytes) {
   if (*bytes < need) return fail(ACCH_EINVAL, "output buffer too small");
   if (which == ACCH_EXPORT_JACOBIAN) {
     HIP_TRY(hipMemcpyAsync(out, c->J, need, hipMemcpyDeviceToDevice, c->stream));
+  } else if (which == ACCH_EXPORT_BAND) {
+    if (!c->factored) return fail(ACCH_EINVAL, "no factorisation");
+    LAUNCH(c, launch_band_export(c->bg, G.nsub, c->bandf, c->p.precision == ACCH_PREC_MIXED, (double *)out, c->stream));
   } else if (which == ACCH_EXPORT_FACTORS) {
     if (!c->factored) return fail(ACCH_EINVAL, "no factorisation");
+    if (c->band) return fail(ACCH_EINVAL, "the factors of ILU(k) / exact LU are exported by ACCH_EXPORT_BAND");
     if (c->d3)
       LAUNCH(c, launch_export_factors3d(G, c->fac, c->p.precision == ACCH_PREC_MIXED, (double *)out, c->stream));
     else
