@@ -207,6 +207,19 @@ int acch_solve_step(acch_ctx *c, double dt, acch_step_info *info);
 enum { ACCH_EXPORT_JACOBIAN = 0, ACCH_EXPORT_FACTORS = 1, ACCH_EXPORT_BOXES = 2, ACCH_EXPORT_BAND = 3 };
 int acch_export(acch_ctx *c, int which, void *out, size_t *bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): acch_residual without a
+ * context or workspace.  p describes the grid and the coefficients (dim 2; of the
+ * device fields only p->stream is used, NULL = default stream); X, Xn and F are
+ * device state vectors of 2*nx*ny doubles owned by the caller.  F receives F(X; Xn, dt),
+ * *fnorm2 and *inadmissible (host, may be NULL) as for acch_residual.  The norm's block
+ * partials and result live in a static 1 MiB device array of the library (one per
+ * GPU, held until the process ends), so grids of more than 65504 tiles of 32 x 8
+ * cells (about 16.7 M cells) are rejected with ACCH_EINVAL before any device work.
+ * Calls that overlap on one GPU race on that array.  Synchronises p->stream. */
+int acch_residual_noalloc(const acch_params *p, const double *X, const double *Xn, double dt, double *F,
+                          double *fnorm2, int *inadmissible);
+
 /* Number of cells and of subdomains, the padded box size, and the kernel-launch
  * statistics of the last acch_step call (launches, host synchronisations). */
 int acch_info(acch_ctx *c, long *ncell, int *nsub, int *box_w, int *box_h);

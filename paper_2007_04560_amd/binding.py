@@ -27,7 +27,7 @@ EXPORTED = [
     "acch_apply_jacobian_transpose", "acch_precondition_transpose", "acch_energy_gradient", "acch_adjoint_step",
     "acch_batch_workspace_bytes", "acch_batch_create", "acch_batch_step", "acch_batch_energy",
     "acch_batch_get_fields", "acch_batch_set_option", "acch_batch_counters", "acch_batch_destroy",
-    "acch_batch_precondition", "acch_batch_info",
+    "acch_batch_precondition", "acch_batch_info", "acch_residual_noalloc",
 ]
 KERNEL_KINDS = ["residual", "jacobian", "factor", "ras", "spmv_dots", "orth", "gmres_start", "gmres_update",
                 "energy", "spmv", "other"]
@@ -95,6 +95,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "acch_set_fields": (ctypes.c_int, [ctx, vp, vp]),
         "acch_get_time": (ctypes.c_int, [ctx, dp, dp, dp]),
         "acch_residual": (ctypes.c_int, [ctx, vp, vp, ctypes.c_double, vp, dp, ip]),
+        "acch_residual_noalloc": (ctypes.c_int, [ctypes.POINTER(Params), vp, vp, ctypes.c_double, vp, dp, ip]),
         "acch_jacobian": (ctypes.c_int, [ctx, vp, vp, ctypes.c_double]),
         "acch_apply_jacobian": (ctypes.c_int, [ctx, vp, vp]),
         "acch_factor": (ctypes.c_int, [ctx]),

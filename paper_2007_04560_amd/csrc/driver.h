@@ -112,6 +112,8 @@ struct LineSearch {
 };
 
 int validate_params(const acch_params &p);
+// The stencil kernels' description of a grid and its coefficients (validated params).
+Phys phys_of(const acch_params &p);
 int build_geometry(const acch_params &p, Geometry &geo);
 
 }  // namespace acch

@@ -273,6 +273,27 @@ static int build_geometry3(const acch_params &p, Geometry &geo) {
   return ACCH_OK;
 }
 
+Phys acch::phys_of(const acch_params &p) {
+  Phys P{};
+  P.nx = p.n[0];
+  P.ny = p.n[1];
+  P.nz = p.dim == 3 ? p.n[2] : 1;
+  P.periodic = p.bc == ACCH_BC_PERIODIC;
+  const double hx = p.L[0] / p.n[0], hy = p.L[1] / p.n[1];
+  const double hz = p.dim == 3 ? p.L[2] / p.n[2] : 1.0;
+  P.wx = 1.0 / (hx * hx);
+  P.wy = 1.0 / (hy * hy);
+  P.wz = p.dim == 3 ? 1.0 / (hz * hz) : 0.0;
+  P.alpha = p.alpha;
+  P.beta = p.beta;
+  P.theta = p.theta;
+  P.gamma = p.gamma;
+  P.rho = p.rho;
+  P.S = p.S;
+  P.mob = p.mobility_mode;
+  return P;
+}
+
 int acch::build_geometry(const acch_params &p, Geometry &geo) {
   if (p.dim == 3) return build_geometry3(p, geo);
   const int nx = p.n[0], ny = p.n[1], d = p.overlap;
@@ -809,24 +830,9 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->red.partials = (double *)(c->ws + L.off_part);
   c->red.counter = (unsigned *)(c->ws + L.off_cnt);
   c->red.out = (double *)(c->ws + L.off_out);
-  c->P.nx = p.n[0];
-  c->P.ny = p.n[1];
-  c->P.nz = p.dim == 3 ? p.n[2] : 1;
-  c->P.periodic = p.bc == ACCH_BC_PERIODIC;
-  const double hx = p.L[0] / p.n[0], hy = p.L[1] / p.n[1];
-  const double hz = p.dim == 3 ? p.L[2] / p.n[2] : 1.0;
-  c->P.wx = 1.0 / (hx * hx);
-  c->P.wy = 1.0 / (hy * hy);
-  c->P.wz = p.dim == 3 ? 1.0 / (hz * hz) : 0.0;
-  c->hvol = hx * hy * hz;
+  c->P = phys_of(p);
+  c->hvol = (p.L[0] / p.n[0]) * (p.L[1] / p.n[1]) * (p.dim == 3 ? p.L[2] / p.n[2] : 1.0);
   c->d3 = p.dim == 3;
-  c->P.alpha = p.alpha;
-  c->P.beta = p.beta;
-  c->P.theta = p.theta;
-  c->P.gamma = p.gamma;
-  c->P.rho = p.rho;
-  c->P.S = p.S;
-  c->P.mob = p.mobility_mode;
   c->eta = p.eta0;
   c->bl = single_launch(c->P, c->geo.G.nsub);
   c->ras.kind = p.ras_type;
