@@ -132,11 +132,19 @@ def subdomain_matrix(J, sub: Subdomain, shape) -> Dict[int, Dict[int, float]]:
     dim = len(shape)
     ncell = int(np.prod(shape))
     J = J.tocsr()
+    J.sort_indices()
     local = {c: i for i, c in enumerate(sub.cells)}
     rows: Dict[int, Dict[int, float]] = {}
     for i, c in enumerate(sub.cells):
         for t in (0, 1):
             rows[2 * i + t] = {}
+
+    def entry(grow, gcol):
+        """J[grow, gcol] (zero when not stored), read from the CSR arrays."""
+        lo, hi = J.indptr[grow], J.indptr[grow + 1]
+        k = lo + int(np.searchsorted(J.indices[lo:hi], gcol))
+        return float(J.data[k]) if k < hi and J.indices[k] == gcol else 0.0
+
     for rt, off, ct in row_pattern(dim):
         for i, c in enumerate(sub.cells):
             nb = tuple(c[a] + off[a] for a in range(dim))
@@ -145,7 +153,7 @@ def subdomain_matrix(J, sub: Subdomain, shape) -> Dict[int, Dict[int, float]]:
                 continue
             grow = int(sub.gcell[i]) + rt * ncell
             gcol = int(sub.gcell[j]) + ct * ncell
-            rows[2 * i + rt][2 * j + ct] = float(J[grow, gcol])
+            rows[2 * i + rt][2 * j + ct] = entry(grow, gcol)
     return rows
 
 

@@ -191,3 +191,45 @@ def test_window_and_box_buffer_applies_agree_at_full_box_size(window):
     set_option("ras3d_window", 1 - window)
     z2 = s.precondition(r).cpu().numpy()
     assert rel(z, z2) <= 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-4)])
+def test_window_apply_on_workload_sized_boxes_matches_oracle(precision, tol):
+    """Boxes of 18^3 cells (16^3 owned, overlap 1): the box of the 128^3 workload's
+    8x8x8 split, on a 32^3 grid split 2x2x2.  M^{-1} r of the windowed apply against the
+    oracle's left-RAS with shifted ILU(0) on the same boxes."""
+    shape = (32, 32, 32)
+    u1, v1, u0, v0 = perturbed_pair(shape, 79, amp=0.03)
+    s = Solver(u0, v0, bc="neumann", sub=(2, 2, 2), overlap=1, ilu_shift=0.02, precision=precision)
+    assert s.info()["box_w"] == 18
+    s.jacobian(dev(vec(u1, v1)), dev(vec(u0, v0)), 2e-3)
+    s.factor()
+    r = np.random.default_rng(14).standard_normal(2 * u1.size)
+    z = s.precondition(dev(r)).cpu().numpy()
+    Jo = jacobian.jacobian(u1, v1, u0, v0, 2e-3, Problem(bc="neumann", lengths=(1.0, 1.0, 1.0)))
+    zo = schwarz.Schwarz(Jo, shape, (2, 2, 2), 1, "neumann", kind="left", shift=0.02).apply(r)
+    if precision == "fp64":
+        assert rel(z, zo) <= tol
+    else:
+        assert np.linalg.norm(z - zo) <= tol * np.linalg.norm(zo)
+
+
+def test_neumann128_3d_first_newton_solve_root():
+    """The 128^3 workload's first time step (dt_min = 1e-4, 8x8x8 subdomains, overlap 1):
+    the GPU's Newton root leaves an oracle residual below 1e-9 of the initial one, and the
+    mass of u is unchanged to 1e-12."""
+    shape = (128, 128, 128)
+    u0, v0 = random_ic(shape, 0)
+    P = Problem(bc="neumann", lengths=(1.0, 1.0, 1.0))
+    with Solver(u0, v0, bc="neumann", sub=(8, 8, 8), overlap=1, ilu_shift=0.02, newton_rtol=1e-11,
+                gmres_rtol=1e-10) as s:
+        info = s.solve_step(1e-4)
+        ug, vg = s.fields()
+    F0u, F0v = scheme.residual(u0, v0, u0, v0, 1e-4, P)
+    Fu, Fv = scheme.residual(ug, vg, u0, v0, 1e-4, P)
+    f0 = np.sqrt(np.sum(F0u ** 2) + np.sum(F0v ** 2))
+    f1 = np.sqrt(np.sum(Fu ** 2) + np.sum(Fv ** 2))
+    assert f1 <= 1e-9 * f0, (f1, f0, info)
+    M0, M1 = scheme.mass(u0, P), scheme.mass(ug, P)
+    assert abs(M1 - M0) <= 1e-12 * M0
+    assert info["newton_its"] >= 2
