@@ -351,6 +351,59 @@ STUDY2D = dict(shape=(128, 128), bc="neumann", sub=(6, 4), dt_fixed=1e-4, steps=
                phys=dict(alpha=4.0, beta=2.0, gamma=0.005, theta=0.1, rho=0.001))
 
 
+STUDY3D = dict(shape=(128, 128, 128), bc="neumann", sub=(8, 8, 8), dt_fixed=1e-4, steps=10, u_mean=0.55, seed=0,
+               newton_rtol=1e-6, newton_atol=1e-13, gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30,
+               phys=dict(alpha=4.0, beta=2.0, gamma=0.005, theta=0.1, rho=0.001))
+
+
+def study3d_line(args):
+    """Table 3's 3D half (128^3 Neumann, 512 subdomains): the Schwarz variants x overlap
+    with ILU(0) (shift 0.02, factored once per step): Newton iterations, GMRES iterations
+    per Newton iteration and time for 10 steps at dt = 1e-4."""
+    import torch
+    from acch_inputs import random_ic
+    from paper_2007_04560_amd import Solver
+    w = STUDY3D
+    u0, v0 = random_ic(w["shape"], w["seed"], u_mean=w["u_mean"])
+    base = dict(bc=w["bc"], sub=w["sub"], dt_fixed=w["dt_fixed"], newton_rtol=w["newton_rtol"],
+                newton_atol=w["newton_atol"], gmres_rtol=w["gmres_rtol"], gmres_atol=w["gmres_atol"],
+                gmres_restart=w["gmres_restart"], ilu_shift=0.02, **w["phys"])
+    table3 = {}
+    for kind in ("classical", "left", "right"):
+        for ov in (0, 1, 2):
+            if kind != "classical" and ov == 0:
+                continue
+            try:
+                s = Solver(u0, v0, schwarz=kind, overlap=ov, **base)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                recs = s.step(w["steps"])
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                s.close()
+                nit = sum(int(x["newton_its"]) for x in recs)
+                git = sum(int(x["gmres_its"]) for x in recs)
+                table3[f"{kind} overlap {ov}"] = {"newton": nit, "gmres_per_newton": round(git / max(nit, 1), 2),
+                                                  "seconds": round(el, 4)}
+            except Exception as e:
+                table3[f"{kind} overlap {ov}"] = {"failed": str(e)[:160]}
+            print(json.dumps({"study3d": kind, "overlap": ov, **table3[f"{kind} overlap {ov}"]}), file=sys.stderr,
+                  flush=True)
+    best = table3.get("left overlap 1", {})
+    line = {"metric": "time of the first 10 steps (paper's 3D solver study)", "value": best.get("seconds"),
+            "unit": "s", "n_gpus": 1, "steps": w["steps"], "warmup": 0,
+            "ms_per_step": round(best["seconds"] / w["steps"] * 1e3, 3) if "seconds" in best else None,
+            "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "study3d: 3D Neumann 128^3, alpha 4, beta 2, gamma 5e-3, theta 0.1, rho 1e-3, "
+                                   "u0 = 0.55 + 0.05 U(-1,1), 10 steps dt = 1e-4, Newton eps_r 1e-6, GMRES(30) "
+                                   "xi_r 1e-8, 8x8x8 subdomains, ILU(0) shift 0.02 reuse; value = left-RAS overlap 1",
+                       "table3_ilu0_reuse": table3},
+            "roofline": None}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def study_line(args):
     """Table 2 (subdomain solvers under classical AS, overlap 1, with and without the
     factor reuse) and Table 3 (Schwarz variants x overlap, ILU(0) reuse) on one GPU:
@@ -446,7 +499,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP-event timers")
     ap.add_argument("--workload", default="periodic512",
-                    choices=sorted(WORKLOADS) + ["batch96", "adjoint512", "adjoint3d128", "study2d"])
+                    choices=sorted(WORKLOADS) + ["batch96", "adjoint512", "adjoint3d128", "study2d", "study3d"])
     ap.add_argument("--no-sequential", action="store_true", help="batch96: skip the one-by-one FP64 comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 64 MiB FP64 tensor 3 times (reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -470,11 +523,11 @@ def main():
         if args.steps is None:
             args.steps = 20
         return adjoint_line(args, WORKLOADS["periodic512" if args.workload == "adjoint512" else "neumann128_3d"])
-    if args.workload == "study2d":
+    if args.workload in ("study2d", "study3d"):
         if args.gpus != 1:
             print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
             return 2
-        return study_line(args)
+        return study_line(args) if args.workload == "study2d" else study3d_line(args)
     if args.workload == "batch96":
         if args.gpus != 1:
             print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)

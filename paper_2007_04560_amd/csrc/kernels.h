@@ -77,8 +77,8 @@ hipError_t launch_ilu_factor2d(const BatchLaunch &bl, const BoxGeom &G, const Su
 // add whole boxes and need the owner maps (single-instance launches only).
 struct RasVariant {
   int kind = 0;
-  const int *own_x = nullptr, *own_y = nullptr;
-  int px = 0, py = 0;
+  const int *own_x = nullptr, *own_y = nullptr;   // 3D: own_x is the whole x | y | z owner map
+  int px = 0, py = 0, pz = 1;
 };
 hipError_t launch_ras_apply2d(const BatchLaunch &bl, const BoxGeom &G, const SubInfo *subs, const int *lvl,
                               const void *fac, void *ybuf, const double *r, double *z, double *dump,
@@ -153,9 +153,11 @@ hipError_t launch_energy_grad3d(const Phys &P, const double *X, double vol, doub
 // wfac (may be null): also fill the level-major copy of the windowed apply
 hipError_t launch_ilu_factor3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
                                const double *J, double shift, void *fac, void *wfac, int fp32, hipStream_t s);
+// rv: the Schwarz variant; right-restricted and classical run the box-buffer sweeps and
+// sum the boxes of each cell (owner maps in rv.own_x: x, then y, then z)
 hipError_t launch_ras_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
                               const void *fac, const void *wfac, void *ybuf, const double *r, double *z,
-                              const GmresState *st, long vstride, int fp32, hipStream_t s);
+                              const GmresState *st, long vstride, int fp32, hipStream_t s, const RasVariant &rv);
 // wfact (may be null): transposed-record copy of the windowed form, filled from fac
 // unless *packed (set once filled); tbox: 2 ncb doubles per box
 hipError_t launch_ras_t_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl,

@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void k_ras_apply3d(Phys P, BoxGeom G, const Su
                                                      const int *__restrict__ lvl, const int *__restrict__ cells,
                                                      const FT *__restrict__ fac, double2 *__restrict__ ybuf,
                                                      const double *__restrict__ r, double *__restrict__ z,
-                                                     const GmresState *st, long vstride) {
+                                                     const GmresState *st, long vstride, int kind) {
   double sc = 1.0;
   if (st) {
     if (st->done) return;
@@ -356,7 +356,9 @@ __global__ __launch_bounds__(256) void k_ras_apply3d(Phys P, BoxGeom G, const Su
     int i, j, k;
     decode(e, B, i, j, k);
     const long g = box3_to_global(si, i, j, k, P);
-    yb[e] = g >= 0 ? make_double2(sc * r[g], sc * r[n + g]) : make_double2(0.0, 0.0);
+    // the right-restricted variant restricts the input to the owned cells
+    const bool take = g >= 0 && (kind != ACCH_RAS_RIGHT || owned3(si, i, j, k));
+    yb[e] = take ? make_double2(sc * r[g], sc * r[n + g]) : make_double2(0.0, 0.0);
   }
   __syncthreads();
   // L y = R r
@@ -421,6 +423,9 @@ __global__ __launch_bounds__(256) void k_ras_apply3d(Phys P, BoxGeom G, const Su
     }
     __syncthreads();
   }
+  // right-restricted / classical: the whole box stays in the box buffer and is summed
+  // over the boxes of each cell by k_ras_t_gather3d
+  if (kind != ACCH_RAS_LEFT) return;
   for (int e = threadIdx.x; e < G.ncb; e += blockDim.x) {
     int i, j, k;
     decode(e, B, i, j, k);
@@ -1150,16 +1155,23 @@ void set_ras3d_window(bool on) { g_ras3d_window = on; }
 
 hipError_t launch_ras_apply3d(const Phys &P, const BoxGeom &G, const SubInfo *subs, const int *lvl, const int *cells,
                               const void *fac, const void *wfac, void *ybuf, const double *r, double *z,
-                              const GmresState *st, long vstride, int fp32, hipStream_t s) {
-  if (fp32 ? ras_apply3d_win<float>(P, G, subs, cells, wfac, ybuf, r, z, st, vstride, s)
-           : ras_apply3d_win<double>(P, G, subs, cells, wfac, ybuf, r, z, st, vstride, s))
+                              const GmresState *st, long vstride, int fp32, hipStream_t s, const RasVariant &rv) {
+  const int kind = rv.kind;
+  if (kind != ACCH_RAS_LEFT && !rv.own_x) return hipErrorInvalidValue;
+  if (kind == ACCH_RAS_LEFT && (fp32 ? ras_apply3d_win<float>(P, G, subs, cells, wfac, ybuf, r, z, st, vstride, s)
+                                     : ras_apply3d_win<double>(P, G, subs, cells, wfac, ybuf, r, z, st, vstride, s)))
     return hipGetLastError();
   if (fp32)
     hipLaunchKernelGGL(k_ras_apply3d<float>, dim3(G.nsub), dim3(256), 0, s, P, G, subs, lvl, cells,
-                       (const float *)fac, (double2 *)ybuf, r, z, st, vstride);
+                       (const float *)fac, (double2 *)ybuf, r, z, st, vstride, kind);
   else
     hipLaunchKernelGGL(k_ras_apply3d<double>, dim3(G.nsub), dim3(256), 0, s, P, G, subs, lvl, cells,
-                       (const double *)fac, (double2 *)ybuf, r, z, st, vstride);
+                       (const double *)fac, (double2 *)ybuf, r, z, st, vstride, kind);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || kind == ACCH_RAS_LEFT) return e;
+  const int nb = reduce_blocks((long)P.nx * P.ny * P.nz);
+  hipLaunchKernelGGL(k_ras_t_gather3d, dim3(nb), dim3(256), 0, s, P, G, subs, rv.px, rv.py, rv.pz, rv.own_x,
+                     (const double2 *)ybuf, z, st, vstride);
   return hipGetLastError();
 }
 

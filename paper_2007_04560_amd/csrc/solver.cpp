@@ -127,8 +127,6 @@ int acch::validate_params(const acch_params &p) {
   for (int d = 0; d < nd; ++d)
     if (p.bc == ACCH_BC_PERIODIC && p.n[d] < 5)
       return fail(ACCH_EINVAL, "periodic grids need at least 5 cells per direction");
-  if (nd == 3 && p.ras_type != ACCH_RAS_LEFT)
-    return fail(ACCH_EUNSUPPORTED, "3D runs use the left-restricted Schwarz variant");
   if (!(p.alpha > 0 && p.beta > 0 && p.theta > 0 && p.gamma > 0 && p.rho > 0))
     return fail(ACCH_EINVAL, "alpha, beta, theta, gamma, rho must be positive");
   if (p.S < 1 || p.S > kMaxS) return fail(ACCH_EINVAL, "S out of range");
@@ -595,7 +593,7 @@ hipError_t run_ras(acch_ctx *c, const double *r, double *z, const GmresState *st
                                fp32_of(c), c->stream, c->ras);
   if (c->d3)
     return launch_ras_apply3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->fac, c->wfac, c->ybuf, r, z,
-                              st, vs, fp32_of(c), c->stream);
+                              st, vs, fp32_of(c), c->stream, c->ras);
   return launch_ras_apply2d(c->bl, c->geo.G, c->d_subs, c->d_lvl, c->fac, c->ybuf, r, z, c->dump, st, vs, fp32_of(c),
                             c->stream, c->ras);
 }
@@ -838,6 +836,7 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->ras.kind = p.ras_type;
   c->ras.px = p.sub[0];
   c->ras.py = p.sub[1];
+  c->ras.pz = p.dim == 3 ? p.sub[2] : 1;
   c->band = p.subsolver != ACCH_SUB_ILU0;
   std::vector<unsigned> maskh;
   if (c->band) {
@@ -1122,6 +1121,8 @@ extern "C" int acch_apply_jacobian_transpose(acch_ctx *c, const double *x, doubl
 }
 
 static int adjoint_ready(acch_ctx *c) {
+  if (c->d3 && c->p.ras_type != ACCH_RAS_LEFT)
+    return fail(ACCH_EUNSUPPORTED, "the 3D transposed Schwarz operator is built for the left-restricted variant");
   if (c->band) return fail(ACCH_EUNSUPPORTED, "the transposed Schwarz operator uses the ILU(0) subdomain solver");
   if (c->p.overlap > c->geo.min_part)
     return fail(ACCH_EUNSUPPORTED, "transposed Schwarz operator needs overlap <= the smallest subdomain width");
