@@ -152,9 +152,10 @@ def run_gpu(steps: int, warmup: int, timing: bool, w=None):
     launches, syncs = s.counters()
     info = s.info()
     E1, M1 = s.energy()
+    fields = s.fields()
     s.close()
     return dict(elapsed=t1 - t0, recs=recs, stats=stats, info=info, launches=launches, syncs=syncs,
-                E0=E0, E1=E1, M0=M0, M1=M1, ncell=u0.size)
+                E0=E0, E1=E1, M0=M0, M1=M1, ncell=u0.size, fields=fields)
 
 
 def batch_inputs():
@@ -491,12 +492,72 @@ def cpu_baseline(budget_s: float = 20.0):
                       f"SuperLU and NumPy single-threaded, host has {os.cpu_count()} logical CPUs"}
 
 
+def _rel_l2(a, b):
+    import numpy as np
+    return float(np.sqrt(np.sum((a[0] - b[0]) ** 2 + (a[1] - b[1]) ** 2) / np.sum(b[0] ** 2 + b[1] ** 2)))
+
+
+def forms_summary(args, w, fp64_run):
+    """The chosen forms next to the plain FP64 run: (1) mixed precision on the same
+    workload (time, speedup, final-field difference to the FP64 run), (2) the batched
+    workload (batched FP64 and mixed against the instances solved one by one), and the
+    error of the GPU's FP64 and mixed results against the FP64 oracle on the 64 x 64
+    periodic workload (10 steps at dt = 1e-3, both sides at Newton tolerance 1e-8)."""
+    import numpy as np
+    from acch_inputs import random_ic
+    from oracle import controller, newton, scheme
+    from oracle.params import Problem
+    from paper_2007_04560_amd import Solver
+    out = {}
+    wm = dict(w)
+    wm["precision"] = "mixed"
+    rm = run_gpu(args.steps, 0, timing=False, w=wm)
+    nm = sum(int(x["newton_its"]) for x in rm["recs"])
+    out["mixed"] = {"seconds": round(rm["elapsed"], 4), "fp64_seconds": round(fp64_run["elapsed"], 4),
+                    "value": round(2 * rm["ncell"] * nm / rm["elapsed"], 1),
+                    "speedup_vs_fp64": round(fp64_run["elapsed"] / rm["elapsed"], 3),
+                    "newton_its": nm, "gmres_its": sum(int(x["gmres_its"]) for x in rm["recs"]),
+                    "final_fields_rel_l2_vs_fp64": _rel_l2(rm["fields"], fp64_run["fields"]),
+                    "mass_drift_rel": abs(rm["M1"] - rm["M0"]) / rm["M0"]}
+    b = run_batch(BATCH["steps"], 1, with_sequential=True)
+    out["batched"] = {"workload": BATCH["text"], "batched_fp64_s": round(b["fp64"]["elapsed"], 4),
+                      "batched_mixed_s": round(b["mixed"]["elapsed"], 4),
+                      "sequential_fp64_s": round(b["sequential"]["elapsed"], 4),
+                      "speedup_batched_vs_sequential": round(b["sequential"]["elapsed"] / b["fp64"]["elapsed"], 3),
+                      "speedup_mixed_batched_vs_sequential": round(b["sequential"]["elapsed"] / b["mixed"]["elapsed"],
+                                                                   3),
+                      "value_fp64": round(b["fp64"]["dof_newton"] / b["fp64"]["elapsed"], 1)}
+    shape = (64, 64)
+    u0, v0 = random_ic(shape, 0)
+    P = Problem(bc="periodic")
+    run = controller.Run(P, u0.copy(), v0.copy(), adaptive=False, dt_fixed=1e-3,
+                         newton=newton.NewtonOptions(rtol=1e-8, atol=1e-13))
+    ref = []
+    for _ in range(10):
+        run.step()
+        ref.append((run.u.copy(), run.v.copy()))
+    M0 = scheme.mass(u0, P)
+    par = {}
+    for prec in ("fp64", "mixed"):
+        with Solver(u0, v0, bc="periodic", sub=(2, 2), overlap=1, dt_fixed=1e-3, precision=prec) as s:
+            errs, drift = [], 0.0
+            for k in range(10):
+                info = s.step(1)[0]
+                errs.append(_rel_l2(s.fields(), ref[k]))
+                drift = max(drift, abs(info["mass"] - M0) / M0)
+        par[prec] = {"max_step_rel_l2_vs_oracle": max(errs), "mass_drift_rel": drift}
+    out["error_vs_oracle_64x64"] = par
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="default: the workload's step count")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="default workload: skip the mixed-precision, batched and 64x64 oracle comparisons")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP-event timers")
     ap.add_argument("--workload", default="periodic512",
                     choices=sorted(WORKLOADS) + ["batch96", "adjoint512", "adjoint3d128", "study2d", "study3d"])
@@ -616,6 +677,8 @@ def main():
         fixed = recs[-1]["t"] / w["dt_min"]
         line["config"]["fixed_dt_min_steps"] = round(fixed)
         line["config"]["adaptive_step_saving"] = round(1.0 - len(recs) / fixed, 4)
+    if not args.no_forms and args.workload == "periodic512" and w["precision"] == "fp64":
+        line["config"]["forms"] = forms_summary(args, w, r)
     if not args.no_cpu_baseline and args.workload == "periodic512":
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
