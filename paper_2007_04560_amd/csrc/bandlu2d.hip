@@ -146,6 +146,37 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
       m[p] |= inpat(R, C) ? (1u << q) : 0u;
     }
   }
+  // Rows and columns enter the window kPf steps after their loads are issued: the
+  // thread row (column) of the slot freed at step kk is kk mod 16, so a thread has at
+  // most one pending row and one pending column (kPf < 16).
+  constexpr int kPf = 8;
+  double prow[NR], pcol[NR];
+  unsigned pmrow = 0, pmcol = 0;
+  // row or column held by slot s after step kk
+  auto held_after = [&](int kk, int s) {
+    const int kw = kk % W;
+    return s == kw ? kk + W : kk + (s > kw ? s - kw : s - kw + W);
+  };
+  auto issue_row = [&](int kk) {   // row kk + W at the columns this thread owns after step kk
+    pmrow = 0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int C = held_after(kk, tx + 16 * q);
+      prow[q] = orig(kk + W, C);
+      pmrow |= inpat(kk + W, C) ? (1u << q) : 0u;
+    }
+  };
+  auto issue_col = [&](int kk) {   // column kk + W at the rows this thread owns after step kk
+    pmcol = 0;
+#pragma unroll
+    for (int p = 0; p < NR; ++p) {
+      const int R = held_after(kk, ty + 16 * p);
+      pcol[p] = orig(R, kk + W);
+      pmcol |= inpat(R, kk + W) ? (1u << p) : 0u;
+    }
+  };
+  if (ty < kPf) issue_row(ty);
+  if (tx < kPf) issue_col(tx);
   __syncthreads();
 
   int ks = 0;   // window slot of the pivot row and column: k mod W
@@ -204,36 +235,31 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
         if (off >= 1 && off <= kl && k + off < n) Bk[band_at(B, k + off, kl - off)] = (FT)l[p];
       }
     }
-    // slot ks takes row k + W and column k + W; the other slots keep theirs
-    const int knew = k + W;
+    // slot ks takes row k + W and column k + W (loaded kPf steps ahead); the other
+    // slots keep theirs
     if (ty == tr) {
 #pragma unroll
       for (int p = 0; p < NR; ++p)
         if (p == pr) {
-          m[p] = 0;
 #pragma unroll
-          for (int q = 0; q < NR; ++q) {
-            const int s = tx + 16 * q;
-            const int C = s == ks ? knew : k + (s > ks ? s - ks : s - ks + W);
-            a[p][q] = orig(knew, C);
-            m[p] |= inpat(knew, C) ? (1u << q) : 0u;
-          }
+          for (int q = 0; q < NR; ++q) a[p][q] = prow[q];
+          m[p] = pmrow;
         }
     }
     if (tx == tr) {
 #pragma unroll
-      for (int p = 0; p < NR; ++p) {
-        const int s = ty + 16 * p;
-        const int R = s == ks ? knew : k + (s > ks ? s - ks : s - ks + W);
-        const double v = orig(R, knew);
-        const bool b = inpat(R, knew);
+      for (int p = 0; p < NR; ++p)
 #pragma unroll
         for (int q = 0; q < NR; ++q)
           if (q == pr) {
-            a[p][q] = v;
-            m[p] = (m[p] & ~(1u << q)) | (b ? (1u << q) : 0u);
+            a[p][q] = pcol[p];
+            m[p] = (m[p] & ~(1u << q)) | (((pmcol >> p) & 1u) << q);
           }
-      }
+    }
+    {
+      const int kk = k + kPf;
+      if (ty == (kk & 15)) issue_row(kk);
+      if (tx == (kk & 15)) issue_col(kk);
     }
     ks = ks + 1 == W ? 0 : ks + 1;
   }
@@ -248,6 +274,28 @@ ACCH_DEV double bcast(double v, int s) {
 }
 
 constexpr int kRing = 512;   // finished values kept for the band (kl + 64 <= kRing)
+constexpr int kBatch = 16;   // band coefficients loaded together by a solve sweep
+
+// use(dp, load(dp)) for dp = 1..kl in order, the loads issued kBatch at a time with the
+// next batch in flight while the current one is used (loads past kl read dp = kl again)
+template <typename Load, typename Use>
+ACCH_DEV void sweep_batches(int kl, Load &&load, Use &&use) {
+  double cur[kBatch], nxt[kBatch];
+#pragma unroll
+  for (int u = 0; u < kBatch; ++u) cur[u] = (double)load(min(1 + u, kl));
+  for (int d0 = 1; d0 <= kl; d0 += 2 * kBatch) {
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) nxt[u] = (double)load(min(d0 + kBatch + u, kl));
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (d0 + u <= kl) use(d0 + u, cur[u]);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) cur[u] = (double)load(min(d0 + 2 * kBatch + u, kl));
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (d0 + kBatch + u <= kl) use(d0 + kBatch + u, nxt[u]);
+  }
+}
 
 template <typename FT>
 __global__ __launch_bounds__(64) void k_band_solve2d(Phys P, BandGeom B, BoxGeom G, const SubInfo *__restrict__ subs,
@@ -292,12 +340,12 @@ __global__ __launch_bounds__(64) void k_band_solve2d(Phys P, BandGeom B, BoxGeom
     const long g = cell_of(R, own);
     double acc = (g >= 0 && (kind != ACCH_RAS_RIGHT || own)) ? sc * r[g + (R & 1) * n] : 0.0;
     const FT *Lc = Bk + (long)c * nd * 64 + lane;
-#pragma unroll 8
-    for (int dp = 1; dp <= kl; ++dp) {
-      const double coef = (double)Lc[(long)(kl - dp) * 64];
+    // diagonals dp = 1..kl in batches of kBatch loads, the next batch in flight while
+    // this one is used
+    sweep_batches(kl, [&](int dp) { return Lc[(long)(kl - dp) * 64]; }, [&](int dp, double coef) {
       if (dp <= lane) tri[dp][lane] = coef;
       else acc -= coef * ring[(R - dp) & (kRing - 1)];
-    }
+    });
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < 63; ++s) {
@@ -315,12 +363,10 @@ __global__ __launch_bounds__(64) void k_band_solve2d(Phys P, BandGeom B, BoxGeom
     const int R = 64 * c + lane;
     double acc = yk[R];
     const FT *Uc = Bk + (long)c * nd * 64 + lane;
-#pragma unroll 8
-    for (int dp = 1; dp <= kl; ++dp) {
-      const double coef = (double)Uc[(long)(kl + dp) * 64];
+    sweep_batches(kl, [&](int dp) { return Uc[(long)(kl + dp) * 64]; }, [&](int dp, double coef) {
       if (dp <= 63 - lane) tri[dp][lane] = coef;
       else acc -= coef * ring[(R + dp) & (kRing - 1)];
-    }
+    });
     const double inv = (double)Uc[(long)kl * 64];
     __syncthreads();
 #pragma unroll
