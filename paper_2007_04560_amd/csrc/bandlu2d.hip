@@ -16,12 +16,13 @@
 // (a bit per band entry, from the host's symbolic level-of-fill elimination) updates
 // of entries outside the pattern are dropped, which is ILU(k) in IKJ form.
 //
-// Solve (one wave per box): forward substitution with L, then backward with U, 64 rows
-// at a time.  For a chunk, each lane subtracts the contributions of the up to kl earlier
-// (later) rows that lie in finished chunks -- coalesced loads along each diagonal and the
-// finished values from an LDS ring -- and keeps the coefficients of its own chunk in LDS;
-// the 64 rows of the chunk are then finished one after another with the current value
-// broadcast from its lane.  Arithmetic is FP64; the factors are FP64 or FP32.
+// Solve (four waves per box): forward substitution with L, then backward with U, 64 rows
+// at a time.  For a chunk, the four waves split the up to kl earlier (later) rows that lie
+// in finished chunks and subtract their contributions -- coalesced loads along each
+// diagonal, the finished values from an LDS ring -- keeping the coefficients of the
+// chunk's own columns in LDS; one wave then sums the four partial sums and finishes the
+// 64 rows one after another, each broadcast from its lane.  Arithmetic is FP64; the
+// factors are FP64 or FP32.
 #include <algorithm>
 
 #include "../../include/acch.h"
@@ -97,6 +98,14 @@ __global__ __launch_bounds__(256) void k_band_extract2d(Phys P, BandGeom B, cons
       Bk[band_at(B, R, C - R + B.kl)] = (FT)v;
     }
   }
+}
+
+// Barrier for values exchanged through LDS only: device-memory loads and stores issued
+// before it stay in flight (__syncthreads would wait for them).
+ACCH_DEV void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Selects register row p == sel of a[NR][NR] (sel uniform over the block).
@@ -199,7 +208,9 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
         acol[buf][ty + 16 * p] = v;
       }
     }
-    __syncthreads();
+    // LDS only: the band stores of earlier steps and the loads of entering rows and
+    // columns (kPf steps ahead) touch disjoint entries and stay in flight
+    lds_barrier();
     const double inv = 1.0 / urow[buf][ks];
     double l[NR], u[NR];
 #pragma unroll
@@ -276,29 +287,32 @@ ACCH_DEV double bcast(double v, int s) {
 constexpr int kRing = 512;   // finished values kept for the band (kl + 64 <= kRing)
 constexpr int kBatch = 16;   // band coefficients loaded together by a solve sweep
 
-// use(dp, load(dp)) for dp = 1..kl in order, the loads issued kBatch at a time with the
-// next batch in flight while the current one is used (loads past kl read dp = kl again)
+// use(dp, load(dp)) for dp = lo..hi in order, the loads issued kBatch at a time with
+// the next batch in flight while the current one is used (loads past hi read dp = hi)
 template <typename Load, typename Use>
-ACCH_DEV void sweep_batches(int kl, Load &&load, Use &&use) {
+ACCH_DEV void sweep_batches(int lo, int hi, Load &&load, Use &&use) {
+  if (lo > hi) return;
   double cur[kBatch], nxt[kBatch];
 #pragma unroll
-  for (int u = 0; u < kBatch; ++u) cur[u] = (double)load(min(1 + u, kl));
-  for (int d0 = 1; d0 <= kl; d0 += 2 * kBatch) {
+  for (int u = 0; u < kBatch; ++u) cur[u] = (double)load(min(lo + u, hi));
+  for (int d0 = lo; d0 <= hi; d0 += 2 * kBatch) {
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) nxt[u] = (double)load(min(d0 + kBatch + u, kl));
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (d0 + u <= kl) use(d0 + u, cur[u]);
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) cur[u] = (double)load(min(d0 + 2 * kBatch + u, kl));
+    for (int u = 0; u < kBatch; ++u) nxt[u] = (double)load(min(d0 + kBatch + u, hi));
 #pragma unroll
     for (int u = 0; u < kBatch; ++u)
-      if (d0 + kBatch + u <= kl) use(d0 + kBatch + u, nxt[u]);
+      if (d0 + u <= hi) use(d0 + u, cur[u]);
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) cur[u] = (double)load(min(d0 + 2 * kBatch + u, hi));
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (d0 + kBatch + u <= hi) use(d0 + kBatch + u, nxt[u]);
   }
 }
 
+constexpr int kSolveWaves = 4;   // waves per box: all share the finished-chunk terms
+
 template <typename FT>
-__global__ __launch_bounds__(64) void k_band_solve2d(Phys P, BandGeom B, BoxGeom G, const SubInfo *__restrict__ subs,
+__global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandGeom B, BoxGeom G, const SubInfo *__restrict__ subs,
                                                       const FT *__restrict__ band, double *__restrict__ ybox,
                                                       void *__restrict__ boxbuf_, const double *__restrict__ r,
                                                       double *__restrict__ z, const GmresState *st, long vstride,
@@ -313,15 +327,19 @@ __global__ __launch_bounds__(64) void k_band_solve2d(Phys P, BandGeom B, BoxGeom
   }
   __shared__ double ring[kRing];
   __shared__ double tri[64][64];
-  const int lane = threadIdx.x;
+  __shared__ double psum[kSolveWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const SubInfo si = subs[blockIdx.x];
   const Rect rc = inside_rect(si, B, P.nx, P.ny, P.periodic);
   const FT *Bk = band + (long)blockIdx.x * B.box_elems;
   double *yk = ybox + (long)blockIdx.x * B.nchunk * 64;
   const long n = (long)P.nx * P.ny;
   const int kl = B.kl, nd = B.nd;
-  for (int e = lane; e < kRing; e += 64) ring[e] = 0.0;
+  for (int e = threadIdx.x; e < kRing; e += 64 * kSolveWaves) ring[e] = 0.0;
   __syncthreads();
+  // this wave's share of the diagonals 1..kl
+  const int per = (kl + kSolveWaves - 1) / kSolveWaves;
+  const int dlo = 1 + wave * per, dhi = min(kl, (wave + 1) * per);
 
   // grid cell of box row R (-1: none), whether its cell is owned
   auto cell_of = [&](int R, bool &own) -> long {
@@ -334,59 +352,77 @@ __global__ __launch_bounds__(64) void k_band_solve2d(Phys P, BandGeom B, BoxGeom
   };
 
   // ---- forward: L y = R_k r
+  // Phase 1: the terms of columns in finished chunks, branch-free over four partial
+  // sums; the coefficients of this chunk's own columns go to tri[s][lane] (column s of
+  // the chunk, row lane).  Phase 2: the 64 rows in order, row s broadcast from its lane.
   for (int c = 0; c < B.nchunk; ++c) {
     const int R = 64 * c + lane;
     bool own;
     const long g = cell_of(R, own);
-    double acc = (g >= 0 && (kind != ACCH_RAS_RIGHT || own)) ? sc * r[g + (R & 1) * n] : 0.0;
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    if (wave == 0 && g >= 0 && (kind != ACCH_RAS_RIGHT || own)) part[0] = sc * r[g + (R & 1) * n];
     const FT *Lc = Bk + (long)c * nd * 64 + lane;
-    // diagonals dp = 1..kl in batches of kBatch loads, the next batch in flight while
-    // this one is used
-    sweep_batches(kl, [&](int dp) { return Lc[(long)(kl - dp) * 64]; }, [&](int dp, double coef) {
-      if (dp <= lane) tri[dp][lane] = coef;
-      else acc -= coef * ring[(R - dp) & (kRing - 1)];
+    sweep_batches(dlo, dhi, [&](int dp) { return Lc[(long)(kl - dp) * 64]; }, [&](int dp, double coef) {
+      const bool fin = dp > lane;
+      const double y = ring[(R - dp) & (kRing - 1)];
+      part[dp & 3] -= (fin ? coef : 0.0) * y;
+      if (!fin) tri[lane - dp][lane] = coef;
     });
-    __syncthreads();
+    psum[wave][lane] = (part[0] + part[1]) + (part[2] + part[3]);
+    lds_barrier();
+    if (wave == 0) {
+      double acc = psum[0][lane];
 #pragma unroll
-    for (int s = 0; s < 63; ++s) {
-      const double ys = bcast(acc, s);
-      if (lane > s) acc -= tri[lane - s][lane] * ys;
+      for (int q = 1; q < kSolveWaves; ++q) acc += psum[q][lane];
+#pragma unroll
+      for (int s = 0; s < 63; ++s) {
+        const double cs = lane > s ? tri[s][lane] : 0.0;
+        acc -= cs * bcast(acc, s);
+      }
+      ring[R & (kRing - 1)] = acc;
+      yk[R] = acc;
     }
-    ring[R & (kRing - 1)] = acc;
-    yk[R] = acc;
-    __syncthreads();
+    lds_barrier();
   }
   // ---- backward: U x = y
   FT *boxbuf = (FT *)boxbuf_;
   const long ncb = (long)G.nlev * G.bh;
   for (int c = B.nchunk - 1; c >= 0; --c) {
     const int R = 64 * c + lane;
-    double acc = yk[R];
+    double part[4] = {wave == 0 ? yk[R] : 0.0, 0.0, 0.0, 0.0};
     const FT *Uc = Bk + (long)c * nd * 64 + lane;
-    sweep_batches(kl, [&](int dp) { return Uc[(long)(kl + dp) * 64]; }, [&](int dp, double coef) {
-      if (dp <= 63 - lane) tri[dp][lane] = coef;
-      else acc -= coef * ring[(R + dp) & (kRing - 1)];
+    sweep_batches(dlo, dhi, [&](int dp) { return Uc[(long)(kl + dp) * 64]; }, [&](int dp, double coef) {
+      const bool fin = dp > 63 - lane;
+      const double x = ring[(R + dp) & (kRing - 1)];
+      part[dp & 3] -= (fin ? coef : 0.0) * x;
+      if (!fin) tri[lane + dp][lane] = coef;
     });
-    const double inv = (double)Uc[(long)kl * 64];
-    __syncthreads();
+    psum[wave][lane] = (part[0] + part[1]) + (part[2] + part[3]);
+    lds_barrier();
+    if (wave == 0) {
+      double acc = psum[0][lane];
 #pragma unroll
-    for (int s = 63; s >= 0; --s) {
-      if (lane == s) acc *= inv;
-      const double xs = bcast(acc, s);
-      if (lane < s) acc -= tri[s - lane][lane] * xs;
-    }
-    ring[R & (kRing - 1)] = acc;
-    bool own;
-    const long g = cell_of(R, own);
-    if (g >= 0) {
-      if (kind == ACCH_RAS_LEFT) {
-        if (own) z[g + (R & 1) * n] = acc;
-      } else {
-        const int cc = R >> 1, j = cc / B.bw, i = cc - j * B.bw;
-        boxbuf[2 * ((long)blockIdx.x * (ncb + 1) + (long)(i + 2 * j) * G.bh + j) + (R & 1)] = (FT)acc;
+      for (int q = 1; q < kSolveWaves; ++q) acc += psum[q][lane];
+      const double inv = (double)Uc[(long)kl * 64];
+#pragma unroll
+      for (int s = 63; s >= 0; --s) {
+        if (lane == s) acc *= inv;
+        const double cs = lane < s ? tri[s][lane] : 0.0;
+        acc -= cs * bcast(acc, s);
+      }
+      ring[R & (kRing - 1)] = acc;
+      bool own;
+      const long g = cell_of(R, own);
+      if (g >= 0) {
+        if (kind == ACCH_RAS_LEFT) {
+          if (own) z[g + (R & 1) * n] = acc;
+        } else {
+          const int cc = R >> 1, j = cc / B.bw, i = cc - j * B.bw;
+          boxbuf[2 * ((long)blockIdx.x * (ncb + 1) + (long)(i + 2 * j) * G.bh + j) + (R & 1)] = (FT)acc;
+        }
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -439,10 +475,10 @@ hipError_t launch_band_apply2d(const BatchLaunch &bl, const BandGeom &B, const B
   if (bl.bt.map[kFamSub] != nullptr) return hipErrorInvalidValue;
   if (rv.kind != ACCH_RAS_LEFT && !rv.own_x) return hipErrorInvalidValue;
   if (fp32)
-    hipLaunchKernelGGL(k_band_solve2d<float>, dim3(G.nsub), dim3(64), 0, s, bl.P0, B, G, subs, (const float *)band,
+    hipLaunchKernelGGL(k_band_solve2d<float>, dim3(G.nsub), dim3(64 * kSolveWaves), 0, s, bl.P0, B, G, subs, (const float *)band,
                        ybox, boxbuf, r, z, st, vstride, rv.kind);
   else
-    hipLaunchKernelGGL(k_band_solve2d<double>, dim3(G.nsub), dim3(64), 0, s, bl.P0, B, G, subs,
+    hipLaunchKernelGGL(k_band_solve2d<double>, dim3(G.nsub), dim3(64 * kSolveWaves), 0, s, bl.P0, B, G, subs,
                        (const double *)band, ybox, boxbuf, r, z, st, vstride, rv.kind);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || rv.kind == ACCH_RAS_LEFT) return e;
