@@ -455,3 +455,64 @@ def test_zero_filled_params_through_the_c_abi():
         assert _rel_l2(ug, vg, run.u, run.v) <= 1e-7
     finally:
         lib.acch_destroy(ctx)
+
+
+def _oracle_root_check(ug, vg, up, vp, dt, P, tol):
+    """The oracle residual at a GPU root, relative to the residual at the step's start."""
+    Fu, Fv = scheme.residual(ug, vg, up, vp, dt, P)
+    F0u, F0v = scheme.residual(up, vp, up, vp, dt, P)
+    f1 = math.sqrt(np.sum(Fu ** 2 + Fv ** 2))
+    f0 = math.sqrt(np.sum(F0u ** 2 + F0v ** 2))
+    assert f1 <= tol * f0, (f1, f0)
+
+
+def test_periodic512_workload_roots_at_sampled_steps():
+    """The 512x512 periodic workload as the benchmark runs it (adaptive, tolerance 1e-8):
+    at steps 1, 25 and 60 the oracle's residual of the GPU's new state, taken with the
+    step's dt and the GPU's previous state, is at the Newton tolerance; mass is exact and
+    the energy decreases."""
+    shape = (512, 512)
+    u0, v0 = random_ic(shape, 0)
+    P = prob("periodic")
+    s = solver(u0, v0, "periodic", sub=(8, 8), overlap=2, adaptive=True, dt_min=1e-4, dt_max=1e-1, eta0=1e4,
+               ilu_shift=0.02)
+    M0 = scheme.mass(u0, P)
+    done = 0
+    for k in (1, 25, 60):
+        if k - 1 > done:
+            s.step(k - 1 - done)
+        up, vp = s.fields()
+        info = s.step(1)[0]
+        done = k
+        ug, vg = s.fields()
+        _oracle_root_check(ug, vg, up, vp, info["dt"], P, 2e-8)
+        assert abs(scheme.mass(ug, P) - M0) <= 1e-12 * M0
+        assert scheme.energy(ug, vg, P) < scheme.energy(up, vp, P)
+
+
+def test_neumann2048_setup_at_256_mixed():
+    """The 2048^2 Neumann configuration's setup (FP32 subdomain factors and solves, 16x16
+    subdomains, overlap 2, adaptive dt in [1e-4, 1e-1]) on the 256^2 grid where it
+    converges, at the configuration's tolerance 1e-8: three steps whose mixed-precision
+    roots the oracle's residual confirms, equal to the FP64 GPU run's roots to 1e-7 per
+    step, with exact mass.  Neumann boxes need the larger shift 0.05 (with 0.02 the ILU(0)
+    pivots of the boundary boxes change sign and GMRES stalls)."""
+    shape = (256, 256)
+    u0, v0 = random_ic(shape, 0)
+    P = prob("neumann")
+    kw = dict(sub=(16, 16), overlap=2, adaptive=True, dt_min=1e-4, dt_max=1e-1, eta0=1e4, ilu_shift=0.05,
+              gmres_max_restarts=30)
+    sm = solver(u0, v0, "neumann", precision="mixed", **kw)
+    sd = solver(u0, v0, "neumann", precision="fp64", **kw)
+    M0 = scheme.mass(u0, P)
+    up, vp = u0, v0
+    for k in range(3):
+        im = sm.step(1)[0]
+        idd = sd.step(1)[0]
+        assert im["dt"] == idd["dt"]
+        um, vm = sm.fields()
+        ud, vd = sd.fields()
+        _oracle_root_check(um, vm, up, vp, im["dt"], P, 2e-8)
+        assert _rel_l2(um, vm, ud, vd) <= 1e-7
+        assert abs(scheme.mass(um, P) - M0) <= 1e-12 * M0
+        up, vp = um, vm
