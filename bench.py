@@ -74,6 +74,16 @@ WORKLOADS = {
                        text="long128_lu: the paper's long adaptive 2D run (Section 4.2 parameters, 128x128 periodic, "
                             "dt in [1e-4,10], eta0 = 1e4) to late times: 6000 steps, FP64 NKS, left-RAS 8x8 overlap 1, "
                             "exact subdomain LU, GMRES(30), Newton eps_r 1e-8 with eps_a 1e-6"),
+    # the 2048^2 Neumann configuration's coefficients and form (FP32 subdomain solves, adaptive
+    # dt, 50 steps) at the largest grid where a one-level Schwarz method converges here:
+    # 1024^2 with exact subdomain LU on 32x8 boxes with overlap 8 (19 GMRES per Newton step)
+    "neumann1024_lu": dict(name="neumann1024_lu", shape=(1024, 1024), bc="neumann", sub=(32, 8), overlap=8,
+                           adaptive=True, dt_min=1e-4, dt_max=1e-1, eta0=1e4, newton_rtol=1e-8, newton_atol=1e-13,
+                           gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30, ilu_shift=0.0, precision="mixed",
+                           seed=0, steps=50, subsolver="lu",
+                           text="neumann1024_lu: 2D Neumann 1024x1024, 50 adaptive steps dt in [1e-4,1e-1], FP64 NKS "
+                                "with FP32 exact subdomain LU factors/solves, left-RAS 32x8 overlap 8, GMRES(30), "
+                                "tol 1e-8"),
     "long128_lu_neumann": dict(name="long128_lu_neumann", shape=(128, 128), bc="neumann", sub=(8, 8), overlap=1,
                                adaptive=True, dt_min=1e-4, dt_max=10.0, eta0=1e4, newton_rtol=1e-8,
                                newton_atol=1e-6, gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30, ilu_shift=0.0,
@@ -714,6 +724,16 @@ def main():
         line["config"]["adaptive_step_saving"] = round(1.0 - len(recs) / fixed, 4)
     if not args.no_forms and args.workload == "periodic512" and w["precision"] == "fp64":
         line["config"]["forms"] = forms_summary(args, w, r)
+    if not args.no_forms and args.workload == "neumann1024_lu" and w["precision"] == "mixed":
+        # the same run in plain FP64: time-to-solution and the difference of the results
+        wd = dict(w)
+        wd["precision"] = "fp64"
+        rd = run_gpu(args.steps, 0, timing=False, w=wd)
+        line["config"]["fp64"] = {"seconds": round(rd["elapsed"], 4), "mixed_seconds": round(r["elapsed"], 4),
+                                  "mixed_speedup": round(rd["elapsed"] / r["elapsed"], 3),
+                                  "final_fields_rel_l2_mixed_vs_fp64": _rel_l2(r["fields"], rd["fields"]),
+                                  "newton_its": sum(int(x["newton_its"]) for x in rd["recs"]),
+                                  "gmres_its": sum(int(x["gmres_its"]) for x in rd["recs"])}
     if not args.no_cpu_baseline and args.workload == "periodic512":
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -16,14 +16,16 @@
 // (a bit per band entry, from the host's symbolic level-of-fill elimination) updates
 // of entries outside the pattern are dropped, which is ILU(k) in IKJ form.
 //
-// Solve (four waves per box): forward substitution with L, then backward with U, 64 rows
-// at a time.  For a chunk, the four waves split the up to kl earlier (later) rows that lie
+// Solve (eight waves per box): forward substitution with L, then backward with U, 64 rows
+// at a time.  For a chunk, the eight waves split the up to kl earlier (later) rows that lie
 // in finished chunks and subtract their contributions -- coalesced loads along each
 // diagonal, the finished values from an LDS ring -- keeping the coefficients of the
-// chunk's own columns in LDS; one wave then sums the four partial sums and finishes the
+// chunk's own columns in LDS; one wave then sums the partial sums and finishes the
 // 64 rows one after another, each broadcast from its lane.  Arithmetic is FP64; the
 // factors are FP64 or FP32.
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 
 #include "../../include/acch.h"
 #include "band.h"
@@ -108,171 +110,190 @@ ACCH_DEV void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Selects register row p == sel of a[NR][NR] (sel uniform over the block).
-template <int NR>
-ACCH_DEV void row_out(const double (&a)[NR][NR], int sel, double (&out)[NR]) {
-#pragma unroll
-  for (int p = 0; p < NR; ++p)
-    if (p == sel) {
-#pragma unroll
-      for (int q = 0; q < NR; ++q) out[q] = a[p][q];
-    }
-}
-
-template <typename FT, int NR>
+// Band LU (or ILU(k) on the pattern `mask`, MASKED) of one box matrix per block, in
+// place.  Right-looking elimination through a W x W register window (W = 16 NR >= kl + 1)
+// that holds the active part of the Schur complement; all fill of the band LU stays
+// within kl of the diagonal, so nothing outside the window is touched.  Steps go in
+// groups of 16: before the steps 16 g .. 16 g + 15, register tile (p, q) of thread
+// (ty, tx) holds entry (16 g + 16 p + ty, 16 g + 16 q + tx).  Step k = 16 g + tr pivots
+// on tile row and column 0 of the threads with ty == tr and tx == tr, publishes the pivot
+// row and column through LDS, updates the window, stores row k of U and column k of L,
+// and puts row and column k + W of the original matrix in the pivot's place.  After the
+// group the tiles rotate by one (tile 0, now holding rows and columns 16 g + W + ..., is
+// the last), so the pivot tile is always tile 0 and every register is named at compile
+// time.
+//
+// The rows and columns that enter during group g are loaded at the start of group
+// g - 1: thread (ty, tx) loads the row entering at step 16 g + ty and the column entering
+// at step 16 g + tx into registers and moves them to LDS at the start of group g.  The
+// only wait for device memory is therefore the one at a group's start, for loads issued
+// 16 steps earlier.
+template <typename FT, int NR, bool MASKED>
 __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restrict__ band,
                                                         const unsigned *__restrict__ mask) {
   constexpr int W = 16 * NR;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   FT *Bk = band + (long)blockIdx.x * B.box_elems;
-  const unsigned *Mk = mask ? mask + (long)blockIdx.x * B.n * B.mwords : nullptr;
+  const unsigned *Mk = MASKED ? mask + (long)blockIdx.x * B.n * B.mwords : nullptr;
   const int n = B.n, kl = B.kl, nd = B.nd;
   __shared__ double urow[2][W], acol[2][W];
+  __shared__ double srow[NR][256], scol[NR][256];
+  __shared__ unsigned srw[MASKED ? NR : 1][256], scw[MASKED ? NR : 1][256];
 
-  // original entry (R, C) of A_k, zero outside the matrix or the band
-  auto orig = [&](int R, int C) -> double {
+  auto in_band = [&](int R, int C) {
     const int d = C - R + kl;
-    if (R >= n || C >= n || (unsigned)d >= (unsigned)nd) return 0.0;
-    return (double)Bk[band_at(B, R, d)];
+    return R < n && C < n && (unsigned)d < (unsigned)nd;
   };
-  // (R, C) in the ILU(k) pattern (always, for the exact LU)
-  auto inpat = [&](int R, int C) -> bool {
-    if (!Mk) return true;
-    const int d = C - R + kl;
-    if (R >= n || C >= n || (unsigned)d >= (unsigned)nd) return false;
-    return (Mk[(long)R * B.mwords + (d >> 5)] >> (d & 31)) & 1u;
+  // entry (R, C) of the stored matrix; entries outside the matrix or the band read
+  // stored entry 0 (a padding zero) and are replaced by zero where they are used
+  auto raw = [&](int R, int C) -> double { return (double)Bk[in_band(R, C) ? band_at(B, R, C - R + kl) : 0]; };
+  // the ILU(k) pattern word holding (R, C)
+  auto raw_mask = [&](int R, int C) -> unsigned {
+    return Mk[in_band(R, C) ? (long)R * B.mwords + ((C - R + kl) >> 5) : 0];
   };
+  auto mask_bit = [&](int R, int C, unsigned word) -> unsigned {
+    return (in_band(R, C) && ((word >> ((C - R + kl) & 31)) & 1u)) ? 1u : 0u;
+  };
+  // column of tile q of this thread after step kg + t of the group starting at kg (row of
+  // tile p: the same with ty)
+  auto col_after = [&](int kg, int t, int q) { return kg + 16 * q + tx + (q == 0 && tx <= t ? W : 0); };
+  auto row_after = [&](int kg, int t, int p) { return kg + 16 * p + ty + (p == 0 && ty <= t ? W : 0); };
 
   double a[NR][NR];
-  unsigned m[NR];   // bit q: entry (row of slot p, column of slot q) may be updated
+  unsigned m[NR];   // bit q: entry (row of tile p, column of tile q) is in the pattern
 #pragma unroll
   for (int p = 0; p < NR; ++p) {
     m[p] = 0;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       const int R = ty + 16 * p, C = tx + 16 * q;
-      a[p][q] = orig(R, C);
-      m[p] |= inpat(R, C) ? (1u << q) : 0u;
+      a[p][q] = in_band(R, C) ? raw(R, C) : 0.0;
+      if (MASKED) m[p] |= mask_bit(R, C, raw_mask(R, C)) << q;
     }
   }
-  // Rows and columns enter the window kPf steps after their loads are issued: the
-  // thread row (column) of the slot freed at step kk is kk mod 16, so a thread has at
-  // most one pending row and one pending column (kPf < 16).
-  constexpr int kPf = 8;
-  double prow[NR], pcol[NR];
-  unsigned pmrow = 0, pmcol = 0;
-  // row or column held by slot s after step kk
-  auto held_after = [&](int kk, int s) {
-    const int kw = kk % W;
-    return s == kw ? kk + W : kk + (s > kw ? s - kw : s - kw + W);
-  };
-  auto issue_row = [&](int kk) {   // row kk + W at the columns this thread owns after step kk
-    pmrow = 0;
+
+  // rows (at this thread's columns) and columns (at its rows) entering during the next
+  // group, in registers; those of the current group in LDS (read by the same thread)
+  double nrow[NR], ncol[NR];
+  unsigned nrw[NR], ncw[NR];
+  auto load_group = [&](int kg) {
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      const int C = held_after(kk, tx + 16 * q);
-      prow[q] = orig(kk + W, C);
-      pmrow |= inpat(kk + W, C) ? (1u << q) : 0u;
+      const int C = col_after(kg, ty, q);
+      nrow[q] = raw(kg + ty + W, C);
+      if (MASKED) nrw[q] = raw_mask(kg + ty + W, C);
     }
-  };
-  auto issue_col = [&](int kk) {   // column kk + W at the rows this thread owns after step kk
-    pmcol = 0;
 #pragma unroll
     for (int p = 0; p < NR; ++p) {
-      const int R = held_after(kk, ty + 16 * p);
-      pcol[p] = orig(R, kk + W);
-      pmcol |= inpat(R, kk + W) ? (1u << p) : 0u;
+      const int R = row_after(kg, tx, p);
+      ncol[p] = raw(R, kg + tx + W);
+      if (MASKED) ncw[p] = raw_mask(R, kg + tx + W);
     }
   };
-  if (ty < kPf) issue_row(ty);
-  if (tx < kPf) issue_col(tx);
+  load_group(0);
   __syncthreads();
 
-  int ks = 0;   // window slot of the pivot row and column: k mod W
-  for (int k = 0; k < n; ++k) {
-    const int buf = k & 1;
-    const int pr = ks >> 4, tr = ks & 15;
-    if (ty == tr) {
-      double row[NR];
-      row_out<NR>(a, pr, row);
-#pragma unroll
-      for (int q = 0; q < NR; ++q) urow[buf][tx + 16 * q] = row[q];
-    }
-    if (tx == tr) {
-#pragma unroll
-      for (int p = 0; p < NR; ++p) {
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < NR; ++q)
-          if (q == pr) v = a[p][q];
-        acol[buf][ty + 16 * p] = v;
-      }
-    }
-    // LDS only: the band stores of earlier steps and the loads of entering rows and
-    // columns (kPf steps ahead) touch disjoint entries and stay in flight
-    lds_barrier();
-    const double inv = 1.0 / urow[buf][ks];
-    double l[NR], u[NR];
-#pragma unroll
-    for (int p = 0; p < NR; ++p) {
-      const int s = ty + 16 * p;
-      l[p] = s == ks ? 0.0 : acol[buf][s] * inv;
-    }
+  for (int kg = 0; kg < n; kg += 16) {
+    // this group's entering rows and columns (loaded a group ago) move to LDS; the
+    // next group's loads start
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      const int s = tx + 16 * q;
-      u[q] = s == ks ? 0.0 : urow[buf][s];
-    }
-#pragma unroll
-    for (int p = 0; p < NR; ++p)
-#pragma unroll
-      for (int q = 0; q < NR; ++q)
-        if ((m[p] >> q) & 1u) a[p][q] -= l[p] * u[q];
-
-    // row k of U (1/u_kk on the diagonal) and column k of L over the band
-    if (ty == tr) {
-#pragma unroll
-      for (int q = 0; q < NR; ++q) {
-        const int s = tx + 16 * q;
-        const int off = s >= ks ? s - ks : s - ks + W;   // column k + off
-        if (off <= kl && k + off < n) Bk[band_at(B, k, kl + off)] = (FT)(off == 0 ? inv : urow[buf][s]);
+      srow[q][tid] = nrow[q];
+      scol[q][tid] = ncol[q];
+      if (MASKED) {
+        srw[q][tid] = nrw[q];
+        scw[q][tid] = ncw[q];
       }
     }
-    if (tx == tr) {
+    if (kg + 16 < n) load_group(kg + 16);
+    const int tend = min(16, n - kg);
+    for (int tr = 0; tr < tend; ++tr) {
+      const int k = kg + tr, buf = k & 1;
+      const bool prow_t = ty == tr, pcol_t = tx == tr;   // owns the pivot row / column
+      if (prow_t) {
 #pragma unroll
-      for (int p = 0; p < NR; ++p) {
-        const int s = ty + 16 * p;
-        const int off = s >= ks ? s - ks : s - ks + W;   // row k + off
-        if (off >= 1 && off <= kl && k + off < n) Bk[band_at(B, k + off, kl - off)] = (FT)l[p];
+        for (int q = 0; q < NR; ++q) urow[buf][tx + 16 * q] = a[0][q];
       }
-    }
-    // slot ks takes row k + W and column k + W (loaded kPf steps ahead); the other
-    // slots keep theirs
-    if (ty == tr) {
+      if (pcol_t) {
 #pragma unroll
-      for (int p = 0; p < NR; ++p)
-        if (p == pr) {
+        for (int p = 0; p < NR; ++p) acol[buf][ty + 16 * p] = a[p][0];
+      }
+      // LDS only: the band stores of earlier steps and the loads of the next group
+      // touch other entries and stay in flight
+      lds_barrier();
+      const double inv = 1.0 / urow[buf][tr];
+      double l[NR], u[NR];
 #pragma unroll
-          for (int q = 0; q < NR; ++q) a[p][q] = prow[q];
-          m[p] = pmrow;
-        }
-    }
-    if (tx == tr) {
+      for (int p = 0; p < NR; ++p) l[p] = acol[buf][ty + 16 * p] * inv;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) u[q] = urow[buf][tx + 16 * q];
+      if (prow_t) l[0] = 0.0;   // the pivot row and column are not updated
+      if (pcol_t) u[0] = 0.0;
 #pragma unroll
       for (int p = 0; p < NR; ++p)
 #pragma unroll
-        for (int q = 0; q < NR; ++q)
-          if (q == pr) {
-            a[p][q] = pcol[p];
-            m[p] = (m[p] & ~(1u << q)) | (((pmcol >> p) & 1u) << q);
+        for (int q = 0; q < NR; ++q) {
+          if (MASKED) {
+            if ((m[p] >> q) & 1u) a[p][q] -= l[p] * u[q];
+          } else {
+            a[p][q] -= l[p] * u[q];
           }
+        }
+
+      // row k of U (1/u_kk on the diagonal) and column k of L over the band
+      if (prow_t) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          const int off = 16 * q + tx - tr + (q == 0 && tx < tr ? W : 0);   // column k + off
+          if (off <= kl && k + off < n) Bk[band_at(B, k, kl + off)] = (FT)(off == 0 ? inv : u[q]);
+        }
+      }
+      if (pcol_t) {
+#pragma unroll
+        for (int p = 0; p < NR; ++p) {
+          const int off = 16 * p + ty - tr + (p == 0 && ty < tr ? W : 0);   // row k + off
+          if (off >= 1 && off <= kl && k + off < n) Bk[band_at(B, k + off, kl - off)] = (FT)l[p];
+        }
+      }
+      // row and column k + W take the pivot's place
+      if (prow_t) {
+        unsigned mr = 0;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          const int C = col_after(kg, tr, q);
+          a[0][q] = in_band(k + W, C) ? srow[q][tid] : 0.0;
+          if (MASKED) mr |= mask_bit(k + W, C, srw[q][tid]) << q;
+        }
+        if (MASKED) m[0] = mr;
+      }
+      if (pcol_t) {
+#pragma unroll
+        for (int p = 0; p < NR; ++p) {
+          const int R = row_after(kg, tr, p);
+          a[p][0] = in_band(R, k + W) ? scol[p][tid] : 0.0;
+          if (MASKED) m[p] = (m[p] & ~1u) | mask_bit(R, k + W, scw[p][tid]);
+        }
+      }
     }
+    // tiles move down by one: tile (p, q) takes tile (p + 1, q + 1), cyclically
     {
-      const int kk = k + kPf;
-      if (ty == (kk & 15)) issue_row(kk);
-      if (tx == (kk & 15)) issue_col(kk);
+      double t[NR];
+#pragma unroll
+      for (int q = 0; q < NR; ++q) t[q] = a[0][q];
+#pragma unroll
+      for (int p = 0; p + 1 < NR; ++p)
+#pragma unroll
+        for (int q = 0; q < NR; ++q) a[p][q] = a[p + 1][(q + 1) % NR];
+#pragma unroll
+      for (int q = 0; q < NR; ++q) a[NR - 1][q] = t[(q + 1) % NR];
+      if (MASKED) {
+        const unsigned full = (1u << NR) - 1u;
+        const unsigned m0 = m[0];
+#pragma unroll
+        for (int p = 0; p + 1 < NR; ++p) m[p] = ((m[p + 1] >> 1) | (m[p + 1] << (NR - 1))) & full;
+        m[NR - 1] = ((m0 >> 1) | (m0 << (NR - 1))) & full;
+      }
     }
-    ks = ks + 1 == W ? 0 : ks + 1;
   }
 }
 
@@ -309,7 +330,7 @@ ACCH_DEV void sweep_batches(int lo, int hi, Load &&load, Use &&use) {
   }
 }
 
-constexpr int kSolveWaves = 4;   // waves per box: all share the finished-chunk terms
+constexpr int kSolveWaves = 8;   // waves per box: all share the finished-chunk terms
 
 template <typename FT>
 __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandGeom B, BoxGeom G, const SubInfo *__restrict__ subs,
@@ -447,14 +468,22 @@ hipError_t factor_t(const Phys &P, const BandGeom &B, int nsub, const SubInfo *s
   int blocks = (int)std::min<long>((total + 255) / 256, 8192);
   hipLaunchKernelGGL(k_band_zero<FT>, dim3(blocks), dim3(256), 0, s, bd, total);
   hipLaunchKernelGGL(k_band_extract2d<FT>, dim3(nsub), dim3(256), 0, s, P, B, subs, J, shift, bd);
-  switch (B.nr) {
-    case 4: hipLaunchKernelGGL((k_band_factor2d<FT, 4>), dim3(nsub), dim3(256), 0, s, B, bd, mask); break;
-    case 6: hipLaunchKernelGGL((k_band_factor2d<FT, 6>), dim3(nsub), dim3(256), 0, s, B, bd, mask); break;
-    case 8: hipLaunchKernelGGL((k_band_factor2d<FT, 8>), dim3(nsub), dim3(256), 0, s, B, bd, mask); break;
-    case 10: hipLaunchKernelGGL((k_band_factor2d<FT, 10>), dim3(nsub), dim3(256), 0, s, B, bd, mask); break;
-    case 12: hipLaunchKernelGGL((k_band_factor2d<FT, 12>), dim3(nsub), dim3(256), 0, s, B, bd, mask); break;
-    case 14: hipLaunchKernelGGL((k_band_factor2d<FT, 14>), dim3(nsub), dim3(256), 0, s, B, bd, mask); break;
-    default: return hipErrorInvalidValue;
+  if (mask) {
+    switch (B.nr) {
+#define ACCH_FACTOR(NR) \
+  case NR: hipLaunchKernelGGL((k_band_factor2d<FT, NR, true>), dim3(nsub), dim3(256), 0, s, B, bd, mask); break;
+      ACCH_FACTOR(4) ACCH_FACTOR(6) ACCH_FACTOR(8) ACCH_FACTOR(10) ACCH_FACTOR(12) ACCH_FACTOR(13) ACCH_FACTOR(14)
+#undef ACCH_FACTOR
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (B.nr) {
+#define ACCH_FACTOR(NR) \
+  case NR: hipLaunchKernelGGL((k_band_factor2d<FT, NR, false>), dim3(nsub), dim3(256), 0, s, B, bd, nullptr); break;
+      ACCH_FACTOR(4) ACCH_FACTOR(6) ACCH_FACTOR(8) ACCH_FACTOR(10) ACCH_FACTOR(12) ACCH_FACTOR(13) ACCH_FACTOR(14)
+#undef ACCH_FACTOR
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
