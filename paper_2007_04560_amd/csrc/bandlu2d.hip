@@ -306,33 +306,23 @@ ACCH_DEV double bcast(double v, int s) {
 }
 
 constexpr int kRing = 512;   // finished values kept for the band (kl + 64 <= kRing)
-constexpr int kBatch = 16;   // band coefficients loaded together by a solve sweep
-
-// use(dp, load(dp)) for dp = lo..hi in order, the loads issued kBatch at a time with
-// the next batch in flight while the current one is used (loads past hi read dp = hi)
-template <typename Load, typename Use>
-ACCH_DEV void sweep_batches(int lo, int hi, Load &&load, Use &&use) {
-  if (lo > hi) return;
-  double cur[kBatch], nxt[kBatch];
-#pragma unroll
-  for (int u = 0; u < kBatch; ++u) cur[u] = (double)load(min(lo + u, hi));
-  for (int d0 = lo; d0 <= hi; d0 += 2 * kBatch) {
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) nxt[u] = (double)load(min(d0 + kBatch + u, hi));
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (d0 + u <= hi) use(d0 + u, cur[u]);
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) cur[u] = (double)load(min(d0 + 2 * kBatch + u, hi));
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (d0 + kBatch + u <= hi) use(d0 + kBatch + u, nxt[u]);
-  }
-}
-
 constexpr int kSolveWaves = 8;   // waves per box: all share the finished-chunk terms
 
-template <typename FT>
+// Forward and backward substitution with the band factors of one box per block, for
+// z = sum_k R_k^T (LU)_k^{-1} R_k r (left RAS: owned cells only; right and classical:
+// into the box buffer for the overlap sum).  The 64 rows of a chunk are solved together.
+// Phase 1 adds the terms of all columns within kl of the rows (diagonals 1..kl split
+// between the waves, partial sums through LDS); the ring slots of the chunk's own rows
+// hold zeros at that point, so the terms of its own columns vanish there, and their
+// coefficients go to tri (column s of the chunk, row lane) for phase 2, in which one wave
+// takes the 64 rows in order, row s broadcast from its lane.  The lower (forward) and
+// upper (backward) tri are separate and start as zeros, so phase 2 needs no masks; the
+// backward sweep broadcasts acc / u_ss and scales every row by 1 / u_ss at the end.
+// Each wave's coefficients of the next chunk (and the right-hand side values of its
+// rows) are loaded while the current chunk is solved, into the other of two register
+// buffers; the loads use clamped addresses and no condition, so the only wait is for
+// data issued a chunk earlier.
+template <typename FT, int PER>
 __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandGeom B, BoxGeom G, const SubInfo *__restrict__ subs,
                                                       const FT *__restrict__ band, double *__restrict__ ybox,
                                                       void *__restrict__ boxbuf_, const double *__restrict__ r,
@@ -347,20 +337,27 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
     sc = st->inv_norm[jj];
   }
   __shared__ double ring[kRing];
-  __shared__ double tri[64][64];
+  __shared__ double trl[65][64], tru[65][64];   // row 64: stores that are never read
   __shared__ double psum[kSolveWaves][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar
   const SubInfo si = subs[blockIdx.x];
   const Rect rc = inside_rect(si, B, P.nx, P.ny, P.periodic);
   const FT *Bk = band + (long)blockIdx.x * B.box_elems;
   double *yk = ybox + (long)blockIdx.x * B.nchunk * 64;
   const long n = (long)P.nx * P.ny;
-  const int kl = B.kl, nd = B.nd;
+  const int kl = B.kl, nd = B.nd, nch = B.nchunk;
   for (int e = threadIdx.x; e < kRing; e += 64 * kSolveWaves) ring[e] = 0.0;
+  for (int e = threadIdx.x; e < 65 * 64; e += 64 * kSolveWaves) {
+    (&trl[0][0])[e] = 0.0;
+    (&tru[0][0])[e] = 0.0;
+  }
   __syncthreads();
-  // this wave's share of the diagonals 1..kl
+  // this wave's share of the diagonals: dlo .. dlo + cnt - 1 (cnt <= PER, maybe 0)
   const int per = (kl + kSolveWaves - 1) / kSolveWaves;
-  const int dlo = 1 + wave * per, dhi = min(kl, (wave + 1) * per);
+  const int dlo = 1 + wave * per;
+  const int cnt = max(0, min(kl, (wave + 1) * per) - dlo + 1);
+  const int dcl = max(1, min(kl, dlo + cnt - 1));   // clamp of the loaded diagonals
 
   // grid cell of box row R (-1: none), whether its cell is owned
   auto cell_of = [&](int R, bool &own) -> long {
@@ -373,77 +370,123 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
   };
 
   // ---- forward: L y = R_k r
-  // Phase 1: the terms of columns in finished chunks, branch-free over four partial
-  // sums; the coefficients of this chunk's own columns go to tri[s][lane] (column s of
-  // the chunk, row lane).  Phase 2: the 64 rows in order, row s broadcast from its lane.
-  for (int c = 0; c < B.nchunk; ++c) {
-    const int R = 64 * c + lane;
-    bool own;
-    const long g = cell_of(R, own);
-    double part[4] = {0.0, 0.0, 0.0, 0.0};
-    if (wave == 0 && g >= 0 && (kind != ACCH_RAS_RIGHT || own)) part[0] = sc * r[g + (R & 1) * n];
-    const FT *Lc = Bk + (long)c * nd * 64 + lane;
-    sweep_batches(dlo, dhi, [&](int dp) { return Lc[(long)(kl - dp) * 64]; }, [&](int dp, double coef) {
-      const bool fin = dp > lane;
-      const double y = ring[(R - dp) & (kRing - 1)];
-      part[dp & 3] -= (fin ? coef : 0.0) * y;
-      if (!fin) tri[lane - dp][lane] = coef;
-    });
-    psum[wave][lane] = (part[0] + part[1]) + (part[2] + part[3]);
-    lds_barrier();
-    if (wave == 0) {
-      double acc = psum[0][lane];
+  {
+    FT ca[PER], cb[PER];
+    double ra = 0.0, rb = 0.0;
+    auto load = [&](int c, FT (&cf)[PER], double &rv) {
+      const int cc = min(c, nch - 1);
+      const FT *Lc = Bk + (long)cc * nd * 64 + lane;
 #pragma unroll
-      for (int q = 1; q < kSolveWaves; ++q) acc += psum[q][lane];
-#pragma unroll
-      for (int s = 0; s < 63; ++s) {
-        const double cs = lane > s ? tri[s][lane] : 0.0;
-        acc -= cs * bcast(acc, s);
+      for (int i = 0; i < PER; ++i) cf[i] = Lc[(long)(kl - min(dlo + i, dcl)) * 64];
+      if (wave == 0) {
+        bool own;
+        const int R = 64 * cc + lane;
+        const long g = cell_of(R, own);
+        rv = r[max(g, 0L) + (R & 1) * n];
       }
-      ring[R & (kRing - 1)] = acc;
-      yk[R] = acc;
+    };
+    auto chunk = [&](int c, const FT (&cf)[PER], double rv) {
+      const int R = 64 * c + lane;
+      double part[4] = {0.0, 0.0, 0.0, 0.0};
+      if (wave == 0) {
+        bool own;
+        const long g = cell_of(R, own);
+        part[0] = g >= 0 && (kind != ACCH_RAS_RIGHT || own) ? sc * rv : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        if (i >= cnt) break;
+        const int dp = dlo + i;
+        const double coef = (double)cf[i];
+        part[i & 3] -= coef * ring[(R - dp) & (kRing - 1)];
+        trl[min((unsigned)(lane - dp), 64u)][lane] = coef;
+      }
+      psum[wave][lane] = (part[0] + part[1]) + (part[2] + part[3]);
+      lds_barrier();
+      if (wave == 0) {
+        double acc = psum[0][lane];
+#pragma unroll
+        for (int q = 1; q < kSolveWaves; ++q) acc += psum[q][lane];
+#pragma unroll
+        for (int s = 0; s < 63; ++s) acc -= trl[s][lane] * bcast(acc, s);
+        ring[R & (kRing - 1)] = acc;
+        ring[(R + 64) & (kRing - 1)] = 0.0;   // the next chunk's rows
+        yk[R] = acc;
+      }
+      lds_barrier();
+    };
+    load(0, ca, ra);
+    for (int c = 0; c < nch; c += 2) {
+      load(c + 1, cb, rb);
+      chunk(c, ca, ra);
+      if (c + 1 >= nch) break;
+      load(c + 2, ca, ra);
+      chunk(c + 1, cb, rb);
     }
-    lds_barrier();
   }
   // ---- backward: U x = y
+  if (wave == 0) ring[(64 * (nch - 1) + lane) & (kRing - 1)] = 0.0;   // the last chunk's rows
+  __syncthreads();
   FT *boxbuf = (FT *)boxbuf_;
   const long ncb = (long)G.nlev * G.bh;
-  for (int c = B.nchunk - 1; c >= 0; --c) {
-    const int R = 64 * c + lane;
-    double part[4] = {wave == 0 ? yk[R] : 0.0, 0.0, 0.0, 0.0};
-    const FT *Uc = Bk + (long)c * nd * 64 + lane;
-    sweep_batches(dlo, dhi, [&](int dp) { return Uc[(long)(kl + dp) * 64]; }, [&](int dp, double coef) {
-      const bool fin = dp > 63 - lane;
-      const double x = ring[(R + dp) & (kRing - 1)];
-      part[dp & 3] -= (fin ? coef : 0.0) * x;
-      if (!fin) tri[lane + dp][lane] = coef;
-    });
-    psum[wave][lane] = (part[0] + part[1]) + (part[2] + part[3]);
-    lds_barrier();
-    if (wave == 0) {
-      double acc = psum[0][lane];
+  {
+    FT ca[PER], cb[PER];
+    double ya = 0.0, yb = 0.0, ia = 0.0, ib = 0.0;
+    auto load = [&](int c, FT (&cf)[PER], double &yv, double &iv) {
+      const int cc = max(c, 0);
+      const FT *Uc = Bk + (long)cc * nd * 64 + lane;
 #pragma unroll
-      for (int q = 1; q < kSolveWaves; ++q) acc += psum[q][lane];
-      const double inv = (double)Uc[(long)kl * 64];
-#pragma unroll
-      for (int s = 63; s >= 0; --s) {
-        if (lane == s) acc *= inv;
-        const double cs = lane < s ? tri[s][lane] : 0.0;
-        acc -= cs * bcast(acc, s);
+      for (int i = 0; i < PER; ++i) cf[i] = Uc[(long)(kl + min(dlo + i, dcl)) * 64];
+      if (wave == 0) {
+        yv = yk[64 * cc + lane];
+        iv = (double)Uc[(long)kl * 64];
       }
-      ring[R & (kRing - 1)] = acc;
-      bool own;
-      const long g = cell_of(R, own);
-      if (g >= 0) {
-        if (kind == ACCH_RAS_LEFT) {
-          if (own) z[g + (R & 1) * n] = acc;
-        } else {
-          const int cc = R >> 1, j = cc / B.bw, i = cc - j * B.bw;
-          boxbuf[2 * ((long)blockIdx.x * (ncb + 1) + (long)(i + 2 * j) * G.bh + j) + (R & 1)] = (FT)acc;
+    };
+    auto chunk = [&](int c, const FT (&cf)[PER], double yv, double inv) {
+      const int R = 64 * c + lane;
+      double part[4] = {wave == 0 ? yv : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        if (i >= cnt) break;
+        const int dp = dlo + i;
+        const double coef = (double)cf[i];
+        part[i & 3] -= coef * ring[(R + dp) & (kRing - 1)];
+        tru[min((unsigned)(lane + dp), 64u)][lane] = coef;
+      }
+      psum[wave][lane] = (part[0] + part[1]) + (part[2] + part[3]);
+      lds_barrier();
+      if (wave == 0) {
+        double acc = psum[0][lane];
+#pragma unroll
+        for (int q = 1; q < kSolveWaves; ++q) acc += psum[q][lane];
+#pragma unroll
+        for (int s = 63; s >= 1; --s) acc -= tru[s][lane] * bcast(acc * inv, s);
+        acc *= inv;
+        ring[R & (kRing - 1)] = acc;
+        ring[(R - 64) & (kRing - 1)] = 0.0;   // the next chunk's rows
+        bool own;
+        const long g = cell_of(R, own);
+        if (g >= 0) {
+          if (kind == ACCH_RAS_LEFT) {
+            if (own) z[g + (R & 1) * n] = acc;
+          } else {
+            const int cc = R >> 1, j = cc / B.bw, i = cc - j * B.bw;
+            boxbuf[2 * ((long)blockIdx.x * (ncb + 1) + (long)(i + 2 * j) * G.bh + j) + (R & 1)] = (FT)acc;
+          }
         }
       }
+      lds_barrier();
+    };
+    // the y values of the chunk were stored by the same threads (wave 0) in the forward
+    // sweep
+    load(nch - 1, ca, ya, ia);
+    for (int c = nch - 1; c >= 0; c -= 2) {
+      load(c - 1, cb, yb, ib);
+      chunk(c, ca, ya, ia);
+      if (c - 1 < 0) break;
+      load(c - 2, ca, ya, ia);
+      chunk(c - 1, cb, yb, ib);
     }
-    lds_barrier();
   }
 }
 
@@ -488,6 +531,31 @@ hipError_t factor_t(const Phys &P, const BandGeom &B, int nsub, const SubInfo *s
   return hipGetLastError();
 }
 
+template <typename FT>
+hipError_t solve_t(int per, const Phys &P, const BandGeom &B, const BoxGeom &G, const SubInfo *subs, const void *band,
+                   double *ybox, void *boxbuf, const double *r, double *z, const GmresState *st, long vstride,
+                   int kind, hipStream_t s) {
+  const FT *bd = (const FT *)band;
+  const dim3 grid(G.nsub), block(64 * kSolveWaves);
+  if (per <= 4)
+    hipLaunchKernelGGL((k_band_solve2d<FT, 4>), grid, block, 0, s, P, B, G, subs, bd, ybox, boxbuf, r, z, st, vstride, kind);
+  else if (per <= 8)
+    hipLaunchKernelGGL((k_band_solve2d<FT, 8>), grid, block, 0, s, P, B, G, subs, bd, ybox, boxbuf, r, z, st, vstride, kind);
+  else if (per <= 12)
+    hipLaunchKernelGGL((k_band_solve2d<FT, 12>), grid, block, 0, s, P, B, G, subs, bd, ybox, boxbuf, r, z, st, vstride, kind);
+  else if (per <= 16)
+    hipLaunchKernelGGL((k_band_solve2d<FT, 16>), grid, block, 0, s, P, B, G, subs, bd, ybox, boxbuf, r, z, st, vstride, kind);
+  else if (per <= 20)
+    hipLaunchKernelGGL((k_band_solve2d<FT, 20>), grid, block, 0, s, P, B, G, subs, bd, ybox, boxbuf, r, z, st, vstride, kind);
+  else if (per <= 24)
+    hipLaunchKernelGGL((k_band_solve2d<FT, 24>), grid, block, 0, s, P, B, G, subs, bd, ybox, boxbuf, r, z, st, vstride, kind);
+  else if (per <= 28)
+    hipLaunchKernelGGL((k_band_solve2d<FT, 28>), grid, block, 0, s, P, B, G, subs, bd, ybox, boxbuf, r, z, st, vstride, kind);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_band_factor2d(const BatchLaunch &bl, const BandGeom &B, int nsub, const SubInfo *subs,
@@ -503,13 +571,11 @@ hipError_t launch_band_apply2d(const BatchLaunch &bl, const BandGeom &B, const B
                                const GmresState *st, long vstride, int fp32, hipStream_t s, const RasVariant &rv) {
   if (bl.bt.map[kFamSub] != nullptr) return hipErrorInvalidValue;
   if (rv.kind != ACCH_RAS_LEFT && !rv.own_x) return hipErrorInvalidValue;
-  if (fp32)
-    hipLaunchKernelGGL(k_band_solve2d<float>, dim3(G.nsub), dim3(64 * kSolveWaves), 0, s, bl.P0, B, G, subs, (const float *)band,
-                       ybox, boxbuf, r, z, st, vstride, rv.kind);
-  else
-    hipLaunchKernelGGL(k_band_solve2d<double>, dim3(G.nsub), dim3(64 * kSolveWaves), 0, s, bl.P0, B, G, subs,
-                       (const double *)band, ybox, boxbuf, r, z, st, vstride, rv.kind);
-  hipError_t e = hipGetLastError();
+  const int per = (B.kl + kSolveWaves - 1) / kSolveWaves;
+  hipError_t e = fp32 ? solve_t<float>(per, bl.P0, B, G, subs, band, ybox, boxbuf, r, z, st, vstride, rv.kind, s)
+                      : solve_t<double>(per, bl.P0, B, G, subs, band, ybox, boxbuf, r, z, st, vstride, rv.kind, s);
+  if (e != hipSuccess) return e;
+  e = hipGetLastError();
   if (e != hipSuccess || rv.kind == ACCH_RAS_LEFT) return e;
   return launch_ras_sum2d(bl, G, subs, boxbuf, z, st, vstride, fp32, s, rv);
 }
