@@ -162,6 +162,7 @@ def run_gpu(steps: int, warmup: int, timing: bool, w=None):
               dt_max=w["dt_max"], eta0=w["eta0"], newton_rtol=w["newton_rtol"], newton_atol=w["newton_atol"],
               gmres_rtol=w["gmres_rtol"], gmres_atol=w["gmres_atol"], gmres_restart=w["gmres_restart"],
               ilu_shift=w["ilu_shift"], precision=w["precision"], subsolver=w.get("subsolver", "ilu0"),
+              fill_level=w.get("fill_level", 0),
               **w.get("phys", {}))
     if warmup > 0:
         with Solver(u0, v0, **kw) as s:
@@ -602,6 +603,9 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--sub", default=None, help="subdomains per axis, x,y[,z] (default: the workload's)")
     ap.add_argument("--overlap", type=int, default=None, help="subdomain overlap (default: the workload's)")
+    ap.add_argument("--subsolver", default=None, choices=["ilu0", "ilu1", "ilu2", "lu"],
+                    help="subdomain solver (Table 2; default: the workload's)")
+    ap.add_argument("--ilu-shift", type=float, default=None, help="diagonal shift of the subdomain matrices")
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -638,6 +642,15 @@ def main():
         w["sub"] = tuple(int(x) for x in args.sub.split(",")) if args.sub else w["sub"]
         w["overlap"] = w["overlap"] if args.overlap is None else args.overlap
         w["text"] += f" [subdomains {'x'.join(map(str, w['sub']))}, overlap {w['overlap']}]"
+    if args.subsolver or args.ilu_shift is not None:
+        if args.subsolver:
+            w["subsolver"] = {"ilu1": "iluk", "ilu2": "iluk"}.get(args.subsolver, args.subsolver)
+            w["fill_level"] = {"ilu1": 1, "ilu2": 2}.get(args.subsolver, 0)
+            if args.subsolver == "lu" and args.ilu_shift is None:
+                w["ilu_shift"] = 0.0
+        if args.ilu_shift is not None:
+            w["ilu_shift"] = args.ilu_shift
+        w["text"] += f" [subdomain solver {args.subsolver or w.get('subsolver', 'ilu0')}, shift {w['ilu_shift']}]"
     if args.steps is None:
         args.steps = w["steps"]
     if args.gpus != 1:

@@ -6,23 +6,15 @@
 // identity rows, as in the ILU(0) path.
 //
 // Factorisation (one workgroup of 256 threads per box): Gaussian elimination without
-// pivoting in the natural order.  The active part of the band -- rows k..k+W-1 and
-// columns k..k+W-1 at step k, W = 16 nr >= kl + 1 -- lives in registers: thread
-// (ty, tx) of the 16 x 16 grid owns the window rows R = ty (mod 16) and columns
-// C = tx (mod 16), at the circular slots R mod W and C mod W.  A step publishes the
-// pivot row and column through LDS (double buffered, one barrier per step), applies
-// the rank-1 update to every owned entry, stores row k of U and column k of L over the
-// band, and loads row k+W and column k+W into the freed slots.  With an ILU(k) pattern
-// (a bit per band entry, from the host's symbolic level-of-fill elimination) updates
-// of entries outside the pattern are dropped, which is ILU(k) in IKJ form.
+// pivoting in the natural order, through a register window of the active part of the
+// band (details at k_band_factor2d).  With an ILU(k) pattern (a bit per band entry, from
+// the host's symbolic level-of-fill elimination) updates of entries outside the pattern
+// are dropped, which is ILU(k) in IKJ form.  The elimination runs in the precision of
+// the stored factors: FP64 factors in FP64, FP32 factors (the mixed-precision form) in
+// FP32.
 //
 // Solve (eight waves per box): forward substitution with L, then backward with U, 64 rows
-// at a time.  For a chunk, the eight waves split the up to kl earlier (later) rows that lie
-// in finished chunks and subtract their contributions -- coalesced loads along each
-// diagonal, the finished values from an LDS ring -- keeping the coefficients of the
-// chunk's own columns in LDS; one wave then sums the partial sums and finishes the
-// 64 rows one after another, each broadcast from its lane.  Arithmetic is FP64; the
-// factors are FP64 or FP32.
+// at a time (details at k_band_solve2d), in FP64 arithmetic on FP64 or FP32 factors.
 #include <algorithm>
 #include <type_traits>
 #include <utility>
@@ -30,6 +22,7 @@
 #include "../../include/acch.h"
 #include "band.h"
 #include "boxes.h"
+#include "bufio.h"
 #include "kernels.h"
 
 namespace acch {
@@ -136,30 +129,35 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
   FT *Bk = band + (long)blockIdx.x * B.box_elems;
   const unsigned *Mk = MASKED ? mask + (long)blockIdx.x * B.n * B.mwords : nullptr;
   const int n = B.n, kl = B.kl, nd = B.nd;
-  __shared__ double urow[2][W], acol[2][W];
-  __shared__ double srow[NR][256], scol[NR][256];
+  __shared__ FT urow[2][W], acol[2][W];
+  __shared__ FT srow[NR][256], scol[NR][256];
   __shared__ unsigned srw[MASKED ? NR : 1][256], scw[MASKED ? NR : 1][256];
 
   auto in_band = [&](int R, int C) {
     const int d = C - R + kl;
     return R < n && C < n && (unsigned)d < (unsigned)nd;
   };
-  // entry (R, C) of the stored matrix; entries outside the matrix or the band read
-  // stored entry 0 (a padding zero) and are replaced by zero where they are used
-  auto raw = [&](int R, int C) -> double { return (double)Bk[in_band(R, C) ? band_at(B, R, C - R + kl) : 0]; };
+  // Range-checked buffer accesses: an entry outside the matrix or the band has an offset
+  // past the end, so it loads as zero (pattern word zero) and a store to it is dropped.
+  const __amdgpu_buffer_rsrc_t rsB = buffer_rsrc(Bk, (unsigned)(B.box_elems * sizeof(FT)));
+  const __amdgpu_buffer_rsrc_t rsM = buffer_rsrc(Mk, MASKED ? (unsigned)(B.n * B.mwords * 4) : 0u);
+  auto boff = [&](int R, int C) -> unsigned {
+    return in_band(R, C) ? (unsigned)band_at(B, R, C - R + kl) * (unsigned)sizeof(FT) : kPastEnd;
+  };
+  auto raw = [&](int R, int C) -> FT { return load_one(rsB, boff(R, C), 0, (const FT *)nullptr); };
   // the ILU(k) pattern word holding (R, C)
   auto raw_mask = [&](int R, int C) -> unsigned {
-    return Mk[in_band(R, C) ? (long)R * B.mwords + ((C - R + kl) >> 5) : 0];
+    const unsigned o = in_band(R, C) ? (unsigned)(R * B.mwords + ((C - R + kl) >> 5)) * 4u : kPastEnd;
+    return load_one(rsM, o, 0, (const unsigned *)nullptr);
   };
-  auto mask_bit = [&](int R, int C, unsigned word) -> unsigned {
-    return (in_band(R, C) && ((word >> ((C - R + kl) & 31)) & 1u)) ? 1u : 0u;
-  };
+  // bit of (R, C) in its pattern word (a word loaded for an entry outside the band is 0)
+  auto mask_bit = [&](int R, int C, unsigned word) -> unsigned { return (word >> ((C - R + kl) & 31)) & 1u; };
   // column of tile q of this thread after step kg + t of the group starting at kg (row of
   // tile p: the same with ty)
   auto col_after = [&](int kg, int t, int q) { return kg + 16 * q + tx + (q == 0 && tx <= t ? W : 0); };
   auto row_after = [&](int kg, int t, int p) { return kg + 16 * p + ty + (p == 0 && ty <= t ? W : 0); };
 
-  double a[NR][NR];
+  FT a[NR][NR];
   unsigned m[NR];   // bit q: entry (row of tile p, column of tile q) is in the pattern
 #pragma unroll
   for (int p = 0; p < NR; ++p) {
@@ -167,14 +165,14 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       const int R = ty + 16 * p, C = tx + 16 * q;
-      a[p][q] = in_band(R, C) ? raw(R, C) : 0.0;
+      a[p][q] = raw(R, C);
       if (MASKED) m[p] |= mask_bit(R, C, raw_mask(R, C)) << q;
     }
   }
 
   // rows (at this thread's columns) and columns (at its rows) entering during the next
   // group, in registers; those of the current group in LDS (read by the same thread)
-  double nrow[NR], ncol[NR];
+  FT nrow[NR], ncol[NR];
   unsigned nrw[NR], ncw[NR];
   auto load_group = [&](int kg) {
 #pragma unroll
@@ -221,14 +219,14 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
       // LDS only: the band stores of earlier steps and the loads of the next group
       // touch other entries and stay in flight
       lds_barrier();
-      const double inv = 1.0 / urow[buf][tr];
-      double l[NR], u[NR];
+      const FT inv = (FT)1 / urow[buf][tr];
+      FT l[NR], u[NR];
 #pragma unroll
       for (int p = 0; p < NR; ++p) l[p] = acol[buf][ty + 16 * p] * inv;
 #pragma unroll
       for (int q = 0; q < NR; ++q) u[q] = urow[buf][tx + 16 * q];
-      if (prow_t) l[0] = 0.0;   // the pivot row and column are not updated
-      if (pcol_t) u[0] = 0.0;
+      if (prow_t) l[0] = (FT)0;   // the pivot row and column are not updated
+      if (pcol_t) u[0] = (FT)0;
 #pragma unroll
       for (int p = 0; p < NR; ++p)
 #pragma unroll
@@ -245,14 +243,14 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
           const int off = 16 * q + tx - tr + (q == 0 && tx < tr ? W : 0);   // column k + off
-          if (off <= kl && k + off < n) Bk[band_at(B, k, kl + off)] = (FT)(off == 0 ? inv : u[q]);
+          store_one(rsB, off <= kl ? boff(k, k + off) : kPastEnd, 0, off == 0 ? inv : u[q]);
         }
       }
       if (pcol_t) {
 #pragma unroll
         for (int p = 0; p < NR; ++p) {
           const int off = 16 * p + ty - tr + (p == 0 && ty < tr ? W : 0);   // row k + off
-          if (off >= 1 && off <= kl && k + off < n) Bk[band_at(B, k + off, kl - off)] = (FT)l[p];
+          store_one(rsB, off >= 1 && off <= kl ? boff(k + off, k) : kPastEnd, 0, l[p]);
         }
       }
       // row and column k + W take the pivot's place
@@ -261,7 +259,7 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
           const int C = col_after(kg, tr, q);
-          a[0][q] = in_band(k + W, C) ? srow[q][tid] : 0.0;
+          a[0][q] = srow[q][tid];
           if (MASKED) mr |= mask_bit(k + W, C, srw[q][tid]) << q;
         }
         if (MASKED) m[0] = mr;
@@ -270,14 +268,14 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
 #pragma unroll
         for (int p = 0; p < NR; ++p) {
           const int R = row_after(kg, tr, p);
-          a[p][0] = in_band(R, k + W) ? scol[p][tid] : 0.0;
+          a[p][0] = scol[p][tid];
           if (MASKED) m[p] = (m[p] & ~1u) | mask_bit(R, k + W, scw[p][tid]);
         }
       }
     }
     // tiles move down by one: tile (p, q) takes tile (p + 1, q + 1), cyclically
     {
-      double t[NR];
+      FT t[NR];
 #pragma unroll
       for (int q = 0; q < NR; ++q) t[q] = a[0][q];
 #pragma unroll

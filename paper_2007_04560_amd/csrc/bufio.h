@@ -47,4 +47,21 @@ ACCH_DEV void store_pair(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(word2, f), rs, voff, soff, 0);
 }
 
+// one value at voff + soff
+ACCH_DEV double load_one(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const double *) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+ACCH_DEV float load_one(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const float *) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+ACCH_DEV unsigned load_one(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const unsigned *) {
+  return __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0);
+}
+ACCH_DEV void store_one(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(word2, v), rs, voff, soff, 0);
+}
+ACCH_DEV void store_one(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, voff, soff, 0);
+}
+
 }  // namespace acch

@@ -147,6 +147,11 @@ int acch::validate_params(const acch_params &p) {
     if (bw > kBandMaxWidth)
       return fail(ACCH_EUNSUPPORTED, "ILU(k) / exact-LU subdomain boxes must be at most " +
                                          std::to_string(kBandMaxWidth) + " cells wide (owned width + 2 overlap)");
+    // one box's band is addressed with 31-bit byte offsets
+    const int bh = (p.n[1] + p.sub[1] - 1) / p.sub[1] + 2 * p.overlap;
+    const BandGeom bg = make_band_geom(bw, bh);
+    if ((double)bg.box_elems * (p.precision == ACCH_PREC_MIXED ? 4.0 : 8.0) >= 2147483648.0)
+      return fail(ACCH_EUNSUPPORTED, "ILU(k) / exact-LU subdomain box too large (its band must stay below 2 GiB)");
   }
   if (p.adaptive) {
     if (!(p.dt_min > 0 && p.dt_max >= p.dt_min && p.eta0 > 0)) return fail(ACCH_EINVAL, "dt_min, dt_max, eta0");
