@@ -23,6 +23,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -214,12 +215,17 @@ def run_batch(steps: int, warmup: int, with_sequential: bool = True):
 
     fields, params = batch_inputs()
     common = BATCH["common"]
-    best, tune = autotune(fields, params, boxes=BATCH["boxes"], steps=1, **common)
     shapes = [u.shape for u, _ in fields]
-    sub_params = with_boxes(shapes, params, best, BATCH["overlap"])
     dof = np.array([2 * u.size for u, _ in fields])
-    out = {"box": best, "autotune_s_per_step": {str(k): round(v, 4) for k, v in tune.items()}}
+    out = {"box": {}, "autotune_s_per_step": {}}
+    cache = os.path.join(tempfile.gettempdir(), "acch_batch_tune.json")
     for prec in ("fp64", "mixed"):
+        # box width tuned per precision (cached per instance-size mix, precision, overlap)
+        best, tune = autotune(fields, params, boxes=BATCH["boxes"], steps=1, cache=cache, precision=prec, **common)
+        out["box"][prec] = best
+        out["autotune_s_per_step"][prec] = {str(k): round(v, 4) for k, v in tune.items()}
+        sub_params = with_boxes(shapes, params, best, BATCH["overlap"])
+        out.setdefault("sub_params_by_precision", {})[prec] = sub_params
         if warmup > 0:
             with BatchSolver(fields, sub_params, precision=prec, **common) as b:
                 b.step(warmup)
@@ -247,6 +253,7 @@ def run_batch(steps: int, warmup: int, with_sequential: bool = True):
             r["info"] = info
         b.close()
         out[prec] = r
+    sub_params = out.pop("sub_params_by_precision")["fp64"]   # the FP64 batch's boxes
     if with_sequential:
         t_seq = 0.0
         n_seq = 0

@@ -4,12 +4,16 @@ The batched driver (acch_batch_*) runs all instances' subdomain solves in one la
 per stage; the subdomain box size trades parallelism (more, smaller boxes: more
 workgroups, shorter wavefront chains) against preconditioner quality (fewer GMRES
 iterations with larger boxes).  The autotuner times whole batched steps for a few
-box sizes on a copy of the batch and keeps the fastest.
+box sizes on a copy of the batch and keeps the fastest, per tuning problem (the mix of
+instance sizes, the precision and the overlap), optionally cached in a JSON file.
 """
 from __future__ import annotations
 
+import json
+import os
+import tempfile
 import time
-from typing import Dict, List, Sequence, Tuple
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 from .binding import BatchSolver
 
@@ -35,21 +39,67 @@ def with_boxes(shapes: Sequence[Tuple[int, int]], params: List[Dict], box: int, 
     return out
 
 
-def autotune(fields, params, boxes: Sequence[int] = (24, 32, 48, 64), steps: int = 1, **common):
-    """Time `steps` batched steps (after one untimed step that also records the
-    graphs) for each candidate box size; returns (best box, {box: seconds per step})."""
+def tune_key(shapes: Sequence[Tuple[int, int]], precision: str, overlap: int, boxes: Sequence[int]) -> str:
+    """Cache key of a tuning problem: the multiset of instance sizes, the precision, the
+    overlap and the candidate box widths."""
+    counts: Dict[Tuple[int, int], int] = {}
+    for s in shapes:
+        counts[tuple(int(x) for x in s)] = counts.get(tuple(int(x) for x in s), 0) + 1
+    return json.dumps({"shapes": sorted([list(k), v] for k, v in counts.items()), "precision": precision,
+                       "overlap": int(overlap), "boxes": [int(b) for b in boxes]}, sort_keys=True)
+
+
+def _load_cache(path: str) -> Dict[str, dict]:
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(path: str, data: Dict[str, dict]) -> None:
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    fd, tmp = tempfile.mkstemp(dir=d, suffix=".tmp")
+    with os.fdopen(fd, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)   # readers see the old or the new file, never a partial one
+
+
+def time_box(fields, params, box: int, steps: int, **common) -> float:
+    """Seconds per batched step with owned box width `box`, after one untimed step that
+    also records the graphs."""
     import torch
     overlap = common.get("overlap", 1)
     shapes = [u.shape for u, _ in fields]
-    timings = {}
-    for box in boxes:
-        with BatchSolver(fields, with_boxes(shapes, params, box, overlap), **common) as b:
-            b.step(1)
-            b.stream.synchronize()
-            t0 = time.perf_counter()
-            b.step(steps)
-            b.stream.synchronize()
-            timings[box] = (time.perf_counter() - t0) / steps
-        torch.cuda.synchronize()
+    with BatchSolver(fields, with_boxes(shapes, params, box, overlap), **common) as b:
+        b.step(1)
+        b.stream.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        b.stream.synchronize()
+        t = (time.perf_counter() - t0) / steps
+    torch.cuda.synchronize()
+    return t
+
+
+def autotune(fields, params, boxes: Sequence[int] = (24, 32, 48, 64), steps: int = 1, cache: Optional[str] = None,
+             timer: Optional[Callable[..., float]] = None, **common):
+    """Time `steps` batched steps for each candidate box size and return (best box,
+    {box: seconds per step}).  With `cache` (a JSON file), a tuning problem already in
+    the file (same instance sizes, precision, overlap and candidates) is answered from
+    it without timing, and a new result is added to it."""
+    timer = timer or time_box
+    key = tune_key([u.shape for u, _ in fields], common.get("precision", "fp64"), common.get("overlap", 1), boxes)
+    if cache:
+        hit = _load_cache(cache).get(key)
+        if hit is not None:
+            return int(hit["box"]), {int(k): float(v) for k, v in hit["seconds_per_step"].items()}
+    timings = {int(box): timer(fields, params, box, steps, **common) for box in boxes}
     best = min(timings, key=timings.get)
+    if cache:
+        data = _load_cache(cache)
+        data[key] = {"box": best, "seconds_per_step": {str(k): v for k, v in timings.items()}}
+        _save_cache(cache, data)
     return best, timings
