@@ -342,6 +342,8 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
   const SubInfo si = subs[blockIdx.x];
   const Rect rc = inside_rect(si, B, P.nx, P.ny, P.periodic);
   const FT *Bk = band + (long)blockIdx.x * B.box_elems;
+  // the coefficients through a buffer: 32-bit offsets, the diagonal's in a scalar register
+  const __amdgpu_buffer_rsrc_t rsB = buffer_rsrc(Bk, (unsigned)(B.box_elems * sizeof(FT)));
   double *yk = ybox + (long)blockIdx.x * B.nchunk * 64;
   const long n = (long)P.nx * P.ny;
   const int kl = B.kl, nd = B.nd, nch = B.nchunk;
@@ -373,9 +375,10 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
     double ra = 0.0, rb = 0.0;
     auto load = [&](int c, FT (&cf)[PER], double &rv) {
       const int cc = min(c, nch - 1);
-      const FT *Lc = Bk + (long)cc * nd * 64 + lane;
+      const unsigned vo = (unsigned)(cc * nd * 64 + lane) * (unsigned)sizeof(FT);
 #pragma unroll
-      for (int i = 0; i < PER; ++i) cf[i] = Lc[(long)(kl - min(dlo + i, dcl)) * 64];
+      for (int i = 0; i < PER; ++i)
+        cf[i] = load_one(rsB, vo, (unsigned)((kl - min(dlo + i, dcl)) * 64) * (unsigned)sizeof(FT), (const FT *)nullptr);
       if (wave == 0) {
         bool own;
         const int R = 64 * cc + lane;
@@ -432,12 +435,13 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
     double ya = 0.0, yb = 0.0, ia = 0.0, ib = 0.0;
     auto load = [&](int c, FT (&cf)[PER], double &yv, double &iv) {
       const int cc = max(c, 0);
-      const FT *Uc = Bk + (long)cc * nd * 64 + lane;
+      const unsigned vo = (unsigned)(cc * nd * 64 + lane) * (unsigned)sizeof(FT);
 #pragma unroll
-      for (int i = 0; i < PER; ++i) cf[i] = Uc[(long)(kl + min(dlo + i, dcl)) * 64];
+      for (int i = 0; i < PER; ++i)
+        cf[i] = load_one(rsB, vo, (unsigned)((kl + min(dlo + i, dcl)) * 64) * (unsigned)sizeof(FT), (const FT *)nullptr);
       if (wave == 0) {
         yv = yk[64 * cc + lane];
-        iv = (double)Uc[(long)kl * 64];
+        iv = (double)load_one(rsB, vo, (unsigned)(kl * 64) * (unsigned)sizeof(FT), (const FT *)nullptr);
       }
     };
     auto chunk = [&](int c, const FT (&cf)[PER], double yv, double inv) {
