@@ -116,6 +116,34 @@ def spmv_dots_bytes_per_cell(j_avg: float) -> float:
     return 24 * 8 + 16 + 16 + 16 * (j_avg + 1)
 
 
+def arnoldi_bytes_per_cell(k: float, m: int = 30) -> float:
+    """Sum over the k Arnoldi steps of one Newton solve (cycles of m) of B_arn(j) =
+    32 (j + 1) + 64 per cell (CGS: one read of basis vectors 0..j for the dots, one for
+    the update, plus the new vector); k may be fractional (a mean over Newton solves)."""
+    total, left = 0.0, k
+    while left > 0:
+        kk = min(left, m)
+        total += 32.0 * kk * (kk + 1) / 2.0 + 64.0 * kk
+        left -= kk
+    return total
+
+
+def step_bytes_per_cell(newton: int, gmres: int, steps: int, nnz: int, omega: float, sp: int, m: int = 30) -> float:
+    """Algorithmic bytes per cell of a run (the minimum the method moves: one read of
+    each operand and one write of each result): per Newton iteration B_res (two
+    evaluations: the iteration's residual and an accepted full step) + B_jac + B_fact
+    (one factorisation per step, factor reuse) + sum over its GMRES iterations of B_spmv
+    + B_ras + B_arn(j) + B_upd, with the mean GMRES count per Newton iteration."""
+    if newton <= 0:
+        return 0.0
+    k = gmres / newton
+    b_res, b_jac, b_spmv = 48.0, 32.0 + 8.0 * nnz, 8.0 * nnz + 32.0
+    b_ras = omega * 16.0 + omega * nnz * sp + 16.0
+    b_fact = omega * nnz * (8.0 + sp) * steps / newton
+    per_newton = 2 * b_res + b_jac + b_fact + k * (b_spmv + b_ras) + arnoldi_bytes_per_cell(k, m) + 16.0 * (k + 1)
+    return newton * per_newton
+
+
 # The dominant (Schwarz) kernel of each workload, as rocprofv3 names it, and its source.
 RAS_KERNELS = {
     "periodic512": ("void k_ras_apply2d<double, 1, 5, false>", "schwarz2d.hip"),
@@ -737,6 +765,15 @@ def main():
                    "kernel_ms": {k: round(v[0], 3) for k, v in stats.items() if v[1]}},
         "roofline": roofline,
     }
+    if not band:   # the whole run against the HBM roofline (ILU(0) subdomain solver)
+        omega = box / owned
+        tot = step_bytes_per_cell(newton_its, gmres_its, len(recs), nslot, omega, 4 if w["precision"] == "mixed" else 8,
+                                  w["gmres_restart"]) * r["ncell"]
+        line["config"]["whole_run_roofline"] = {
+            "algorithmic_bytes": int(tot), "achieved_GBps": round(tot / r["elapsed"] / 1e9, 1),
+            "frac": round(tot / r["elapsed"] / 1e9 / HBM_PEAK_GBS, 4),
+            "model": "per Newton iteration: 2 residuals + Jacobian + factorisation/step + per GMRES iteration "
+                     "(SpMV + left-RAS + CGS Arnoldi) + update, mean GMRES count per Newton iteration"}
     if w["adaptive"] and recs:
         # the same interval at the smallest step would take t_final / dt_min steps
         fixed = recs[-1]["t"] / w["dt_min"]
