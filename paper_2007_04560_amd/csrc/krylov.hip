@@ -132,7 +132,26 @@ __global__ __launch_bounds__(256) void k_gmres_orth(Batch bt, long n2s, double *
 // column, the rotations and g in LDS (one round trip), thread 0 works on LDS only,
 // then the block writes the results back; the earlier columns of H are read only for
 // the back substitution at the end of a cycle.
-ACCH_DEV void orth_tail(GmresState *st, double sum) {
+// The state it reads (new column, rotations, g) is loaded by the caller's threads
+// together with the partial sums of ||W_{j+1}||^2, so the two loads overlap.
+struct OrthIn {
+  double hc, g, c, s;   // this thread's entries (thread t: row / rotation t)
+};
+ACCH_DEV OrthIn orth_load(const GmresState *st) {
+  const int tid = threadIdx.x;
+  const int j = st->j;
+  OrthIn in{0.0, 0.0, 0.0, 0.0};
+  if (tid <= j) {
+    in.hc = st->hcol[tid];
+    in.g = st->g[tid];
+  }
+  if (tid < j) {
+    in.c = st->cs[tid];
+    in.s = st->sn[tid];
+  }
+  return in;
+}
+ACCH_DEV void orth_tail(GmresState *st, double sum, const OrthIn &in) {
   constexpr int M1 = kMaxRestart + 1;
   __shared__ double sH[M1 * kMaxRestart];   // columns 0..j, for the back substitution
   __shared__ double shc[M1];                // the new column j
@@ -141,12 +160,12 @@ ACCH_DEV void orth_tail(GmresState *st, double sum) {
   const int tid = threadIdx.x;
   const int j = st->j;
   if (tid <= j) {
-    shc[tid] = st->hcol[tid];
-    sg[tid] = st->g[tid];
+    shc[tid] = in.hc;
+    sg[tid] = in.g;
   }
   if (tid < j) {
-    sc_[tid] = st->cs[tid];
-    ss_[tid] = st->sn[tid];
+    sc_[tid] = in.c;
+    ss_[tid] = in.s;
   }
   __syncthreads();
   const double hn = sqrt(sum);
@@ -315,12 +334,13 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
     if (!sb->done || sb->applied) return;
   }
   if constexpr (MODE == kFinOrth) {
+    const OrthIn in = orth_load(sb);
     double acc[1];
     final_sum<1>(partials, stride, R.b0, R.nb, threadIdx.x, 256, acc);
     __shared__ double s_sum;
     if (threadIdx.x == 0) s_sum = acc[0];
     __syncthreads();
-    orth_tail(sb, s_sum);
+    orth_tail(sb, s_sum, in);
   } else if constexpr (MODE == kFinPlain) {
     double acc[4];
     final_sum<4>(partials, stride, R.b0, R.nb, threadIdx.x, 256, acc, nv);
