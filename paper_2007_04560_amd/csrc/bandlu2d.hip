@@ -316,9 +316,9 @@ constexpr int kSolveWaves = 8;   // waves per box: all share the finished-chunk 
 // takes the 64 rows in order, row s broadcast from its lane.  The lower (forward) and
 // upper (backward) tri are separate and start as zeros, so phase 2 needs no masks; the
 // backward sweep broadcasts acc / u_ss and scales every row by 1 / u_ss at the end.
-// Each wave's coefficients of the next chunk (and the right-hand side values of its
-// rows) are loaded while the current chunk is solved, into the other of two register
-// buffers; the loads use clamped addresses and no condition, so the only wait is for
+// Each wave's coefficients of the chunk after next (and the right-hand side values of
+// its rows) are loaded while the current chunk is solved, into the third of three
+// register sets; the loads use clamped addresses and no condition, so the only wait is for
 // data issued a chunk earlier.
 template <typename FT, int PER>
 __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandGeom B, BoxGeom G, const SubInfo *__restrict__ subs,
@@ -334,8 +334,11 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
     z += (long)jj * vstride;
     sc = st->inv_norm[jj];
   }
-  __shared__ double ring[kRing];
-  __shared__ double trl[65][64], tru[65][64];   // row 64: stores that are never read
+  // finished values: row x at x mod kRing and again kRing further, so the kl rows before
+  // (after) a chunk's rows lie at increasing addresses without wrapping
+  __shared__ double ring[2 * kRing];
+  // the chunk's own coefficients; rows 64..127 take stores of other columns, never read
+  __shared__ double trl[128][64], tru[128][64];
   __shared__ double psum[kSolveWaves][64];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar
@@ -347,17 +350,24 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
   double *yk = ybox + (long)blockIdx.x * B.nchunk * 64;
   const long n = (long)P.nx * P.ny;
   const int kl = B.kl, nd = B.nd, nch = B.nchunk;
-  for (int e = threadIdx.x; e < kRing; e += 64 * kSolveWaves) ring[e] = 0.0;
-  for (int e = threadIdx.x; e < 65 * 64; e += 64 * kSolveWaves) {
+  for (int e = threadIdx.x; e < 2 * kRing; e += 64 * kSolveWaves) ring[e] = 0.0;
+  for (int e = threadIdx.x; e < 128 * 64; e += 64 * kSolveWaves) {
     (&trl[0][0])[e] = 0.0;
     (&tru[0][0])[e] = 0.0;
   }
+  // value of row x (both copies) and the ring rows of a chunk's rows
+  auto ring_put = [&](int x, double v) {
+    ring[x & (kRing - 1)] = v;
+    ring[(x & (kRing - 1)) + kRing] = v;
+  };
   __syncthreads();
-  // this wave's share of the diagonals: dlo .. dlo + cnt - 1 (cnt <= PER, maybe 0)
-  const int per = (kl + kSolveWaves - 1) / kSolveWaves;
-  const int dlo = 1 + wave * per;
-  const int cnt = max(0, min(kl, (wave + 1) * per) - dlo + 1);
-  const int dcl = max(1, min(kl, dlo + cnt - 1));   // clamp of the loaded diagonals
+  // this wave's diagonals: dlo .. dlo + PER - 1 (8 PER >= kl); those beyond kl belong to no
+  // other wave and load as zero (offset past the end of the buffer)
+  const int dlo = 1 + wave * PER;
+  // offset (relative to the chunk's row) of diagonal d = kl - dp (L) or kl + dp (U)
+  auto coef_off = [&](int dp, int sign) -> unsigned {
+    return dp <= kl ? (unsigned)((kl + sign * dp) * 64) * (unsigned)sizeof(FT) : kPastEnd;
+  };
 
   // grid cell of box row R (-1: none), whether its cell is owned
   auto cell_of = [&](int R, bool &own) -> long {
@@ -371,36 +381,32 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
 
   // ---- forward: L y = R_k r
   {
-    FT ca[PER], cb[PER];
-    double ra = 0.0, rb = 0.0;
-    auto load = [&](int c, FT (&cf)[PER], double &rv) {
+    FT ca[PER], cb[PER], cc3[PER];
+    double ra = 0.0, rb = 0.0, rc3 = 0.0, fa = 0.0, fb = 0.0, fc = 0.0;   // wave 0: r of the rows, its scale
+    auto load = [&](int c, FT (&cf)[PER], double &rv, double &rf) {
       const int cc = min(c, nch - 1);
       const unsigned vo = (unsigned)(cc * nd * 64 + lane) * (unsigned)sizeof(FT);
 #pragma unroll
-      for (int i = 0; i < PER; ++i)
-        cf[i] = load_one(rsB, vo, (unsigned)((kl - min(dlo + i, dcl)) * 64) * (unsigned)sizeof(FT), (const FT *)nullptr);
+      for (int i = 0; i < PER; ++i) cf[i] = load_one(rsB, vo, coef_off(dlo + i, -1), (const FT *)nullptr);
       if (wave == 0) {
         bool own;
         const int R = 64 * cc + lane;
         const long g = cell_of(R, own);
         rv = r[max(g, 0L) + (R & 1) * n];
+        rf = g >= 0 && (kind != ACCH_RAS_RIGHT || own) ? sc : 0.0;   // R_k: rows of the box
       }
     };
-    auto chunk = [&](int c, const FT (&cf)[PER], double rv) {
+    auto chunk = [&](int c, const FT (&cf)[PER], double rv, double rf) {
       const int R = 64 * c + lane;
-      double part[4] = {0.0, 0.0, 0.0, 0.0};
-      if (wave == 0) {
-        bool own;
-        const long g = cell_of(R, own);
-        part[0] = g >= 0 && (kind != ACCH_RAS_RIGHT || own) ? sc * rv : 0.0;
-      }
+      double part[4] = {wave == 0 ? rf * rv : 0.0, 0.0, 0.0, 0.0};
+      // rd[PER - 1 - i]: row R - (dlo + i); the coefficient goes to trl row 63 - s for the
+      // chunk's own column s = lane - dp, to a row >= 64 (not read) for the others
+      const double *rd = &ring[(R & (kRing - 1)) + kRing - dlo - (PER - 1)];
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
-        if (i >= cnt) break;
-        const int dp = dlo + i;
         const double coef = (double)cf[i];
-        part[i & 3] -= coef * ring[(R - dp) & (kRing - 1)];
-        trl[min((unsigned)(lane - dp), 64u)][lane] = coef;
+        part[i & 3] -= coef * rd[PER - 1 - i];
+        trl[min(63 - lane + dlo + i, 127)][lane] = coef;
       }
       psum[wave][lane] = (part[0] + part[1]) + (part[2] + part[3]);
       lds_barrier();
@@ -409,36 +415,40 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
 #pragma unroll
         for (int q = 1; q < kSolveWaves; ++q) acc += psum[q][lane];
 #pragma unroll
-        for (int s = 0; s < 63; ++s) acc -= trl[s][lane] * bcast(acc, s);
-        ring[R & (kRing - 1)] = acc;
-        ring[(R + 64) & (kRing - 1)] = 0.0;   // the next chunk's rows
+        for (int s = 0; s < 63; ++s) acc -= trl[63 - s][lane] * bcast(acc, s);
+        ring_put(R, acc);
+        ring_put(R + 64, 0.0);   // the next chunk's rows
         yk[R] = acc;
       }
       lds_barrier();
     };
-    load(0, ca, ra);
-    for (int c = 0; c < nch; c += 2) {
-      load(c + 1, cb, rb);
-      chunk(c, ca, ra);
+    // three register sets rotate by name: chunk c + 2 loads while chunk c is solved
+    load(0, ca, ra, fa);
+    load(1, cb, rb, fb);
+    for (int c = 0; c < nch; c += 3) {
+      load(c + 2, cc3, rc3, fc);
+      chunk(c, ca, ra, fa);
       if (c + 1 >= nch) break;
-      load(c + 2, ca, ra);
-      chunk(c + 1, cb, rb);
+      load(c + 3, ca, ra, fa);
+      chunk(c + 1, cb, rb, fb);
+      if (c + 2 >= nch) break;
+      load(c + 4, cb, rb, fb);
+      chunk(c + 2, cc3, rc3, fc);
     }
   }
   // ---- backward: U x = y
-  if (wave == 0) ring[(64 * (nch - 1) + lane) & (kRing - 1)] = 0.0;   // the last chunk's rows
+  if (wave == 0) ring_put(64 * (nch - 1) + lane, 0.0);   // the last chunk's rows
   __syncthreads();
   FT *boxbuf = (FT *)boxbuf_;
   const long ncb = (long)G.nlev * G.bh;
   {
-    FT ca[PER], cb[PER];
-    double ya = 0.0, yb = 0.0, ia = 0.0, ib = 0.0;
+    FT ca[PER], cb[PER], cc3[PER];
+    double ya = 0.0, yb = 0.0, yc = 0.0, ia = 0.0, ib = 0.0, ic = 0.0;
     auto load = [&](int c, FT (&cf)[PER], double &yv, double &iv) {
       const int cc = max(c, 0);
       const unsigned vo = (unsigned)(cc * nd * 64 + lane) * (unsigned)sizeof(FT);
 #pragma unroll
-      for (int i = 0; i < PER; ++i)
-        cf[i] = load_one(rsB, vo, (unsigned)((kl + min(dlo + i, dcl)) * 64) * (unsigned)sizeof(FT), (const FT *)nullptr);
+      for (int i = 0; i < PER; ++i) cf[i] = load_one(rsB, vo, coef_off(dlo + i, 1), (const FT *)nullptr);
       if (wave == 0) {
         yv = yk[64 * cc + lane];
         iv = (double)load_one(rsB, vo, (unsigned)(kl * 64) * (unsigned)sizeof(FT), (const FT *)nullptr);
@@ -447,13 +457,14 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
     auto chunk = [&](int c, const FT (&cf)[PER], double yv, double inv) {
       const int R = 64 * c + lane;
       double part[4] = {wave == 0 ? yv : 0.0, 0.0, 0.0, 0.0};
+      // rd[i]: row R + dlo + i; the coefficient goes to tru row s = lane + dp for the
+      // chunk's own column s <= 63, to a row >= 64 (not read) for the others
+      const double *rd = &ring[(R & (kRing - 1)) + dlo];
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
-        if (i >= cnt) break;
-        const int dp = dlo + i;
         const double coef = (double)cf[i];
-        part[i & 3] -= coef * ring[(R + dp) & (kRing - 1)];
-        tru[min((unsigned)(lane + dp), 64u)][lane] = coef;
+        part[i & 3] -= coef * rd[i];
+        tru[min(lane + dlo + i, 127)][lane] = coef;
       }
       psum[wave][lane] = (part[0] + part[1]) + (part[2] + part[3]);
       lds_barrier();
@@ -464,8 +475,8 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
 #pragma unroll
         for (int s = 63; s >= 1; --s) acc -= tru[s][lane] * bcast(acc * inv, s);
         acc *= inv;
-        ring[R & (kRing - 1)] = acc;
-        ring[(R - 64) & (kRing - 1)] = 0.0;   // the next chunk's rows
+        ring_put(R, acc);
+        ring_put(R - 64, 0.0);   // the next chunk's rows
         bool own;
         const long g = cell_of(R, own);
         if (g >= 0) {
@@ -482,12 +493,16 @@ __global__ __launch_bounds__(64 * kSolveWaves) void k_band_solve2d(Phys P, BandG
     // the y values of the chunk were stored by the same threads (wave 0) in the forward
     // sweep
     load(nch - 1, ca, ya, ia);
-    for (int c = nch - 1; c >= 0; c -= 2) {
-      load(c - 1, cb, yb, ib);
+    load(nch - 2, cb, yb, ib);
+    for (int c = nch - 1; c >= 0; c -= 3) {
+      load(c - 2, cc3, yc, ic);
       chunk(c, ca, ya, ia);
       if (c - 1 < 0) break;
-      load(c - 2, ca, ya, ia);
+      load(c - 3, ca, ya, ia);
       chunk(c - 1, cb, yb, ib);
+      if (c - 2 < 0) break;
+      load(c - 4, cb, yb, ib);
+      chunk(c - 2, cc3, yc, ic);
     }
   }
 }
