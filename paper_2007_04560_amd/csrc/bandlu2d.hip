@@ -8,10 +8,10 @@
 // Factorisation (one workgroup of 256 threads per box): Gaussian elimination without
 // pivoting in the natural order, through a register window of the active part of the
 // band (details at k_band_factor2d).  With an ILU(k) pattern (a bit per band entry, from
-// the host's symbolic level-of-fill elimination) updates of entries outside the pattern
-// are dropped, which is ILU(k) in IKJ form.  The elimination runs in the precision of
-// the stored factors: FP64 factors in FP64, FP32 factors (the mixed-precision form) in
-// FP32.
+// the host's symbolic level-of-fill elimination) the entries outside the pattern are
+// zero wherever they are used, which is ILU(k) in IKJ form.  The elimination runs in the
+// precision of the stored factors: FP64 factors in FP64, FP32 factors (the
+// mixed-precision form) in FP32.
 //
 // Solve (eight waves per box): forward substitution with L, then backward with U, 64 rows
 // at a time (details at k_band_solve2d), in FP64 arithmetic on FP64 or FP32 factors.
@@ -208,13 +208,17 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
     for (int tr = 0; tr < tend; ++tr) {
       const int k = kg + tr, buf = k & 1;
       const bool prow_t = ty == tr, pcol_t = tx == tr;   // owns the pivot row / column
+      // ILU(k): entries off the pattern are updated like the others but never read --
+      // they are dropped here, the only place an entry's value is used (as part of the
+      // pivot row or column), which is the same as dropping every update to them
       if (prow_t) {
 #pragma unroll
-        for (int q = 0; q < NR; ++q) urow[buf][tx + 16 * q] = a[0][q];
+        for (int q = 0; q < NR; ++q)
+          urow[buf][tx + 16 * q] = (!MASKED || ((m[0] >> q) & 1u)) ? a[0][q] : (FT)0;
       }
       if (pcol_t) {
 #pragma unroll
-        for (int p = 0; p < NR; ++p) acol[buf][ty + 16 * p] = a[p][0];
+        for (int p = 0; p < NR; ++p) acol[buf][ty + 16 * p] = (!MASKED || (m[p] & 1u)) ? a[p][0] : (FT)0;
       }
       // LDS only: the band stores of earlier steps and the loads of the next group
       // touch other entries and stay in flight
@@ -230,13 +234,7 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
 #pragma unroll
       for (int p = 0; p < NR; ++p)
 #pragma unroll
-        for (int q = 0; q < NR; ++q) {
-          if (MASKED) {
-            if ((m[p] >> q) & 1u) a[p][q] -= l[p] * u[q];
-          } else {
-            a[p][q] -= l[p] * u[q];
-          }
-        }
+        for (int q = 0; q < NR; ++q) a[p][q] -= l[p] * u[q];
 
       // row k of U (1/u_kk on the diagonal) and column k of L over the band
       if (prow_t) {
