@@ -236,19 +236,26 @@ __global__ __launch_bounds__(256) void k_band_factor2d(BandGeom B, FT *__restric
 #pragma unroll
         for (int q = 0; q < NR; ++q) a[p][q] -= l[p] * u[q];
 
-      // row k of U (1/u_kk on the diagonal) and column k of L over the band
+      // row k of U (1/u_kk on the diagonal) and column k of L over the band: entry (k, k + off)
+      // lies kl + off diagonals into row k's chunk (a uniform base plus 64 off), entry
+      // (k + off, k) at diagonal kl - off of row k + off
       if (prow_t) {
+        const unsigned u0 = (unsigned)(((k >> 6) * nd + kl) * 64 + (k & 63));
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
           const int off = 16 * q + tx - tr + (q == 0 && tx < tr ? W : 0);   // column k + off
-          store_one(rsB, off <= kl ? boff(k, k + off) : kPastEnd, 0, off == 0 ? inv : u[q]);
+          const bool ok = off <= kl && k + off < n;
+          store_one(rsB, ok ? (u0 + 64u * (unsigned)off) * (unsigned)sizeof(FT) : kPastEnd, 0, off == 0 ? inv : u[q]);
         }
       }
       if (pcol_t) {
 #pragma unroll
         for (int p = 0; p < NR; ++p) {
           const int off = 16 * p + ty - tr + (p == 0 && ty < tr ? W : 0);   // row k + off
-          store_one(rsB, off >= 1 && off <= kl ? boff(k + off, k) : kPastEnd, 0, l[p]);
+          const int R = k + off;
+          const bool ok = off >= 1 && off <= kl && R < n;
+          const unsigned o = (unsigned)(((R >> 6) * nd + kl - off) * 64 + (R & 63));
+          store_one(rsB, ok ? o * (unsigned)sizeof(FT) : kPastEnd, 0, l[p]);
         }
       }
       // row and column k + W take the pivot's place
