@@ -26,7 +26,7 @@ struct BandGeom {
 };
 
 // Window tiles of the factorisation (16 nr window rows and columns >= kl + 1).
-constexpr int kBandTiles[] = {4, 6, 8, 10, 12, 13, 14};
+constexpr int kBandTiles[] = {4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14};
 constexpr int kBandMaxWidth = (16 * 14 - 1) / 4;   // widest padded box: 55 cells
 
 inline BandGeom make_band_geom(int bw, int bh) {

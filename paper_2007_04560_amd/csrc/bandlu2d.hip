@@ -537,7 +537,8 @@ hipError_t factor_t(const Phys &P, const BandGeom &B, int nsub, const SubInfo *s
     switch (B.nr) {
 #define ACCH_FACTOR(NR) \
   case NR: hipLaunchKernelGGL((k_band_factor2d<FT, NR, true>), dim3(nsub), dim3(256), 0, s, B, bd, mask); break;
-      ACCH_FACTOR(4) ACCH_FACTOR(6) ACCH_FACTOR(8) ACCH_FACTOR(10) ACCH_FACTOR(12) ACCH_FACTOR(13) ACCH_FACTOR(14)
+      ACCH_FACTOR(4) ACCH_FACTOR(5) ACCH_FACTOR(6) ACCH_FACTOR(7) ACCH_FACTOR(8) ACCH_FACTOR(9) ACCH_FACTOR(10)
+      ACCH_FACTOR(11) ACCH_FACTOR(12) ACCH_FACTOR(13) ACCH_FACTOR(14)
 #undef ACCH_FACTOR
       default: return hipErrorInvalidValue;
     }
@@ -545,7 +546,8 @@ hipError_t factor_t(const Phys &P, const BandGeom &B, int nsub, const SubInfo *s
     switch (B.nr) {
 #define ACCH_FACTOR(NR) \
   case NR: hipLaunchKernelGGL((k_band_factor2d<FT, NR, false>), dim3(nsub), dim3(256), 0, s, B, bd, nullptr); break;
-      ACCH_FACTOR(4) ACCH_FACTOR(6) ACCH_FACTOR(8) ACCH_FACTOR(10) ACCH_FACTOR(12) ACCH_FACTOR(13) ACCH_FACTOR(14)
+      ACCH_FACTOR(4) ACCH_FACTOR(5) ACCH_FACTOR(6) ACCH_FACTOR(7) ACCH_FACTOR(8) ACCH_FACTOR(9) ACCH_FACTOR(10)
+      ACCH_FACTOR(11) ACCH_FACTOR(12) ACCH_FACTOR(13) ACCH_FACTOR(14)
 #undef ACCH_FACTOR
       default: return hipErrorInvalidValue;
     }
