@@ -154,3 +154,25 @@ def test_steps_with_band_subsolvers_match_oracle(subsolver, level):
         assert _rel_l2(ug, vg, run.u, run.v) <= 1e-10, k
         assert info["newton_its"] == rec.newton_its
     assert its < its0
+
+
+# box widths whose register windows take 6, 8, 10, 11, 12 and 13 tiles of 16 (the smallest
+# nr with 16 nr >= 4 bw + 1); two subdomains along x, overlap 2, Neumann
+@pytest.mark.parametrize("bw,nr", [(22, 6), (30, 8), (38, 10), (42, 11), (46, 12), (50, 13)])
+@pytest.mark.parametrize("subsolver,level,precision", [("lu", 0, "fp64"), ("iluk", 1, "fp64"), ("lu", 0, "mixed")])
+def test_band_window_sizes_match_oracle(bw, nr, subsolver, level, precision):
+    """M^{-1} r with each register-window size of the band factorisation (FP32 factors
+    are eliminated in FP32) against the oracle's Schwarz operator with the same
+    subdomain solver."""
+    ov = 2
+    shape, bc, sub = (24, 2 * (bw - 2 * ov)), "neumann", (2, 1)
+    assert 16 * nr >= 4 * bw + 1 > 16 * (nr - 1)
+    s, Jo = _setup(shape, bc, sub, ov, subsolver, level, precision=precision, dt=1e-3)
+    assert s.info()["box_w"] == bw
+    r = np.random.default_rng(11).standard_normal(Jo.shape[0])
+    z = s.precondition(dev(r)).cpu().numpy()
+    zo = schwarz.Schwarz(Jo, shape, (sub[1], sub[0]), ov, bc, kind="left", solver=subsolver, level=level).apply(r)
+    if precision == "fp64":
+        assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
+    else:
+        assert np.linalg.norm(z - zo) <= 1e-4 * np.linalg.norm(zo)
