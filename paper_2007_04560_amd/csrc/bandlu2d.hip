@@ -16,8 +16,6 @@
 // Solve (eight waves per box): forward substitution with L, then backward with U, 64 rows
 // at a time (details at k_band_solve2d), in FP64 arithmetic on FP64 or FP32 factors.
 #include <algorithm>
-#include <type_traits>
-#include <utility>
 
 #include "../../include/acch.h"
 #include "band.h"
