@@ -21,14 +21,20 @@ Readings where the paper is silent (shared with the HIP path):
   the star and u at the cell), independent of numerically zero values.
 
 Subdomain solvers (Table 2): ILU(0), ILU(k) on the level-of-fill pattern, and the
-exact LU.
+exact LU.  A second base pattern for ILU(0) and ILU(k), the "box" pattern: every
+coupling between two box cells at most 2 apart along each axis, u and v both ways
+(the nonzero structure a structured-grid sparse-matrix library allocates for a
+stencil of width 2 that reaches the diagonal neighbours, explicit zeros included);
+the paper does not state its ILU pattern, and this is the reading under which plain
+ILU(0) converges as Table 2 reports.
 
 Pins: textbook ILU(0) property (LU)_ij = A_ij on the pattern; ILU(0) equals the
 exact LU when the pattern admits no fill; one subdomain with zero overlap and an
 exact subdomain solve reproduces the global solve; ILU(k) levels equal the
 fill-path characterisation (shortest path through lower-numbered vertices) and
 (LU)_ij = A_ij on the level-k pattern; ILU(k) for k beyond the fill reaches the
-exact LU (tests).
+exact LU (tests); on boxes at most 3 cells wide in x the box pattern holds all the
+fill of the natural order, so its ILU(0) is the exact LU (tests).
 """
 from __future__ import annotations
 
@@ -165,6 +171,25 @@ def ilu0(rows: Dict[int, Dict[int, float]]):
     return ilu_on_pattern(rows)
 
 
+def box_pattern(rows: Dict[int, Dict[int, float]], sub: Subdomain, width: int = 2):
+    """The rows of A_k extended by explicit zeros to the box pattern: entry (2i+t, 2j+t')
+    for every pair of box cells i, j whose coordinates differ by at most ``width`` along
+    every axis, and t, t' in {u, v}.  Values of A_k are kept."""
+    local = {c: i for i, c in enumerate(sub.cells)}
+    dim = len(sub.cells[0]) if sub.cells else 0
+    out = {i: dict(r) for i, r in rows.items()}
+    offs = list(np.ndindex(*([2 * width + 1] * dim)))
+    for i, c in enumerate(sub.cells):
+        for d in offs:
+            j = local.get(tuple(c[a] + d[a] - width for a in range(dim)))
+            if j is None:
+                continue
+            for t in (0, 1):
+                for tc in (0, 1):
+                    out[2 * i + t].setdefault(2 * j + tc, 0.0)
+    return out
+
+
 def fill_levels(rows: Dict[int, Dict[int, float]], k: int) -> Dict[int, Dict[int, int]]:
     """Level-of-fill pattern of ILU(k) (Table 2's ILU(1), ILU(2)): every entry of A has
     level 0; eliminating pivot p from row i creates or updates entry (i, j), j > p,
@@ -275,7 +300,8 @@ class Schwarz:
 
     kind: "left" (restricted extension; the paper's choice), "right" (restricted
     restriction) or "classical" (eq. invM).  solver (Section 3.1 and Table 2):
-    "ilu0"; "iluk" with ``level`` = k (ILU(1), ILU(2)); "lu", the exact subdomain
+    "ilu0"; "iluk" with ``level`` = k (ILU(1), ILU(2)); "iluk_box", ILU(k) whose level-0
+    pattern is ``box_pattern`` (k = 0: ILU(0) on the box pattern); "lu", the exact subdomain
     solve (a sparse direct factorisation of A_k; the result does not depend on its
     ordering).  ``exact=True`` is the same as solver="lu"."""
 
@@ -296,6 +322,8 @@ class Schwarz:
                 self.factors.append(spla.splu(to_sparse(rows)))
             elif self.solver == "iluk":
                 self.factors.append(iluk(rows, level))
+            elif self.solver == "iluk_box":
+                self.factors.append(iluk(box_pattern(rows, sub), level))
             elif self.solver == "ilu0":
                 self.factors.append(ilu0(rows))
             else:

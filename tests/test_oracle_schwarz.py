@@ -198,7 +198,75 @@ def test_iluk_zero_is_ilu0_and_full_level_is_exact_lu():
     assert np.max(np.abs(L @ U - A)) <= 1e-12 * np.max(np.abs(A))
 
 
-@pytest.mark.parametrize("solver,level", [("iluk", 1), ("iluk", 2), ("lu", 0)])
+def test_box_pattern_extends_the_stencil_pattern():
+    """The box pattern holds every entry of A_k (values kept) and adds zeros so that an
+    interior cell's two rows couple to all 25 cells at Chebyshev distance <= 2, both
+    types: 50 entries per row; no entry couples cells further apart."""
+    shape = (12, 14)
+    J = _J(shape, "neumann")
+    sub = schwarz.decompose(shape, (2, 2), 1, "neumann")[0]
+    rows = schwarz.subdomain_matrix(J, sub, shape)
+    box = schwarz.box_pattern(rows, sub)
+    for i, r in rows.items():
+        for j, v in r.items():
+            assert box[i][j] == v
+    for i, r in box.items():
+        ci = sub.cells[i // 2]
+        for j, v in r.items():
+            cj = sub.cells[j // 2]
+            assert max(abs(ci[0] - cj[0]), abs(ci[1] - cj[1])) <= 2
+            if j not in rows[i]:
+                assert v == 0.0
+    ci = sub.cells.index((4, 4))
+    assert len(box[2 * ci]) == len(box[2 * ci + 1]) == 50
+
+
+def test_box_ilu0_is_exact_lu_on_narrow_boxes():
+    """On a box 3 cells wide every cell of rows y-2 .. y+2 is within distance 2 of a cell
+    in row y, so the box pattern is the whole envelope of the natural order, which holds
+    all LU fill: ILU(0) on it is the exact LU.  The same box with the width-1 pattern
+    drops fill (control)."""
+    shape = (9, 3)
+    J = _J(shape, "neumann", dt=1e-3)
+    sub = schwarz.decompose(shape, (1, 1), 0, "neumann")[0]
+    rows = schwarz.subdomain_matrix(J, sub, shape)
+    A = schwarz.to_dense(rows)
+    b = np.random.default_rng(3).standard_normal(len(A))
+    for width, exact in ((2, True), (1, False)):
+        fac = schwarz.ilu0(schwarz.box_pattern(rows, sub, width))
+        F = schwarz.to_dense(fac)
+        L = np.tril(F, -1) + np.eye(len(F))
+        err = np.max(np.abs(L @ np.triu(F) - A)) / np.max(np.abs(A))
+        if exact:
+            assert err <= 1e-13
+            x = schwarz.ilu_solve(fac, b)
+            assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-10 * np.linalg.norm(x)
+        else:
+            assert err > 1e-10   # dropped fill, far above rounding
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_box_iluk_defining_property(k):
+    """ILU(k) on the box base pattern: (LU)_ij = A_ij on the level-k pattern of the box
+    pattern, zero outside it."""
+    shape = (12, 14)
+    J = _J(shape, "periodic")
+    sub = schwarz.decompose(shape, (2, 2), 1, "periodic")[3]
+    rows = schwarz.box_pattern(schwarz.subdomain_matrix(J, sub, shape), sub)
+    lev = schwarz.fill_levels(rows, k)
+    F = schwarz.to_dense(schwarz.iluk(rows, k))
+    n = len(F)
+    L = np.tril(F, -1) + np.eye(n)
+    A = schwarz.to_dense(rows)
+    mask = np.zeros((n, n), dtype=bool)
+    for i, r in lev.items():
+        for j in r:
+            mask[i, j] = True
+    assert np.all(F[~mask] == 0.0)
+    assert np.max(np.abs((L @ np.triu(F) - A)[mask])) <= 1e-12 * np.max(np.abs(A))
+
+
+@pytest.mark.parametrize("solver,level", [("iluk", 1), ("iluk", 2), ("lu", 0), ("iluk_box", 0), ("iluk_box", 1)])
 def test_subdomain_solvers_precondition_gmres(solver, level):
     """Left-RAS with each Table 2 subdomain solver drives GMRES to the direct solution;
     the exact subdomain LU solves A_k x = r_k to rounding."""
