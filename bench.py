@@ -511,15 +511,19 @@ def study_line(args):
     table2 = {}
     for name, kw in [("ILU(0)", dict(subsolver="ilu0")), ("ILU(0) shift 0.02", dict(subsolver="ilu0", ilu_shift=0.02)),
                      ("ILU(1)", dict(subsolver="iluk", fill_level=1)), ("ILU(2)", dict(subsolver="iluk", fill_level=2)),
-                     ("LU", dict(subsolver="lu"))]:
+                     ("LU", dict(subsolver="lu")),
+                     ("ILU(0) box pattern", dict(subsolver="iluk_box", fill_level=0)),
+                     ("ILU(1) box pattern", dict(subsolver="iluk_box", fill_level=1)),
+                     ("ILU(2) box pattern", dict(subsolver="iluk_box", fill_level=2))]:
         table2[name] = {"refactor": run(schwarz="classical", overlap=1, ilu_reuse=False, **kw),
                         "reuse": run(schwarz="classical", overlap=1, ilu_reuse=True, **kw)}
-    table3 = {}
+    table3, table3_box = {}, {}
     for kind in ("classical", "left", "right"):
         for ov in (0, 1, 2):
             if kind != "classical" and ov == 0:
                 continue   # without overlap both restricted variants are classical AS
             table3[f"{kind} overlap {ov}"] = run(schwarz=kind, overlap=ov, ilu_shift=0.02)
+            table3_box[f"{kind} overlap {ov}"] = run(schwarz=kind, overlap=ov, subsolver="iluk_box", fill_level=0)
     best = table3.get("left overlap 1", {})
     line = {"metric": "time of the first 10 steps (paper's 2D solver study)", "value": best.get("seconds"),
             "unit": "s", "n_gpus": 1, "steps": w["steps"], "warmup": 1,
@@ -529,7 +533,8 @@ def study_line(args):
             "config": {"workload": "study2d: 2D Neumann 128x128, alpha 4, beta 2, gamma 5e-3, theta 0.1, rho 1e-3, "
                                    "u0 = 0.55 + 0.05 U(-1,1), 10 steps dt = 1e-4, Newton eps_r 1e-6, GMRES(30) "
                                    "xi_r 1e-8, 6x4 subdomains; value = left-RAS overlap 1, ILU(0) shift 0.02, reuse",
-                       "table2_classical_overlap1": table2, "table3_ilu0_reuse": table3},
+                       "table2_classical_overlap1": table2, "table3_ilu0_reuse": table3,
+                       "table3_box_ilu0_reuse": table3_box},
             "roofline": None}
     print(json.dumps(line), flush=True)
     return 0
@@ -638,8 +643,9 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--sub", default=None, help="subdomains per axis, x,y[,z] (default: the workload's)")
     ap.add_argument("--overlap", type=int, default=None, help="subdomain overlap (default: the workload's)")
-    ap.add_argument("--subsolver", default=None, choices=["ilu0", "ilu1", "ilu2", "lu"],
-                    help="subdomain solver (Table 2; default: the workload's)")
+    ap.add_argument("--subsolver", default=None, choices=["ilu0", "ilu1", "ilu2", "lu", "ilu0box", "ilu1box", "ilu2box"],
+                    help="subdomain solver (Table 2; default: the workload's); the *box solvers take the width-2 "
+                         "box of cell couplings as the level-0 pattern")
     ap.add_argument("--ilu-shift", type=float, default=None, help="diagonal shift of the subdomain matrices")
     args = ap.parse_args()
     if args.calibrate_copy:
@@ -679,8 +685,9 @@ def main():
         w["text"] += f" [subdomains {'x'.join(map(str, w['sub']))}, overlap {w['overlap']}]"
     if args.subsolver or args.ilu_shift is not None:
         if args.subsolver:
-            w["subsolver"] = {"ilu1": "iluk", "ilu2": "iluk"}.get(args.subsolver, args.subsolver)
-            w["fill_level"] = {"ilu1": 1, "ilu2": 2}.get(args.subsolver, 0)
+            w["subsolver"] = {"ilu1": "iluk", "ilu2": "iluk", "ilu0box": "iluk_box", "ilu1box": "iluk_box",
+                              "ilu2box": "iluk_box"}.get(args.subsolver, args.subsolver)
+            w["fill_level"] = {"ilu1": 1, "ilu2": 2, "ilu1box": 1, "ilu2box": 2}.get(args.subsolver, 0)
             if args.subsolver == "lu" and args.ilu_shift is None:
                 w["ilu_shift"] = 0.0
         if args.ilu_shift is not None:
@@ -721,7 +728,8 @@ def main():
         if band:   # the band solve reads every stored diagonal of each box once
             bw, bh = info["box_w"], info["box_h"]
             nrow = 2 * bw * bh
-            bytes_launch = info["nsub"] * (nrow * (8 * bw + 1) * sp + 16 * bw * bh) + 16 * r["ncell"]
+            nd = 8 * bw + 1 + (10 if w.get("subsolver") == "iluk_box" else 0)   # stored diagonals
+            bytes_launch = info["nsub"] * (nrow * nd * sp + 16 * bw * bh) + 16 * r["ncell"]
         else:
             bytes_launch = ras_bytes_per_cell(box, owned, nslot=nslot, sp=sp) * r["ncell"]
         achieved = bytes_launch / avg_s / 1e9

@@ -47,13 +47,18 @@ enum { ACCH_OFF = -1, ACCH_SWITCH_DEFAULT = 0, ACCH_ON = 1 };
 /* Schwarz variant (Section 3.1): left-restricted (restricted extension, the paper's
  * choice), right-restricted (restricted restriction) or classical (eq. invM). */
 enum { ACCH_RAS_LEFT = 0, ACCH_RAS_RIGHT = 1, ACCH_AS_CLASSICAL = 2 };
-/* Subdomain solver for inv(A_k) (Section 3.1: "a sparse LU factorization or incomplete
- * LU factorization"; the four solvers of Table 2): ILU(0) on the Jacobian stencil
- * (default), ILU(k) on the level-of-fill pattern with k = acch_params.fill_level, or
- * the exact LU.  ILU(k) and LU are 2D, single-instance, and need padded subdomain boxes
- * (owned width + 2 overlap) of at most 55 cells in x: they store the band of A_k in
- * the natural order (half bandwidth 4 box widths) and factor it without pivoting. */
-enum { ACCH_SUB_ILU0 = 0, ACCH_SUB_ILUK = 1, ACCH_SUB_LU = 2 };
+/* Subdomain solver for inv(A_k) (Section 3.1: sparse LU or incomplete LU; the four
+ * solvers of Table 2): ILU(0) on the Jacobian stencil (default), ILU(k) on the
+ * level-of-fill pattern with k = acch_params.fill_level, the exact LU, or ILU(k) whose
+ * level-0 pattern is the "box" pattern (every coupling of two cells at most 2 apart
+ * along each axis, u and v both ways: the structure a structured-grid sparse-matrix
+ * library allocates for this stencil; k = fill_level, 0 allowed, 0 is ILU(0) on it).
+ * The paper does not state its ILU pattern.  ILU(k), box ILU(k) and LU are 2D,
+ * single-instance, and need padded subdomain boxes (owned width + 2 overlap) of at
+ * most 55 cells in x (54 with the box pattern): they store the band of A_k in the
+ * natural order (half bandwidth 4 box widths, plus 5 with the box pattern) and factor
+ * it without pivoting. */
+enum { ACCH_SUB_ILU0 = 0, ACCH_SUB_ILUK = 1, ACCH_SUB_LU = 2, ACCH_SUB_ILUK_BOX = 3 };
 /* Precision of the subdomain ILU(0) factors and triangular solves; the residual,
  * Jacobian products, Arnoldi process, Newton update and diagnostics stay FP64. */
 enum { ACCH_PREC_FP64 = 0, ACCH_PREC_MIXED = 1 };
@@ -93,7 +98,8 @@ typedef struct {
                                              A_k + sigma diag(A_k); 0 is plain ILU(0)
                                              (also ILU(k); the exact LU ignores it)    */
   int subsolver;                          /* ACCH_SUB_* (0: ILU(0))                      */
-  int fill_level;                         /* k of ACCH_SUB_ILUK, 1..8                    */
+  int fill_level;                         /* k of ACCH_SUB_ILUK (1..8) and of
+                                             ACCH_SUB_ILUK_BOX (0..8)                  */
   void *workspace;                        /* device buffer, >= acch_workspace_bytes    */
   size_t workspace_bytes;
   void *stream;                           /* hipStream_t                              */
@@ -201,7 +207,8 @@ int acch_solve_step(acch_ctx *c, double dt, acch_step_info *info);
  *     width, height (all boxes padded to the same width/height).
  *   ACCH_EXPORT_BAND: the ILU(k) / exact-LU factors as FP64 [sub][R][d], R over the
  *     2 bw bh unknowns of the padded box (cell (i, j) of the box: R = 2 (j bw + i) for
- *     u, + 1 for v), d = 0 .. 8 bw for column R + d - 4 bw; L below the diagonal
+ *     u, + 1 for v), d = 0 .. 2 kl for column R + d - kl (kl = 4 bw, or 4 bw + 5 for
+ *     ACCH_SUB_ILUK_BOX); L below the diagonal
  *     (unit diagonal implied), U on and above it, with 1/u_RR stored on the diagonal.
  *     Box cells outside the grid are identity rows. */
 enum { ACCH_EXPORT_JACOBIAN = 0, ACCH_EXPORT_FACTORS = 1, ACCH_EXPORT_BOXES = 2, ACCH_EXPORT_BAND = 3 };

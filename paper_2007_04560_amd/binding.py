@@ -156,7 +156,7 @@ _BC = {"periodic": 0, "neumann": 1}
 _SCHWARZ = {"left": 0, "right": 1, "classical": 2}
 _PREC = {"fp64": 0, "mixed": 1}
 _MOB = {"midpoint": 0, "average": 1, "explicit": 2}
-_SUBSOLVER = {"ilu0": 0, "iluk": 1, "lu": 2}
+_SUBSOLVER = {"ilu0": 0, "iluk": 1, "lu": 2, "iluk_box": 3}
 
 
 def make_params(shape: Sequence[int], *, bc="periodic", L=(1.0, 1.0), alpha=1.2, beta=1.2, theta=0.1,
@@ -407,7 +407,7 @@ class Solver:
         """ILU(k) / exact-LU factors [sub][R][d] (include/acch.h, ACCH_EXPORT_BAND)."""
         i = self.info()
         n = 2 * i["box_w"] * i["box_h"]
-        return self._export(EXPORT_BAND, np.float64).reshape(i["nsub"], n, 8 * i["box_w"] + 1)
+        return self._export(EXPORT_BAND, np.float64).reshape(i["nsub"], n, -1)   # 2 kl + 1 diagonals
 
 
 class BatchSolver:

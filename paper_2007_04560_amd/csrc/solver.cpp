@@ -137,19 +137,24 @@ int acch::validate_params(const acch_params &p) {
   if (p.mobility_mode < 0 || p.mobility_mode > 2) return fail(ACCH_EINVAL, "mobility_mode");
   if (p.overlap < 0) return fail(ACCH_EINVAL, "overlap");
   if (!(p.ilu_shift >= 0.0 && p.ilu_shift < 10.0)) return fail(ACCH_EINVAL, "ilu_shift must be in [0, 10)");
-  if (p.subsolver != ACCH_SUB_ILU0 && p.subsolver != ACCH_SUB_ILUK && p.subsolver != ACCH_SUB_LU)
+  if (p.subsolver != ACCH_SUB_ILU0 && p.subsolver != ACCH_SUB_ILUK && p.subsolver != ACCH_SUB_LU &&
+      p.subsolver != ACCH_SUB_ILUK_BOX)
     return fail(ACCH_EINVAL, "subsolver");
   if (p.subsolver == ACCH_SUB_ILUK && (p.fill_level < 1 || p.fill_level > 8))
     return fail(ACCH_EINVAL, "fill_level must be 1..8 for ILU(k)");
+  if (p.subsolver == ACCH_SUB_ILUK_BOX && (p.fill_level < 0 || p.fill_level > 8))
+    return fail(ACCH_EINVAL, "fill_level must be 0..8 for box ILU(k)");
   if (p.subsolver != ACCH_SUB_ILU0) {
     if (nd != 2) return fail(ACCH_EUNSUPPORTED, "ILU(k) and exact-LU subdomain solvers are 2D");
+    const bool box = p.subsolver == ACCH_SUB_ILUK_BOX;
+    const int maxw = box ? kBandMaxWidthBox : kBandMaxWidth;
     const int bw = (p.n[0] + p.sub[0] - 1) / p.sub[0] + 2 * p.overlap;
-    if (bw > kBandMaxWidth)
-      return fail(ACCH_EUNSUPPORTED, "ILU(k) / exact-LU subdomain boxes must be at most " +
-                                         std::to_string(kBandMaxWidth) + " cells wide (owned width + 2 overlap)");
+    if (bw > maxw)
+      return fail(ACCH_EUNSUPPORTED, "ILU(k) / exact-LU subdomain boxes must be at most " + std::to_string(maxw) +
+                                         " cells wide (owned width + 2 overlap)");
     // one box's band is addressed with 31-bit byte offsets
     const int bh = (p.n[1] + p.sub[1] - 1) / p.sub[1] + 2 * p.overlap;
-    const BandGeom bg = make_band_geom(bw, bh);
+    const BandGeom bg = make_band_geom(bw, bh, box);
     if ((double)bg.box_elems * (p.precision == ACCH_PREC_MIXED ? 4.0 : 8.0) >= 2147483648.0)
       return fail(ACCH_EUNSUPPORTED, "ILU(k) / exact-LU subdomain box too large (its band must stay below 2 GiB)");
   }
@@ -350,6 +355,11 @@ int acch::build_geometry(const acch_params &p, Geometry &geo) {
   return ACCH_OK;
 }
 
+// Subdomain solvers whose band factorisation keeps a pattern (the mask words).
+static bool masked_sub(const acch_params &p) {
+  return p.subsolver == ACCH_SUB_ILUK || p.subsolver == ACCH_SUB_ILUK_BOX;
+}
+
 static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   const size_t n2 = 2 * (size_t)geo.ncell * sizeof(double);
   const int m = p.gmres_restart;
@@ -395,10 +405,10 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_out = take(64 * sizeof(double));
   L.off_tbox = take(d3 ? (size_t)geo.G.nsub * 2 * geo.G.ncb * sizeof(double) : 0);   // 3D transposed boxes
   L.off_own = take(geo.own.size() * sizeof(int));
-  const BandGeom B = make_band_geom(geo.G.bw, geo.G.bh);
+  const BandGeom B = make_band_geom(geo.G.bw, geo.G.bh, p.subsolver == ACCH_SUB_ILUK_BOX);
   L.off_band = take(band ? (size_t)geo.G.nsub * B.box_elems * fsz : 0);
   L.off_bandy = take(band ? (size_t)geo.G.nsub * B.nchunk * 64 * sizeof(double) : 0);
-  L.off_mask = take(p.subsolver == ACCH_SUB_ILUK ? (size_t)geo.G.nsub * B.n * B.mwords * sizeof(unsigned) : 0);
+  L.off_mask = take(masked_sub(p) ? (size_t)geo.G.nsub * B.n * B.mwords * sizeof(unsigned) : 0);
   L.total = o;
 }
 
@@ -427,14 +437,15 @@ static bool admissible_host(const double *u, const double *v, long n) {
 
 // ---------------------------------------------------------------------------
 // ILU(k) pattern of a box matrix (band.h numbering): symbolic elimination with
-// levels of fill.  Entries of A_k have level 0; eliminating pivot p from row R gives
+// levels of fill.  Entries of A_k (with box: every coupling of two cells at most 2
+// apart along each axis, both types) have level 0; eliminating pivot p from row R gives
 // entry (R, C), C > p, the level lev(R, p) + lev(p, C) + 1 (the smallest over the
 // pivots); entries of level above k are dropped.  Rows are processed in order and the
 // pivots of a row in increasing column order, fill of the same row included.  Cells
 // of the padded box outside the rectangle [ilo, ihi) x [jlo, jhi) are identity rows.
 // Bit d of word d / 32 of row R is set for entry (R, R + d - kl).
 // ---------------------------------------------------------------------------
-static void iluk_pattern(const BandGeom &B, int ilo, int ihi, int jlo, int jhi, int k, unsigned *bits) {
+static void iluk_pattern(const BandGeom &B, int ilo, int ihi, int jlo, int jhi, int k, bool box, unsigned *bits) {
   static const int kSl[24][4] = {{0, 0, 0, 0},  {0, 0, -1, 0}, {0, 0, 1, 0},  {0, 0, 0, -1}, {0, 0, 0, 1},
                                  {0, 0, -2, 0}, {0, 0, 2, 0},  {0, 0, 0, -2}, {0, 0, 0, 2},  {0, 0, -1, -1},
                                  {0, 0, 1, -1}, {0, 0, -1, 1}, {0, 0, 1, 1},  {0, 1, 0, 0},  {0, 1, -1, 0},
@@ -453,7 +464,12 @@ static void iluk_pattern(const BandGeom &B, int ilo, int ihi, int jlo, int jhi, 
       lev[C] = l;
       cols.push_back(C);
     };
-    if (inside(i, j)) {
+    if (inside(i, j) && box) {   // level 0: both types of every cell up to 2 away per axis
+      for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx)
+          if (inside(i + dx, j + dy))
+            for (int tc = 0; tc < 2; ++tc) add(2 * ((j + dy) * bw + i + dx) + tc, 0);
+    } else if (inside(i, j)) {
       for (const auto &q : kSl) {
         if (q[0] != t || !inside(i + q[2], j + q[3])) continue;
         add(2 * ((j + q[3]) * bw + i + q[2]) + q[1], 0);
@@ -845,10 +861,10 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->band = p.subsolver != ACCH_SUB_ILU0;
   std::vector<unsigned> maskh;
   if (c->band) {
-    c->bg = make_band_geom(c->geo.G.bw, c->geo.G.bh);
+    c->bg = make_band_geom(c->geo.G.bw, c->geo.G.bh, p.subsolver == ACCH_SUB_ILUK_BOX);
     c->bandf = c->ws + L.off_band;
     c->bandy = (double *)(c->ws + L.off_bandy);
-    if (p.subsolver == ACCH_SUB_ILUK) {
+    if (masked_sub(p)) {
       c->bandmask = (unsigned *)(c->ws + L.off_mask);
       // one pattern per distinct rectangle of grid cells inside the padded box
       const size_t per = (size_t)c->bg.n * c->bg.mwords;
@@ -871,7 +887,8 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
         if (at == keys.size()) {
           keys.push_back(key);
           first.push_back((size_t)b);
-          iluk_pattern(c->bg, ilo, ihi, jlo, jhi, p.fill_level, maskh.data() + per * b);
+          iluk_pattern(c->bg, ilo, ihi, jlo, jhi, p.fill_level, p.subsolver == ACCH_SUB_ILUK_BOX,
+                       maskh.data() + per * b);
         } else {
           std::memcpy(maskh.data() + per * b, maskh.data() + per * first[at], per * sizeof(unsigned));
         }

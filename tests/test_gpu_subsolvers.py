@@ -47,19 +47,24 @@ def _setup(shape, bc, sub, ov, subsolver, level=0, precision="fp64", schwarz_kin
 
 
 @pytest.mark.parametrize("shape,bc,sub,ov", CASES)
-@pytest.mark.parametrize("level", [1, 2])
-def test_iluk_band_factors_match_oracle(shape, bc, sub, ov, level):
+@pytest.mark.parametrize("subsolver,level", [("iluk", 1), ("iluk", 2), ("iluk_box", 0), ("iluk_box", 1)])
+def test_iluk_band_factors_match_oracle(shape, bc, sub, ov, subsolver, level):
     """Every entry of the GPU's ILU(k) factors (band storage) equals the oracle's
-    textbook ILU(k) on the level-k pattern, and the band is zero off that pattern."""
-    s, Jo = _setup(shape, bc, sub, ov, "iluk", level)
+    textbook ILU(k) on the level-k pattern (of the stencil or of the box base
+    pattern), and the band is zero off that pattern."""
+    s, Jo = _setup(shape, bc, sub, ov, subsolver, level)
     band = s.export_band().cpu().numpy()
     info = s.info()
     bw = info["box_w"]
-    kl = 4 * bw
+    kl = 4 * bw + (5 if subsolver == "iluk_box" else 0)
+    assert band.shape[2] == 2 * kl + 1
     subs = schwarz.decompose(shape, (sub[1], sub[0]), ov, bc)
     worst, scale = 0.0, 0.0
     for k, sd in enumerate(subs):
-        fac = schwarz.iluk(schwarz.subdomain_matrix(Jo, sd, shape), level)
+        rows = schwarz.subdomain_matrix(Jo, sd, shape)
+        if subsolver == "iluk_box":
+            rows = schwarz.box_pattern(rows, sd)
+        fac = schwarz.iluk(rows, level)
         seen = np.zeros(band.shape[1:], dtype=bool)
         for i, (by, bx) in enumerate(sd.cells):
             for t in (0, 1):
@@ -80,7 +85,7 @@ def test_iluk_band_factors_match_oracle(shape, bc, sub, ov, level):
 
 
 @pytest.mark.parametrize("shape,bc,sub,ov", CASES)
-@pytest.mark.parametrize("subsolver,level", [("iluk", 1), ("iluk", 2), ("lu", 0)])
+@pytest.mark.parametrize("subsolver,level", [("iluk", 1), ("iluk", 2), ("lu", 0), ("iluk_box", 0), ("iluk_box", 2)])
 def test_band_preconditioner_matches_oracle(shape, bc, sub, ov, subsolver, level):
     s, Jo = _setup(shape, bc, sub, ov, subsolver, level)
     r = np.random.default_rng(7).standard_normal(Jo.shape[0])
@@ -91,7 +96,7 @@ def test_band_preconditioner_matches_oracle(shape, bc, sub, ov, subsolver, level
 
 
 @pytest.mark.parametrize("kind", ["right", "classical"])
-@pytest.mark.parametrize("subsolver,level", [("iluk", 2), ("lu", 0)])
+@pytest.mark.parametrize("subsolver,level", [("iluk", 2), ("lu", 0), ("iluk_box", 0)])
 def test_band_preconditioner_variants_match_oracle(kind, subsolver, level):
     shape, bc, sub, ov = (45, 58), "neumann", (3, 2), 2
     s, Jo = _setup(shape, bc, sub, ov, subsolver, level, schwarz_kind=kind)
@@ -102,7 +107,7 @@ def test_band_preconditioner_variants_match_oracle(kind, subsolver, level):
     assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
 
 
-@pytest.mark.parametrize("subsolver,level", [("iluk", 2), ("lu", 0)])
+@pytest.mark.parametrize("subsolver,level", [("iluk", 2), ("lu", 0), ("iluk_box", 0)])
 def test_band_mixed_precision_preconditioner(subsolver, level):
     """FP32 band factors: M^{-1} r within FP32 rounding (amplified by the box matrices'
     conditioning) of the FP64 oracle."""
@@ -127,11 +132,30 @@ def test_widest_band_box(subsolver):
     assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
 
 
+def test_widest_box_pattern_box():
+    """The box base pattern widens the band by 5 diagonals: padded boxes 54 cells wide
+    take the largest register window (kl = 221), ragged Neumann split."""
+    shape, bc, sub, ov = (80, 99), "neumann", (2, 2), 2
+    s, Jo = _setup(shape, bc, sub, ov, "iluk_box", 0, dt=1e-3)
+    assert s.info()["box_w"] == 54
+    r = np.random.default_rng(12).standard_normal(Jo.shape[0])
+    z = s.precondition(dev(r)).cpu().numpy()
+    zo = schwarz.Schwarz(Jo, shape, (sub[1], sub[0]), ov, bc, kind="left", solver="iluk_box", level=0).apply(r)
+    assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
+
+
+def test_box_pattern_rejects_boxes_wider_than_its_window():
+    u0, v0 = random_ic((24, 101), 0)
+    with pytest.raises(Exception):
+        Solver(u0, v0, bc="neumann", sub=(2, 1), overlap=2, subsolver="iluk_box", fill_level=0)
+    Solver(u0, v0, bc="neumann", sub=(2, 1), overlap=2, subsolver="iluk", fill_level=1).close()
+
+
 def _rel_l2(u, v, uo, vo):
     return math.sqrt(np.sum((u - uo) ** 2 + (v - vo) ** 2) / np.sum(uo ** 2 + vo ** 2))
 
 
-@pytest.mark.parametrize("subsolver,level", [("iluk", 1), ("iluk", 2), ("lu", 0)])
+@pytest.mark.parametrize("subsolver,level", [("iluk", 1), ("iluk", 2), ("lu", 0), ("iluk_box", 0)])
 def test_steps_with_band_subsolvers_match_oracle(subsolver, level):
     """Four steps of the 64x64 periodic workload (2x2 subdomains, overlap 1) with each
     subdomain solver: roots = the oracle's to 1e-10 per step, the same Newton counts,
