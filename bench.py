@@ -720,7 +720,8 @@ def main():
     nslot = 40 if len(w["shape"]) == 3 else 24
     roofline = None
     stats = r["stats"]
-    band = w.get("subsolver", "ilu0") != "ilu0"
+    boxilu = w.get("subsolver") == "iluk_box" and w.get("fill_level", 0) == 0
+    band = w.get("subsolver", "ilu0") != "ilu0" and not boxilu
     if stats and stats["ras"][1] > 0:
         ras_ms, ras_n = stats["ras"]
         avg_s = ras_ms / ras_n * 1e-3
@@ -730,14 +731,17 @@ def main():
             nrow = 2 * bw * bh
             nd = 8 * bw + 1 + (10 if w.get("subsolver") == "iluk_box" else 0)   # stored diagonals
             bytes_launch = info["nsub"] * (nrow * nd * sp + 16 * bw * bh) + 16 * r["ncell"]
+        elif boxilu:   # both records of every box cell, its y written and read back, r read; z written
+            bytes_launch = info["nsub"] * info["box_w"] * info["box_h"] * (108 * sp + 16) + 16 * r["ncell"]
         else:
             bytes_launch = ras_bytes_per_cell(box, owned, nslot=nslot, sp=sp) * r["ncell"]
         achieved = bytes_launch / avg_s / 1e9
+        same_kernel = w.get("subsolver", "ilu0") == WORKLOADS[w["name"]].get("subsolver", "ilu0")
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(w["name"]) if sp == 8 and w["sub"] == WORKLOADS[w["name"]]["sub"]
-                    else None,
-                    "kernel": "k_band_solve2d" if band else
+                    "traffic": measured_traffic(w["name"])
+                    if sp == 8 and w["sub"] == WORKLOADS[w["name"]]["sub"] and same_kernel else None,
+                    "kernel": "k_band_solve2d" if band else "k_boxilu_apply2d" if boxilu else
                               ("k_ras_apply3d_win" if len(w["shape"]) == 3 else "k_ras_apply2d"),
                     "avg_us": round(avg_s * 1e6, 2), "timed_launches": ras_n,
                     "timing": "HIP events on the library stream around 1 in 16 Schwarz launches of the timed region",

@@ -396,6 +396,9 @@ class Solver:
 
     def export_factors(self):
         i = self.info()
+        if self.params.subsolver == _SUBSOLVER["iluk_box"] and self.params.fill_level == 0:
+            # box-pattern ILU(0): [sub][cell j*bw + i][L record (52), U record (52)]
+            return self._export(EXPORT_FACTORS, np.float64).reshape(i["nsub"], i["box_w"] * i["box_h"], 104)
         if len(self.shape) == 3:
             return self._export(EXPORT_FACTORS, np.float64).reshape(i["nsub"], 40, -1)
         return self._export(EXPORT_FACTORS, np.float64).reshape(i["nsub"], 24, i["box_h"], i["box_w"])

@@ -14,7 +14,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libacch.so")
-SOURCES = ["stencil2d.hip", "schwarz2d.hip", "bandlu2d.hip", "krylov.hip", "adjoint2d.hip", "stencil3d.hip",
+SOURCES = ["stencil2d.hip", "schwarz2d.hip", "bandlu2d.hip", "boxilu2d.hip", "krylov.hip", "adjoint2d.hip", "stencil3d.hip",
            "schwarz3d.hip", "noalloc.hip", "solver.cpp", "batch.cpp"]
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

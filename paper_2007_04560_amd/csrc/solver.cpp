@@ -38,6 +38,7 @@ struct Layout {
   size_t off_J, off_V, off_Z, off_fac, off_wfac, off_wfact, off_q3, off_y, off_dump, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
   size_t off_tbox, off_own;
   size_t off_band, off_bandy, off_mask;   // exact-LU / ILU(k) subdomain solvers (2D)
+  size_t off_bxL, off_bxU, off_bxy, off_lvoff;   // box-pattern ILU(0) (2D)
   size_t total;
 };
 
@@ -92,6 +93,12 @@ struct acch_ctx {
   void *bandf = nullptr;        // band factors
   double *bandy = nullptr;      // forward-sweep values of the band solve
   unsigned *bandmask = nullptr; // ILU(k) pattern bits (null: exact LU)
+  bool boxilu = false;          // ILU(0) on the box pattern (its own kernels)
+  BoxIluGeom bx{};
+  std::vector<int> lvoff_h;     // wavefront offsets of the box records
+  void *bxL = nullptr, *bxU = nullptr;
+  double *bxy = nullptr;        // forward-sweep values, (u, v) per box cell
+  int *d_lvoff = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -116,6 +123,14 @@ extern "C" void acch_params_default(acch_params *p) {
   if (p->ilu_reuse == 0) p->ilu_reuse = ACCH_ON;
   if (p->mass_projection == 0) p->mass_projection = ACCH_ON;
   if (p->log_energy == 0) p->log_energy = ACCH_ON;
+}
+
+// ILU(0) on the box pattern: its own kernels (boxilu2d.hip); levels >= 1 use the band.
+static bool box_ilu0(const acch_params &p) { return p.subsolver == ACCH_SUB_ILUK_BOX && p.fill_level == 0; }
+// Subdomain solvers in band storage, and those whose band factorisation keeps a pattern.
+static bool band_sub(const acch_params &p) { return p.subsolver != ACCH_SUB_ILU0 && !box_ilu0(p); }
+static bool masked_sub(const acch_params &p) {
+  return band_sub(p) && (p.subsolver == ACCH_SUB_ILUK || p.subsolver == ACCH_SUB_ILUK_BOX);
 }
 
 int acch::validate_params(const acch_params &p) {
@@ -144,7 +159,15 @@ int acch::validate_params(const acch_params &p) {
     return fail(ACCH_EINVAL, "fill_level must be 1..8 for ILU(k)");
   if (p.subsolver == ACCH_SUB_ILUK_BOX && (p.fill_level < 0 || p.fill_level > 8))
     return fail(ACCH_EINVAL, "fill_level must be 0..8 for box ILU(k)");
-  if (p.subsolver != ACCH_SUB_ILU0) {
+  if (box_ilu0(p)) {
+    if (nd != 2) return fail(ACCH_EUNSUPPORTED, "the box-pattern subdomain ILU(0) is 2D");
+    const int bw = (p.n[0] + p.sub[0] - 1) / p.sub[0] + 2 * p.overlap;
+    const int bh = (p.n[1] + p.sub[1] - 1) / p.sub[1] + 2 * p.overlap;
+    if (!boxilu_fits(make_boxilu_geom(bw, bh, nullptr)))
+      return fail(ACCH_EUNSUPPORTED, "box-pattern ILU(0) subdomain boxes must be at most " +
+                                         std::to_string(kBoxIluMaxW) + " x " + std::to_string(kBoxIluMaxH) +
+                                         " cells (owned size + 2 overlap)");
+  } else if (p.subsolver != ACCH_SUB_ILU0) {
     if (nd != 2) return fail(ACCH_EUNSUPPORTED, "ILU(k) and exact-LU subdomain solvers are 2D");
     const bool box = p.subsolver == ACCH_SUB_ILUK_BOX;
     const int maxw = box ? kBandMaxWidthBox : kBandMaxWidth;
@@ -355,11 +378,6 @@ int acch::build_geometry(const acch_params &p, Geometry &geo) {
   return ACCH_OK;
 }
 
-// Subdomain solvers whose band factorisation keeps a pattern (the mask words).
-static bool masked_sub(const acch_params &p) {
-  return p.subsolver == ACCH_SUB_ILUK || p.subsolver == ACCH_SUB_ILUK_BOX;
-}
-
 static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   const size_t n2 = 2 * (size_t)geo.ncell * sizeof(double);
   const int m = p.gmres_restart;
@@ -379,7 +397,7 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_S = take(n2);
   L.off_W = take(n2);
   const bool d3 = p.dim == 3;
-  const bool band = p.subsolver != ACCH_SUB_ILU0;
+  const bool band = p.subsolver != ACCH_SUB_ILU0;   // neither path keeps 24-slot factors
   const int nslot = d3 ? kNSlot3D : kNSlot2D;
   L.off_J = take((size_t)nslot * geo.ncell * sizeof(double));
   L.off_V = take((size_t)(m + 1) * n2);
@@ -406,9 +424,15 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_tbox = take(d3 ? (size_t)geo.G.nsub * 2 * geo.G.ncb * sizeof(double) : 0);   // 3D transposed boxes
   L.off_own = take(geo.own.size() * sizeof(int));
   const BandGeom B = make_band_geom(geo.G.bw, geo.G.bh, p.subsolver == ACCH_SUB_ILUK_BOX);
-  L.off_band = take(band ? (size_t)geo.G.nsub * B.box_elems * fsz : 0);
-  L.off_bandy = take(band ? (size_t)geo.G.nsub * B.nchunk * 64 * sizeof(double) : 0);
+  L.off_band = take(band_sub(p) ? (size_t)geo.G.nsub * B.box_elems * fsz : 0);
+  L.off_bandy = take(band_sub(p) ? (size_t)geo.G.nsub * B.nchunk * 64 * sizeof(double) : 0);
   L.off_mask = take(masked_sub(p) ? (size_t)geo.G.nsub * B.n * B.mwords * sizeof(unsigned) : 0);
+  const bool bx = box_ilu0(p);
+  const BoxIluGeom X = bx ? make_boxilu_geom(geo.G.bw, geo.G.bh, nullptr) : BoxIluGeom{};
+  L.off_bxL = take(bx ? (size_t)geo.G.nsub * X.ncell * kBoxIluRec * fsz : 0);
+  L.off_bxU = take(bx ? (size_t)geo.G.nsub * X.ncell * kBoxIluRec * fsz : 0);
+  L.off_bxy = take(bx ? (size_t)geo.G.nsub * X.ncell * 2 * sizeof(double) : 0);
+  L.off_lvoff = take(bx ? (size_t)(X.nlev + 1) * sizeof(int) : 0);
   L.total = o;
 }
 
@@ -598,6 +622,9 @@ hipError_t run_energy(acch_ctx *c, const double *X) {
 }
 hipError_t run_factor(acch_ctx *c) {
   c->tpacked = false;
+  if (c->boxilu)
+    return launch_boxilu_factor2d(c->bl, c->bx, c->geo.G.nsub, c->d_subs, c->d_lvoff, c->J, c->p.ilu_shift, c->bxL,
+                                  c->bxU, fp32_of(c), c->stream);
   if (c->band)
     return launch_band_factor2d(c->bl, c->bg, c->geo.G.nsub, c->d_subs, c->J,
                                 c->p.subsolver == ACCH_SUB_LU ? 0.0 : c->p.ilu_shift, c->bandmask, c->bandf,
@@ -609,6 +636,9 @@ hipError_t run_factor(acch_ctx *c) {
                              c->stream);
 }
 hipError_t run_ras(acch_ctx *c, const double *r, double *z, const GmresState *st, long vs) {
+  if (c->boxilu)
+    return launch_boxilu_apply2d(c->bl, c->bx, c->geo.G, c->d_subs, c->d_lvoff, c->bxL, c->bxU, c->bxy, c->ybuf, r, z,
+                                 st, vs, fp32_of(c), c->stream, c->ras);
   if (c->band)
     return launch_band_apply2d(c->bl, c->bg, c->geo.G, c->d_subs, c->bandf, c->bandy, c->ybuf, r, z, st, vs,
                                fp32_of(c), c->stream, c->ras);
@@ -858,7 +888,15 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->ras.px = p.sub[0];
   c->ras.py = p.sub[1];
   c->ras.pz = p.dim == 3 ? p.sub[2] : 1;
-  c->band = p.subsolver != ACCH_SUB_ILU0;
+  c->band = band_sub(p);
+  c->boxilu = box_ilu0(p);
+  if (c->boxilu) {
+    c->bx = make_boxilu_geom(c->geo.G.bw, c->geo.G.bh, &c->lvoff_h);
+    c->bxL = c->ws + L.off_bxL;
+    c->bxU = c->ws + L.off_bxU;
+    c->bxy = (double *)(c->ws + L.off_bxy);
+    c->d_lvoff = (int *)(c->ws + L.off_lvoff);
+  }
   std::vector<unsigned> maskh;
   if (c->band) {
     c->bg = make_band_geom(c->geo.G.bw, c->geo.G.bh, p.subsolver == ACCH_SUB_ILUK_BOX);
@@ -920,6 +958,8 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
       hipMemsetAsync(c->st, 0, sizeof(GmresState), c->stream) != hipSuccess ||
       (!maskh.empty() && hipMemcpyAsync(c->bandmask, maskh.data(), maskh.size() * sizeof(unsigned),
                                         hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
+      (c->boxilu && hipMemcpyAsync(c->d_lvoff, c->lvoff_h.data(), c->lvoff_h.size() * sizeof(int),
+                                   hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return cleanup(fail(ACCH_EDEVICE, "initial upload failed"));
   *out = c;
@@ -1145,7 +1185,8 @@ extern "C" int acch_apply_jacobian_transpose(acch_ctx *c, const double *x, doubl
 static int adjoint_ready(acch_ctx *c) {
   if (c->d3 && c->p.ras_type != ACCH_RAS_LEFT)
     return fail(ACCH_EUNSUPPORTED, "the 3D transposed Schwarz operator is built for the left-restricted variant");
-  if (c->band) return fail(ACCH_EUNSUPPORTED, "the transposed Schwarz operator uses the ILU(0) subdomain solver");
+  if (c->band || c->boxilu)
+    return fail(ACCH_EUNSUPPORTED, "the transposed Schwarz operator uses the ILU(0) subdomain solver");
   if (c->p.overlap > c->geo.min_part)
     return fail(ACCH_EUNSUPPORTED, "transposed Schwarz operator needs overlap <= the smallest subdomain width");
   return ACCH_OK;
@@ -1230,6 +1271,7 @@ extern "C" int acch_export(acch_ctx *c, int which, void *out, size_t *bytes) {
   size_t need = 0;
   const int nslot = c->d3 ? kNSlot3D : kNSlot2D;
   if (which == ACCH_EXPORT_JACOBIAN) need = (size_t)nslot * c->geo.ncell * sizeof(double);
+  else if (which == ACCH_EXPORT_FACTORS && c->boxilu) need = (size_t)G.nsub * c->bx.ncell * 2 * kBoxIluRec * sizeof(double);
   else if (which == ACCH_EXPORT_FACTORS) need = (size_t)G.nsub * nslot * G.ncb * sizeof(double);
   else if (which == ACCH_EXPORT_BOXES) need = (size_t)G.nsub * 4 * sizeof(int);
   else if (which == ACCH_EXPORT_BAND && c->band) need = (size_t)G.nsub * c->bg.n * c->bg.nd * sizeof(double);
@@ -1247,7 +1289,9 @@ extern "C" int acch_export(acch_ctx *c, int which, void *out, size_t *bytes) {
   } else if (which == ACCH_EXPORT_FACTORS) {
     if (!c->factored) return fail(ACCH_EINVAL, "no factorisation");
     if (c->band) return fail(ACCH_EINVAL, "the factors of ILU(k) / exact LU are exported by ACCH_EXPORT_BAND");
-    if (c->d3)
+    if (c->boxilu)
+      LAUNCH(c, launch_boxilu_export(c->bx, G.nsub, c->d_lvoff, c->bxL, c->bxU, fp32_of(c), (double *)out, c->stream));
+    else if (c->d3)
       LAUNCH(c, launch_export_factors3d(G, c->fac, c->p.precision == ACCH_PREC_MIXED, (double *)out, c->stream));
     else
       LAUNCH(c, launch_export_factors2d(G, c->d_lvl, c->fac, c->p.precision == ACCH_PREC_MIXED, (double *)out,

@@ -1,0 +1,183 @@
+"""GPU parity of the box-pattern ILU(0) subdomain solver (Section 3.1, Table 2's ILU(0)
+under the box-pattern reading) against the oracle: every factor entry against the
+oracle's textbook ILU(0) on the box pattern, M^{-1} r against the oracle's Schwarz
+operator for the three variants, FP64 and FP32 factors, boxes up to the largest the
+kernels take, and whole Newton steps against the oracle's roots."""
+import math
+
+import numpy as np
+import pytest
+
+from acch_inputs import perturbed_pair, random_ic
+from oracle import controller, jacobian, newton, schwarz
+from oracle.params import Problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2007_04560_amd import Solver  # noqa: E402
+
+# (shape (ny, nx), bc, sub (x, y), overlap)
+CASES = [((37, 29), "periodic", (2, 2), 1), ((45, 58), "neumann", (3, 2), 2), ((33, 17), "neumann", (1, 1), 0),
+         ((26, 40), "periodic", (3, 2), 2)]
+
+# lower and upper cells of the records, (dx, dy) in unknown order
+LOWER = [(dx, -2) for dx in range(-2, 3)] + [(dx, -1) for dx in range(-2, 3)] + [(-2, 0), (-1, 0)]
+UPPER = [(1, 0), (2, 0)] + [(dx, 1) for dx in range(-2, 3)] + [(dx, 2) for dx in range(-2, 3)]
+
+
+def prob(bc):
+    return Problem(bc=bc, alpha=1.2, beta=1.2, theta=0.1, gamma=1e-3, rho=1.0)
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x)).cuda()
+
+
+def vec(u, v):
+    return np.concatenate([u.ravel(), v.ravel()])
+
+
+def _setup(shape, bc, sub, ov, precision="fp64", kind="left", dt=2e-3, seed=31, shift=0.0):
+    u1, v1, u0, v0 = perturbed_pair(shape, seed, amp=0.03)
+    s = Solver(u0, v0, bc=bc, sub=sub, overlap=ov, subsolver="iluk_box", fill_level=0, precision=precision,
+               schwarz=kind, ilu_shift=shift)
+    s.jacobian(dev(vec(u1, v1)), dev(vec(u0, v0)), dt)
+    s.factor()
+    return s, jacobian.jacobian(u1, v1, u0, v0, dt, prob(bc))
+
+
+@pytest.mark.parametrize("shape,bc,sub,ov", CASES)
+@pytest.mark.parametrize("shift", [0.0, 0.02])
+def test_box_ilu0_factors_match_oracle(shape, bc, sub, ov, shift):
+    """Each record slot equals the oracle's ILU(0) on the box pattern of A_k (+ shift
+    diag(A_k)): L entries, U entries, the stored reciprocal pivots; zeros towards cells
+    outside the grid; padding cells are identity rows."""
+    s, Jo = _setup(shape, bc, sub, ov, shift=shift)
+    info = s.info()
+    bw, bh = info["box_w"], info["box_h"]
+    rec = s.export_factors().cpu().numpy()
+    assert rec.shape == (info["nsub"], bw * bh, 104)
+    subs = schwarz.decompose(shape, (sub[1], sub[0]), ov, bc)
+    worst, scale = 0.0, 0.0
+    for k, sd in enumerate(subs):
+        rows = schwarz.subdomain_matrix(Jo, sd, shape)
+        if shift:
+            rows = schwarz.shifted(rows, shift)
+        fac = schwarz.iluk(schwarz.box_pattern(rows, sd), 0)
+        local = {c: i for i, c in enumerate(sd.cells)}
+        seen = np.zeros((bw * bh, 104), dtype=bool)
+        for c, oi in local.items():
+            by, bx = c
+            cell = by * bw + bx
+            want = np.zeros(104)
+            for q, (dx, dy) in enumerate(LOWER):
+                oj = local.get((by + dy, bx + dx))
+                if oj is not None:
+                    want[4 * q:4 * q + 4] = [fac[2 * oi].get(2 * oj, 0.0), fac[2 * oi].get(2 * oj + 1, 0.0),
+                                             fac[2 * oi + 1].get(2 * oj, 0.0), fac[2 * oi + 1].get(2 * oj + 1, 0.0)]
+            want[48] = fac[2 * oi + 1][2 * oi]
+            for q, (dx, dy) in enumerate(UPPER):
+                oj = local.get((by + dy, bx + dx))
+                if oj is not None:
+                    want[52 + 4 * q:56 + 4 * q] = [fac[2 * oi].get(2 * oj, 0.0), fac[2 * oi].get(2 * oj + 1, 0.0),
+                                                   fac[2 * oi + 1].get(2 * oj, 0.0),
+                                                   fac[2 * oi + 1].get(2 * oj + 1, 0.0)]
+            want[100] = 1.0 / fac[2 * oi][2 * oi]
+            want[101] = fac[2 * oi][2 * oi + 1]
+            want[102] = 1.0 / fac[2 * oi + 1][2 * oi + 1]
+            got = rec[k, cell]
+            err = np.abs(got - want)
+            rel = np.array([100, 102])
+            err[rel] /= np.abs(want[rel])
+            worst = max(worst, float(np.max(err)))
+            scale = max(scale, float(np.max(np.abs(want))))
+            seen[cell] = True
+        # padding and cells outside the grid: identity rows
+        for cell in range(bw * bh):
+            if not seen[cell].any():
+                ident = np.zeros(104)
+                ident[100] = ident[102] = 1.0
+                assert np.array_equal(rec[k, cell], ident), (k, cell)
+    assert worst <= 1e-11 * max(scale, 1.0)
+
+
+@pytest.mark.parametrize("shape,bc,sub,ov", CASES)
+@pytest.mark.parametrize("kind", ["left", "right", "classical"])
+def test_box_ilu0_preconditioner_matches_oracle(shape, bc, sub, ov, kind):
+    s, Jo = _setup(shape, bc, sub, ov, kind=kind)
+    r = np.random.default_rng(7).standard_normal(Jo.shape[0])
+    z = s.precondition(dev(r)).cpu().numpy()
+    zo = schwarz.Schwarz(Jo, shape, (sub[1], sub[0]), ov, bc, kind=kind, solver="iluk_box", level=0).apply(r)
+    assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
+
+
+@pytest.mark.parametrize("shape,bc,sub,ov", CASES[:2])
+def test_box_ilu0_mixed_precision(shape, bc, sub, ov):
+    """FP32 records (the pivot rows of the elimination are read back in FP32): M^{-1} r
+    within FP32 rounding of the FP64 oracle."""
+    s, Jo = _setup(shape, bc, sub, ov, precision="mixed")
+    r = np.random.default_rng(9).standard_normal(Jo.shape[0])
+    z = s.precondition(dev(r)).cpu().numpy()
+    zo = schwarz.Schwarz(Jo, shape, (sub[1], sub[0]), ov, bc, kind="left", solver="iluk_box", level=0).apply(r)
+    assert np.linalg.norm(z - zo) <= 1e-4 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_box_ilu0_largest_boxes(precision):
+    """Padded boxes 144 wide (48 cells per wavefront, the most the LDS stages take) and
+    a ragged split; then a box 160 tall (the most rows of the LDS ring)."""
+    for shape, sub, ov, bw, bh in (((30, 279), (2, 1), 2, 144, 34), ((315, 20), (1, 2), 1, 22, 160)):
+        s, Jo = _setup(shape, "neumann", sub, ov, precision=precision, dt=1e-3)
+        info = s.info()
+        assert (info["box_w"], info["box_h"]) == (bw, bh)
+        r = np.random.default_rng(10).standard_normal(Jo.shape[0])
+        z = s.precondition(dev(r)).cpu().numpy()
+        zo = schwarz.Schwarz(Jo, shape, (sub[1], sub[0]), ov, "neumann", kind="left", solver="iluk_box",
+                             level=0).apply(r)
+        if precision == "fp64":
+            assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
+        else:
+            assert np.linalg.norm(z - zo) <= 1e-4 * np.linalg.norm(zo)
+        s.close()
+
+
+def test_box_ilu0_rejects_boxes_beyond_its_limits():
+    u0, v0 = random_ic((24, 283), 0)
+    with pytest.raises(Exception):   # 146 wide
+        Solver(u0, v0, bc="neumann", sub=(2, 1), overlap=2, subsolver="iluk_box", fill_level=0)
+    u0, v0 = random_ic((317, 20), 0)
+    with pytest.raises(Exception):   # 161 tall
+        Solver(u0, v0, bc="neumann", sub=(1, 2), overlap=1, subsolver="iluk_box", fill_level=0)
+
+
+def _rel_l2(u, v, uo, vo):
+    return math.sqrt(np.sum((u - uo) ** 2 + (v - vo) ** 2) / np.sum(uo ** 2 + vo ** 2))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_box_ilu0_steps_match_oracle(precision):
+    """Four steps of the 64x64 periodic workload (2x2 subdomains, overlap 1) with plain
+    (unshifted) box-pattern ILU(0): roots = the oracle's to 1e-10 per step, the same
+    Newton counts, and fewer GMRES iterations than shifted stencil-pattern ILU(0)."""
+    shape = (64, 64)
+    u0, v0 = random_ic(shape, 0)
+    kw = dict(bc="periodic", sub=(2, 2), overlap=1, dt_fixed=1e-3, newton_rtol=1e-12, newton_atol=1e-13,
+              gmres_rtol=1e-12, precision=precision)
+    s = Solver(u0, v0, subsolver="iluk_box", fill_level=0, **kw)
+    s0 = Solver(u0, v0, ilu_shift=0.02, **kw)
+    run = controller.Run(prob("periodic"), u0.copy(), v0.copy(), adaptive=False, dt_fixed=1e-3,
+                         newton=newton.NewtonOptions(rtol=1e-12, atol=1e-13))
+    its, its0 = 0, 0
+    for k in range(4):
+        info = s.step(1)[0]
+        its += info["gmres_its"]
+        its0 += s0.step(1)[0]["gmres_its"]
+        rec = run.step()
+        ug, vg = s.fields()
+        assert _rel_l2(ug, vg, run.u, run.v) <= 1e-10, k
+        assert info["newton_its"] == rec.newton_its
+    assert its < its0

@@ -47,7 +47,7 @@ def _setup(shape, bc, sub, ov, subsolver, level=0, precision="fp64", schwarz_kin
 
 
 @pytest.mark.parametrize("shape,bc,sub,ov", CASES)
-@pytest.mark.parametrize("subsolver,level", [("iluk", 1), ("iluk", 2), ("iluk_box", 0), ("iluk_box", 1)])
+@pytest.mark.parametrize("subsolver,level", [("iluk", 1), ("iluk", 2), ("iluk_box", 1), ("iluk_box", 2)])
 def test_iluk_band_factors_match_oracle(shape, bc, sub, ov, subsolver, level):
     """Every entry of the GPU's ILU(k) factors (band storage) equals the oracle's
     textbook ILU(k) on the level-k pattern (of the stencil or of the box base
@@ -134,20 +134,21 @@ def test_widest_band_box(subsolver):
 
 def test_widest_box_pattern_box():
     """The box base pattern widens the band by 5 diagonals: padded boxes 54 cells wide
-    take the largest register window (kl = 221), ragged Neumann split."""
+    take the largest register window (kl = 221), ragged Neumann split (ILU(1) on the
+    box pattern; its ILU(0) has kernels of its own)."""
     shape, bc, sub, ov = (80, 99), "neumann", (2, 2), 2
-    s, Jo = _setup(shape, bc, sub, ov, "iluk_box", 0, dt=1e-3)
+    s, Jo = _setup(shape, bc, sub, ov, "iluk_box", 1, dt=1e-3)
     assert s.info()["box_w"] == 54
     r = np.random.default_rng(12).standard_normal(Jo.shape[0])
     z = s.precondition(dev(r)).cpu().numpy()
-    zo = schwarz.Schwarz(Jo, shape, (sub[1], sub[0]), ov, bc, kind="left", solver="iluk_box", level=0).apply(r)
+    zo = schwarz.Schwarz(Jo, shape, (sub[1], sub[0]), ov, bc, kind="left", solver="iluk_box", level=1).apply(r)
     assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
 
 
 def test_box_pattern_rejects_boxes_wider_than_its_window():
     u0, v0 = random_ic((24, 101), 0)
     with pytest.raises(Exception):
-        Solver(u0, v0, bc="neumann", sub=(2, 1), overlap=2, subsolver="iluk_box", fill_level=0)
+        Solver(u0, v0, bc="neumann", sub=(2, 1), overlap=2, subsolver="iluk_box", fill_level=1)
     Solver(u0, v0, bc="neumann", sub=(2, 1), overlap=2, subsolver="iluk", fill_level=1).close()
 
 
