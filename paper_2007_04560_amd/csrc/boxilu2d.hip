@@ -351,11 +351,14 @@ __global__ __launch_bounds__(kBoxIluThreads) void k_boxilu_apply2d(
     sc = (FT)st->inv_norm[jj];
   }
   __shared__ word4 stage[2][NCH * kBoxIluThreads];
-  __shared__ V2 ring[kBoxIluMaxH + 4][2 * kRingW];   // box row j at ring row j + 2
+  // ring: box row j at ring row j + 2, bh + 4 rows (dynamic LDS, so that blocks of small
+  // boxes share a CU)
+  extern __shared__ char dyn_lds[];
+  V2(*ring)[2 * kRingW] = reinterpret_cast<V2(*)[2 * kRingW]>(dyn_lds);
   const int t = threadIdx.x;
   const int p = t >> 2, part = t & 3;   // the wavefront's cell p; its neighbours 3 part .. 3 part + 2
   const int nlev = X.nlev;
-  for (int e = t; e < (kBoxIluMaxH + 4) * 2 * kRingW; e += kBoxIluThreads) (&ring[0][0])[e] = V2{(FT)0, (FT)0};
+  for (int e = t; e < (X.bh + 4) * 2 * kRingW; e += kBoxIluThreads) (&ring[0][0])[e] = V2{(FT)0, (FT)0};
   const SubInfo si = subs[blockIdx.x];
   const Rect rc = grid_rect(si, X.bw, X.bh, P.nx, P.ny, P.periodic);
   const long n = (long)P.nx * P.ny;
@@ -545,8 +548,9 @@ template <typename FT, int NCH>
 void apply_launch(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const void *L,
                   const void *U, double *ybox, void *boxbuf, const double *r, double *z,
                   const GmresState *st, long vstride, int kind, hipStream_t s) {
-  hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, (NCH <= 3 ? 6 : 4)>), dim3(G.nsub), dim3(kBoxIluThreads), 0, s, P, X, G,
-                     subs, (const FT *)L, (const FT *)U, (void *)ybox, boxbuf, r, z, st, vstride, kind);
+  const size_t ring_bytes = (size_t)(X.bh + 4) * 2 * kRingW * 2 * sizeof(FT);
+  hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, (NCH <= 3 ? 6 : 4)>), dim3(G.nsub), dim3(kBoxIluThreads), ring_bytes, s,
+                     P, X, G, subs, (const FT *)L, (const FT *)U, (void *)ybox, boxbuf, r, z, st, vstride, kind);
 }
 
 template <typename FT>
