@@ -29,17 +29,22 @@ __host__ __device__ inline int level_jlo(int w, int bw) {
   return d > 0 ? (d + 2) / 3 : 0;
 }
 
-// Wavefront offsets (nlev + 1 entries) and the geometry of a bw x bh box.
-inline BoxIluGeom make_boxilu_geom(int bw, int bh, std::vector<int> *lvoff) {
+// Wavefront offsets (nlev + 1 entries), the box cell (j << 16 | i) of each record
+// position (cellof, optional) and the geometry of a bw x bh box.
+inline BoxIluGeom make_boxilu_geom(int bw, int bh, std::vector<int> *lvoff, std::vector<int> *cellof = nullptr) {
   BoxIluGeom X{};
   X.bw = bw;
   X.bh = bh;
   X.nlev = bw + 3 * (bh - 1);
   X.ncell = bw * bh;
   if (lvoff) lvoff->assign(X.nlev + 1, 0);
+  if (cellof) cellof->clear();
   for (int w = 0; w < X.nlev; ++w) {
     int cnt = 0;
-    for (int j = level_jlo(w, bw); j < bh && 3 * j <= w; ++j) ++cnt;
+    for (int j = level_jlo(w, bw); j < bh && 3 * j <= w; ++j) {
+      if (cellof) cellof->push_back(j << 16 | (w - 3 * j));
+      ++cnt;
+    }
     X.maxcount = cnt > X.maxcount ? cnt : X.maxcount;
     if (lvoff) (*lvoff)[w + 1] = (*lvoff)[w] + cnt;
   }

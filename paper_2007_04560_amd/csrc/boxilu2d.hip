@@ -328,51 +328,172 @@ ACCH_DEV void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// The apply runs in three kernels: a gather of R_k r into the box vector ybox (in the
+// cell order of the records), the two sweeps, which overwrite ybox with y and then x, and a
+// scatter of x to z (left RAS) or to the box buffer of the overlap sum.
+template <typename FT>
+__global__ __launch_bounds__(256) void k_boxilu_gather(Phys P, BoxIluGeom X, const SubInfo *__restrict__ subs,
+                                                       const int *__restrict__ cellof, const double *__restrict__ r,
+                                                       void *__restrict__ ybox_, const GmresState *st, long vstride,
+                                                       int kind) {
+  using V2 = typename ChunkOf2<FT>::T;
+  double sc = 1.0;
+  if (st) {
+    if (st->done) return;
+    r += (long)st->j * vstride;
+    sc = st->inv_norm[st->j];
+  }
+  const int pos = blockIdx.x * 256 + threadIdx.x;
+  if (pos >= X.ncell) return;
+  const SubInfo si = subs[blockIdx.y];
+  const Rect rc = grid_rect(si, X.bw, X.bh, P.nx, P.ny, P.periodic);
+  const int ij = cellof[pos], i = ij & 0xffff, j = ij >> 16;
+  V2 v{(FT)0, (FT)0};
+  if (rc.in(i, j)) {
+    const long g = box_to_global(si, i, j, P.nx, P.ny, P.periodic);
+    const bool own = i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1;
+    if (kind != ACCH_RAS_RIGHT || own) v = V2{(FT)(sc * r[g]), (FT)(sc * r[g + (long)P.nx * P.ny])};
+  }
+  ((V2 *)ybox_)[(long)blockIdx.y * X.ncell + pos] = v;
+}
+
+template <typename FT>
+__global__ __launch_bounds__(256) void k_boxilu_scatter(Phys P, BoxIluGeom X, BoxGeom G,
+                                                        const SubInfo *__restrict__ subs,
+                                                        const int *__restrict__ cellof,
+                                                        const void *__restrict__ ybox_, void *__restrict__ boxbuf_,
+                                                        double *__restrict__ z, const GmresState *st, long vstride,
+                                                        int kind) {
+  using V2 = typename ChunkOf2<FT>::T;
+  if (st) {
+    if (st->done) return;
+    z += (long)st->j * vstride;
+  }
+  const int pos = blockIdx.x * 256 + threadIdx.x;
+  if (pos >= X.ncell) return;
+  const SubInfo si = subs[blockIdx.y];
+  const Rect rc = grid_rect(si, X.bw, X.bh, P.nx, P.ny, P.periodic);
+  const int ij = cellof[pos], i = ij & 0xffff, j = ij >> 16;
+  if (!rc.in(i, j)) return;
+  const V2 x = ((const V2 *)ybox_)[(long)blockIdx.y * X.ncell + pos];
+  if (kind == ACCH_RAS_LEFT) {
+    if (i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1) {
+      const long g = box_to_global(si, i, j, P.nx, P.ny, P.periodic);
+      z[g] = (double)x.x;
+      z[g + (long)P.nx * P.ny] = (double)x.y;
+    }
+  } else {
+    const long ncb = (long)G.nlev * G.bh;
+    ((V2 *)boxbuf_)[(long)blockIdx.y * (ncb + 1) + (long)(i + 2 * j) * G.bh + j] = x;
+  }
+}
+
 // Every global access of the sweeps is a buffer access issued by every thread on every
 // step; a thread without a cell there passes an offset past the end (bufio.h).  A sweep
 // runs D steps before its first wavefront (nothing to compute, only loads) and is padded
 // to a multiple of D steps, so every access is issued inside a loop unrolled D times and
 // each step issues the same accesses: step s handles wavefront s - D of the sweep's order,
-// copies the records of the next wavefront (loaded D - 1 steps earlier) to LDS and loads
-// the records and the cells' values for wavefront s.  The two waits of a step are exact
-// counts of the accesses issued after the ones it needs.
-template <typename FT, int NCH, int D>
-__global__ __launch_bounds__(kBoxIluThreads) void k_boxilu_apply2d(
-    Phys P, BoxIluGeom X, BoxGeom G, const SubInfo *__restrict__ subs, const FT *__restrict__ Lrec,
-    const FT *__restrict__ Urec, void *__restrict__ ybox_, void *__restrict__ boxbuf_, const double *__restrict__ r,
-    double *__restrict__ z, const GmresState *st, long vstride, int kind) {
+// copies the records and box values of the next wavefront (loaded D - 1 steps earlier) to
+// LDS and loads those of wavefront s.  The two waits of a step are exact counts of the
+// accesses issued after the ones it needs.
+template <typename FT, int NCH, int D, bool FWD>
+ACCH_DEV void sweep(const BoxIluGeom &X, __amdgpu_buffer_rsrc_t rsRec, __amdgpu_buffer_rsrc_t rsV,
+                    word4 (*stage)[NCH * kBoxIluThreads], typename ChunkOf2<FT>::T (*stv)[64],
+                    typename ChunkOf2<FT>::T (*ring)[2 * kRingW], const int (&off)[3]) {
   using V2 = typename ChunkOf2<FT>::T;
-  FT sc = (FT)1;
-  if (st) {
-    if (st->done) return;
-    const int jj = st->j;
-    r += (long)jj * vstride;
-    z += (long)jj * vstride;
-    sc = (FT)st->inv_norm[jj];
+  const int t = threadIdx.x, p = t >> 2, part = t & 3;
+  const int nlev = X.nlev;
+  const int nstep = (nlev + D + D - 1) / D * D;   // D lead-in steps, padded to a multiple of D
+  constexpr int kOps = NCH + 2;                    // a step: 1 store, NCH + 1 loads
+  auto count = [&](int w) { return level_count(w, X.bw, X.bh, nlev); };
+  word4 R[D][NCH];
+  V2 RV[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    RV[d] = V2{(FT)0, (FT)0};
+#pragma unroll
+    for (int m = 0; m < NCH; ++m) R[d][m] = word4{0u, 0u, 0u, 0u};
   }
+  const int top = nlev - 1;
+  // first record of wavefronts w and the one D further in the sweep's order
+  int first_c = FWD ? 0 : X.ncell, first_l = FWD ? 0 : X.ncell - count(top);
+  for (int s0 = 0; s0 < nstep; s0 += D) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int w = FWD ? s0 + k - D : top - (s0 + k - D);
+      const int wl = FWD ? w + D : w - D;          // wavefront loaded on this step
+      const int wn = FWD ? w + 1 : w - 1;          // next wavefront
+      const int cw = count(w), cl = count(wl);
+      lds_barrier();
+      const bool act = p < cw;
+      const int j = level_jlo(w, X.bw) + p, i = w - 3 * j;
+      V2 v = stv[w & 1][p & 63];
+      if (act) {   // whole quads
+        const FT *rec = (const FT *)&stage[w & 1][0] + p * kBoxIluRec;
+        const V2 *rb = &ring[j + 2][(i - 2) & (kRingW - 1)];
+        FT au = (FT)0, av = (FT)0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const V2 x = rb[off[m]];
+          FT c0, c1, c2, c3;
+          slots4(rec + 12 * part, m, c0, c1, c2, c3);
+          au += c0 * x.x + c1 * x.y;
+          av += c2 * x.x + c3 * x.y;
+        }
+        v.x -= quad_sum(au);
+        v.y -= quad_sum(av);
+        if constexpr (FWD) {
+          v.y -= rec[48] * v.x;
+        } else {
+          v.y *= rec[50];
+          v.x = (v.x - rec[49] * v.y) * rec[48];
+        }
+        if (part == 0) {
+          ring[j + 2][i & (kRingW - 1)] = v;
+          ring[j + 2][(i & (kRingW - 1)) + kRingW] = v;
+        }
+      }
+      store_pair(rsV, act && part == 0 ? (unsigned)((first_c + p) * sizeof(V2)) : kPastEnd, 0, v);
+      // the records and values of the next wavefront (loaded D - 1 steps ago) to LDS
+      wait_vm<(D - 2) * kOps + 1>();
+      __builtin_amdgcn_sched_barrier(0);
+      stage_store<NCH>(&stage[wn & 1][0], R[(k + 1) % D]);
+      if (t < 64) stv[wn & 1][t] = RV[(k + 1) % D];
+      stage_load<FT, NCH>(rsRec, first_l, cl, R[k]);
+      RV[k] = load_pair(rsV, t < cl ? (unsigned)((first_l + t) * sizeof(V2)) : kPastEnd, 0, (const V2 *)nullptr);
+      if (FWD) {
+        first_c += cw;
+        first_l += cl;
+      } else {
+        first_c -= count(w - 1);
+        first_l -= count(wl - 1);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+template <typename FT, int NCH, int D>
+__global__ __launch_bounds__(kBoxIluThreads) void k_boxilu_apply2d(BoxIluGeom X, const FT *__restrict__ Lrec,
+                                                                  const FT *__restrict__ Urec,
+                                                                  void *__restrict__ ybox_, const GmresState *st) {
+  using V2 = typename ChunkOf2<FT>::T;
+  if (st && st->done) return;
   __shared__ word4 stage[2][NCH * kBoxIluThreads];
+  __shared__ V2 stv[2][64];
   // ring: box row j at ring row j + 2, bh + 4 rows (dynamic LDS, so that blocks of small
   // boxes share a CU)
   extern __shared__ char dyn_lds[];
   V2(*ring)[2 * kRingW] = reinterpret_cast<V2(*)[2 * kRingW]>(dyn_lds);
   const int t = threadIdx.x;
-  const int p = t >> 2, part = t & 3;   // the wavefront's cell p; its neighbours 3 part .. 3 part + 2
-  const int nlev = X.nlev;
+  const int part = t & 3;   // the lane's 3 of the cell's 12 neighbour cells: 3 part .. 3 part + 2
   for (int e = t; e < (X.bh + 4) * 2 * kRingW; e += kBoxIluThreads) (&ring[0][0])[e] = V2{(FT)0, (FT)0};
-  const SubInfo si = subs[blockIdx.x];
-  const Rect rc = grid_rect(si, X.bw, X.bh, P.nx, P.ny, P.periodic);
-  const long n = (long)P.nx * P.ny;
   const long cbase = (long)blockIdx.x * X.ncell;
   const unsigned rbytes = (unsigned)(X.ncell * kBoxIluRec * sizeof(FT));
   const __amdgpu_buffer_rsrc_t rsL = buffer_rsrc(Lrec + cbase * kBoxIluRec, rbytes);
   const __amdgpu_buffer_rsrc_t rsU = buffer_rsrc(Urec + cbase * kBoxIluRec, rbytes);
-  const __amdgpu_buffer_rsrc_t rsY = buffer_rsrc((V2 *)ybox_ + cbase, (unsigned)(X.ncell * sizeof(V2)));
-  const __amdgpu_buffer_rsrc_t rsR = buffer_rsrc(r, (unsigned)(2 * n * sizeof(double)));
-  const __amdgpu_buffer_rsrc_t rsZ = buffer_rsrc(z, (unsigned)(2 * n * sizeof(double)));
-  const long ncb = (long)G.nlev * G.bh;   // wavefront-ordered box buffers of the overlap sum
-  const __amdgpu_buffer_rsrc_t rsB =
-      buffer_rsrc((FT *)boxbuf_ + 2 * (long)blockIdx.x * (ncb + 1), (unsigned)(2 * (ncb + 1) * sizeof(FT)));
-  // ring offsets (from column (i - 2) mod 16 of the cell's row) of this thread's 3 neighbours
+  const __amdgpu_buffer_rsrc_t rsV = buffer_rsrc((V2 *)ybox_ + cbase, (unsigned)(X.ncell * sizeof(V2)));
+  // ring offsets (from column (i - 2) mod 16 of the cell's row) of this lane's neighbours
   int offL[3], offU[3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
@@ -380,153 +501,11 @@ __global__ __launch_bounds__(kBoxIluThreads) void k_boxilu_apply2d(
     offL[m] = lo.dy * 2 * kRingW + lo.dx + 2;
     offU[m] = up.dy * 2 * kRingW + up.dx + 2;
   }
-  // cell p of wavefront w: box column i (-1: none), row j, grid cell (-1: outside the
-  // grid) and whether it is owned
-  struct Cell {
-    int i, j;
-    long g;
-    bool own;
-  };
-  auto cell_on = [&](int w) -> Cell {
-    Cell c{-1, 0, -1, false};
-    if (p >= level_count(w, X.bw, X.bh, nlev)) return c;
-    c.j = level_jlo(w, X.bw) + p;
-    c.i = w - 3 * c.j;
-    if (rc.in(c.i, c.j)) {
-      c.g = box_to_global(si, c.i, c.j, P.nx, P.ny, P.periodic);
-      c.own = c.i >= si.own_x0 && c.i < si.own_x1 && c.j >= si.own_y0 && c.j < si.own_y1;
-    }
-    return c;
-  };
-  auto count = [&](int w) { return level_count(w, X.bw, X.bh, nlev); };
   __syncthreads();
-  const FT *stg0 = (const FT *)&stage[0][0];
-  const FT *stg1 = (const FT *)&stage[1][0];
-  const int nstep = (nlev + D + D - 1) / D * D;   // D lead-in steps, padded to a multiple of D
-
-  // ---- forward: L y = R_k r; a step: store y, NCH record loads, 2 value loads
-  {
-    constexpr int kOps = NCH + 3;
-    word4 R[D][NCH];
-    FT rvu[D], rvv[D];   // R_k r of the thread's cell on the wavefront of the slot
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      rvu[d] = rvv[d] = (FT)0;
-#pragma unroll
-      for (int m = 0; m < NCH; ++m) R[d][m] = word4{0u, 0u, 0u, 0u};
-    }
-    int first_c = 0, first_l = 0;   // first record of wavefronts w and w + D
-    for (int s0 = 0; s0 < nstep; s0 += D) {
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const int w = s0 + k - D;
-        wait_vm<(D - 1) * kOps>();   // this step's values (issued D steps ago)
-        __builtin_amdgcn_sched_barrier(0);
-        lds_barrier();
-        const Cell c = cell_on(w);
-        FT yu = sc * rvu[k], yv = sc * rvv[k];
-        if (c.i >= 0) {   // whole quads
-          const FT *rec = ((w & 1) ? stg1 : stg0) + p * kBoxIluRec;
-          const V2 *rb = &ring[c.j + 2][(c.i - 2) & (kRingW - 1)];
-          FT au = (FT)0, av = (FT)0;
-#pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            const V2 x = rb[offL[m]];
-            FT c0, c1, c2, c3;
-            slots4(rec + 12 * part, m, c0, c1, c2, c3);
-            au += c0 * x.x + c1 * x.y;
-            av += c2 * x.x + c3 * x.y;
-          }
-          yu -= quad_sum(au);
-          yv -= quad_sum(av);
-          yv -= rec[48] * yu;
-          if (part == 0) {
-            ring[c.j + 2][c.i & (kRingW - 1)] = V2{yu, yv};
-            ring[c.j + 2][(c.i & (kRingW - 1)) + kRingW] = V2{yu, yv};
-          }
-        }
-        store_pair(rsY, c.i >= 0 && part == 0 ? (unsigned)((first_c + p) * sizeof(V2)) : kPastEnd, 0, V2{yu, yv});
-        // the records of wavefront w + 1 (loaded D - 1 steps ago) to LDS
-        wait_vm<2 + (D - 2) * kOps + 1>();
-        __builtin_amdgcn_sched_barrier(0);
-        stage_store<NCH>(((w + 1) & 1) ? &stage[1][0] : &stage[0][0], R[(k + 1) % D]);
-        stage_load<FT, NCH>(rsL, first_l, count(w + D), R[k]);   // wavefront s, stored D - 1 steps on
-        const Cell cn = cell_on(w + D);
-        const bool in = cn.g >= 0 && (kind != ACCH_RAS_RIGHT || cn.own);
-        rvu[k] = (FT)load_one(rsR, in ? (unsigned)(cn.g * sizeof(double)) : kPastEnd, 0, (const double *)nullptr);
-        rvv[k] =
-            (FT)load_one(rsR, in ? (unsigned)((cn.g + n) * sizeof(double)) : kPastEnd, 0, (const double *)nullptr);
-        first_c += count(w);
-        first_l += count(w + D);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-  }
+  sweep<FT, NCH, D, true>(X, rsL, rsV, stage, stv, ring, offL);
   wait_vm<0>();
-  lds_barrier();
-  // ---- backward: U x = y; a step: 3 stores, NCH record loads, 1 value load
-  {
-    constexpr int kOps = NCH + 4;
-    word4 R[D][NCH];
-    V2 yv2[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      yv2[d] = V2{(FT)0, (FT)0};
-#pragma unroll
-      for (int m = 0; m < NCH; ++m) R[d][m] = word4{0u, 0u, 0u, 0u};
-    }
-    const int top = nlev - 1;
-    // first record of wavefronts w and w - D (wavefronts beyond the box: ncell)
-    int first_c = X.ncell, first_l = X.ncell - count(top);
-    for (int s0 = 0; s0 < nstep; s0 += D) {
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const int w = top - (s0 + k - D);
-        wait_vm<(D - 1) * kOps>();
-        __builtin_amdgcn_sched_barrier(0);
-        lds_barrier();
-        const Cell c = cell_on(w);
-        FT xu = yv2[k].x, xv = yv2[k].y;
-        if (c.i >= 0) {   // whole quads
-          const FT *rec = ((w & 1) ? stg1 : stg0) + p * kBoxIluRec;
-          const V2 *rb = &ring[c.j + 2][(c.i - 2) & (kRingW - 1)];
-          FT au = (FT)0, av = (FT)0;
-#pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            const V2 x = rb[offU[m]];
-            FT c0, c1, c2, c3;
-            slots4(rec + 12 * part, m, c0, c1, c2, c3);
-            au += c0 * x.x + c1 * x.y;
-            av += c2 * x.x + c3 * x.y;
-          }
-          xu -= quad_sum(au);
-          xv -= quad_sum(av);
-          xv *= rec[50];
-          xu = (xu - rec[49] * xv) * rec[48];
-          if (part == 0) {
-            ring[c.j + 2][c.i & (kRingW - 1)] = V2{xu, xv};
-            ring[c.j + 2][(c.i & (kRingW - 1)) + kRingW] = V2{xu, xv};
-          }
-        }
-        // left RAS: the owned cells to z; otherwise the box cells to the box buffer
-        const bool zl = kind == ACCH_RAS_LEFT && c.own && part == 0;
-        const bool bl = kind != ACCH_RAS_LEFT && c.g >= 0 && part == 0;
-        store_one(rsZ, zl ? (unsigned)(c.g * sizeof(double)) : kPastEnd, 0, (double)xu);
-        store_one(rsZ, zl ? (unsigned)((c.g + n) * sizeof(double)) : kPastEnd, 0, (double)xv);
-        const long bi = (long)(c.i + 2 * c.j) * G.bh + c.j;
-        store_pair(rsB, bl ? (unsigned)(bi * 2 * sizeof(FT)) : kPastEnd, 0, V2{xu, xv});
-        wait_vm<1 + (D - 2) * kOps + 3>();
-        __builtin_amdgcn_sched_barrier(0);
-        stage_store<NCH>(((w - 1) & 1) ? &stage[1][0] : &stage[0][0], R[(k + 1) % D]);
-        stage_load<FT, NCH>(rsU, first_l, count(w - D), R[k]);
-        const Cell cn = cell_on(w - D);
-        yv2[k] = load_pair(rsY, cn.i >= 0 ? (unsigned)((first_l + p) * sizeof(V2)) : kPastEnd, 0, (const V2 *)nullptr);
-        first_c -= count(w - 1);
-        first_l -= count(w - D - 1);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-  }
+  __syncthreads();   // y of every cell in ybox, written by other threads, before the U sweep
+  sweep<FT, NCH, D, false>(X, rsU, rsV, stage, stv, ring, offU);
 }
 
 // Factors (FT records) -> FP64 [sub][cell j bw + i][L record, U record].
@@ -545,27 +524,31 @@ __global__ void k_boxilu_export(BoxIluGeom X, int nsub, const int *__restrict__ 
 }
 
 template <typename FT, int NCH>
-void apply_launch(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const void *L,
-                  const void *U, double *ybox, void *boxbuf, const double *r, double *z,
-                  const GmresState *st, long vstride, int kind, hipStream_t s) {
+void apply_launch(const BoxIluGeom &X, const BoxGeom &G, const void *L, const void *U, double *ybox,
+                  const GmresState *st, hipStream_t s) {
   const size_t ring_bytes = (size_t)(X.bh + 4) * 2 * kRingW * 2 * sizeof(FT);
   hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, (NCH <= 3 ? 6 : 4)>), dim3(G.nsub), dim3(kBoxIluThreads), ring_bytes, s,
-                     P, X, G, subs, (const FT *)L, (const FT *)U, (void *)ybox, boxbuf, r, z, st, vstride, kind);
+                     X, (const FT *)L, (const FT *)U, (void *)ybox, st);
 }
 
 template <typename FT>
-hipError_t apply_t(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const void *L,
-                   const void *U, double *ybox, void *boxbuf, const double *r, double *z,
+hipError_t apply_t(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const int *cellof,
+                   const void *L, const void *U, double *ybox, void *boxbuf, const double *r, double *z,
                    const GmresState *st, long vstride, int kind, hipStream_t s) {
+  const dim3 cells((X.ncell + 255) / 256, G.nsub);
+  hipLaunchKernelGGL(k_boxilu_gather<FT>, cells, dim3(256), 0, s, P, X, subs, cellof, r, (void *)ybox, st, vstride,
+                     kind);
   const int nch = (X.maxcount * kBoxIluRec * (int)sizeof(FT) + 16 * kBoxIluThreads - 1) / (16 * kBoxIluThreads);
   switch (nch) {
-    case 1: apply_launch<FT, 1>(P, X, G, subs, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
-    case 2: apply_launch<FT, 2>(P, X, G, subs, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
-    case 3: apply_launch<FT, 3>(P, X, G, subs, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
-    case 4: apply_launch<FT, 4>(P, X, G, subs, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
-    case 5: apply_launch<FT, 5>(P, X, G, subs, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
+    case 1: apply_launch<FT, 1>(X, G, L, U, ybox, st, s); break;
+    case 2: apply_launch<FT, 2>(X, G, L, U, ybox, st, s); break;
+    case 3: apply_launch<FT, 3>(X, G, L, U, ybox, st, s); break;
+    case 4: apply_launch<FT, 4>(X, G, L, U, ybox, st, s); break;
+    case 5: apply_launch<FT, 5>(X, G, L, U, ybox, st, s); break;
     default: return hipErrorInvalidValue;
   }
+  hipLaunchKernelGGL(k_boxilu_scatter<FT>, cells, dim3(256), 0, s, P, X, G, subs, cellof, (const void *)ybox, boxbuf,
+                     z, st, vstride, kind);
   return hipGetLastError();
 }
 
@@ -590,14 +573,13 @@ hipError_t launch_boxilu_factor2d(const BatchLaunch &bl, const BoxIluGeom &X, in
 }
 
 hipError_t launch_boxilu_apply2d(const BatchLaunch &bl, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs,
-                                 const int *lvoff, const void *L, const void *U, double *ybox, void *boxbuf,
+                                 const int *cellof, const void *L, const void *U, double *ybox, void *boxbuf,
                                  const double *r, double *z, const GmresState *st, long vstride, int fp32,
                                  hipStream_t s, const RasVariant &rv) {
   if (bl.bt.map[kFamSub] != nullptr || !boxilu_fits(X)) return hipErrorInvalidValue;
   if (rv.kind != ACCH_RAS_LEFT && !rv.own_x) return hipErrorInvalidValue;
-  (void)lvoff;   // the sweeps count the cells of each wavefront themselves
-  hipError_t e = fp32 ? apply_t<float>(bl.P0, X, G, subs, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, s)
-                      : apply_t<double>(bl.P0, X, G, subs, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, s);
+  hipError_t e = fp32 ? apply_t<float>(bl.P0, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, s)
+                      : apply_t<double>(bl.P0, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, s);
   if (e != hipSuccess || rv.kind == ACCH_RAS_LEFT) return e;
   return launch_ras_sum2d(bl, G, subs, boxbuf, z, st, vstride, fp32, s, rv);
 }

@@ -105,13 +105,14 @@ hipError_t launch_band_apply2d(const BatchLaunch &bl, const BandGeom &B, const B
 hipError_t launch_band_export(const BandGeom &B, int nsub, const void *band, int fp32, double *out, hipStream_t s);
 
 // boxilu2d.hip: ILU(0) on the width-2 box pattern (boxilu.h); L, U: nsub * ncell * 52
-// FT records each; ybox: nsub * ncell (u, v) pairs; boxbuf as for the band solve.
+// FT records each; ybox: nsub * ncell (u, v) pairs; boxbuf as for the band solve; lvoff:
+// the wavefront offsets; cellof: box cell (j << 16 | i) of each record position.
 bool boxilu_fits(const BoxIluGeom &X);
 hipError_t launch_boxilu_factor2d(const BatchLaunch &bl, const BoxIluGeom &X, int nsub, const SubInfo *subs,
                                   const int *lvoff, const double *J, double shift, void *L, void *U, int fp32,
                                   hipStream_t s);
 hipError_t launch_boxilu_apply2d(const BatchLaunch &bl, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs,
-                                 const int *lvoff, const void *L, const void *U, double *ybox, void *boxbuf,
+                                 const int *cellof, const void *L, const void *U, double *ybox, void *boxbuf,
                                  const double *r, double *z, const GmresState *st, long vstride, int fp32,
                                  hipStream_t s, const RasVariant &rv);
 hipError_t launch_boxilu_export(const BoxIluGeom &X, int nsub, const int *lvoff, const void *L, const void *U,

@@ -38,7 +38,7 @@ struct Layout {
   size_t off_J, off_V, off_Z, off_fac, off_wfac, off_wfact, off_q3, off_y, off_dump, off_subs, off_lvl, off_state, off_part, off_cnt, off_out;
   size_t off_tbox, off_own;
   size_t off_band, off_bandy, off_mask;   // exact-LU / ILU(k) subdomain solvers (2D)
-  size_t off_bxL, off_bxU, off_bxy, off_lvoff;   // box-pattern ILU(0) (2D)
+  size_t off_bxL, off_bxU, off_bxy, off_lvoff, off_cellof;   // box-pattern ILU(0) (2D)
   size_t total;
 };
 
@@ -96,9 +96,11 @@ struct acch_ctx {
   bool boxilu = false;          // ILU(0) on the box pattern (its own kernels)
   BoxIluGeom bx{};
   std::vector<int> lvoff_h;     // wavefront offsets of the box records
+  std::vector<int> cellof_h;    // box cell of each record position
   void *bxL = nullptr, *bxU = nullptr;
   double *bxy = nullptr;        // forward-sweep values, (u, v) per box cell
   int *d_lvoff = nullptr;
+  int *d_cellof = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -433,6 +435,7 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_bxU = take(bx ? (size_t)geo.G.nsub * X.ncell * kBoxIluRec * fsz : 0);
   L.off_bxy = take(bx ? (size_t)geo.G.nsub * X.ncell * 2 * sizeof(double) : 0);
   L.off_lvoff = take(bx ? (size_t)(X.nlev + 1) * sizeof(int) : 0);
+  L.off_cellof = take(bx ? (size_t)X.ncell * sizeof(int) : 0);
   L.total = o;
 }
 
@@ -637,7 +640,7 @@ hipError_t run_factor(acch_ctx *c) {
 }
 hipError_t run_ras(acch_ctx *c, const double *r, double *z, const GmresState *st, long vs) {
   if (c->boxilu)
-    return launch_boxilu_apply2d(c->bl, c->bx, c->geo.G, c->d_subs, c->d_lvoff, c->bxL, c->bxU, c->bxy, c->ybuf, r, z,
+    return launch_boxilu_apply2d(c->bl, c->bx, c->geo.G, c->d_subs, c->d_cellof, c->bxL, c->bxU, c->bxy, c->ybuf, r, z,
                                  st, vs, fp32_of(c), c->stream, c->ras);
   if (c->band)
     return launch_band_apply2d(c->bl, c->bg, c->geo.G, c->d_subs, c->bandf, c->bandy, c->ybuf, r, z, st, vs,
@@ -891,11 +894,12 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
   c->band = band_sub(p);
   c->boxilu = box_ilu0(p);
   if (c->boxilu) {
-    c->bx = make_boxilu_geom(c->geo.G.bw, c->geo.G.bh, &c->lvoff_h);
+    c->bx = make_boxilu_geom(c->geo.G.bw, c->geo.G.bh, &c->lvoff_h, &c->cellof_h);
     c->bxL = c->ws + L.off_bxL;
     c->bxU = c->ws + L.off_bxU;
     c->bxy = (double *)(c->ws + L.off_bxy);
     c->d_lvoff = (int *)(c->ws + L.off_lvoff);
+    c->d_cellof = (int *)(c->ws + L.off_cellof);
   }
   std::vector<unsigned> maskh;
   if (c->band) {
@@ -959,6 +963,8 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
       (!maskh.empty() && hipMemcpyAsync(c->bandmask, maskh.data(), maskh.size() * sizeof(unsigned),
                                         hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
       (c->boxilu && hipMemcpyAsync(c->d_lvoff, c->lvoff_h.data(), c->lvoff_h.size() * sizeof(int),
+                                   hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
+      (c->boxilu && hipMemcpyAsync(c->d_cellof, c->cellof_h.data(), c->cellof_h.size() * sizeof(int),
                                    hipMemcpyHostToDevice, c->stream) != hipSuccess) ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return cleanup(fail(ACCH_EDEVICE, "initial upload failed"));
