@@ -303,21 +303,21 @@ ACCH_DEV int level_count(int w, int bw, int bh, int nlev) {
 }
 
 // Records of the wavefront whose first record is `first` and which has `cnt` cells:
-// 16-byte chunks t + 256 m.
-template <typename FT, int NCH>
+// 16-byte chunks t + TH m of a block of TH threads.
+template <typename FT, int NCH, int TH>
 ACCH_DEV void stage_load(__amdgpu_buffer_rsrc_t rs, int first, int cnt, word4 (&R)[NCH]) {
   const unsigned base = (unsigned)first * kBoxIluRec * (unsigned)sizeof(FT);
   const unsigned bytes = (unsigned)cnt * kBoxIluRec * (unsigned)sizeof(FT);
 #pragma unroll
   for (int m = 0; m < NCH; ++m) {
-    const unsigned e = (unsigned)(threadIdx.x + kBoxIluThreads * m) * 16u;
+    const unsigned e = (unsigned)(threadIdx.x + TH * m) * 16u;
     R[m] = __builtin_amdgcn_raw_buffer_load_b128(rs, e < bytes ? base + e : kPastEnd, 0, 0);
   }
 }
-template <int NCH>
+template <int NCH, int TH>
 ACCH_DEV void stage_store(word4 *buf, const word4 (&R)[NCH]) {
 #pragma unroll
-  for (int m = 0; m < NCH; ++m) buf[threadIdx.x + kBoxIluThreads * m] = R[m];
+  for (int m = 0; m < NCH; ++m) buf[threadIdx.x + TH * m] = R[m];
 }
 
 // Waits until at most N vector-memory operations (loads and stores) of this wave are
@@ -396,9 +396,9 @@ __global__ __launch_bounds__(256) void k_boxilu_scatter(Phys P, BoxIluGeom X, Bo
 // copies the records and box values of the next wavefront (loaded D - 1 steps earlier) to
 // LDS and loads those of wavefront s.  The two waits of a step are exact counts of the
 // accesses issued after the ones it needs.
-template <typename FT, int NCH, int D, bool FWD>
+template <typename FT, int NCH, int D, int TH, bool FWD>
 ACCH_DEV void sweep(const BoxIluGeom &X, __amdgpu_buffer_rsrc_t rsRec, __amdgpu_buffer_rsrc_t rsV,
-                    word4 (*stage)[NCH * kBoxIluThreads], typename ChunkOf2<FT>::T (*stv)[64],
+                    word4 (*stage)[NCH * TH], typename ChunkOf2<FT>::T (*stv)[64],
                     typename ChunkOf2<FT>::T (*ring)[2 * kRingW], const int (&off)[3]) {
   using V2 = typename ChunkOf2<FT>::T;
   const int t = threadIdx.x, p = t >> 2, part = t & 3;
@@ -424,7 +424,7 @@ ACCH_DEV void sweep(const BoxIluGeom &X, __amdgpu_buffer_rsrc_t rsRec, __amdgpu_
       const int wl = FWD ? w + D : w - D;          // wavefront loaded on this step
       const int wn = FWD ? w + 1 : w - 1;          // next wavefront
       const int cw = count(w), cl = count(wl);
-      lds_barrier();
+      if constexpr (TH > 64) lds_barrier();   // one wave: its LDS accesses are performed in order
       const bool act = p < cw;
       const int j = level_jlo(w, X.bw) + p, i = w - 3 * j;
       V2 v = stv[w & 1][p & 63];
@@ -457,9 +457,9 @@ ACCH_DEV void sweep(const BoxIluGeom &X, __amdgpu_buffer_rsrc_t rsRec, __amdgpu_
       // the records and values of the next wavefront (loaded D - 1 steps ago) to LDS
       wait_vm<(D - 2) * kOps + 1>();
       __builtin_amdgcn_sched_barrier(0);
-      stage_store<NCH>(&stage[wn & 1][0], R[(k + 1) % D]);
+      stage_store<NCH, TH>(&stage[wn & 1][0], R[(k + 1) % D]);
       if (t < 64) stv[wn & 1][t] = RV[(k + 1) % D];
-      stage_load<FT, NCH>(rsRec, first_l, cl, R[k]);
+      stage_load<FT, NCH, TH>(rsRec, first_l, cl, R[k]);
       RV[k] = load_pair(rsV, t < cl ? (unsigned)((first_l + t) * sizeof(V2)) : kPastEnd, 0, (const V2 *)nullptr);
       if (FWD) {
         first_c += cw;
@@ -473,13 +473,13 @@ ACCH_DEV void sweep(const BoxIluGeom &X, __amdgpu_buffer_rsrc_t rsRec, __amdgpu_
   }
 }
 
-template <typename FT, int NCH, int D>
-__global__ __launch_bounds__(kBoxIluThreads) void k_boxilu_apply2d(BoxIluGeom X, const FT *__restrict__ Lrec,
+template <typename FT, int NCH, int D, int TH>
+__global__ __launch_bounds__(TH) void k_boxilu_apply2d(BoxIluGeom X, const FT *__restrict__ Lrec,
                                                                   const FT *__restrict__ Urec,
                                                                   void *__restrict__ ybox_, const GmresState *st) {
   using V2 = typename ChunkOf2<FT>::T;
   if (st && st->done) return;
-  __shared__ word4 stage[2][NCH * kBoxIluThreads];
+  __shared__ word4 stage[2][NCH * TH];
   __shared__ V2 stv[2][64];
   // ring: box row j at ring row j + 2, bh + 4 rows (dynamic LDS, so that blocks of small
   // boxes share a CU)
@@ -487,7 +487,7 @@ __global__ __launch_bounds__(kBoxIluThreads) void k_boxilu_apply2d(BoxIluGeom X,
   V2(*ring)[2 * kRingW] = reinterpret_cast<V2(*)[2 * kRingW]>(dyn_lds);
   const int t = threadIdx.x;
   const int part = t & 3;   // the lane's 3 of the cell's 12 neighbour cells: 3 part .. 3 part + 2
-  for (int e = t; e < (X.bh + 4) * 2 * kRingW; e += kBoxIluThreads) (&ring[0][0])[e] = V2{(FT)0, (FT)0};
+  for (int e = t; e < (X.bh + 4) * 2 * kRingW; e += TH) (&ring[0][0])[e] = V2{(FT)0, (FT)0};
   const long cbase = (long)blockIdx.x * X.ncell;
   const unsigned rbytes = (unsigned)(X.ncell * kBoxIluRec * sizeof(FT));
   const __amdgpu_buffer_rsrc_t rsL = buffer_rsrc(Lrec + cbase * kBoxIluRec, rbytes);
@@ -502,10 +502,10 @@ __global__ __launch_bounds__(kBoxIluThreads) void k_boxilu_apply2d(BoxIluGeom X,
     offU[m] = up.dy * 2 * kRingW + up.dx + 2;
   }
   __syncthreads();
-  sweep<FT, NCH, D, true>(X, rsL, rsV, stage, stv, ring, offL);
+  sweep<FT, NCH, D, TH, true>(X, rsL, rsV, stage, stv, ring, offL);
   wait_vm<0>();
   __syncthreads();   // y of every cell in ybox, written by other threads, before the U sweep
-  sweep<FT, NCH, D, false>(X, rsU, rsV, stage, stv, ring, offU);
+  sweep<FT, NCH, D, TH, false>(X, rsU, rsV, stage, stv, ring, offU);
 }
 
 // Factors (FT records) -> FP64 [sub][cell j bw + i][L record, U record].
@@ -523,12 +523,13 @@ __global__ void k_boxilu_export(BoxIluGeom X, int nsub, const int *__restrict__ 
   }
 }
 
-template <typename FT, int NCH>
+template <typename FT, int NCH, int TH>
 void apply_launch(const BoxIluGeom &X, const BoxGeom &G, const void *L, const void *U, double *ybox,
                   const GmresState *st, hipStream_t s) {
+  constexpr int D = TH == 64 ? (NCH <= 7 ? 4 : 3) : (NCH <= 3 ? 6 : 4);   // register stages
   const size_t ring_bytes = (size_t)(X.bh + 4) * 2 * kRingW * 2 * sizeof(FT);
-  hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, (NCH <= 3 ? 6 : 4)>), dim3(G.nsub), dim3(kBoxIluThreads), ring_bytes, s,
-                     X, (const FT *)L, (const FT *)U, (void *)ybox, st);
+  hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, D, TH>), dim3(G.nsub), dim3(TH), ring_bytes, s, X, (const FT *)L,
+                     (const FT *)U, (void *)ybox, st);
 }
 
 template <typename FT>
@@ -538,14 +539,33 @@ hipError_t apply_t(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const S
   const dim3 cells((X.ncell + 255) / 256, G.nsub);
   hipLaunchKernelGGL(k_boxilu_gather<FT>, cells, dim3(256), 0, s, P, X, subs, cellof, r, (void *)ybox, st, vstride,
                      kind);
-  const int nch = (X.maxcount * kBoxIluRec * (int)sizeof(FT) + 16 * kBoxIluThreads - 1) / (16 * kBoxIluThreads);
-  switch (nch) {
-    case 1: apply_launch<FT, 1>(X, G, L, U, ybox, st, s); break;
-    case 2: apply_launch<FT, 2>(X, G, L, U, ybox, st, s); break;
-    case 3: apply_launch<FT, 3>(X, G, L, U, ybox, st, s); break;
-    case 4: apply_launch<FT, 4>(X, G, L, U, ybox, st, s); break;
-    case 5: apply_launch<FT, 5>(X, G, L, U, ybox, st, s); break;
-    default: return hipErrorInvalidValue;
+  const int bytes = X.maxcount * kBoxIluRec * (int)sizeof(FT);   // one wavefront's records
+  // One wave per box when the quads of a wavefront fit it (no barriers) and there are
+  // enough boxes for several blocks per CU; otherwise 256 threads, whose four waves share
+  // the loads.
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  if (X.maxcount <= 16 && G.nsub >= 2 * cus) {
+    const int nch = (bytes + 1023) / 1024;
+    if (nch <= 3) apply_launch<FT, 3, 64>(X, G, L, U, ybox, st, s);
+    else if (nch <= 5) apply_launch<FT, 5, 64>(X, G, L, U, ybox, st, s);
+    else if (nch <= 7) apply_launch<FT, 7, 64>(X, G, L, U, ybox, st, s);
+    else if (nch <= 10) apply_launch<FT, 10, 64>(X, G, L, U, ybox, st, s);
+    else apply_launch<FT, 13, 64>(X, G, L, U, ybox, st, s);
+  } else {
+    switch ((bytes + 16 * kBoxIluThreads - 1) / (16 * kBoxIluThreads)) {
+      case 1: apply_launch<FT, 1, kBoxIluThreads>(X, G, L, U, ybox, st, s); break;
+      case 2: apply_launch<FT, 2, kBoxIluThreads>(X, G, L, U, ybox, st, s); break;
+      case 3: apply_launch<FT, 3, kBoxIluThreads>(X, G, L, U, ybox, st, s); break;
+      case 4: apply_launch<FT, 4, kBoxIluThreads>(X, G, L, U, ybox, st, s); break;
+      case 5: apply_launch<FT, 5, kBoxIluThreads>(X, G, L, U, ybox, st, s); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   hipLaunchKernelGGL(k_boxilu_scatter<FT>, cells, dim3(256), 0, s, P, X, G, subs, cellof, (const void *)ybox, boxbuf,
                      z, st, vstride, kind);
