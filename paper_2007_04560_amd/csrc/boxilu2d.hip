@@ -174,8 +174,8 @@ ACCH_DEV void eliminate(double (&a)[50], double (&b)[50], const FT *Uk, const in
   (eliminate_cell<FT, K>(a, b, Uk, lvoff, rc, i, j, bw), ...);
 }
 
-template <typename FT>
-__global__ __launch_bounds__(kBoxIluThreads) void k_boxilu_factor2d(Phys P, BoxIluGeom X, const SubInfo *__restrict__ subs,
+template <typename FT, int TH>
+__global__ __launch_bounds__(TH) void k_boxilu_factor2d(Phys P, BoxIluGeom X, const SubInfo *__restrict__ subs,
                                                                   const int *__restrict__ lvoff,
                                                                   const double *__restrict__ J, double shift,
                                                                   FT *__restrict__ Lrec, FT *__restrict__ Urec) {
@@ -579,16 +579,31 @@ bool boxilu_fits(const BoxIluGeom &X) {
          X.maxcount * kBoxIluRec * 8 <= 5 * 16 * kBoxIluThreads;
 }
 
+namespace {
+template <typename FT, int TH>
+void factor_launch(const BatchLaunch &bl, const BoxIluGeom &X, int nsub, const SubInfo *subs, const int *lvoff,
+                   const double *J, double shift, void *L, void *U, hipStream_t s) {
+  hipLaunchKernelGGL((k_boxilu_factor2d<FT, TH>), dim3(nsub), dim3(TH), 0, s, bl.P0, X, subs, lvoff, J, shift,
+                     (FT *)L, (FT *)U);
+}
+template <typename FT>
+void factor_t(const BatchLaunch &bl, const BoxIluGeom &X, int nsub, const SubInfo *subs, const int *lvoff,
+              const double *J, double shift, void *L, void *U, hipStream_t s) {
+  // one thread per box row; short boxes take smaller blocks, so that several share a CU
+  if (X.bh <= 64) factor_launch<FT, 64>(bl, X, nsub, subs, lvoff, J, shift, L, U, s);
+  else if (X.bh <= 128) factor_launch<FT, 128>(bl, X, nsub, subs, lvoff, J, shift, L, U, s);
+  else factor_launch<FT, kBoxIluThreads>(bl, X, nsub, subs, lvoff, J, shift, L, U, s);
+}
+}  // namespace
+
 hipError_t launch_boxilu_factor2d(const BatchLaunch &bl, const BoxIluGeom &X, int nsub, const SubInfo *subs,
                                   const int *lvoff, const double *J, double shift, void *L, void *U, int fp32,
                                   hipStream_t s) {
   if (bl.bt.map[kFamSub] != nullptr || !boxilu_fits(X)) return hipErrorInvalidValue;
   if (fp32)
-    hipLaunchKernelGGL(k_boxilu_factor2d<float>, dim3(nsub), dim3(kBoxIluThreads), 0, s, bl.P0, X, subs, lvoff, J,
-                       shift, (float *)L, (float *)U);
+    factor_t<float>(bl, X, nsub, subs, lvoff, J, shift, L, U, s);
   else
-    hipLaunchKernelGGL(k_boxilu_factor2d<double>, dim3(nsub), dim3(kBoxIluThreads), 0, s, bl.P0, X, subs, lvoff, J,
-                       shift, (double *)L, (double *)U);
+    factor_t<double>(bl, X, nsub, subs, lvoff, J, shift, L, U, s);
   return hipGetLastError();
 }
 
