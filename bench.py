@@ -38,6 +38,15 @@ WORKLOADS = {
                         seed=0, steps=200,
                         text="periodic512: 2D periodic 512x512, 200 adaptive steps dt in [1e-4,1e-1], FP64 NKS, "
                              "left-RAS 8x8 overlap 2, ILU(0) shift 0.02, GMRES(30), tol 1e-8"),
+    # the same run with the subdomain ILU(0) on the width-2 box pattern (no shift) over 32x32
+    # subdomains, its fastest layout at this size
+    "periodic512_box32": dict(name="periodic512_box32", shape=(512, 512), bc="periodic", sub=(32, 32), overlap=2,
+                              adaptive=True, dt_min=1e-4, dt_max=1e-1, eta0=1e4, newton_rtol=1e-8,
+                              newton_atol=1e-13, gmres_rtol=1e-8, gmres_atol=1e-14, gmres_restart=30, ilu_shift=0.0,
+                              precision="fp64", seed=0, steps=200, subsolver="iluk_box", fill_level=0,
+                              text="periodic512_box32: 2D periodic 512x512, 200 adaptive steps dt in [1e-4,1e-1], "
+                                   "FP64 NKS, left-RAS 32x32 overlap 2, ILU(0) on the width-2 box pattern (no "
+                                   "shift), GMRES(30), tol 1e-8"),
     # the 2048^2 Neumann configuration with FP32 subdomain factors and solves
     "neumann2048": dict(name="neumann2048", shape=(2048, 2048), bc="neumann", sub=(16, 16), overlap=2,
                         adaptive=True, dt_min=1e-4, dt_max=1e-1, eta0=1e4, newton_rtol=1e-8, newton_atol=1e-13,
@@ -128,18 +137,22 @@ def arnoldi_bytes_per_cell(k: float, m: int = 30) -> float:
     return total
 
 
-def step_bytes_per_cell(newton: int, gmres: int, steps: int, nnz: int, omega: float, sp: int, m: int = 30) -> float:
+def step_bytes_per_cell(newton: int, gmres: int, steps: int, nnz: int, omega: float, sp: int, m: int = 30,
+                        fac_slots: int = 0, ras_slots: int = 0) -> float:
     """Algorithmic bytes per cell of a run (the minimum the method moves: one read of
     each operand and one write of each result): per Newton iteration B_res (two
     evaluations: the iteration's residual and an accepted full step) + B_jac + B_fact
     (one factorisation per step, factor reuse) + sum over its GMRES iterations of B_spmv
-    + B_ras + B_arn(j) + B_upd, with the mean GMRES count per Newton iteration."""
+    + B_ras + B_arn(j) + B_upd, with the mean GMRES count per Newton iteration.
+    fac_slots / ras_slots: factor values per box cell written by the factorisation and
+    read (with the box vector) by one Schwarz apply; default nnz (the stencil-pattern
+    ILU(0), whose records have the Jacobian's slots)."""
     if newton <= 0:
         return 0.0
     k = gmres / newton
     b_res, b_jac, b_spmv = 48.0, 32.0 + 8.0 * nnz, 8.0 * nnz + 32.0
-    b_ras = omega * 16.0 + omega * nnz * sp + 16.0
-    b_fact = omega * nnz * (8.0 + sp) * steps / newton
+    b_ras = omega * 16.0 + omega * (ras_slots or nnz) * sp + 16.0
+    b_fact = omega * (nnz * 8.0 + (fac_slots or nnz) * sp) * steps / newton
     per_newton = 2 * b_res + b_jac + b_fact + k * (b_spmv + b_ras) + arnoldi_bytes_per_cell(k, m) + 16.0 * (k + 1)
     return newton * per_newton
 
@@ -779,8 +792,11 @@ def main():
     }
     if not band:   # the whole run against the HBM roofline (ILU(0) subdomain solver)
         omega = box / owned
+        # box-pattern ILU(0): 2 x 52 record slots per box cell, and the box vector written and
+        # read back by the sweeps (4 more values)
+        slots = dict(fac_slots=104, ras_slots=108) if boxilu else {}
         tot = step_bytes_per_cell(newton_its, gmres_its, len(recs), nslot, omega, 4 if w["precision"] == "mixed" else 8,
-                                  w["gmres_restart"]) * r["ncell"]
+                                  w["gmres_restart"], **slots) * r["ncell"]
         line["config"]["whole_run_roofline"] = {
             "algorithmic_bytes": int(tot), "achieved_GBps": round(tot / r["elapsed"] / 1e9, 1),
             "frac": round(tot / r["elapsed"] / 1e9 / HBM_PEAK_GBS, 4),
