@@ -181,3 +181,34 @@ def test_box_ilu0_steps_match_oracle(precision):
         assert _rel_l2(ug, vg, run.u, run.v) <= 1e-10, k
         assert info["newton_its"] == rec.newton_its
     assert its < its0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind", ["left", "classical"])
+def test_box_ilu0_one_wave_form_matches_oracle(precision, kind):
+    """576 boxes of 6x6 cells (24x24 subdomains of a 96x96 periodic grid, overlap 1): at
+    least two boxes per CU with at most 16 cells per wavefront, so the sweeps run one wave
+    per box without barriers; M^{-1} r against the oracle."""
+    shape, bc, sub, ov = (96, 96), "periodic", (24, 24), 1
+    s, Jo = _setup(shape, bc, sub, ov, precision=precision, kind=kind)
+    info = s.info()
+    assert info["nsub"] == 576 and (info["box_w"], info["box_h"]) == (6, 6)
+    r = np.random.default_rng(13).standard_normal(Jo.shape[0])
+    z = s.precondition(dev(r)).cpu().numpy()
+    zo = schwarz.Schwarz(Jo, shape, (sub[1], sub[0]), ov, bc, kind=kind, solver="iluk_box", level=0).apply(r)
+    if precision == "fp64":
+        assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
+    else:
+        assert np.linalg.norm(z - zo) <= 1e-4 * np.linalg.norm(zo)
+
+
+def test_box_ilu0_factor_blocks_of_128_rows():
+    """A box 69 rows tall takes the 128-thread factorisation blocks: records and M^{-1} r
+    against the oracle."""
+    shape, bc, sub, ov = (130, 20), "neumann", (1, 2), 2
+    s, Jo = _setup(shape, bc, sub, ov, dt=1e-3)
+    assert s.info()["box_h"] == 69
+    r = np.random.default_rng(14).standard_normal(Jo.shape[0])
+    z = s.precondition(dev(r)).cpu().numpy()
+    zo = schwarz.Schwarz(Jo, shape, (sub[1], sub[0]), ov, bc, kind="left", solver="iluk_box", level=0).apply(r)
+    assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
