@@ -56,3 +56,23 @@ def test_long_run_energy_mass_and_step_growth(bc):
     assert max(dts) > 4e-4, "dt never left dt_min"
     ts = [r["t"] for r in recs]
     assert all(b > a for a, b in zip(ts, ts[1:]))
+
+
+def test_long_run_with_plain_box_pattern_ilu0_leaves_small_steps():
+    """The 128x128 periodic long run (8x8 subdomains, overlap 1, the late-time tolerance
+    eps_a = 1e-6) with plain (unshifted) ILU(0) on the box pattern: 2000 steps with the
+    energy non-increasing and the mass conserved at every step, and dt growing past 1e-2.
+    Over the same 2000 steps shifted ILU(0) on the stencil pattern stays at dt <= 1.2e-3:
+    GMRES fails as dt grows, and every failure doubles eta."""
+    shape = (128, 128)
+    u0, v0 = random_ic(shape, 0, u_mean=0.55)
+    s = Solver(u0, v0, bc="periodic", sub=(8, 8), overlap=1, subsolver="iluk_box", fill_level=0, ilu_shift=0.0,
+               newton_atol=1e-6, **PHYS, **CTRL)
+    E0, M0 = s.energy()
+    recs = []
+    for _ in range(20):
+        recs += s.step(100)
+    E = [E0] + [r["energy"] for r in recs]
+    assert all(b <= a + 1e-12 * abs(a) for a, b in zip(E, E[1:])), "energy increased"
+    assert all(abs(r["mass"] - M0) <= 1e-12 * M0 for r in recs)
+    assert max(r["dt"] for r in recs) > 1e-2
