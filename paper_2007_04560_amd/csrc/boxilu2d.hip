@@ -328,63 +328,72 @@ ACCH_DEV void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// The apply runs in three kernels: a gather of R_k r into the box vector ybox (in the
-// cell order of the records), the two sweeps, which overwrite ybox with y and then x, and a
-// scatter of x to z (left RAS) or to the box buffer of the overlap sum.
-template <typename FT>
-__global__ __launch_bounds__(256) void k_boxilu_gather(Phys P, BoxIluGeom X, const SubInfo *__restrict__ subs,
-                                                       const int *__restrict__ cellof, const double *__restrict__ r,
-                                                       void *__restrict__ ybox_, const GmresState *st, long vstride,
-                                                       int kind) {
+// Gather of R_k r into the box vector (in the cell order of the records) and scatter of x
+// from it to z (left RAS) or to the box buffer of the overlap sum, by the threads of the
+// box's block before and after the sweeps; kGS cells per thread are handled together, so
+// their loads are in flight at once.
+constexpr int kGS = 4;
+
+template <typename FT, int TH>
+ACCH_DEV void gather_box(const Phys &P, const BoxIluGeom &X, const SubInfo &si, const Rect &rc,
+                         const int *__restrict__ cellof, const double *__restrict__ r, double sc,
+                         typename ChunkOf2<FT>::T *yk, int kind) {
   using V2 = typename ChunkOf2<FT>::T;
-  double sc = 1.0;
-  if (st) {
-    if (st->done) return;
-    r += (long)st->j * vstride;
-    sc = st->inv_norm[st->j];
+  const long n = (long)P.nx * P.ny;
+  for (int p0 = 0; p0 < X.ncell; p0 += kGS * TH) {
+    long g[kGS];
+    int pos[kGS];
+#pragma unroll
+    for (int u = 0; u < kGS; ++u) {
+      pos[u] = p0 + u * TH + (int)threadIdx.x;
+      const int ij = pos[u] < X.ncell ? cellof[pos[u]] : 0, i = ij & 0xffff, j = ij >> 16;
+      g[u] = -1;
+      if (pos[u] < X.ncell && rc.in(i, j)) {
+        const bool own = i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1;
+        if (kind != ACCH_RAS_RIGHT || own) g[u] = box_to_global(si, i, j, P.nx, P.ny, P.periodic);
+      }
+    }
+    V2 v[kGS];
+#pragma unroll
+    for (int u = 0; u < kGS; ++u)
+      v[u] = g[u] >= 0 ? V2{(FT)(sc * r[g[u]]), (FT)(sc * r[g[u] + n])} : V2{(FT)0, (FT)0};
+#pragma unroll
+    for (int u = 0; u < kGS; ++u)
+      if (pos[u] < X.ncell) yk[pos[u]] = v[u];
   }
-  const int pos = blockIdx.x * 256 + threadIdx.x;
-  if (pos >= X.ncell) return;
-  const SubInfo si = subs[blockIdx.y];
-  const Rect rc = grid_rect(si, X.bw, X.bh, P.nx, P.ny, P.periodic);
-  const int ij = cellof[pos], i = ij & 0xffff, j = ij >> 16;
-  V2 v{(FT)0, (FT)0};
-  if (rc.in(i, j)) {
-    const long g = box_to_global(si, i, j, P.nx, P.ny, P.periodic);
-    const bool own = i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1;
-    if (kind != ACCH_RAS_RIGHT || own) v = V2{(FT)(sc * r[g]), (FT)(sc * r[g + (long)P.nx * P.ny])};
-  }
-  ((V2 *)ybox_)[(long)blockIdx.y * X.ncell + pos] = v;
 }
 
-template <typename FT>
-__global__ __launch_bounds__(256) void k_boxilu_scatter(Phys P, BoxIluGeom X, BoxGeom G,
-                                                        const SubInfo *__restrict__ subs,
-                                                        const int *__restrict__ cellof,
-                                                        const void *__restrict__ ybox_, void *__restrict__ boxbuf_,
-                                                        double *__restrict__ z, const GmresState *st, long vstride,
-                                                        int kind) {
+template <typename FT, int TH>
+ACCH_DEV void scatter_box(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const SubInfo &si, const Rect &rc,
+                          const int *__restrict__ cellof, const typename ChunkOf2<FT>::T *yk, FT *boxbuf,
+                          double *__restrict__ z, int kind) {
   using V2 = typename ChunkOf2<FT>::T;
-  if (st) {
-    if (st->done) return;
-    z += (long)st->j * vstride;
-  }
-  const int pos = blockIdx.x * 256 + threadIdx.x;
-  if (pos >= X.ncell) return;
-  const SubInfo si = subs[blockIdx.y];
-  const Rect rc = grid_rect(si, X.bw, X.bh, P.nx, P.ny, P.periodic);
-  const int ij = cellof[pos], i = ij & 0xffff, j = ij >> 16;
-  if (!rc.in(i, j)) return;
-  const V2 x = ((const V2 *)ybox_)[(long)blockIdx.y * X.ncell + pos];
-  if (kind == ACCH_RAS_LEFT) {
-    if (i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1) {
-      const long g = box_to_global(si, i, j, P.nx, P.ny, P.periodic);
-      z[g] = (double)x.x;
-      z[g + (long)P.nx * P.ny] = (double)x.y;
+  const long n = (long)P.nx * P.ny;
+  const long ncb = (long)G.nlev * G.bh;
+  for (int p0 = 0; p0 < X.ncell; p0 += kGS * TH) {
+    int ij[kGS];
+    V2 x[kGS];
+#pragma unroll
+    for (int u = 0; u < kGS; ++u) {
+      const int pos = p0 + u * TH + (int)threadIdx.x;
+      ij[u] = pos < X.ncell ? cellof[pos] : -1;
+      x[u] = pos < X.ncell ? yk[pos] : V2{(FT)0, (FT)0};
     }
-  } else {
-    const long ncb = (long)G.nlev * G.bh;
-    ((V2 *)boxbuf_)[(long)blockIdx.y * (ncb + 1) + (long)(i + 2 * j) * G.bh + j] = x;
+#pragma unroll
+    for (int u = 0; u < kGS; ++u) {
+      if (ij[u] < 0) continue;
+      const int i = ij[u] & 0xffff, j = ij[u] >> 16;
+      if (!rc.in(i, j)) continue;
+      if (kind == ACCH_RAS_LEFT) {
+        if (i >= si.own_x0 && i < si.own_x1 && j >= si.own_y0 && j < si.own_y1) {
+          const long g = box_to_global(si, i, j, P.nx, P.ny, P.periodic);
+          z[g] = (double)x[u].x;
+          z[g + n] = (double)x[u].y;
+        }
+      } else {
+        ((V2 *)boxbuf)[(long)blockIdx.x * (ncb + 1) + (long)(i + 2 * j) * G.bh + j] = x[u];
+      }
+    }
   }
 }
 
@@ -474,11 +483,20 @@ ACCH_DEV void sweep(const BoxIluGeom &X, __amdgpu_buffer_rsrc_t rsRec, __amdgpu_
 }
 
 template <typename FT, int NCH, int D, int TH>
-__global__ __launch_bounds__(TH) void k_boxilu_apply2d(BoxIluGeom X, const FT *__restrict__ Lrec,
-                                                                  const FT *__restrict__ Urec,
-                                                                  void *__restrict__ ybox_, const GmresState *st) {
+__global__ __launch_bounds__(TH) void k_boxilu_apply2d(Phys P, BoxIluGeom X, BoxGeom G, const SubInfo *__restrict__ subs,
+                                                      const int *__restrict__ cellof, const FT *__restrict__ Lrec,
+                                                      const FT *__restrict__ Urec, void *__restrict__ ybox_,
+                                                      void *__restrict__ boxbuf, const double *__restrict__ r,
+                                                      double *__restrict__ z, const GmresState *st, long vstride,
+                                                      int kind) {
   using V2 = typename ChunkOf2<FT>::T;
-  if (st && st->done) return;
+  double sc = 1.0;
+  if (st) {
+    if (st->done) return;
+    r += (long)st->j * vstride;
+    z += (long)st->j * vstride;
+    sc = st->inv_norm[st->j];
+  }
   __shared__ word4 stage[2][NCH * TH];
   __shared__ V2 stv[2][64];
   // ring: box row j at ring row j + 2, bh + 4 rows (dynamic LDS, so that blocks of small
@@ -501,11 +519,18 @@ __global__ __launch_bounds__(TH) void k_boxilu_apply2d(BoxIluGeom X, const FT *_
     offL[m] = lo.dy * 2 * kRingW + lo.dx + 2;
     offU[m] = up.dy * 2 * kRingW + up.dx + 2;
   }
-  __syncthreads();
+  const SubInfo si = subs[blockIdx.x];
+  const Rect rc = grid_rect(si, X.bw, X.bh, P.nx, P.ny, P.periodic);
+  V2 *yk = (V2 *)ybox_ + cbase;
+  gather_box<FT, TH>(P, X, si, rc, cellof, r, sc, yk, kind);
+  __syncthreads();   // the box vector, written by other threads, before the L sweep loads it
   sweep<FT, NCH, D, TH, true>(X, rsL, rsV, stage, stv, ring, offL);
   wait_vm<0>();
   __syncthreads();   // y of every cell in ybox, written by other threads, before the U sweep
   sweep<FT, NCH, D, TH, false>(X, rsU, rsV, stage, stv, ring, offU);
+  wait_vm<0>();
+  __syncthreads();   // x of every cell, before the scatter reads it
+  scatter_box<FT, TH>(P, X, G, si, rc, cellof, yk, (FT *)boxbuf, z, kind);
 }
 
 // Factors (FT records) -> FP64 [sub][cell j bw + i][L record, U record].
@@ -524,21 +549,19 @@ __global__ void k_boxilu_export(BoxIluGeom X, int nsub, const int *__restrict__ 
 }
 
 template <typename FT, int NCH, int TH>
-void apply_launch(const BoxIluGeom &X, const BoxGeom &G, const void *L, const void *U, double *ybox,
-                  const GmresState *st, hipStream_t s) {
+void apply_launch(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const int *cellof,
+                  const void *L, const void *U, double *ybox, void *boxbuf, const double *r, double *z,
+                  const GmresState *st, long vstride, int kind, hipStream_t s) {
   constexpr int D = TH == 64 ? (NCH <= 7 ? 4 : 3) : (NCH <= 3 ? 6 : 4);   // register stages
   const size_t ring_bytes = (size_t)(X.bh + 4) * 2 * kRingW * 2 * sizeof(FT);
-  hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, D, TH>), dim3(G.nsub), dim3(TH), ring_bytes, s, X, (const FT *)L,
-                     (const FT *)U, (void *)ybox, st);
+  hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, D, TH>), dim3(G.nsub), dim3(TH), ring_bytes, s, P, X, G, subs, cellof,
+                     (const FT *)L, (const FT *)U, (void *)ybox, boxbuf, r, z, st, vstride, kind);
 }
 
 template <typename FT>
 hipError_t apply_t(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const int *cellof,
                    const void *L, const void *U, double *ybox, void *boxbuf, const double *r, double *z,
                    const GmresState *st, long vstride, int kind, hipStream_t s) {
-  const dim3 cells((X.ncell + 255) / 256, G.nsub);
-  hipLaunchKernelGGL(k_boxilu_gather<FT>, cells, dim3(256), 0, s, P, X, subs, cellof, r, (void *)ybox, st, vstride,
-                     kind);
   const int bytes = X.maxcount * kBoxIluRec * (int)sizeof(FT);   // one wavefront's records
   // One wave per box when the quads of a wavefront fit it (no barriers) and there are
   // enough boxes for several blocks per CU; otherwise 256 threads, whose four waves share
@@ -552,23 +575,21 @@ hipError_t apply_t(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const S
   }
   if (X.maxcount <= 16 && G.nsub >= 2 * cus) {
     const int nch = (bytes + 1023) / 1024;
-    if (nch <= 3) apply_launch<FT, 3, 64>(X, G, L, U, ybox, st, s);
-    else if (nch <= 5) apply_launch<FT, 5, 64>(X, G, L, U, ybox, st, s);
-    else if (nch <= 7) apply_launch<FT, 7, 64>(X, G, L, U, ybox, st, s);
-    else if (nch <= 10) apply_launch<FT, 10, 64>(X, G, L, U, ybox, st, s);
-    else apply_launch<FT, 13, 64>(X, G, L, U, ybox, st, s);
+    if (nch <= 3) apply_launch<FT, 3, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s);
+    else if (nch <= 5) apply_launch<FT, 5, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s);
+    else if (nch <= 7) apply_launch<FT, 7, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s);
+    else if (nch <= 10) apply_launch<FT, 10, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s);
+    else apply_launch<FT, 13, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s);
   } else {
     switch ((bytes + 16 * kBoxIluThreads - 1) / (16 * kBoxIluThreads)) {
-      case 1: apply_launch<FT, 1, kBoxIluThreads>(X, G, L, U, ybox, st, s); break;
-      case 2: apply_launch<FT, 2, kBoxIluThreads>(X, G, L, U, ybox, st, s); break;
-      case 3: apply_launch<FT, 3, kBoxIluThreads>(X, G, L, U, ybox, st, s); break;
-      case 4: apply_launch<FT, 4, kBoxIluThreads>(X, G, L, U, ybox, st, s); break;
-      case 5: apply_launch<FT, 5, kBoxIluThreads>(X, G, L, U, ybox, st, s); break;
+      case 1: apply_launch<FT, 1, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
+      case 2: apply_launch<FT, 2, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
+      case 3: apply_launch<FT, 3, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
+      case 4: apply_launch<FT, 4, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
+      case 5: apply_launch<FT, 5, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
       default: return hipErrorInvalidValue;
     }
   }
-  hipLaunchKernelGGL(k_boxilu_scatter<FT>, cells, dim3(256), 0, s, P, X, G, subs, cellof, (const void *)ybox, boxbuf,
-                     z, st, vstride, kind);
   return hipGetLastError();
 }
 
