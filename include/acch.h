@@ -53,11 +53,12 @@ enum { ACCH_RAS_LEFT = 0, ACCH_RAS_RIGHT = 1, ACCH_AS_CLASSICAL = 2 };
  * level-0 pattern is the "box" pattern (every coupling of two cells at most 2 apart
  * along each axis, u and v both ways: the structure a structured-grid sparse-matrix
  * library allocates for this stencil; k = fill_level, 0 allowed, 0 is ILU(0) on it).
- * The paper does not state its ILU pattern.  ILU(k), box ILU(k) and LU are 2D,
- * single-instance, and need padded subdomain boxes (owned width + 2 overlap) of at
- * most 55 cells in x (54 with the box pattern): they store the band of A_k in the
- * natural order (half bandwidth 4 box widths, plus 5 with the box pattern) and factor
- * it without pivoting. */
+ * The paper does not state its ILU pattern.  All but ILU(0) on the stencil are 2D and
+ * single-instance.  ILU(k), box ILU(k) with k >= 1 and LU need padded subdomain boxes
+ * (owned width + 2 overlap) of at most 55 cells in x (54 with the box pattern): they
+ * store the band of A_k in the natural order (half bandwidth 4 box widths, plus 5 with
+ * the box pattern) and factor it without pivoting.  Box ILU(0) has kernels of its own
+ * (compact records, wavefront sweeps) and takes padded boxes up to 144 x 160 cells. */
 enum { ACCH_SUB_ILU0 = 0, ACCH_SUB_ILUK = 1, ACCH_SUB_LU = 2, ACCH_SUB_ILUK_BOX = 3 };
 /* Precision of the subdomain ILU(0) factors and triangular solves; the residual,
  * Jacobian products, Arnoldi process, Newton update and diagnostics stay FP64. */
