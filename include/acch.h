@@ -275,8 +275,9 @@ int acch_counters(acch_ctx *c, long *launches, long *syncs);
 int acch_apply_jacobian_transpose(acch_ctx *c, const double *x, double *y);
 
 /* z = M^{-T} r: the exact transpose of the Schwarz preconditioner with the current
- * factors, sum_k (R_k^delta)^T (L_k U_k)^{-T} R_k^0 r.  Needs overlap <= the
- * smallest subdomain width (ACCH_EUNSUPPORTED otherwise). */
+ * factors, sum_k (R_k^delta)^T (L_k U_k)^{-T} R_k^0 r (left-restricted; the other
+ * variants likewise).  Needs overlap <= the smallest subdomain width and an ILU(0)
+ * subdomain solver, on the stencil or the box pattern (ACCH_EUNSUPPORTED otherwise). */
 int acch_precondition_transpose(acch_ctx *c, const double *r, double *z);
 
 /* Gradient of the discrete energy E~ (eqs. relations, freeenergy) at the device

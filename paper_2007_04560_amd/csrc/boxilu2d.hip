@@ -405,7 +405,7 @@ ACCH_DEV void scatter_box(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, 
 // copies the records and box values of the next wavefront (loaded D - 1 steps earlier) to
 // LDS and loads those of wavefront s.  The two waits of a step are exact counts of the
 // accesses issued after the ones it needs.
-template <typename FT, int NCH, int D, int TH, bool FWD>
+template <typename FT, int NCH, int D, int TH, bool FWD, bool TRANS = false>
 ACCH_DEV void sweep(const BoxIluGeom &X, __amdgpu_buffer_rsrc_t rsRec, __amdgpu_buffer_rsrc_t rsV,
                     word4 (*stage)[NCH * TH], typename ChunkOf2<FT>::T (*stv)[64],
                     typename ChunkOf2<FT>::T (*ring)[2 * kRingW], const int (&off)[3]) {
@@ -451,7 +451,10 @@ ACCH_DEV void sweep(const BoxIluGeom &X, __amdgpu_buffer_rsrc_t rsRec, __amdgpu_
         }
         v.x -= quad_sum(au);
         v.y -= quad_sum(av);
-        if constexpr (FWD) {
+        if constexpr (FWD && TRANS) {   // U^T: 1/U(u,u) at 49, U(u,v) at 48, 1/U(v,v) at 50
+          v.x *= rec[49];
+          v.y = (v.y - rec[48] * v.x) * rec[50];
+        } else if constexpr (FWD) {
           v.y -= rec[48] * v.x;
         } else {
           v.y *= rec[50];
@@ -482,7 +485,7 @@ ACCH_DEV void sweep(const BoxIluGeom &X, __amdgpu_buffer_rsrc_t rsRec, __amdgpu_
   }
 }
 
-template <typename FT, int NCH, int D, int TH>
+template <typename FT, int NCH, int D, int TH, bool TRANS>
 __global__ __launch_bounds__(TH) void k_boxilu_apply2d(Phys P, BoxIluGeom X, BoxGeom G, const SubInfo *__restrict__ subs,
                                                       const int *__restrict__ cellof, const FT *__restrict__ Lrec,
                                                       const FT *__restrict__ Urec, void *__restrict__ ybox_,
@@ -524,13 +527,65 @@ __global__ __launch_bounds__(TH) void k_boxilu_apply2d(Phys P, BoxIluGeom X, Box
   V2 *yk = (V2 *)ybox_ + cbase;
   gather_box<FT, TH>(P, X, si, rc, cellof, r, sc, yk, kind);
   __syncthreads();   // the box vector, written by other threads, before the L sweep loads it
-  sweep<FT, NCH, D, TH, true>(X, rsL, rsV, stage, stv, ring, offL);
+  sweep<FT, NCH, D, TH, true, TRANS>(X, rsL, rsV, stage, stv, ring, offL);
   wait_vm<0>();
   __syncthreads();   // y of every cell in ybox, written by other threads, before the U sweep
   sweep<FT, NCH, D, TH, false>(X, rsU, rsV, stage, stv, ring, offU);
   wait_vm<0>();
   __syncthreads();   // x of every cell, before the scatter reads it
   scatter_box<FT, TH>(P, X, G, si, rc, cellof, yk, (FT *)boxbuf, z, kind);
+}
+
+// Records of the transposed solves (L U)^{-T}: U^T is swept forward, L^T backward, with the
+// same sweeps.  The U^T record of cell p holds, for its lower cell k (q = p + lower(k), so
+// p = q + upper(11 - k)), the entries of q's U row towards p: U(u_q,u_p) U(v_q,u_p)
+// U(u_q,v_p) U(v_q,v_p) at 4k .. 4k+3, then U(u_p,v_p), 1/U(u_p,u_p), 1/U(v_p,v_p) at 48..50.
+// The L^T record holds, for its upper cell k (q = p + upper(k), p = q + lower(11 - k)),
+// L(u_q,u_p) L(v_q,u_p) L(u_q,v_p) L(v_q,v_p), then 1, L(v_p,u_p), 1 at 48..50 (the
+// backward sweep's diagonal form with a unit diagonal).
+template <typename FT>
+__global__ __launch_bounds__(256) void k_boxilu_pack_t(BoxIluGeom X, const int *__restrict__ lvoff,
+                                                       const int *__restrict__ cellof, const FT *__restrict__ Lrec,
+                                                       const FT *__restrict__ Urec, FT *__restrict__ Tf,
+                                                       FT *__restrict__ Tb) {
+  const int pos = blockIdx.x * 256 + threadIdx.x;
+  if (pos >= X.ncell) return;
+  const long base = (long)blockIdx.y * X.ncell;
+  const int ij = cellof[pos], i = ij & 0xffff, j = ij >> 16;
+  const FT *Lp = Lrec + (base + pos) * kBoxIluRec, *Up = Urec + (base + pos) * kBoxIluRec;
+  FT *F = Tf + (base + pos) * kBoxIluRec, *B = Tb + (base + pos) * kBoxIluRec;
+  auto in_box = [&](int a, int b) { return a >= 0 && a < X.bw && b >= 0 && b < X.bh; };
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const Off lo = lower_cell(k), up = upper_cell(k);
+    const int s = 4 * (11 - k);
+    if (in_box(i + lo.dx, j + lo.dy)) {
+      const FT *Uq = Urec + (base + cell_pos(lvoff, i + lo.dx, j + lo.dy, X.bw)) * kBoxIluRec;
+      F[4 * k] = Uq[s];
+      F[4 * k + 1] = Uq[s + 2];
+      F[4 * k + 2] = Uq[s + 1];
+      F[4 * k + 3] = Uq[s + 3];
+    } else {
+      F[4 * k] = F[4 * k + 1] = F[4 * k + 2] = F[4 * k + 3] = (FT)0;
+    }
+    if (in_box(i + up.dx, j + up.dy)) {
+      const FT *Lq = Lrec + (base + cell_pos(lvoff, i + up.dx, j + up.dy, X.bw)) * kBoxIluRec;
+      B[4 * k] = Lq[s];
+      B[4 * k + 1] = Lq[s + 2];
+      B[4 * k + 2] = Lq[s + 1];
+      B[4 * k + 3] = Lq[s + 3];
+    } else {
+      B[4 * k] = B[4 * k + 1] = B[4 * k + 2] = B[4 * k + 3] = (FT)0;
+    }
+  }
+  F[48] = Up[49];
+  F[49] = Up[48];
+  F[50] = Up[50];
+  F[51] = (FT)0;
+  B[48] = (FT)1;
+  B[49] = Lp[48];
+  B[50] = (FT)1;
+  B[51] = (FT)0;
 }
 
 // Factors (FT records) -> FP64 [sub][cell j bw + i][L record, U record].
@@ -551,17 +606,21 @@ __global__ void k_boxilu_export(BoxIluGeom X, int nsub, const int *__restrict__ 
 template <typename FT, int NCH, int TH>
 void apply_launch(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const int *cellof,
                   const void *L, const void *U, double *ybox, void *boxbuf, const double *r, double *z,
-                  const GmresState *st, long vstride, int kind, hipStream_t s) {
+                  const GmresState *st, long vstride, int kind, bool trans, hipStream_t s) {
   constexpr int D = TH == 64 ? (NCH <= 7 ? 4 : 3) : (NCH <= 3 ? 6 : 4);   // register stages
   const size_t ring_bytes = (size_t)(X.bh + 4) * 2 * kRingW * 2 * sizeof(FT);
-  hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, D, TH>), dim3(G.nsub), dim3(TH), ring_bytes, s, P, X, G, subs, cellof,
-                     (const FT *)L, (const FT *)U, (void *)ybox, boxbuf, r, z, st, vstride, kind);
+  if (trans)
+    hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, D, TH, true>), dim3(G.nsub), dim3(TH), ring_bytes, s, P, X, G, subs,
+                       cellof, (const FT *)L, (const FT *)U, (void *)ybox, boxbuf, r, z, st, vstride, kind);
+  else
+    hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, D, TH, false>), dim3(G.nsub), dim3(TH), ring_bytes, s, P, X, G, subs,
+                       cellof, (const FT *)L, (const FT *)U, (void *)ybox, boxbuf, r, z, st, vstride, kind);
 }
 
 template <typename FT>
 hipError_t apply_t(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const int *cellof,
                    const void *L, const void *U, double *ybox, void *boxbuf, const double *r, double *z,
-                   const GmresState *st, long vstride, int kind, hipStream_t s) {
+                   const GmresState *st, long vstride, int kind, bool trans, hipStream_t s) {
   const int bytes = X.maxcount * kBoxIluRec * (int)sizeof(FT);   // one wavefront's records
   // One wave per box when the quads of a wavefront fit it (no barriers) and there are
   // enough boxes for several blocks per CU; otherwise 256 threads, whose four waves share
@@ -575,18 +634,18 @@ hipError_t apply_t(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const S
   }
   if (X.maxcount <= 16 && G.nsub >= 2 * cus) {
     const int nch = (bytes + 1023) / 1024;
-    if (nch <= 3) apply_launch<FT, 3, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s);
-    else if (nch <= 5) apply_launch<FT, 5, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s);
-    else if (nch <= 7) apply_launch<FT, 7, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s);
-    else if (nch <= 10) apply_launch<FT, 10, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s);
-    else apply_launch<FT, 13, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s);
+    if (nch <= 3) apply_launch<FT, 3, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
+    else if (nch <= 5) apply_launch<FT, 5, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
+    else if (nch <= 7) apply_launch<FT, 7, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
+    else if (nch <= 10) apply_launch<FT, 10, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
+    else apply_launch<FT, 13, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
   } else {
     switch ((bytes + 16 * kBoxIluThreads - 1) / (16 * kBoxIluThreads)) {
-      case 1: apply_launch<FT, 1, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
-      case 2: apply_launch<FT, 2, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
-      case 3: apply_launch<FT, 3, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
-      case 4: apply_launch<FT, 4, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
-      case 5: apply_launch<FT, 5, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, s); break;
+      case 1: apply_launch<FT, 1, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
+      case 2: apply_launch<FT, 2, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
+      case 3: apply_launch<FT, 3, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
+      case 4: apply_launch<FT, 4, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
+      case 5: apply_launch<FT, 5, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -631,11 +690,12 @@ hipError_t launch_boxilu_factor2d(const BatchLaunch &bl, const BoxIluGeom &X, in
 hipError_t launch_boxilu_apply2d(const BatchLaunch &bl, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs,
                                  const int *cellof, const void *L, const void *U, double *ybox, void *boxbuf,
                                  const double *r, double *z, const GmresState *st, long vstride, int fp32,
-                                 hipStream_t s, const RasVariant &rv) {
+                                 hipStream_t s, const RasVariant &rv, bool trans) {
   if (bl.bt.map[kFamSub] != nullptr || !boxilu_fits(X)) return hipErrorInvalidValue;
   if (rv.kind != ACCH_RAS_LEFT && !rv.own_x) return hipErrorInvalidValue;
-  hipError_t e = fp32 ? apply_t<float>(bl.P0, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, s)
-                      : apply_t<double>(bl.P0, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, s);
+  hipError_t e = fp32 ? apply_t<float>(bl.P0, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, trans, s)
+                      : apply_t<double>(bl.P0, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, trans,
+                                        s);
   if (e != hipSuccess || rv.kind == ACCH_RAS_LEFT) return e;
   return launch_ras_sum2d(bl, G, subs, boxbuf, z, st, vstride, fp32, s, rv);
 }
@@ -650,6 +710,18 @@ hipError_t launch_boxilu_export(const BoxIluGeom &X, int nsub, const int *lvoff,
   else
     hipLaunchKernelGGL(k_boxilu_export<double>, dim3(blocks), dim3(256), 0, s, X, nsub, lvoff, (const double *)L,
                        (const double *)U, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_boxilu_pack_t(const BoxIluGeom &X, int nsub, const int *lvoff, const int *cellof, const void *L,
+                                const void *U, void *Tf, void *Tb, int fp32, hipStream_t s) {
+  const dim3 grid((X.ncell + 255) / 256, nsub);
+  if (fp32)
+    hipLaunchKernelGGL(k_boxilu_pack_t<float>, grid, dim3(256), 0, s, X, lvoff, cellof, (const float *)L,
+                       (const float *)U, (float *)Tf, (float *)Tb);
+  else
+    hipLaunchKernelGGL(k_boxilu_pack_t<double>, grid, dim3(256), 0, s, X, lvoff, cellof, (const double *)L,
+                       (const double *)U, (double *)Tf, (double *)Tb);
   return hipGetLastError();
 }
 

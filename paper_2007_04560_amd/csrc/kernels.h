@@ -114,7 +114,10 @@ hipError_t launch_boxilu_factor2d(const BatchLaunch &bl, const BoxIluGeom &X, in
 hipError_t launch_boxilu_apply2d(const BatchLaunch &bl, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs,
                                  const int *cellof, const void *L, const void *U, double *ybox, void *boxbuf,
                                  const double *r, double *z, const GmresState *st, long vstride, int fp32,
-                                 hipStream_t s, const RasVariant &rv);
+                                 hipStream_t s, const RasVariant &rv, bool trans = false);
+// Transposed records (Tf for the U^T sweep, Tb for the L^T sweep), same layout and size as L, U.
+hipError_t launch_boxilu_pack_t(const BoxIluGeom &X, int nsub, const int *lvoff, const int *cellof, const void *L,
+                                const void *U, void *Tf, void *Tb, int fp32, hipStream_t s);
 hipError_t launch_boxilu_export(const BoxIluGeom &X, int nsub, const int *lvoff, const void *L, const void *U,
                                 int fp32, double *out, hipStream_t s);
 

@@ -39,6 +39,7 @@ struct Layout {
   size_t off_tbox, off_own;
   size_t off_band, off_bandy, off_mask;   // exact-LU / ILU(k) subdomain solvers (2D)
   size_t off_bxL, off_bxU, off_bxy, off_lvoff, off_cellof;   // box-pattern ILU(0) (2D)
+  size_t off_bxTf, off_bxTb;                                  // its transposed records (adjoint)
   size_t total;
 };
 
@@ -98,6 +99,7 @@ struct acch_ctx {
   std::vector<int> lvoff_h;     // wavefront offsets of the box records
   std::vector<int> cellof_h;    // box cell of each record position
   void *bxL = nullptr, *bxU = nullptr;
+  void *bxTf = nullptr, *bxTb = nullptr;   // transposed records, packed on the first transposed apply
   double *bxy = nullptr;        // forward-sweep values, (u, v) per box cell
   int *d_lvoff = nullptr;
   int *d_cellof = nullptr;
@@ -436,6 +438,8 @@ static void make_layout(const acch_params &p, const Geometry &geo, Layout &L) {
   L.off_bxy = take(bx ? (size_t)geo.G.nsub * X.ncell * 2 * sizeof(double) : 0);
   L.off_lvoff = take(bx ? (size_t)(X.nlev + 1) * sizeof(int) : 0);
   L.off_cellof = take(bx ? (size_t)X.ncell * sizeof(int) : 0);
+  L.off_bxTf = take(bx ? (size_t)geo.G.nsub * X.ncell * kBoxIluRec * fsz : 0);
+  L.off_bxTb = take(bx ? (size_t)geo.G.nsub * X.ncell * kBoxIluRec * fsz : 0);
   L.total = o;
 }
 
@@ -652,6 +656,20 @@ hipError_t run_ras(acch_ctx *c, const double *r, double *z, const GmresState *st
                             c->stream, c->ras);
 }
 hipError_t run_ras_t(acch_ctx *c, const double *r, double *z, const GmresState *st, long vs) {
+  if (c->boxilu) {
+    // M^{-T}: the transposed solves with the restriction and extension of the variant
+    // exchanged (left <-> right; classical is its own transpose)
+    if (!c->tpacked) {
+      hipError_t e = launch_boxilu_pack_t(c->bx, c->geo.G.nsub, c->d_lvoff, c->d_cellof, c->bxL, c->bxU, c->bxTf,
+                                          c->bxTb, fp32_of(c), c->stream);
+      if (e != hipSuccess) return e;
+      c->tpacked = true;
+    }
+    RasVariant rv = c->ras;
+    rv.kind = rv.kind == ACCH_RAS_LEFT ? ACCH_RAS_RIGHT : (rv.kind == ACCH_RAS_RIGHT ? ACCH_RAS_LEFT : rv.kind);
+    return launch_boxilu_apply2d(c->bl, c->bx, c->geo.G, c->d_subs, c->d_cellof, c->bxTf, c->bxTb, c->bxy, c->ybuf, r,
+                                 z, st, vs, fp32_of(c), c->stream, rv, true);
+  }
   if (c->d3)
     return launch_ras_t_apply3d(c->P, c->geo.G, c->d_subs, c->d_lvl, level_cells(c), c->p.sub[0], c->p.sub[1],
                                 c->p.sub[2], c->d_own, c->fac, c->wfact, &c->tpacked, c->ybuf, c->tbox, r, z, st, vs,
@@ -900,6 +918,8 @@ extern "C" int acch_create(const acch_params *pin, const double *u0, const doubl
     c->bxy = (double *)(c->ws + L.off_bxy);
     c->d_lvoff = (int *)(c->ws + L.off_lvoff);
     c->d_cellof = (int *)(c->ws + L.off_cellof);
+    c->bxTf = c->ws + L.off_bxTf;
+    c->bxTb = c->ws + L.off_bxTb;
   }
   std::vector<unsigned> maskh;
   if (c->band) {
@@ -1191,8 +1211,8 @@ extern "C" int acch_apply_jacobian_transpose(acch_ctx *c, const double *x, doubl
 static int adjoint_ready(acch_ctx *c) {
   if (c->d3 && c->p.ras_type != ACCH_RAS_LEFT)
     return fail(ACCH_EUNSUPPORTED, "the 3D transposed Schwarz operator is built for the left-restricted variant");
-  if (c->band || c->boxilu)
-    return fail(ACCH_EUNSUPPORTED, "the transposed Schwarz operator uses the ILU(0) subdomain solver");
+  if (c->band)
+    return fail(ACCH_EUNSUPPORTED, "the transposed Schwarz operator uses an ILU(0) subdomain solver");
   if (c->p.overlap > c->geo.min_part)
     return fail(ACCH_EUNSUPPORTED, "transposed Schwarz operator needs overlap <= the smallest subdomain width");
   return ACCH_OK;
