@@ -161,7 +161,7 @@ def step_bytes_per_cell(newton: int, gmres: int, steps: int, nnz: int, omega: fl
 RAS_KERNELS = {
     "periodic512": ("void k_ras_apply2d<double, 1, 5, false>", "schwarz2d.hip"),
     "neumann128_3d": ("void k_ras_apply3d_win<double, 3>", "schwarz3d.hip"),
-    "periodic512_box32": ("void k_boxilu_apply2d<double, 3, 4, 64>", "boxilu2d.hip"),
+    "periodic512_box32": ("void k_boxilu_apply2d<double, 3, 4, 64, false>", "boxilu2d.hip"),
 }
 
 
