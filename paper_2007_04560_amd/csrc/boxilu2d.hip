@@ -8,7 +8,8 @@
 // unknown order: the 12 lower cells give e = 0..23, the cell itself 24 (u) and 25 (v),
 // the 12 upper cells 26..49.  With wavefronts w = i + 3 j (boxilu.h) all lower cells lie
 // on earlier wavefronts, so the factorisation and both triangular sweeps run the
-// wavefronts in order, one box per workgroup, thread j owning box row j.
+// wavefronts in order, one box per workgroup: in the factorisation thread j owns box
+// row j, in the sweeps four lanes share each cell of the current wavefront.
 //
 // Records (FT, kBoxIluRec = 52 slots per cell, cells in the wavefront order of boxilu.h):
 //   L: for each lower cell k (unknown order) L(u_c,u_q) L(u_c,v_q) L(v_c,u_q) L(v_c,v_q)
