@@ -378,7 +378,8 @@ def adjoint_line(args, w=None):
     kw = dict(bc=w["bc"], sub=w["sub"], overlap=w["overlap"], adaptive=w["adaptive"], dt_min=w["dt_min"],
               dt_max=w["dt_max"], eta0=w["eta0"], newton_rtol=w["newton_rtol"], newton_atol=w["newton_atol"],
               gmres_rtol=w["gmres_rtol"], gmres_atol=w["gmres_atol"], gmres_restart=w["gmres_restart"],
-              ilu_shift=w["ilu_shift"])
+              ilu_shift=w["ilu_shift"], subsolver=w.get("subsolver", "ilu0"), fill_level=w.get("fill_level", 0))
+    boxilu = w.get("subsolver") == "iluk_box"
     steps = args.steps
     params = torch.tensor([1.2, 1.2, 0.1, 1e-3], dtype=torch.float64, requires_grad=True)
     tu = torch.tensor(u0, requires_grad=True)
@@ -410,6 +411,8 @@ def adjoint_line(args, w=None):
         for n_a, p_a in zip(reversed(w["shape"]), w["sub"]):
             box *= n_a / p_a + 2 * w["overlap"]
         bytes_launch = ras_bytes_per_cell(box, owned, nslot=40) * u0.size
+    elif boxilu:   # transposed records of every box cell, the box vector written and read back, r, z
+        bytes_launch = info["nsub"] * info["box_w"] * info["box_h"] * (108 * 8 + 16) + 16 * u0.size
     else:
         bytes_launch = ras_bytes_per_cell(info["box_w"] * info["box_h"], owned) * u0.size
     achieved = bytes_launch / avg_s / 1e9
@@ -423,7 +426,8 @@ def adjoint_line(args, w=None):
                        "grad_v0_norm": float(tv.grad.norm())},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                         "kernel": "transposed Schwarz (sweep + gather)",
+                         "kernel": "k_boxilu_apply2d (transposed records)" if boxilu else
+                                   "transposed Schwarz (sweep + gather)",
                          "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": int(bytes_launch)}}
     print(json.dumps(line), flush=True)
     return 0
@@ -650,7 +654,8 @@ def main():
                     help="default workload: skip the mixed-precision, batched and 64x64 oracle comparisons")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP-event timers")
     ap.add_argument("--workload", default="periodic512",
-                    choices=sorted(WORKLOADS) + ["batch96", "adjoint512", "adjoint3d128", "study2d", "study3d"])
+                    choices=sorted(WORKLOADS) + ["batch96", "adjoint512", "adjoint3d128", "adjoint512_box32", "study2d",
+                                                 "study3d"])
     ap.add_argument("--no-sequential", action="store_true", help="batch96: skip the one-by-one FP64 comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 64 MiB FP64 tensor 3 times (reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -671,13 +676,14 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copied 64 MiB FP64 three times"}), flush=True)
         return 0
-    if args.workload in ("adjoint512", "adjoint3d128"):
+    if args.workload in ("adjoint512", "adjoint3d128", "adjoint512_box32"):
         if args.gpus != 1:
             print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
             return 2
         if args.steps is None:
             args.steps = 20
-        return adjoint_line(args, WORKLOADS["periodic512" if args.workload == "adjoint512" else "neumann128_3d"])
+        return adjoint_line(args, WORKLOADS[{"adjoint512": "periodic512", "adjoint3d128": "neumann128_3d",
+                                             "adjoint512_box32": "periodic512_box32"}[args.workload]])
     if args.workload in ("study2d", "study3d"):
         if args.gpus != 1:
             print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
