@@ -262,3 +262,88 @@ def test_box_ilu0_adjoint_step_matches_oracle():
     g0o, _, dpo = oadj.adjoint_step(u1, v1, u0, v0, dt, Problem(bc=bc), g1)
     assert its > 0
     assert _rel(gprev.cpu().numpy(), g0o) <= 1e-9
+
+
+def _box32(u0, v0, precision="fp64", **kw):
+    """The 512x512 box-pattern workload's Schwarz settings: 32x32 subdomains (1024 boxes of
+    20x20 cells, one wave per box), overlap 2, unshifted ILU(0) on the box pattern."""
+    return Solver(u0, v0, bc="periodic", sub=(32, 32), overlap=2, subsolver="iluk_box", fill_level=0,
+                  ilu_shift=0.0, precision=precision, **kw)
+
+
+def _box32_factored(precision, seed):
+    shape = (512, 512)
+    u0, v0 = random_ic(shape, 0)
+    rng = np.random.default_rng(seed)
+    u1 = u0 + 0.01 * rng.uniform(-1, 1, shape)
+    v1 = v0 + 0.01 * rng.uniform(-1, 1, shape)
+    s = _box32(u0, v0, precision)
+    info = s.info()
+    assert info["nsub"] == 1024 and (info["box_w"], info["box_h"]) == (20, 20)
+    s.jacobian(dev(vec(u1, v1)), dev(vec(u0, v0)), 1e-4)
+    s.factor()
+    return s, (u1, v1, u0, v0), rng
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_box32_workload_sampled_subdomains_match_oracle(precision):
+    """At the full 512x512 size in the benchmark's launch configuration: M^{-1} r on the
+    owned cells of sampled subdomains (the two corner boxes, which wrap, an edge box and an
+    interior one) against the oracle's ILU(0) solve of each subdomain on its own; with the
+    restricted extension an owned cell takes its value from its own box only."""
+    s, (u1, v1, u0, v0), rng = _box32_factored(precision, 61)
+    shape, n = u0.shape, u0.size
+    r = rng.standard_normal(2 * n)
+    z = s.precondition(dev(r)).cpu().numpy()
+    J = jacobian.jacobian(u1, v1, u0, v0, 1e-4, prob("periodic")).tocsr()
+    subs = schwarz.decompose(shape, (32, 32), 2, "periodic")
+    for k in (0, 31, 529, 1023):
+        sub = subs[k]
+        fac = schwarz.iluk(schwarz.box_pattern(schwarz.subdomain_matrix(J, sub, shape), sub), 0)
+        idx = sub.unknowns(n)
+        own = np.repeat(sub.owned, 2)
+        zk = schwarz.ilu_solve(fac, r[idx])[own]
+        zg = z[idx[own]]
+        if precision == "fp64":
+            assert np.max(np.abs(zg - zk)) <= 1e-10 * np.max(np.abs(zk)), k
+        else:
+            assert np.linalg.norm(zg - zk) <= 1e-4 * np.linalg.norm(zk), k
+
+
+def test_box32_workload_transpose_adjoint_identity():
+    """The adjoint workload's transposed operator at 512x512 over 32x32 subdomains:
+    <M^{-T} a, b> = <a, M^{-1} b>."""
+    s, _, rng = _box32_factored("fp64", 62)
+    a = dev(rng.standard_normal(2 * 512 * 512))
+    b = dev(rng.standard_normal(2 * 512 * 512))
+    lhs = float(torch.dot(s.precondition_transpose(a), b))
+    rhs = float(torch.dot(a, s.precondition(b)))
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
+
+
+def test_box32_workload_roots_at_sampled_steps():
+    """The 512x512 box-pattern workload as the benchmark runs it (adaptive, tolerance 1e-8):
+    at steps 1, 25 and 60 the oracle's residual of the GPU's new state, taken with the
+    step's dt and the GPU's previous state, is at the Newton tolerance; mass is exact and
+    the energy decreases."""
+    from oracle import scheme
+    shape = (512, 512)
+    u0, v0 = random_ic(shape, 0)
+    P = prob("periodic")
+    s = _box32(u0, v0, adaptive=True, dt_min=1e-4, dt_max=1e-1, eta0=1e4)
+    M0 = scheme.mass(u0, P)
+    done = 0
+    for k in (1, 25, 60):
+        if k - 1 > done:
+            s.step(k - 1 - done)
+        up, vp = s.fields()
+        info = s.step(1)[0]
+        done = k
+        ug, vg = s.fields()
+        Fu, Fv = scheme.residual(ug, vg, up, vp, info["dt"], P)
+        F0u, F0v = scheme.residual(up, vp, up, vp, info["dt"], P)
+        f1 = math.sqrt(np.sum(Fu ** 2 + Fv ** 2))
+        f0 = math.sqrt(np.sum(F0u ** 2 + F0v ** 2))
+        assert f1 <= 2e-8 * f0, (k, f1, f0)
+        assert abs(scheme.mass(ug, P) - M0) <= 1e-12 * M0
+        assert scheme.energy(ug, vg, P) < scheme.energy(up, vp, P)
