@@ -27,6 +27,7 @@ constexpr int kChunk = 8;   // Arnoldi steps per recorded graph
 struct BLayout {
   size_t off_Xn, off_X, off_Xt, off_F, off_Ft, off_S, off_W, off_J, off_V, off_Z, off_fac, off_y, off_dump;
   size_t off_subs, off_lvl, off_state, off_part, off_out, off_inst, off_map[kFamilies], off_mask[3], off_lam;
+  size_t off_bxL, off_bxU, off_bxy, off_bxlv, off_bxcell;   // box-pattern ILU(0) records and tables
   size_t total;
 };
 
@@ -39,6 +40,9 @@ struct Plan {
   std::vector<int> lvl;
   std::vector<int2> map[kFamilies];
   int grid[kFamilies] = {};
+  bool box = false;               // ILU(0) on the box pattern (its own kernels)
+  BoxIluGeom bx{};                // its record geometry for the common padded box
+  std::vector<int> bxlvoff, bxcellof;
 };
 
 int make_plan(const acch_params *ps, int count, Plan &pl) {
@@ -56,9 +60,13 @@ int make_plan(const acch_params *ps, int count, Plan &pl) {
     if (p.dim != 2) return fail(ACCH_EUNSUPPORTED, "batches are 2D");
     if (p.adaptive) return fail(ACCH_EUNSUPPORTED, "batches step at a common fixed dt (adaptive = 0)");
     if (p.ras_type != ACCH_RAS_LEFT) return fail(ACCH_EUNSUPPORTED, "batches use the left-restricted Schwarz variant");
-    if (p.subsolver != ACCH_SUB_ILU0) return fail(ACCH_EUNSUPPORTED, "batches use the ILU(0) subdomain solver");
-    if (p.overlap != p0.overlap || p.precision != p0.precision || p.dt_fixed != p0.dt_fixed)
-      return fail(ACCH_EINVAL, "instances must share overlap, precision and dt_fixed");
+    const bool box = p.subsolver == ACCH_SUB_ILUK_BOX && p.fill_level == 0;
+    if (p.subsolver != ACCH_SUB_ILU0 && !box)
+      return fail(ACCH_EUNSUPPORTED, "batches use ILU(0) on the stencil or on the box pattern");
+    if (p.overlap != p0.overlap || p.precision != p0.precision || p.dt_fixed != p0.dt_fixed ||
+        p.subsolver != p0.subsolver || p.fill_level != p0.fill_level)
+      return fail(ACCH_EINVAL, "instances must share overlap, precision, dt_fixed and the subdomain solver");
+    pl.box = box;
     rc = build_geometry(p, geos[b]);
     if (rc) return rc;
     bw = std::max(bw, geos[b].G.bw);
@@ -69,6 +77,11 @@ int make_plan(const acch_params *ps, int count, Plan &pl) {
   pl.G.nlev = bw + 2 * (bh - 1);
   pl.G.ncb = bw * bh;
   if (schwarz_waves(pl.G) == 0) return fail(ACCH_EINVAL, "subdomain box too large (at most 511 cells wide, 512 tall)");
+  if (pl.box) {
+    pl.bx = make_boxilu_geom(bw, bh, &pl.bxlvoff, &pl.bxcellof);
+    if (!boxilu_fits(pl.bx))
+      return fail(ACCH_EINVAL, "box-pattern ILU(0): subdomain box too large (at most 144 cells wide, 160 tall)");
+  }
   long xoff = 0, joff = 0;
   int blk[kFamilies] = {};
   for (int b = 0; b < count; ++b) {
@@ -139,7 +152,13 @@ void make_layout(const acch_params &p0, const Plan &pl, BLayout &L) {
   L.off_V = take((size_t)(m + 1) * n2);
   L.off_Z = take((size_t)m * n2);
   const size_t slots = (size_t)pl.G.nlev * pl.G.bh;
-  L.off_fac = take((size_t)pl.G.nsub * kNSlot2D * slots * fsz);
+  L.off_fac = take(pl.box ? 0 : (size_t)pl.G.nsub * kNSlot2D * slots * fsz);
+  const size_t brec = pl.box ? (size_t)pl.G.nsub * pl.bx.ncell * kBoxIluRec * fsz : 0;
+  L.off_bxL = take(brec);
+  L.off_bxU = take(brec);
+  L.off_bxy = take(pl.box ? (size_t)pl.G.nsub * pl.bx.ncell * 2 * sizeof(double) : 0);
+  L.off_bxlv = take(pl.bxlvoff.size() * sizeof(int));
+  L.off_bxcell = take(pl.bxcellof.size() * sizeof(int));
   L.off_y = take((size_t)pl.G.nsub * 2 * (slots + 1) * fsz);
   L.off_dump = take(64 * sizeof(double));
   L.off_subs = take(pl.subs.size() * sizeof(SubInfo));
@@ -169,6 +188,9 @@ struct acch_batch {
   char *ws = nullptr;
   double *Xn, *X, *Xt, *F, *Ft, *S, *W, *J, *V, *Z, *dump, *out, *lam;
   void *fac, *ybuf;
+  void *bxL = nullptr, *bxU = nullptr;   // box-pattern ILU(0) records
+  double *bxy = nullptr;
+  int *d_bxlv = nullptr, *d_bxcell = nullptr;
   SubInfo *d_subs;
   int *d_lvl;
   GmresState *st;
@@ -219,10 +241,18 @@ int read_states(acch_batch *b) {
   return bsync(b);
 }
 
+// z = M^{-1} r over every subdomain of the instances bl selects (left-restricted Schwarz).
+hipError_t apply_m(acch_batch *b, const BatchLaunch &bl, const double *r, double *z, const GmresState *st, long vs,
+                   int fp32) {
+  if (b->pl.box)
+    return launch_boxilu_apply2d(bl, b->pl.bx, b->pl.G, b->d_subs, b->d_bxcell, b->bxL, b->bxU, b->bxy, b->ybuf, r, z,
+                                 st, vs, fp32, b->stream, RasVariant{});
+  return launch_ras_apply2d(bl, b->pl.G, b->d_subs, b->d_lvl, b->fac, b->ybuf, r, z, b->dump, st, vs, fp32, b->stream);
+}
+
 int enqueue_steps(acch_batch *b, int j0, int j1, int fp32, long vs) {
   for (int j = j0; j < j1; ++j) {
-    BLAUNCH(b, launch_ras_apply2d(b->cyc, b->pl.G, b->d_subs, b->d_lvl, b->fac, b->ybuf, b->V, b->Z, b->dump, b->st,
-                                  vs, fp32, b->stream));
+    BLAUNCH(b, apply_m(b, b->cyc, b->V, b->Z, b->st, vs, fp32));
     BLAUNCH(b, launch_spmv_dots2d(b->cyc, b->J, b->Z, b->V, vs, j, 0, b->st, b->red, b->stream));
     BLAUNCH(b, launch_gmres_orth(b->cyc, b->V, vs, j, b->st, b->red, b->stream));
   }
@@ -368,8 +398,12 @@ int nks_batch(acch_batch *b, BStats &stats) {
     if (rc) return rc;
     BLAUNCH(b, launch_jacobian2d(b->newton, b->X, b->Xn, p.dt_fixed, b->J, b->stream));
     if (it == 1 || p.ilu_reuse < 0) {
-      BLAUNCH(b, launch_ilu_factor2d(b->newton, b->pl.G, b->d_subs, b->d_lvl, b->J, p.ilu_shift, b->fac,
-                                     p.precision == ACCH_PREC_MIXED, b->stream));
+      if (b->pl.box)
+        BLAUNCH(b, launch_boxilu_factor2d(b->newton, b->pl.bx, b->pl.G.nsub, b->d_subs, b->d_bxlv, b->J, p.ilu_shift,
+                                          b->bxL, b->bxU, p.precision == ACCH_PREC_MIXED, b->stream));
+      else
+        BLAUNCH(b, launch_ilu_factor2d(b->newton, b->pl.G, b->d_subs, b->d_lvl, b->J, p.ilu_shift, b->fac,
+                                       p.precision == ACCH_PREC_MIXED, b->stream));
       b->factored = true;
     }
     rc = gmres_batch(b, stats.gmres);
@@ -471,6 +505,13 @@ extern "C" int acch_batch_create(const acch_params *inst, int count, const doubl
   b->Z = (double *)(w + L.off_Z);
   b->fac = w + L.off_fac;
   b->ybuf = w + L.off_y;
+  if (b->pl.box) {
+    b->bxL = w + L.off_bxL;
+    b->bxU = w + L.off_bxU;
+    b->bxy = (double *)(w + L.off_bxy);
+    b->d_bxlv = (int *)(w + L.off_bxlv);
+    b->d_bxcell = (int *)(w + L.off_bxcell);
+  }
   b->dump = (double *)(w + L.off_dump);
   b->d_subs = (SubInfo *)(w + L.off_subs);
   b->d_lvl = (int *)(w + L.off_lvl);
@@ -521,7 +562,11 @@ extern "C" int acch_batch_create(const acch_params *inst, int count, const doubl
                            b->stream) == hipSuccess &&
             hipMemcpyAsync(b->d_lvl, b->pl.lvl.data(), b->pl.lvl.size() * sizeof(int), hipMemcpyHostToDevice,
                            b->stream) == hipSuccess &&
-            hipMemsetAsync(b->st, 0, count * sizeof(GmresState), b->stream) == hipSuccess;
+            hipMemsetAsync(b->st, 0, count * sizeof(GmresState), b->stream) == hipSuccess &&
+            (!b->pl.box || (hipMemcpyAsync(b->d_bxlv, b->pl.bxlvoff.data(), b->pl.bxlvoff.size() * sizeof(int),
+                                           hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+                            hipMemcpyAsync(b->d_bxcell, b->pl.bxcellof.data(), b->pl.bxcellof.size() * sizeof(int),
+                                           hipMemcpyHostToDevice, b->stream) == hipSuccess));
   for (int f = 0; ok && f < kFamilies; ++f)
     ok = hipMemcpyAsync((void *)base.bt.map[f], b->pl.map[f].data(), b->pl.map[f].size() * sizeof(int2),
                         hipMemcpyHostToDevice, b->stream) == hipSuccess;
@@ -582,8 +627,7 @@ extern "C" int acch_batch_get_fields(acch_batch *b, int i, double *u, double *v)
 extern "C" int acch_batch_precondition(acch_batch *b, const double *r, double *z) {
   if (!b || !r || !z) return fail(ACCH_EINVAL, "bad arguments");
   if (!b->factored) return fail(ACCH_EINVAL, "no factorisation yet: take a step first");
-  BLAUNCH(b, launch_ras_apply2d(b->all, b->pl.G, b->d_subs, b->d_lvl, b->fac, b->ybuf, r, z, b->dump, nullptr, 0,
-                                b->p.precision == ACCH_PREC_MIXED, b->stream));
+  BLAUNCH(b, apply_m(b, b->all, r, z, nullptr, 0, b->p.precision == ACCH_PREC_MIXED));
   return ACCH_OK;
 }
 

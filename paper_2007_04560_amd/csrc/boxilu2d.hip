@@ -176,10 +176,17 @@ ACCH_DEV void eliminate(double (&a)[50], double (&b)[50], const FT *Uk, const in
 }
 
 template <typename FT, int TH>
-__global__ __launch_bounds__(TH) void k_boxilu_factor2d(Phys P, BoxIluGeom X, const SubInfo *__restrict__ subs,
+__global__ __launch_bounds__(TH) void k_boxilu_factor2d(Phys P0, Batch bt, BoxIluGeom X,
+                                                          const SubInfo *__restrict__ subs,
                                                                   const int *__restrict__ lvoff,
                                                                   const double *__restrict__ J, double shift,
                                                                   FT *__restrict__ Lrec, FT *__restrict__ Urec) {
+  // batched: the block's instance (its grid, its rows of J); the whole block leaves
+  // together when the instance is inactive
+  const Loc Lc = locate(bt, kFamSub);
+  if (!Lc.on) return;
+  const Phys &P = bt.map[kFamSub] ? bt.inst[Lc.b].P : P0;
+  if (bt.map[kFamSub]) J += bt.inst[Lc.b].joff;
   const int j = threadIdx.x;   // box row
   const SubInfo si = subs[blockIdx.x];
   const Rect rc = grid_rect(si, X.bw, X.bh, P.nx, P.ny, P.periodic);
@@ -487,13 +494,23 @@ ACCH_DEV void sweep(const BoxIluGeom &X, __amdgpu_buffer_rsrc_t rsRec, __amdgpu_
 }
 
 template <typename FT, int NCH, int D, int TH, bool TRANS>
-__global__ __launch_bounds__(TH) void k_boxilu_apply2d(Phys P, BoxIluGeom X, BoxGeom G, const SubInfo *__restrict__ subs,
+__global__ __launch_bounds__(TH) void k_boxilu_apply2d(Phys P0, Batch bt, BoxIluGeom X, BoxGeom G,
+                                                      const SubInfo *__restrict__ subs,
                                                       const int *__restrict__ cellof, const FT *__restrict__ Lrec,
                                                       const FT *__restrict__ Urec, void *__restrict__ ybox_,
                                                       void *__restrict__ boxbuf, const double *__restrict__ r,
                                                       double *__restrict__ z, const GmresState *st, long vstride,
                                                       int kind) {
   using V2 = typename ChunkOf2<FT>::T;
+  // batched: the block's instance (its grid, its slice of r and z, its GMRES state)
+  const Loc Lc = locate(bt, kFamSub);
+  if (!Lc.on) return;
+  const Phys &P = bt.map[kFamSub] ? bt.inst[Lc.b].P : P0;
+  if (bt.map[kFamSub]) {
+    r += bt.inst[Lc.b].xoff;
+    z += bt.inst[Lc.b].xoff;
+  }
+  if (st) st += Lc.b;
   double sc = 1.0;
   if (st) {
     if (st->done) return;
@@ -605,21 +622,23 @@ __global__ void k_boxilu_export(BoxIluGeom X, int nsub, const int *__restrict__ 
 }
 
 template <typename FT, int NCH, int TH>
-void apply_launch(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const int *cellof,
+void apply_launch(const BatchLaunch &bl, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const int *cellof,
                   const void *L, const void *U, double *ybox, void *boxbuf, const double *r, double *z,
                   const GmresState *st, long vstride, int kind, bool trans, hipStream_t s) {
   constexpr int D = TH == 64 ? (NCH <= 7 ? 4 : 3) : (NCH <= 3 ? 6 : 4);   // register stages
   const size_t ring_bytes = (size_t)(X.bh + 4) * 2 * kRingW * 2 * sizeof(FT);
   if (trans)
-    hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, D, TH, true>), dim3(G.nsub), dim3(TH), ring_bytes, s, P, X, G, subs,
+    hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, D, TH, true>), dim3(G.nsub), dim3(TH), ring_bytes, s, bl.P0, bl.bt, X,
+                       G, subs,
                        cellof, (const FT *)L, (const FT *)U, (void *)ybox, boxbuf, r, z, st, vstride, kind);
   else
-    hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, D, TH, false>), dim3(G.nsub), dim3(TH), ring_bytes, s, P, X, G, subs,
+    hipLaunchKernelGGL((k_boxilu_apply2d<FT, NCH, D, TH, false>), dim3(G.nsub), dim3(TH), ring_bytes, s, bl.P0, bl.bt, X,
+                       G, subs,
                        cellof, (const FT *)L, (const FT *)U, (void *)ybox, boxbuf, r, z, st, vstride, kind);
 }
 
 template <typename FT>
-hipError_t apply_t(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const int *cellof,
+hipError_t apply_t(const BatchLaunch &bl, const BoxIluGeom &X, const BoxGeom &G, const SubInfo *subs, const int *cellof,
                    const void *L, const void *U, double *ybox, void *boxbuf, const double *r, double *z,
                    const GmresState *st, long vstride, int kind, bool trans, hipStream_t s) {
   const int bytes = X.maxcount * kBoxIluRec * (int)sizeof(FT);   // one wavefront's records
@@ -635,18 +654,18 @@ hipError_t apply_t(const Phys &P, const BoxIluGeom &X, const BoxGeom &G, const S
   }
   if (X.maxcount <= 16 && G.nsub >= 2 * cus) {
     const int nch = (bytes + 1023) / 1024;
-    if (nch <= 3) apply_launch<FT, 3, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
-    else if (nch <= 5) apply_launch<FT, 5, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
-    else if (nch <= 7) apply_launch<FT, 7, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
-    else if (nch <= 10) apply_launch<FT, 10, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
-    else apply_launch<FT, 13, 64>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
+    if (nch <= 3) apply_launch<FT, 3, 64>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
+    else if (nch <= 5) apply_launch<FT, 5, 64>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
+    else if (nch <= 7) apply_launch<FT, 7, 64>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
+    else if (nch <= 10) apply_launch<FT, 10, 64>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
+    else apply_launch<FT, 13, 64>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s);
   } else {
     switch ((bytes + 16 * kBoxIluThreads - 1) / (16 * kBoxIluThreads)) {
-      case 1: apply_launch<FT, 1, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
-      case 2: apply_launch<FT, 2, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
-      case 3: apply_launch<FT, 3, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
-      case 4: apply_launch<FT, 4, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
-      case 5: apply_launch<FT, 5, kBoxIluThreads>(P, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
+      case 1: apply_launch<FT, 1, kBoxIluThreads>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
+      case 2: apply_launch<FT, 2, kBoxIluThreads>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
+      case 3: apply_launch<FT, 3, kBoxIluThreads>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
+      case 4: apply_launch<FT, 4, kBoxIluThreads>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
+      case 5: apply_launch<FT, 5, kBoxIluThreads>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, kind, trans, s); break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -664,7 +683,7 @@ namespace {
 template <typename FT, int TH>
 void factor_launch(const BatchLaunch &bl, const BoxIluGeom &X, int nsub, const SubInfo *subs, const int *lvoff,
                    const double *J, double shift, void *L, void *U, hipStream_t s) {
-  hipLaunchKernelGGL((k_boxilu_factor2d<FT, TH>), dim3(nsub), dim3(TH), 0, s, bl.P0, X, subs, lvoff, J, shift,
+  hipLaunchKernelGGL((k_boxilu_factor2d<FT, TH>), dim3(nsub), dim3(TH), 0, s, bl.P0, bl.bt, X, subs, lvoff, J, shift,
                      (FT *)L, (FT *)U);
 }
 template <typename FT>
@@ -680,7 +699,7 @@ void factor_t(const BatchLaunch &bl, const BoxIluGeom &X, int nsub, const SubInf
 hipError_t launch_boxilu_factor2d(const BatchLaunch &bl, const BoxIluGeom &X, int nsub, const SubInfo *subs,
                                   const int *lvoff, const double *J, double shift, void *L, void *U, int fp32,
                                   hipStream_t s) {
-  if (bl.bt.map[kFamSub] != nullptr || !boxilu_fits(X)) return hipErrorInvalidValue;
+  if (!boxilu_fits(X)) return hipErrorInvalidValue;
   if (fp32)
     factor_t<float>(bl, X, nsub, subs, lvoff, J, shift, L, U, s);
   else
@@ -692,10 +711,12 @@ hipError_t launch_boxilu_apply2d(const BatchLaunch &bl, const BoxIluGeom &X, con
                                  const int *cellof, const void *L, const void *U, double *ybox, void *boxbuf,
                                  const double *r, double *z, const GmresState *st, long vstride, int fp32,
                                  hipStream_t s, const RasVariant &rv, bool trans) {
-  if (bl.bt.map[kFamSub] != nullptr || !boxilu_fits(X)) return hipErrorInvalidValue;
+  if (!boxilu_fits(X)) return hipErrorInvalidValue;
+  // batches: the left-restricted forward operator only
+  if (bl.bt.map[kFamSub] != nullptr && (rv.kind != ACCH_RAS_LEFT || trans)) return hipErrorInvalidValue;
   if (rv.kind != ACCH_RAS_LEFT && !rv.own_x) return hipErrorInvalidValue;
-  hipError_t e = fp32 ? apply_t<float>(bl.P0, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, trans, s)
-                      : apply_t<double>(bl.P0, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, trans,
+  hipError_t e = fp32 ? apply_t<float>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, trans, s)
+                      : apply_t<double>(bl, X, G, subs, cellof, L, U, ybox, boxbuf, r, z, st, vstride, rv.kind, trans,
                                         s);
   if (e != hipSuccess || rv.kind == ACCH_RAS_LEFT) return e;
   return launch_ras_sum2d(bl, G, subs, boxbuf, z, st, vstride, fp32, s, rv);

@@ -81,6 +81,48 @@ def test_batched_preconditioner_equals_each_instance():
         assert np.max(np.abs(z[xo:xo + n2] - zi)) <= 1e-13 * np.max(np.abs(zi)), i
 
 
+BOX = dict(COMMON, ilu_shift=0.0, subsolver="iluk_box", fill_level=0)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_box_pattern_batch_matches_single_instance_runs(graph, precision):
+    """Batches with ILU(0) on the box pattern (its own factorisation and sweep kernels, one
+    launch each over all boxes of all instances, padded to a common box): each instance
+    follows its own single-instance run, with the same Newton and GMRES counts."""
+    fields, params = instances()
+    nsteps = 3
+    ref = single_runs(fields, params, nsteps, precision=precision, **BOX)
+    with BatchSolver(fields, params, graph=graph, precision=precision, **BOX) as b:
+        nit, git = b.step(nsteps)
+        for i, ((u, v), n_it, g_it) in enumerate(ref):
+            ub, vb = b.fields(i)
+            scale = max(np.max(np.abs(u)), np.max(np.abs(v)))
+            assert max(np.max(np.abs(ub - u)), np.max(np.abs(vb - v))) <= 1e-13 * scale, i
+            assert nit[i] == n_it and git[i] == g_it, (i, nit[i], n_it, git[i], g_it)
+        assert (b.counters()["graph_launches"] > 0) == graph
+
+
+def test_box_pattern_batched_preconditioner_equals_each_instance():
+    fields, params = instances()
+    with BatchSolver(fields, params, **BOX) as b:
+        b.step(1)
+        info = b.info()
+        r = np.random.default_rng(12).standard_normal(2 * info["ncell"])
+        z = b.precondition(torch.as_tensor(r).cuda())
+        b.stream.synchronize()
+        z = z.cpu().numpy()
+    for i, ((u, v), p) in enumerate(zip(fields, params)):
+        kw = dict(BOX)
+        kw.update(p)
+        n2 = 2 * u.size
+        xo = info["xoff"][i]
+        with Solver(u, v, **kw) as s:
+            s.step(1)
+            zi = s.precondition(torch.as_tensor(r[xo:xo + n2]).cuda()).cpu().numpy()
+        assert np.max(np.abs(z[xo:xo + n2] - zi)) <= 1e-13 * np.max(np.abs(zi)), i
+
+
 def test_batch_matches_oracle():
     fields, params = instances()
     fields, params = fields[:2], params[:2]
@@ -108,6 +150,10 @@ def test_batch_rejects_bad_configurations():
         BatchSolver(fields[:2], [dict(params[0], adaptive=True), params[1]], **COMMON)
     with pytest.raises(AcchError):
         BatchSolver(fields[:2], [params[0], dict(params[1], overlap=2)], **COMMON)
+    with pytest.raises(AcchError):   # ILU(k >= 1) has no batched kernels
+        BatchSolver(fields[:2], params[:2], **dict(BOX, fill_level=1))
+    with pytest.raises(AcchError):   # one subdomain solver for all instances
+        BatchSolver(fields[:2], [params[0], dict(params[1], subsolver="iluk_box")], **COMMON)
 
 
 def test_autotuner_picks_a_measured_box():
