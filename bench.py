@@ -109,6 +109,11 @@ BATCH = dict(name="batch96", count=96, base_seed=1000, steps=10, overlap=2, boxe
              text="batch96: 96 independent 2D periodic instances, N uniform in {96,128,192,256}, theta~U(0.08,0.12), "
                   "gamma~U(5e-4,2e-3), 10 fixed steps dt=1e-3, one batched NKS per step (left-RAS ILU(0) shift 0.02, "
                   "overlap 2, autotuned boxes, GMRES(30) cycles replayed from HIP graphs), tol 1e-8")
+# the same batch with the subdomain ILU(0) on the width-2 box pattern (no shift)
+BATCH_BOX = dict(BATCH, name="batch96_box", boxes=(24, 32, 48, 64),
+                 common=dict(BATCH["common"], ilu_shift=0.0, subsolver="iluk_box", fill_level=0),
+                 text="batch96_box: the batch96 instances and steps with the subdomain ILU(0) on the width-2 box "
+                      "pattern (no shift), autotuned boxes, one batched NKS per step, tol 1e-8")
 WORKLOAD = WORKLOADS["periodic512"]
 
 
@@ -245,7 +250,7 @@ def batch_inputs():
     return fields, params
 
 
-def run_batch(steps: int, warmup: int, with_sequential: bool = True):
+def run_batch(steps: int, warmup: int, with_sequential: bool = True, B=BATCH):
     """The batched workload: autotune the box size, then time `steps` batched steps in
     FP64 and in mixed precision (fresh batches from the initial data), the batched
     preconditioner launch with HIP events on the batch stream, and the same instances
@@ -256,17 +261,17 @@ def run_batch(steps: int, warmup: int, with_sequential: bool = True):
     from paper_2007_04560_amd.batch import autotune, with_boxes
 
     fields, params = batch_inputs()
-    common = BATCH["common"]
+    common = B["common"]
     shapes = [u.shape for u, _ in fields]
     dof = np.array([2 * u.size for u, _ in fields])
     out = {"box": {}, "autotune_s_per_step": {}}
-    cache = os.path.join(tempfile.gettempdir(), "acch_batch_tune.json")
+    cache = os.path.join(tempfile.gettempdir(), "acch_batch_tune_%s.json" % B["name"])
     for prec in ("fp64", "mixed"):
         # box width tuned per precision (cached per instance-size mix, precision, overlap)
-        best, tune = autotune(fields, params, boxes=BATCH["boxes"], steps=1, cache=cache, precision=prec, **common)
+        best, tune = autotune(fields, params, boxes=B["boxes"], steps=1, cache=cache, precision=prec, **common)
         out["box"][prec] = best
         out["autotune_s_per_step"][prec] = {str(k): round(v, 4) for k, v in tune.items()}
-        sub_params = with_boxes(shapes, params, best, BATCH["overlap"])
+        sub_params = with_boxes(shapes, params, best, B["overlap"])
         out.setdefault("sub_params_by_precision", {})[prec] = sub_params
         if warmup > 0:
             with BatchSolver(fields, sub_params, precision=prec, **common) as b:
@@ -316,18 +321,20 @@ def run_batch(steps: int, warmup: int, with_sequential: bool = True):
     return out
 
 
-def batch_line(args):
-    from paper_2007_04560_amd.batch import parts_for
-    r = run_batch(args.steps, args.warmup, with_sequential=not args.no_sequential)
+def batch_line(args, B=BATCH):
+    r = run_batch(args.steps, args.warmup, with_sequential=not args.no_sequential, B=B)
     f = r["fp64"]
     value = f["dof_newton"] / f["elapsed"]
-    # algorithmic bytes of one batched RAS launch: per instance omega*16 + omega*24*8 + 16 per owned cell
-    d = BATCH["overlap"]
+    # algorithmic bytes of one batched Schwarz launch per instance: stencil pattern omega*16 +
+    # omega*24*8 + 16 per owned cell; box pattern (2*52 + 4)*8 + 16 per box cell (the L and U
+    # records, the box vector written and read in each sweep) + 16 per owned cell
+    box = B["common"].get("subsolver") == "iluk_box"
+    d = B["overlap"]
     bytes_launch = 0.0
     for (ny, nx), p in zip(r["shapes"], r["sub_params"]):
         kx, ky = p["sub"]
         box_cells = (nx + 2 * d * kx) * (ny + 2 * d * ky)
-        bytes_launch += box_cells * (16 + 24 * 8) + 16 * nx * ny
+        bytes_launch += box_cells * ((108 * 8 + 16) if box else (16 + 24 * 8)) + 16 * nx * ny
     achieved = bytes_launch / f["ras_avg_s"] / 1e9
     line = {
         "metric": "dof*Newton-steps/s at 1e-8 tol",
@@ -342,7 +349,7 @@ def batch_line(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": BATCH["text"], "instances": BATCH["count"], "dof": r["dof_total"],
+        "config": {"workload": B["text"], "instances": B["count"], "dof": r["dof_total"],
                    "box": r["box"], "autotune_s_per_step": r["autotune_s_per_step"],
                    "newton_its": f["newton"], "gmres_its": f["gmres"],
                    "batched_fp64_s": round(f["elapsed"], 4),
@@ -351,7 +358,7 @@ def batch_line(args):
                    "counters_fp64": f["counters"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_ras_apply2d (all subdomains of all instances)",
+                     "kernel": ("k_boxilu_apply2d" if box else "k_ras_apply2d") + " (all subdomains of all instances)",
                      "avg_us": round(f["ras_avg_s"] * 1e6, 2), "bytes_per_launch": int(bytes_launch)},
     }
     if "sequential" in r:
@@ -654,8 +661,8 @@ def main():
                     help="default workload: skip the mixed-precision, batched and 64x64 oracle comparisons")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP-event timers")
     ap.add_argument("--workload", default="periodic512",
-                    choices=sorted(WORKLOADS) + ["batch96", "adjoint512", "adjoint3d128", "adjoint512_box32", "study2d",
-                                                 "study3d"])
+                    choices=sorted(WORKLOADS) + ["batch96", "batch96_box", "adjoint512", "adjoint3d128",
+                                                 "adjoint512_box32", "study2d", "study3d"])
     ap.add_argument("--no-sequential", action="store_true", help="batch96: skip the one-by-one FP64 comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 64 MiB FP64 tensor 3 times (reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -689,13 +696,14 @@ def main():
             print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
             return 2
         return study_line(args) if args.workload == "study2d" else study3d_line(args)
-    if args.workload == "batch96":
+    if args.workload in ("batch96", "batch96_box"):
         if args.gpus != 1:
             print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus})", file=sys.stderr)
             return 2
+        B = BATCH if args.workload == "batch96" else BATCH_BOX
         if args.steps is None:
-            args.steps = BATCH["steps"]
-        return batch_line(args)
+            args.steps = B["steps"]
+        return batch_line(args, B)
     w = dict(WORKLOADS[args.workload])
     if args.precision:
         w["precision"] = args.precision
