@@ -297,7 +297,9 @@ int acch_adjoint_step(acch_ctx *c, const double *X1, const double *X0, double dt
 /* ---- Batches of independent instances ----------------------------------------
  * count instances, each described by its own acch_params (grid, boundary,
  * parameters, subdomains), advanced together at the common fixed dt of instance 0
- * (adaptive must be 0; overlap, precision and dt_fixed must agree).  Every kernel of
+ * (adaptive must be 0; overlap, precision, dt_fixed and the subdomain solver must
+ * agree; the left-restricted variant with ILU(0) on the stencil pattern or on the box
+ * pattern, ACCH_SUB_ILUK_BOX with fill_level 0, else ACCH_EUNSUPPORTED).  Every kernel of
  * a Newton-Krylov-Schwarz stage runs once for all instances: all subdomain
  * factorisations and triangular solves of all instances in one launch each; Newton
  * iterations, line searches and GMRES cycles run in lockstep with per-instance
