@@ -123,11 +123,12 @@ def test_box_pattern_batched_preconditioner_equals_each_instance():
         assert np.max(np.abs(z[xo:xo + n2] - zi)) <= 1e-13 * np.max(np.abs(zi)), i
 
 
-def test_batch_matches_oracle():
+@pytest.mark.parametrize("pattern", ["stencil", "box"])
+def test_batch_matches_oracle(pattern):
     fields, params = instances()
     fields, params = fields[:2], params[:2]
-    tight = dict(COMMON, newton_rtol=1e-12, newton_atol=1e-13, gmres_rtol=1e-13, gmres_atol=1e-15,
-                 gmres_max_restarts=30)
+    tight = dict(COMMON if pattern == "stencil" else BOX, newton_rtol=1e-12, newton_atol=1e-13, gmres_rtol=1e-13,
+                 gmres_atol=1e-15, gmres_max_restarts=30)
     with BatchSolver(fields, params, **tight) as b:
         b.step(2)
         E, M = b.energy()
