@@ -39,14 +39,17 @@ def with_boxes(shapes: Sequence[Tuple[int, int]], params: List[Dict], box: int, 
     return out
 
 
-def tune_key(shapes: Sequence[Tuple[int, int]], precision: str, overlap: int, boxes: Sequence[int]) -> str:
+def tune_key(shapes: Sequence[Tuple[int, int]], precision: str, overlap: int, boxes: Sequence[int],
+             solver: Tuple[str, int, float] = ("ilu0", 0, 0.0)) -> str:
     """Cache key of a tuning problem: the multiset of instance sizes, the precision, the
-    overlap and the candidate box widths."""
+    overlap, the candidate box widths and the subdomain solver (name, fill level, diagonal
+    shift), which decides both the iteration counts and the kernels that run."""
     counts: Dict[Tuple[int, int], int] = {}
     for s in shapes:
         counts[tuple(int(x) for x in s)] = counts.get(tuple(int(x) for x in s), 0) + 1
     return json.dumps({"shapes": sorted([list(k), v] for k, v in counts.items()), "precision": precision,
-                       "overlap": int(overlap), "boxes": [int(b) for b in boxes]}, sort_keys=True)
+                       "overlap": int(overlap), "boxes": [int(b) for b in boxes],
+                       "solver": [str(solver[0]), int(solver[1]), float(solver[2])]}, sort_keys=True)
 
 
 def _load_cache(path: str) -> Dict[str, dict]:
@@ -88,10 +91,12 @@ def autotune(fields, params, boxes: Sequence[int] = (24, 32, 48, 64), steps: int
              timer: Optional[Callable[..., float]] = None, **common):
     """Time `steps` batched steps for each candidate box size and return (best box,
     {box: seconds per step}).  With `cache` (a JSON file), a tuning problem already in
-    the file (same instance sizes, precision, overlap and candidates) is answered from
-    it without timing, and a new result is added to it."""
+    the file (same instance sizes, precision, overlap, candidates and subdomain solver) is
+    answered from it without timing, and a new result is added to it."""
     timer = timer or time_box
-    key = tune_key([u.shape for u, _ in fields], common.get("precision", "fp64"), common.get("overlap", 1), boxes)
+    solver = (common.get("subsolver", "ilu0"), common.get("fill_level", 0), common.get("ilu_shift", 0.0))
+    key = tune_key([u.shape for u, _ in fields], common.get("precision", "fp64"), common.get("overlap", 1), boxes,
+                   solver)
     if cache:
         hit = _load_cache(cache).get(key)
         if hit is not None:

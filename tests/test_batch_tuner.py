@@ -1,6 +1,7 @@
 """The batched autotuner's choice and its JSON cache (host logic, no GPU): the fastest
 candidate wins, a repeated tuning problem is answered from the cache without timing,
-and the key separates precisions, overlaps, candidate lists and instance-size mixes."""
+and the key separates precisions, overlaps, candidate lists, instance-size mixes and
+subdomain solvers."""
 import json
 
 import numpy as np
@@ -51,8 +52,21 @@ def test_key_depends_on_the_problem_only():
     for other in (tune_key([(128, 128), (96, 96)], "fp64", 2, (32, 48)),
                   tune_key([(128, 128), (96, 96), (128, 128)], "mixed", 2, (32, 48)),
                   tune_key([(128, 128), (96, 96), (128, 128)], "fp64", 1, (32, 48)),
-                  tune_key([(128, 128), (96, 96), (128, 128)], "fp64", 2, (32, 48, 64))):
+                  tune_key([(128, 128), (96, 96), (128, 128)], "fp64", 2, (32, 48, 64)),
+                  tune_key([(128, 128), (96, 96), (128, 128)], "fp64", 2, (32, 48), ("iluk_box", 0, 0.0)),
+                  tune_key([(128, 128), (96, 96), (128, 128)], "fp64", 2, (32, 48), ("ilu0", 0, 0.02))):
         assert other != base
+
+
+def test_subdomain_solver_is_another_problem(tmp_path):
+    """A width tuned for the stencil-pattern ILU(0) is not reused for the box pattern."""
+    cache = str(tmp_path / "tune.json")
+    fields = _fields([96, 128])
+    timer = FakeTimer(TABLE)
+    autotune(fields, [{}] * 2, boxes=(32, 48), cache=cache, timer=timer, overlap=2, ilu_shift=0.02)
+    autotune(fields, [{}] * 2, boxes=(32, 48), cache=cache, timer=timer, overlap=2, subsolver="iluk_box",
+             fill_level=0, ilu_shift=0.0)
+    assert len(timer.calls) == 4 and len(json.load(open(cache))) == 2
 
 
 def test_unreadable_cache_is_retuned_and_rewritten(tmp_path):
