@@ -601,7 +601,8 @@ def _rel_l2(a, b):
 def forms_summary(args, w, fp64_run):
     """The chosen forms next to the plain FP64 run: (1) mixed precision on the same
     workload (time, speedup, final-field difference to the FP64 run), (2) the batched
-    workload (batched FP64 and mixed against the instances solved one by one), and the
+    workload (batched FP64 and mixed against the instances solved one by one, and the same
+    batch with box-pattern ILU(0)), and the
     error of the GPU's FP64 and mixed results against the FP64 oracle on the 64 x 64
     periodic workload (10 steps at dt = 1e-3, both sides at Newton tolerance 1e-8)."""
     import numpy as np
@@ -628,6 +629,16 @@ def forms_summary(args, w, fp64_run):
                       "speedup_mixed_batched_vs_sequential": round(b["sequential"]["elapsed"] / b["mixed"]["elapsed"],
                                                                    3),
                       "value_fp64": round(b["fp64"]["dof_newton"] / b["fp64"]["elapsed"], 1)}
+    # the same batch with ILU(0) on the box pattern (its own autotuned widths)
+    bb = run_batch(BATCH_BOX["steps"], 1, with_sequential=False, B=BATCH_BOX)
+    out["batched_box"] = {"workload": BATCH_BOX["text"], "box": bb["box"],
+                          "batched_fp64_s": round(bb["fp64"]["elapsed"], 4),
+                          "batched_mixed_s": round(bb["mixed"]["elapsed"], 4),
+                          "gmres_per_newton_fp64": round(bb["fp64"]["gmres"] / max(1, bb["fp64"]["newton"]), 2),
+                          "value_fp64": round(bb["fp64"]["dof_newton"] / bb["fp64"]["elapsed"], 1),
+                          "value_mixed": round(bb["mixed"]["dof_newton"] / bb["mixed"]["elapsed"], 1),
+                          "time_vs_stencil_batch_fp64": round(bb["fp64"]["elapsed"] / b["fp64"]["elapsed"], 3),
+                          "time_vs_stencil_batch_mixed": round(bb["mixed"]["elapsed"] / b["mixed"]["elapsed"], 3)}
     shape = (64, 64)
     u0, v0 = random_ic(shape, 0)
     P = Problem(bc="periodic")
