@@ -347,3 +347,34 @@ def test_box32_workload_roots_at_sampled_steps():
         assert f1 <= 2e-8 * f0, (k, f1, f0)
         assert abs(scheme.mass(ug, P) - M0) <= 1e-12 * M0
         assert scheme.energy(ug, vg, P) < scheme.energy(up, vp, P)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind", ["left", "right", "classical"])
+def test_box_ilu0_wide_wavefronts(precision, kind):
+    """Boxes 54 wide (18 cells on a wavefront, more than one wave's quads hold, so the
+    256-thread sweeps): M^{-1} r against the oracle for the three variants."""
+    shape, bc, sub, ov = (60, 100), "neumann", (2, 1), 2
+    s, Jo = _setup(shape, bc, sub, ov, precision=precision, kind=kind)
+    info = s.info()
+    assert 16 < -(-info["box_w"] // 3) <= 32 and info["box_h"] >= 54   # 17 .. 32 cells on a wavefront
+    r = np.random.default_rng(15).standard_normal(Jo.shape[0])
+    z = s.precondition(dev(r)).cpu().numpy()
+    zo = schwarz.Schwarz(Jo, shape, (sub[1], sub[0]), ov, bc, kind=kind, solver="iluk_box", level=0).apply(r)
+    if precision == "fp64":
+        assert np.max(np.abs(z - zo)) <= 1e-10 * np.max(np.abs(zo))
+    else:
+        assert np.linalg.norm(z - zo) <= 1e-4 * np.linalg.norm(zo)
+
+
+@pytest.mark.parametrize("kind", ["left", "classical"])
+def test_box_ilu0_wide_wavefronts_transpose(kind):
+    """<M^{-T} a, b> = <a, M^{-1} b> on 68 x 68 boxes (23 cells on a wavefront)."""
+    s, _ = _setup((128, 128), "periodic", (2, 2), 2, kind=kind, dt=1e-3, seed=54)
+    assert 16 < -(-s.info()["box_w"] // 3) <= 32
+    rng = np.random.default_rng(16)
+    a = dev(rng.standard_normal(2 * 128 * 128))
+    b = dev(rng.standard_normal(2 * 128 * 128))
+    lhs = float(torch.dot(s.precondition_transpose(a), b))
+    rhs = float(torch.dot(a, s.precondition(b)))
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
