@@ -5,7 +5,8 @@ per stage; the subdomain box size trades parallelism (more, smaller boxes: more
 workgroups, shorter wavefront chains) against preconditioner quality (fewer GMRES
 iterations with larger boxes).  The autotuner times whole batched steps for a few
 box sizes on a copy of the batch and keeps the fastest, per tuning problem (the mix of
-instance sizes, the precision and the overlap), optionally cached in a JSON file.
+instance sizes, the precision, the overlap and the subdomain solver), optionally cached
+in a JSON file.
 """
 from __future__ import annotations
 

@@ -418,8 +418,10 @@ class BatchSolver:
     stage for all instances).  ``fields`` is a list of (u0, v0) host arrays, ``params``
     a list of per-instance keyword dicts for make_params (bc, L, alpha, ..., sub);
     ``common`` holds the settings shared by the batch (dt_fixed, tolerances,
-    precision, overlap, ilu_shift ...).  The batch runs on its own created stream so
-    that its GMRES cycles can be recorded into HIP graphs."""
+    precision, overlap, ilu_shift, and the subdomain solver: ILU(0) on the stencil
+    pattern, or subsolver="iluk_box" with fill_level=0 for ILU(0) on the box pattern).
+    The batch runs on its own created stream so that its GMRES cycles can be recorded
+    into HIP graphs."""
 
     def __init__(self, fields, params=None, device=None, graph: bool = True, **common):
         import torch
