@@ -283,7 +283,8 @@ def run_batch(steps: int, warmup: int, with_sequential: bool = True, B=BATCH):
         b.stream.synchronize()
         el = time.perf_counter() - t0
         r = {"elapsed": el, "newton": int(nit.sum()), "gmres": int(git.sum()),
-             "dof_newton": float((dof * nit).sum()), "counters": b.counters()}
+             "dof_newton": float((dof * nit).sum()), "counters": b.counters(),
+             "fields": [b.fields(i) for i in range(len(fields))]}   # after the timed region
         if prec == "fp64":
             info = b.info()
             x = torch.randn(2 * info["ncell"], dtype=torch.float64, device=b.device)
@@ -301,6 +302,9 @@ def run_batch(steps: int, warmup: int, with_sequential: bool = True, B=BATCH):
         b.close()
         out[prec] = r
     sub_params = out.pop("sub_params_by_precision")["fp64"]   # the FP64 batch's boxes
+    # Form 1 on the batch: the mixed-precision batch's final fields against the FP64 batch's
+    out["mixed_vs_fp64_max_rel_l2"] = max(_rel_l2(m, f) for m, f in zip(out["mixed"].pop("fields"),
+                                                                         out["fp64"].pop("fields")))
     if with_sequential:
         t_seq = 0.0
         n_seq = 0
@@ -355,6 +359,7 @@ def batch_line(args, B=BATCH):
                    "batched_fp64_s": round(f["elapsed"], 4),
                    "batched_mixed_s": round(r["mixed"]["elapsed"], 4),
                    "mixed_value": round(r["mixed"]["dof_newton"] / r["mixed"]["elapsed"], 1),
+                   "mixed_vs_fp64_final_fields_max_rel_l2": r["mixed_vs_fp64_max_rel_l2"],
                    "counters_fp64": f["counters"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -628,7 +633,8 @@ def forms_summary(args, w, fp64_run):
                       "speedup_batched_vs_sequential": round(b["sequential"]["elapsed"] / b["fp64"]["elapsed"], 3),
                       "speedup_mixed_batched_vs_sequential": round(b["sequential"]["elapsed"] / b["mixed"]["elapsed"],
                                                                    3),
-                      "value_fp64": round(b["fp64"]["dof_newton"] / b["fp64"]["elapsed"], 1)}
+                      "value_fp64": round(b["fp64"]["dof_newton"] / b["fp64"]["elapsed"], 1),
+                      "mixed_vs_fp64_final_fields_max_rel_l2": b["mixed_vs_fp64_max_rel_l2"]}
     # the same batch with ILU(0) on the box pattern (its own autotuned widths)
     bb = run_batch(BATCH_BOX["steps"], 1, with_sequential=False, B=BATCH_BOX)
     out["batched_box"] = {"workload": BATCH_BOX["text"], "box": bb["box"],
@@ -638,7 +644,8 @@ def forms_summary(args, w, fp64_run):
                           "value_fp64": round(bb["fp64"]["dof_newton"] / bb["fp64"]["elapsed"], 1),
                           "value_mixed": round(bb["mixed"]["dof_newton"] / bb["mixed"]["elapsed"], 1),
                           "time_vs_stencil_batch_fp64": round(bb["fp64"]["elapsed"] / b["fp64"]["elapsed"], 3),
-                          "time_vs_stencil_batch_mixed": round(bb["mixed"]["elapsed"] / b["mixed"]["elapsed"], 3)}
+                          "time_vs_stencil_batch_mixed": round(bb["mixed"]["elapsed"] / b["mixed"]["elapsed"], 3),
+                          "mixed_vs_fp64_final_fields_max_rel_l2": bb["mixed_vs_fp64_max_rel_l2"]}
     shape = (64, 64)
     u0, v0 = random_ic(shape, 0)
     P = Problem(bc="periodic")
