@@ -76,3 +76,26 @@ def test_zero_filled_switches_mean_the_documented_defaults(lib):
     assert (q.ilu_reuse, q.mass_projection, q.log_energy) == (-1, -1, -1)
     r = pkg.make_params((64, 64), ilu_reuse=False, mass_projection=True, log_energy=False)
     assert (r.ilu_reuse, r.mass_projection, r.log_energy) == (-1, 1, -1)
+
+
+def test_batch_subdomain_solver_rules(lib):
+    """Batches take ILU(0) on the stencil pattern or on the box pattern (its batched
+    kernels), one solver for all instances; ILU(k >= 1) and mixed solvers are refused
+    before any device work."""
+    import paper_2007_04560_amd as pkg
+    shapes, subs = [(24, 24), (40, 32), (33, 47)], [(2, 2), (2, 3), (3, 2)]
+
+    def batch(*kws):
+        arr = (pkg.Params * 3)()
+        for i in range(3):
+            arr[i] = pkg.make_params(shapes[i], sub=subs[i], dt_fixed=1e-3, overlap=1, **kws[i])
+        n = ctypes.c_size_t()
+        return lib.acch_batch_workspace_bytes(arr, 3, ctypes.byref(n)), n.value
+
+    box = dict(subsolver="iluk_box", fill_level=0)
+    rc0, n0 = batch({}, {}, {})
+    rc1, n1 = batch(box, box, box)
+    assert rc0 == 0 and rc1 == 0 and n1 > 0 and n0 > 0
+    assert batch(*[dict(box, fill_level=1)] * 3)[0] != 0           # ILU(1) is not batched
+    assert batch(*[dict(subsolver="lu")] * 3)[0] != 0
+    assert batch({}, box, {})[0] != 0                               # one solver for all instances
